@@ -1,0 +1,236 @@
+/*
+ * aero.h - C ABI of the AERO-MPPI planning-step library for AMD MI355X (gfx950).
+ *
+ * One planning step of the anchor-guided MPPI ensemble (Chen et al., "AERO-MPPI:
+ * Anchor-Guided Ensemble Trajectory Optimization for Agile Mapless Drone
+ * Navigation"):
+ *
+ *   aero_partition_anchors   Sec. IV-A (multi-resolution partition) and
+ *                            Sec. IV-B-1/2 (anchor sampling and refinement)
+ *   aero_build_guides        Sec. IV-B-3, eq. (polynomial): quintic guides
+ *   aero_mppi_step           Sec. III-B eqs. (mppi_rollout), (mppi_weights),
+ *                            (mppi_update) with the Stage-I cost of Sec. IV-C
+ *   aero_select_best         Sec. IV-C, Stage II: explicit rollouts, S2, argmin
+ *   aero_mppi_step_backward  gradient of the summed Stage-I cost with respect to
+ *                            the nominal controls and the five term weights
+ *
+ * Conventions shared by every call
+ *   - Pointers named d_* are device pointers (gfx950 global memory) owned by the
+ *     caller; h_* pointers are host memory read during the call only.  The
+ *     library never keeps or frees a caller pointer after the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *     device work is enqueued asynchronously on it; outputs are valid once the
+ *     stream has reached the end of the call's work.
+ *   - Arguments are validated on the host before anything is enqueued.  On any
+ *     error the call returns a nonzero aero_status, enqueues nothing and leaves
+ *     every output untouched.  Non-finite values inside device buffers are not
+ *     checked (behaviour undefined).
+ *   - Frame: the cloud is given relative to the drone (world axes, z up); the
+ *     state, goal and anchors are expressed in the same frame.
+ *   - Calls on different streams are re-entrant; calls that share an output
+ *     buffer must be ordered by the caller.
+ */
+#ifndef AERO_H
+#define AERO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum aero_status {
+  AERO_OK = 0,
+  AERO_ERR_NULL = 1,      /* a required pointer is NULL                         */
+  AERO_ERR_SHAPE = 2,     /* a size is out of range (see each call)             */
+  AERO_ERR_PARAM = 3,     /* a parameter is non-finite or outside its domain    */
+  AERO_ERR_WORKSPACE = 4, /* workspace NULL or smaller than the size query      */
+  AERO_ERR_DEVICE = 5     /* the HIP runtime reported an error on enqueue       */
+} aero_status;
+
+#define AERO_N_MAX 512        /* longest horizon N                                */
+#define AERO_M_MAX 256        /* most MPPI instances per problem                  */
+#define AERO_K_MAX (1 << 20)  /* most samples per instance                        */
+#define AERO_BATCH_MAX 2048   /* most problems per call                           */
+#define AERO_GRID_MAX 8192    /* most fine cells along one angular axis           */
+
+/* Table I parameters shared by all problems of a call (float32 values). */
+typedef struct aero_params {
+  float dt;           /* RK4 step [s] (> 0)                                        */
+  float lambda;       /* temperature of eq. (mppi_weights) (> 0)                   */
+  float mass;         /* m [kg] (> 0)                                              */
+  float gravity;      /* |g| [m/s^2], g = (0, 0, -gravity)                         */
+  float sigma[4];     /* noise std per channel (F_t, wx, wy, wz) (>= 0)            */
+  float u_min[4];     /* control box, u_min <= u_max per channel                   */
+  float u_max[4];
+  float Q_track, Q_vnorm, Q_c, Q_cdelta, Q_p, Q_v, Q_q;  /* term weights (scalars) */
+  float C;            /* collision scale (>= 0)                                    */
+  float a;            /* collision slope (>= 0)                                    */
+  float d_min, d_max; /* 0 <= d_min < d_max                                        */
+  float w[5];         /* multipliers of (J_track, J_vnorm, J_ctrl, J_goal, J_col)  */
+  uint64_t seed;      /* noise key: Philox key = (seed_lo, seed_hi ^ problem_id)   */
+  uint32_t iter_base; /* noise counter word 3 (the MPPI iteration index)           */
+  uint32_t reserved;  /* must be 0                                                 */
+} aero_params;
+
+/* One planning problem (host struct; device pointers inside). */
+typedef struct aero_problem {
+  const float* cloud;   /* device [n_points][3] float32, collision set              */
+  int32_t n_points;     /* >= 0 (0 = no obstacles)                                  */
+  int32_t M;            /* instances, 1..AERO_M_MAX                                 */
+  int32_t K;            /* samples per instance, 1..AERO_K_MAX                      */
+  int32_t N;            /* horizon, 2..AERO_N_MAX                                   */
+  uint32_t problem_id;  /* mixed into the noise key                                 */
+  float x0[10];         /* p (3), q (w, x, y, z), v (3); |q| > 0                    */
+  float p_goal[3], v_goal[3], q_goal[4];
+  const float* coef;    /* device [M][3][6] guide coefficients a_{i,mu} (Stage I)   */
+  float* u_nom;         /* device [M][N][4] nominal controls; updated in place      */
+  double* S1;           /* optional device [M][K]: Stage-I cost of every sample     */
+  float* delta_eff;     /* optional device [M][N][4][K]: clipped perturbations      */
+  float* min_dist2;     /* optional device [M][N][K]: squared nearest distance      */
+} aero_problem;
+
+/* Angular grid of the multi-resolution partition (Sec. IV-A). */
+typedef struct aero_partition_spec {
+  int32_t n_az_c, n_el_c;  /* coarse cells in azimuth / elevation (>= 1)            */
+  int32_t f_a, f_e;        /* pooling factors: fine grid (n_az_c f_a) x (n_el_c f_e) */
+  int32_t M_h, M_v;        /* anchor block, 1 <= M_h <= n_az_c, 1 <= M_v <= n_el_c   */
+  float r_max;             /* perception range (> 0)                                 */
+  float ell;               /* look-ahead distance of the anchors                     */
+  float p0[3];             /* drone position in the frame of the anchors             */
+  const float* d_tables;   /* device copy of aero_partition_tables() for this grid   */
+} aero_partition_spec;
+
+/* ---- host helpers ------------------------------------------------------------ */
+
+/* Number of floats in the direction tables of an n_az x n_el fine grid. */
+size_t aero_partition_tables_size(int32_t n_az, int32_t n_el);
+
+/* Fill h_out (aero_partition_tables_size floats, host) with the float32 tables
+ * the partition is decided on (Sec. IV-A, eq. (unit direction)):
+ *   [0, 2 n_az)            (cos, sin) of azimuth boundaries -pi + 2 pi i / n_az
+ *   [.., + 2 (n_el + 1))   (cos, sin) of elevation boundaries -pi/2 + pi j / n_el
+ *   [.., + 2 n_az)         (cos, sin) of azimuth cell centres
+ *   [.., + 2 n_el)         (cos, sin) of elevation cell centres
+ * Angles are formed in binary64 and rounded to float32 after cos/sin.
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (n_az < 3, n_el < 1, either > AERO_GRID_MAX,
+ * or n_floats too small).  Host only; touches no device. */
+int aero_partition_tables(int32_t n_az, int32_t n_el, float* h_out, size_t n_floats);
+
+/* Which call a workspace is for. */
+typedef enum aero_call {
+  AERO_CALL_MPPI_STEP = 0,
+  AERO_CALL_SELECT_BEST = 1,
+  AERO_CALL_BACKWARD = 2
+} aero_call;
+
+/* Bytes of device workspace the given call needs for these problems (0 on a
+ * NULL or invalid argument).  Pure host arithmetic. */
+size_t aero_workspace_size(int which_call, const aero_problem* h_problems, int32_t n_problems);
+
+/* Human-readable text of a status code (static storage). */
+const char* aero_status_string(int status);
+
+/* ---- the planning step ---------------------------------------------------------- */
+
+/* Multi-resolution partition and anchors (Sec. IV-A eqs. (unit direction),
+ * (safe-vector); Sec. IV-B-1/2 eq. (anchor-point)).
+ *   d_cloud       [n_points][3] float32, relative to the drone
+ *   h_goal_dir    [3] goal direction (zero vector = +x heading)
+ *   d_fine_key    [n_el_f * n_az_f] float64: min r^2 per cone (r_max^2 if empty),
+ *                 flat index c = j * n_az_f + i (i azimuth, j elevation)
+ *   d_fine_idx    [n_el_f * n_az_f] int32: lowest point index attaining it, -1 if empty
+ *   d_coarse_best [n_el_c * n_az_c] int32: fine index of the max-range cone of each
+ *                 coarse cell (ties: lowest c), coarse flat index J * n_az_c + I
+ *   d_anchor_cell [M_h * M_v] int32 coarse cell of anchor m = o_v * M_h + o_h
+ *   d_anchor_fine [M_h * M_v] int32 fine cone of anchor m
+ *   d_anchors     [M_h * M_v][3] float32: p0 + ell * d(anchor cone)
+ * Integer outputs are decided by exact binary64 predicates on the float32 tables,
+ * so they are reproducible bit for bit.
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (grid or block out of range, n_points < 0),
+ * AERO_ERR_PARAM (r_max <= 0 or non-finite inputs), AERO_ERR_DEVICE. */
+int aero_partition_anchors(const aero_partition_spec* h_spec, const float* d_cloud,
+                           int32_t n_points, const float* h_goal_dir, double* d_fine_key,
+                           int32_t* d_fine_idx, int32_t* d_coarse_best, int32_t* d_anchor_cell,
+                           int32_t* d_anchor_fine, float* d_anchors, void* stream);
+
+/* Quintic guides (Sec. IV-B-3, eq. (polynomial)): per anchor m and axis mu, the six
+ * coefficients of f(t) = sum_i a_i t^i on [0, T] meeting position, velocity and
+ * acceleration at both ends.  Start (h_p0, h_v0, h_a0) (host [3] each); end
+ * (d_anchors[m], end velocity, end acceleration).  d_end_vel / d_end_acc (device
+ * [M][3]) may be NULL: end velocity |v0| * unit(anchor - p0), end acceleration 0.
+ *   d_coef [M][3][6] float32 output.
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (M < 1 or > AERO_M_MAX), AERO_ERR_PARAM
+ * (horizon_T <= 0 or non-finite), AERO_ERR_DEVICE. */
+int aero_build_guides(const float* h_p0, const float* h_v0, const float* h_a0,
+                      const float* d_anchors, const float* d_end_vel, const float* d_end_acc,
+                      float horizon_T, int32_t M, float* d_coef, void* stream);
+
+/* One Stage-I MPPI iteration for every instance of every problem (Sec. III-B,
+ * Sec. IV-C): Philox noise, clipped controls, RK4 rollouts, S1 (brute-force nearest
+ * distance to the raw cloud for J_col), softmax weights and the update of u_nom
+ * (in place).  Problems may differ in cloud size, M, K and N; n_problems > 1 runs
+ * them in one batched launch sequence.
+ *   h_problems  host array [n_problems]
+ *   d_ws        device workspace of aero_workspace_size(AERO_CALL_MPPI_STEP, ...)
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE, AERO_ERR_PARAM (lambda <= 0, dt <= 0,
+ * mass <= 0, sigma < 0, u_min > u_max, d_min >= d_max, non-finite values),
+ * AERO_ERR_WORKSPACE, AERO_ERR_DEVICE. */
+int aero_mppi_step(const aero_params* h_prm, const aero_problem* h_problems,
+                   int32_t n_problems, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Stage II (Sec. IV-C): roll out each instance's u_nom without noise, score it with
+ * S2 = w_goal J_goal + w_col J_col and pick the lowest (ties: lowest m).
+ *   d_S2    [sum_b M_b] float64, problems concatenated
+ *   d_best  [n_problems] int32
+ * coef, S1, delta_eff and min_dist2 of the problems are ignored.
+ * Errors: as aero_mppi_step. */
+int aero_select_best(const aero_params* h_prm, const aero_problem* h_problems,
+                     int32_t n_problems, double* d_S2, int32_t* d_best, void* d_ws,
+                     size_t ws_bytes, void* stream);
+
+/* Adjoint of L = scale * sum_{m,k} S1[m,k] for one problem, evaluated at the
+ * problem's u_nom (read only) with the same noise as aero_mppi_step:
+ *   d_grad_u_nom [M][N][4] float32 = dL/du_nom (zero where the sample was clipped)
+ *   d_grad_w     [5] float32       = dL/dw = scale * sum_{m,k} J_i
+ * The derivative is the exact one of the active smooth piece: clip mask, collision
+ * branch and nearest point (lowest index on ties) held fixed.  Rollout states are
+ * checkpointed every 8 steps and recomputed.
+ * Errors: as aero_mppi_step. */
+int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h_problem,
+                            float scale, float* d_grad_u_nom, float* d_grad_w, void* d_ws,
+                            size_t ws_bytes, void* stream);
+
+/* ---- per-kernel timing (profiling aid) ---------------------------------------- */
+
+/* Kernel identifiers for aero_timing_read. */
+typedef enum aero_kernel {
+  AERO_K_PARTITION = 0,    /* the four partition/anchor kernels of one call         */
+  AERO_K_GUIDES = 1,
+  AERO_K_ROLLOUT = 2,      /* Stage-I noise + RK4 rollout                           */
+  AERO_K_MIN_DIST = 3,     /* Stage-I brute-force nearest distance                  */
+  AERO_K_FINALIZE = 4,     /* Stage-I J_col and S1                                  */
+  AERO_K_UPDATE = 5,       /* softmax weights and control update                    */
+  AERO_K_SEL_ROLLOUT = 6,  /* Stage-II rollout                                      */
+  AERO_K_SEL_MIN_DIST = 7, /* Stage-II nearest distance                             */
+  AERO_K_SEL_FINAL = 8,    /* Stage-II S2 and argmin                                */
+  AERO_K_COUNT = 9
+} aero_kernel;
+
+/* on != 0: from now on every launch of the kernels above is bracketed by two HIP
+ * events recorded on the launch's own stream (adds a few microseconds per launch);
+ * on == 0 stops recording.  Returns AERO_OK. */
+int aero_timing_enable(int on);
+
+/* Total event-measured milliseconds and number of launches recorded for `kernel`
+ * since the last reset; waits for the recorded events.  reset != 0 clears all
+ * counters afterwards.  Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (unknown kernel),
+ * AERO_ERR_DEVICE. */
+int aero_timing_read(int kernel, double* h_total_ms, int64_t* h_launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AERO_H */

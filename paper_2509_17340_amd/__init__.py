@@ -1,0 +1,263 @@
+"""AERO-MPPI planning step on AMD MI355X: thin Python binding of libaero.so.
+
+Every function here only marshals arguments (tensor pointers, the current HIP
+stream, host structs) into the C ABI declared in include/aero.h; all
+arithmetic of the planning step runs in the library's HIP kernels.  Importing
+the package fails loudly if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "AeroError", "lib", "params_struct", "Problem", "partition_tables", "partition_anchors",
+    "build_guides", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
+    "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
+    "KERNELS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaero.so")
+
+CALL_MPPI_STEP, CALL_SELECT_BEST, CALL_BACKWARD = 0, 1, 2
+
+
+class AeroError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.aero_status_string(status).decode() if _lib else str(status)
+        super().__init__(f"{where}: {msg}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_float), ("lambda_", ctypes.c_float), ("mass", ctypes.c_float),
+        ("gravity", ctypes.c_float), ("sigma", ctypes.c_float * 4),
+        ("u_min", ctypes.c_float * 4), ("u_max", ctypes.c_float * 4),
+        ("Q_track", ctypes.c_float), ("Q_vnorm", ctypes.c_float), ("Q_c", ctypes.c_float),
+        ("Q_cdelta", ctypes.c_float), ("Q_p", ctypes.c_float), ("Q_v", ctypes.c_float),
+        ("Q_q", ctypes.c_float), ("C", ctypes.c_float), ("a", ctypes.c_float),
+        ("d_min", ctypes.c_float), ("d_max", ctypes.c_float), ("w", ctypes.c_float * 5),
+        ("seed", ctypes.c_uint64), ("iter_base", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+    ]
+
+
+class ProblemStruct(ctypes.Structure):
+    _fields_ = [
+        ("cloud", ctypes.c_void_p), ("n_points", ctypes.c_int32), ("M", ctypes.c_int32),
+        ("K", ctypes.c_int32), ("N", ctypes.c_int32), ("problem_id", ctypes.c_uint32),
+        ("x0", ctypes.c_float * 10), ("p_goal", ctypes.c_float * 3),
+        ("v_goal", ctypes.c_float * 3), ("q_goal", ctypes.c_float * 4),
+        ("coef", ctypes.c_void_p), ("u_nom", ctypes.c_void_p), ("S1", ctypes.c_void_p),
+        ("delta_eff", ctypes.c_void_p), ("min_dist2", ctypes.c_void_p),
+    ]
+
+
+class PartitionSpec(ctypes.Structure):
+    _fields_ = [
+        ("n_az_c", ctypes.c_int32), ("n_el_c", ctypes.c_int32), ("f_a", ctypes.c_int32),
+        ("f_e", ctypes.c_int32), ("M_h", ctypes.c_int32), ("M_v", ctypes.c_int32),
+        ("r_max", ctypes.c_float), ("ell", ctypes.c_float), ("p0", ctypes.c_float * 3),
+        ("d_tables", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "aero_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "aero_partition_tables_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "aero_partition_tables": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t]),
+    "aero_workspace_size": (ctypes.c_size_t, [ctypes.c_int, _P, ctypes.c_int32]),
+    "aero_partition_anchors": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
+                                              _P]),
+    "aero_build_guides": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32,
+                                         _P, _P]),
+    "aero_mppi_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "aero_select_best": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
+    "aero_mppi_step_backward": (ctypes.c_int, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_size_t,
+                                               _P]),
+    "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "aero_timing_read": (ctypes.c_int, [ctypes.c_int, _P, _P, ctypes.c_int]),
+}
+
+KERNELS = ("partition", "guides", "rollout", "min_dist", "finalize", "update", "sel_rollout",
+           "sel_min_dist", "sel_final")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2509_17340_amd/build.py`")
+    lib_ = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib_, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib_
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(status, where):
+    if status != 0:
+        raise AeroError(status, where)
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor / array, or None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return int(t)
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    import torch
+    if torch.cuda.is_available():
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+def params_struct(prm):
+    """aero_params from a dict with the keys of fixtures.table1_params."""
+    p = Params()
+    p.dt, p.lambda_, p.mass, p.gravity = prm["dt"], prm["lam"], prm["mass"], prm["gravity"]
+    for c in range(4):
+        p.sigma[c], p.u_min[c], p.u_max[c] = prm["sigma"][c], prm["u_min"][c], prm["u_max"][c]
+    for k in ("Q_track", "Q_vnorm", "Q_c", "Q_cdelta", "Q_p", "Q_v", "Q_q", "C", "a", "d_min",
+              "d_max"):
+        setattr(p, k, float(prm[k]))
+    for i in range(5):
+        p.w[i] = float(prm["w"][i])
+    p.seed = int(prm.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    p.iter_base = int(prm.get("iter_base", 0))
+    p.reserved = 0
+    return p
+
+
+class Problem:
+    """One planning problem: device tensors plus host scalars (see aero_problem)."""
+
+    def __init__(self, cloud, M, K, N, x0, p_goal, u_nom, coef=None, v_goal=(0, 0, 0),
+                 q_goal=(1, 0, 0, 0), S1=None, delta_eff=None, min_dist2=None, problem_id=0,
+                 n_points=None):
+        self.cloud, self.M, self.K, self.N = cloud, int(M), int(K), int(N)
+        self.n_points = int(cloud.shape[0]) if n_points is None else int(n_points)
+        self.x0 = np.asarray(x0, np.float32)
+        self.p_goal = np.asarray(p_goal, np.float32)
+        self.v_goal = np.asarray(v_goal, np.float32)
+        self.q_goal = np.asarray(q_goal, np.float32)
+        self.u_nom, self.coef = u_nom, coef
+        self.S1, self.delta_eff, self.min_dist2 = S1, delta_eff, min_dist2
+        self.problem_id = int(problem_id)
+
+    def struct(self):
+        s = ProblemStruct()
+        s.cloud = _ptr(self.cloud) if self.n_points > 0 else None
+        s.n_points, s.M, s.K, s.N = self.n_points, self.M, self.K, self.N
+        s.problem_id = self.problem_id
+        s.x0[:] = [float(v) for v in self.x0]
+        s.p_goal[:] = [float(v) for v in self.p_goal]
+        s.v_goal[:] = [float(v) for v in self.v_goal]
+        s.q_goal[:] = [float(v) for v in self.q_goal]
+        s.coef, s.u_nom = _ptr(self.coef), _ptr(self.u_nom)
+        s.S1, s.delta_eff, s.min_dist2 = _ptr(self.S1), _ptr(self.delta_eff), _ptr(self.min_dist2)
+        return s
+
+
+def _problem_array(problems):
+    arr = (ProblemStruct * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = p.struct()
+    return arr
+
+
+def partition_tables(n_az, n_el):
+    n = _lib.aero_partition_tables_size(n_az, n_el)
+    out = np.zeros(max(int(n), 1), np.float32)
+    _check(_lib.aero_partition_tables(n_az, n_el, out.ctypes.data, out.size), "aero_partition_tables")
+    return out
+
+
+def partition_anchors(n_az_c, n_el_c, f_a, f_e, M_h, M_v, r_max, ell, p0, d_tables, cloud,
+                      goal_dir, fine_key, fine_idx, coarse_best, anchor_cell, anchor_fine, anchors,
+                      n_points=None, stream=None):
+    spec = PartitionSpec()
+    spec.n_az_c, spec.n_el_c, spec.f_a, spec.f_e = n_az_c, n_el_c, f_a, f_e
+    spec.M_h, spec.M_v, spec.r_max, spec.ell = M_h, M_v, float(r_max), float(ell)
+    spec.p0[:] = [float(v) for v in p0]
+    spec.d_tables = _ptr(d_tables)
+    g = np.ascontiguousarray(goal_dir, np.float32)
+    n = int(cloud.shape[0]) if n_points is None else int(n_points)
+    _check(_lib.aero_partition_anchors(
+        ctypes.byref(spec), _ptr(cloud) if n > 0 else None, n, g.ctypes.data, _ptr(fine_key),
+        _ptr(fine_idx), _ptr(coarse_best), _ptr(anchor_cell), _ptr(anchor_fine), _ptr(anchors),
+        _stream(stream)), "aero_partition_anchors")
+
+
+def build_guides(p0, v0, a0, anchors, horizon_T, M, coef, end_vel=None, end_acc=None,
+                 stream=None):
+    p0 = np.ascontiguousarray(p0, np.float32)
+    v0 = np.ascontiguousarray(v0, np.float32)
+    a0 = np.ascontiguousarray(a0, np.float32)
+    _check(_lib.aero_build_guides(p0.ctypes.data, v0.ctypes.data, a0.ctypes.data, _ptr(anchors),
+                                  _ptr(end_vel), _ptr(end_acc), float(horizon_T), int(M),
+                                  _ptr(coef), _stream(stream)), "aero_build_guides")
+
+
+def workspace_size(which, problems):
+    arr = _problem_array(problems)
+    return int(_lib.aero_workspace_size(which, ctypes.cast(arr, ctypes.c_void_p), len(problems)))
+
+
+def mppi_step(prm, problems, ws, ws_bytes=None, stream=None):
+    p = params_struct(prm) if isinstance(prm, dict) else prm
+    arr = _problem_array(problems)
+    nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.aero_mppi_step(ctypes.byref(p), ctypes.cast(arr, ctypes.c_void_p), len(problems),
+                               _ptr(ws), nbytes, _stream(stream)), "aero_mppi_step")
+
+
+def select_best(prm, problems, S2, best, ws, ws_bytes=None, stream=None):
+    p = params_struct(prm) if isinstance(prm, dict) else prm
+    arr = _problem_array(problems)
+    nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.aero_select_best(ctypes.byref(p), ctypes.cast(arr, ctypes.c_void_p), len(problems),
+                                 _ptr(S2), _ptr(best), _ptr(ws), nbytes, _stream(stream)),
+           "aero_select_best")
+
+
+def timing_enable(on=True):
+    _check(_lib.aero_timing_enable(1 if on else 0), "aero_timing_enable")
+
+
+def timing_read(reset=False):
+    """{kernel name: (total ms, launches)} from the library's event timers."""
+    out = {}
+    for i, name in enumerate(KERNELS):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        last = reset and i == len(KERNELS) - 1
+        _check(_lib.aero_timing_read(i, ctypes.byref(ms), ctypes.byref(n), 1 if last else 0),
+               "aero_timing_read")
+        out[name] = (ms.value, n.value)
+    return out
+
+
+def mppi_step_backward(prm, problem, scale, grad_u_nom, grad_w, ws, ws_bytes=None, stream=None):
+    p = params_struct(prm) if isinstance(prm, dict) else prm
+    s = problem.struct()
+    nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.aero_mppi_step_backward(ctypes.byref(p), ctypes.byref(s), float(scale),
+                                        _ptr(grad_u_nom), _ptr(grad_w), _ptr(ws), nbytes,
+                                        _stream(stream)), "aero_mppi_step_backward")

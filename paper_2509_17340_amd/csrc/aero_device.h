@@ -1,0 +1,174 @@
+// Device building blocks of the planning step (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "aero_internal.h"
+
+namespace aero {
+
+// ---------------------------------------------------------------------------
+// Counter-based noise: Philox4x32 with 10 rounds (Salmon et al., SC'11).  Each
+// round multiplies counter words 0 and 2 by the two round constants, folds the
+// high halves into words 1 and 3 with the key, and the key advances by the two
+// Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo0 = 0xD2511F53u * c[0];
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2];
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Box-Muller (1958) in binary64: u1 = (a + 1) 2^-32 in (0, 1], u2 = b 2^-32.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& n0, double& n1) {
+  const double u1 = ((double)a + 1.0) * 0x1p-32;
+  const double u2 = (double)b * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  n0 = r * c;
+  n1 = r * s;
+}
+
+// Four standard normals for (sample k, step t, instance m) of a problem.
+__device__ __forceinline__ void normals4(const DevParams& prm, uint32_t problem_id, uint32_t k,
+                                         uint32_t t, uint32_t m, double n[4]) {
+  uint32_t c[4] = {k, t, m, prm.iter_base};
+  philox4x32_10(c, prm.seed_lo, prm.seed_hi ^ problem_id);
+  box_muller(c[0], c[1], n[0], n[1]);
+  box_muller(c[2], c[3], n[2], n[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Quadrotor model (Sec. III-A): x = [p, q(w,x,y,z), v], u = (F_t, omega_body).
+// ---------------------------------------------------------------------------
+struct Dyn {
+  double inv_m, g;
+};
+
+__device__ __forceinline__ void xdot(const double* x, const double* u, const Dyn& d, double* dx) {
+  const double qw = x[3], qx = x[4], qy = x[5], qz = x[6];
+  const double wx = u[1], wy = u[2], wz = u[3];
+  dx[0] = x[7];
+  dx[1] = x[8];
+  dx[2] = x[9];
+  // q' = 1/2 q (x) (0, omega)
+  dx[3] = 0.5 * (-qx * wx - qy * wy - qz * wz);
+  dx[4] = 0.5 * (qw * wx + qy * wz - qz * wy);
+  dx[5] = 0.5 * (qw * wy - qx * wz + qz * wx);
+  dx[6] = 0.5 * (qw * wz + qx * wy - qy * wx);
+  // v' = (F/m) R(q) e3 + g, R(q) e3 = (2(xz+wy), 2(yz-wx), 1-2(x^2+y^2))
+  const double am = u[0] * d.inv_m;
+  dx[7] = am * (2.0 * (qx * qz + qw * qy));
+  dx[8] = am * (2.0 * (qy * qz - qw * qx));
+  dx[9] = am * (1.0 - 2.0 * (qx * qx + qy * qy)) - d.g;
+}
+
+// One RK4 step with the control held, then quaternion renormalisation.
+__device__ __forceinline__ void rk4(double* x, const double* u, double dt, const Dyn& d) {
+  double k1[10], k2[10], k3[10], k4[10], y[10];
+  xdot(x, u, d, k1);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) y[i] = x[i] + 0.5 * dt * k1[i];
+  xdot(y, u, d, k2);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) y[i] = x[i] + 0.5 * dt * k2[i];
+  xdot(y, u, d, k3);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) y[i] = x[i] + dt * k3[i];
+  xdot(y, u, d, k4);
+  const double h6 = dt / 6.0;
+#pragma unroll
+  for (int i = 0; i < 10; ++i) x[i] = x[i] + h6 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+  const double inv = 1.0 / sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
+  x[3] *= inv;
+  x[4] *= inv;
+  x[5] *= inv;
+  x[6] *= inv;
+}
+
+// R(q) of a unit quaternion, row-major.
+__device__ __forceinline__ void rotmat(double w, double x, double y, double z, double R[9]) {
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// |R(q) Rg^T - I|_F with Rg precomputed.
+__device__ __forceinline__ double attitude_err(const double* x, const double Rg[9]) {
+  double R[9];
+  rotmat(x[3], x[4], x[5], x[6], R);
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double e = R[3 * i] * Rg[3 * j] + R[3 * i + 1] * Rg[3 * j + 1] + R[3 * i + 2] * Rg[3 * j + 2];
+      if (i == j) e -= 1.0;
+      s += e * e;
+    }
+  return sqrt(s);
+}
+
+// Running goal term Q_p |p - pg| + Q_v |v - vg| + Q_q |R Rg^T - I|_F.
+__device__ __forceinline__ double goal_term(const double* x, const double pg[3], const double vg[3],
+                                            const double Rg[9], const DevParams& prm) {
+  const double ex = x[0] - pg[0], ey = x[1] - pg[1], ez = x[2] - pg[2];
+  const double fx = x[7] - vg[0], fy = x[8] - vg[1], fz = x[9] - vg[2];
+  return prm.Q_p * sqrt(ex * ex + ey * ey + ez * ez) + prm.Q_v * sqrt(fx * fx + fy * fy + fz * fz) +
+         prm.Q_q * attitude_err(x, Rg);
+}
+
+// Collision penalty phi(d) (Sec. IV-C, collision cost).
+__device__ __forceinline__ double collision_phi(double d, const DevParams& prm) {
+  if (d < prm.d_min) return prm.C;
+  if (d < prm.d_max) return prm.C * exp(-prm.a * (d - prm.d_min));
+  return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 / block reductions with a fixed combination order (deterministic).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Locate the record owning flat index i in an array of prefix bases.
+template <typename T, typename F>
+__device__ __forceinline__ int find_owner(const T* recs, int n, int64_t i, F base_of) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (base_of(recs[mid]) <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace aero

@@ -1,0 +1,93 @@
+// Host/device shared layout of the AERO-MPPI library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/aero.h"
+
+namespace aero {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kTilePts = 1024;       // cloud points staged in LDS per tile
+constexpr int kQueriesPerLane = 8;   // rollout positions held in registers per lane
+constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
+
+// Per-problem record, built on the host and copied into the workspace.
+struct DevProblem {
+  const float* cloud;
+  int32_t n_points, M, K, N;
+  uint32_t problem_id, pad0;
+  float x0[10];
+  float pg[3], vg[3], qg[4];
+  const float* coef;     // [M][3][6]
+  float* u_nom;          // [M][N][4]
+  double* S1;            // [M][K]
+  double* S_smooth;      // [M][K]  weighted J_track + J_vnorm + J_ctrl + J_goal
+  float* deff;           // [M][N][4][K]
+  float* pos;            // [3][M][N][K] planes x, y, z
+  unsigned* mind2;       // [M][N][K] float bits of the squared nearest distance
+  int64_t sample_base;   // prefix of M*K over problems
+  int64_t row_base;      // prefix of M*N over problems
+};
+
+// One set of query positions scored against one cloud by the distance kernel.
+struct QuerySet {
+  const float* px;
+  const float* py;
+  const float* pz;
+  unsigned* out;         // min squared distance as float bits, pre-filled with +inf
+  const float* cloud;    // [n_points][3]
+  int64_t Q;             // queries
+  int32_t n_points;
+  int32_t n_qblocks;     // ceil(Q / kQueriesPerBlock)
+  int32_t n_chunks;      // splits of the cloud, each a whole number of tiles
+  int32_t n_tiles;       // ceil(n_points / kTilePts)
+  int64_t block_base;    // prefix of n_qblocks * n_chunks over sets
+};
+
+// Parameters promoted once on the host.
+struct DevParams {
+  double dt, lambda, mass, gravity;
+  double sigma[4], u_min[4], u_max[4];
+  double Q_track, Q_vnorm, Q_c, Q_cdelta, Q_p, Q_v, Q_q, C, a, d_min, d_max;
+  double w[5];
+  uint32_t seed_lo, seed_hi, iter_base, pad;
+};
+
+// Per-problem Stage-II record.
+struct DevSelect {
+  const float* cloud;
+  int32_t n_points, M, N, pad0;
+  float x0[10];
+  float pg[3], vg[3], qg[4];
+  const float* u_nom;    // [M][N][4]
+  double* goal_cost;     // [M] weighted J_goal
+  float* pos;            // [3][M][N]
+  unsigned* mind2;       // [M][N]
+  double* S2;            // [M] (caller's array + offset)
+  int32_t* best;         // caller's array + problem index
+  int64_t inst_base;     // prefix of M
+};
+
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_partition(const aero_partition_spec& spec, const float* cloud, int n_points,
+                            const float goal[3], double* fine_key, int32_t* fine_idx,
+                            int32_t* coarse_best, int32_t* anchor_cell, int32_t* anchor_fine,
+                            float* anchors, hipStream_t s);
+hipError_t launch_guides(const double p0[3], const double v0[3], const double a0[3],
+                         const float* anchors, const float* end_vel, const float* end_acc,
+                         double T, int M, float* coef, hipStream_t s);
+hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_samples,
+                          const DevParams& prm, hipStream_t s);
+hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                           hipStream_t s);
+hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_samples,
+                           const DevParams& prm, hipStream_t s);
+hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
+                         const DevParams& prm, hipStream_t s);
+hipError_t launch_select_rollout(const DevSelect* d_sel, int n, int64_t total_inst,
+                                 const DevParams& prm, hipStream_t s);
+hipError_t launch_select_final(const DevSelect* d_sel, int n, const DevParams& prm,
+                               hipStream_t s);
+
+}  // namespace aero

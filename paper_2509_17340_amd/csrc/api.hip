@@ -1,0 +1,569 @@
+// C ABI entry points: host validation, workspace layout, descriptor staging and
+// the launch sequence of each call.  See include/aero.h for the contract.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "aero_internal.h"
+
+using namespace aero;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+inline bool finite(float v) { return std::isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// Descriptor staging: per-device pinned host ring; a slot is reused only after
+// the copy that read it has completed on its stream.
+// ---------------------------------------------------------------------------
+constexpr int kSlots = 16;
+constexpr size_t kSlotBytes = size_t(1) << 20;
+
+struct Staging {
+  char* host = nullptr;
+  hipEvent_t ev[kSlots];
+  bool used[kSlots] = {};
+  int next = 0;
+};
+
+std::mutex g_mu;
+std::vector<Staging*> g_stage;
+
+hipError_t stage_copy(void* d_dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes > kSlotBytes) return hipErrorInvalidValue;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_stage.size() <= dev) g_stage.resize(dev + 1, nullptr);
+  Staging*& st = g_stage[dev];
+  if (!st) {
+    st = new Staging();
+    e = hipHostMalloc((void**)&st->host, kSlotBytes * kSlots, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      delete st;
+      st = nullptr;
+      return e;
+    }
+    for (int i = 0; i < kSlots; ++i) {
+      e = hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+  }
+  const int slot = st->next;
+  st->next = (st->next + 1) % kSlots;
+  if (st->used[slot]) {
+    e = hipEventSynchronize(st->ev[slot]);
+    if (e != hipSuccess) return e;
+  }
+  char* h = st->host + slot * kSlotBytes;
+  memcpy(h, src, bytes);
+  e = hipMemcpyAsync(d_dst, h, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(st->ev[slot], s);
+  st->used[slot] = true;
+  return e;
+}
+
+
+// ---------------------------------------------------------------------------
+// Optional per-kernel event timing.
+// ---------------------------------------------------------------------------
+struct Timing {
+  bool on = false;
+  struct Rec {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[AERO_K_COUNT] = {};
+  int64_t n[AERO_K_COUNT] = {};
+};
+std::mutex g_tmu;
+Timing g_timing;
+
+hipEvent_t pool_event() {
+  if (!g_timing.pool.empty()) {
+    hipEvent_t e = g_timing.pool.back();
+    g_timing.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <typename F>
+hipError_t timed(int kernel, hipStream_t s, F&& launch) {
+  if (!g_timing.on) return launch();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  hipEvent_t a = pool_event(), b = pool_event();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  g_timing.pending.push_back({kernel, a, b});
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+int check_params(const aero_params* p) {
+  if (!p) return AERO_ERR_NULL;
+  const float* f = &p->dt;
+  const size_t nf = offsetof(aero_params, seed) / sizeof(float);
+  for (size_t i = 0; i < nf; ++i)
+    if (!finite(f[i])) return AERO_ERR_PARAM;
+  if (!(p->dt > 0.f) || !(p->lambda > 0.f) || !(p->mass > 0.f)) return AERO_ERR_PARAM;
+  for (int c = 0; c < 4; ++c)
+    if (p->sigma[c] < 0.f || p->u_min[c] > p->u_max[c]) return AERO_ERR_PARAM;
+  if (p->C < 0.f || p->a < 0.f || p->d_min < 0.f || !(p->d_min < p->d_max)) return AERO_ERR_PARAM;
+  if (p->reserved != 0) return AERO_ERR_PARAM;
+  return AERO_OK;
+}
+
+int check_problem(const aero_problem& q, bool need_coef) {
+  if (q.n_points < 0 || q.M < 1 || q.M > AERO_M_MAX || q.K < 1 || q.K > AERO_K_MAX || q.N < 2 ||
+      q.N > AERO_N_MAX)
+    return AERO_ERR_SHAPE;
+  if ((q.n_points > 0 && !q.cloud) || !q.u_nom || (need_coef && !q.coef)) return AERO_ERR_NULL;
+  for (float v : q.x0)
+    if (!finite(v)) return AERO_ERR_PARAM;
+  for (int i = 0; i < 3; ++i)
+    if (!finite(q.p_goal[i]) || !finite(q.v_goal[i])) return AERO_ERR_PARAM;
+  for (float v : q.q_goal)
+    if (!finite(v)) return AERO_ERR_PARAM;
+  const double qn = (double)q.x0[3] * q.x0[3] + (double)q.x0[4] * q.x0[4] +
+                    (double)q.x0[5] * q.x0[5] + (double)q.x0[6] * q.x0[6];
+  if (!(qn > 0.0)) return AERO_ERR_PARAM;
+  return AERO_OK;
+}
+
+int check_problems(const aero_problem* h, int32_t n, bool need_coef) {
+  if (!h) return AERO_ERR_NULL;
+  if (n < 1 || n > AERO_BATCH_MAX) return AERO_ERR_SHAPE;
+  for (int b = 0; b < n; ++b) {
+    const int e = check_problem(h[b], need_coef);
+    if (e) return e;
+  }
+  return AERO_OK;
+}
+
+DevParams promote(const aero_params& p) {
+  DevParams d;
+  d.dt = p.dt;
+  d.lambda = p.lambda;
+  d.mass = p.mass;
+  d.gravity = p.gravity;
+  for (int c = 0; c < 4; ++c) {
+    d.sigma[c] = p.sigma[c];
+    d.u_min[c] = p.u_min[c];
+    d.u_max[c] = p.u_max[c];
+  }
+  d.Q_track = p.Q_track;
+  d.Q_vnorm = p.Q_vnorm;
+  d.Q_c = p.Q_c;
+  d.Q_cdelta = p.Q_cdelta;
+  d.Q_p = p.Q_p;
+  d.Q_v = p.Q_v;
+  d.Q_q = p.Q_q;
+  d.C = p.C;
+  d.a = p.a;
+  d.d_min = p.d_min;
+  d.d_max = p.d_max;
+  for (int i = 0; i < 5; ++i) d.w[i] = p.w[i];
+  d.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
+  d.seed_hi = (uint32_t)(p.seed >> 32);
+  d.iter_base = p.iter_base;
+  d.pad = 0;
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+struct Cursor {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+int chunks_for(int64_t total_qblocks, int n_tiles) {
+  // Fill the chip (about 4 workgroups per CU of 256) and keep chunks short
+  // enough (<= 16 tiles) that uneven problems load-balance.
+  const int64_t target = 1024;
+  int64_t c = (total_qblocks >= target) ? 1 : (target + total_qblocks - 1) / total_qblocks;
+  c = std::max<int64_t>(c, (n_tiles + 15) / 16);
+  return (int)std::min<int64_t>(std::max<int64_t>(c, 1), std::max(n_tiles, 1));
+}
+
+struct MppiPlan {
+  std::vector<DevProblem> probs;
+  std::vector<QuerySet> sets;
+  DevProblem* d_probs = nullptr;
+  QuerySet* d_sets = nullptr;
+  int64_t total_samples = 0, total_rows = 0, total_blocks = 0;
+  size_t bytes = 0;
+};
+
+void plan_mppi(const aero_problem* h, int n, char* ws, MppiPlan& pl) {
+  Cursor cur{ws};
+  pl.d_probs = cur.take<DevProblem>(n);
+  pl.d_sets = cur.take<QuerySet>(n);
+  pl.probs.assign(n, DevProblem{});
+  pl.sets.assign(n, QuerySet{});
+  int64_t qblocks = 0;
+  for (int b = 0; b < n; ++b) {
+    const int64_t Q = (int64_t)h[b].M * h[b].N * h[b].K;
+    if (h[b].n_points > 0) qblocks += (Q + kQueriesPerBlock - 1) / kQueriesPerBlock;
+  }
+  int64_t sb = 0, rb = 0, blk = 0;
+  for (int b = 0; b < n; ++b) {
+    const aero_problem& q = h[b];
+    DevProblem& d = pl.probs[b];
+    const int64_t MK = (int64_t)q.M * q.K, MN = (int64_t)q.M * q.N, MNK = MN * q.K;
+    d.cloud = q.cloud;
+    d.n_points = q.n_points;
+    d.M = q.M;
+    d.K = q.K;
+    d.N = q.N;
+    d.problem_id = q.problem_id;
+    memcpy(d.x0, q.x0, sizeof d.x0);
+    memcpy(d.pg, q.p_goal, sizeof d.pg);
+    memcpy(d.vg, q.v_goal, sizeof d.vg);
+    memcpy(d.qg, q.q_goal, sizeof d.qg);
+    d.coef = q.coef;
+    d.u_nom = q.u_nom;
+    d.S_smooth = cur.take<double>(MK);
+    double* s1 = cur.take<double>(q.S1 ? 0 : MK);
+    d.S1 = q.S1 ? q.S1 : s1;
+    float* de = cur.take<float>(q.delta_eff ? 0 : MNK * 4);
+    d.deff = q.delta_eff ? q.delta_eff : de;
+    d.pos = cur.take<float>(3 * MNK);
+    unsigned* md = cur.take<unsigned>(q.min_dist2 ? 0 : MNK);
+    d.mind2 = q.min_dist2 ? reinterpret_cast<unsigned*>(q.min_dist2) : md;
+    d.sample_base = sb;
+    d.row_base = rb;
+    sb += MK;
+    rb += MN;
+
+    QuerySet& qs = pl.sets[b];
+    qs.px = d.pos;
+    qs.py = d.pos ? d.pos + MNK : nullptr;
+    qs.pz = d.pos ? d.pos + 2 * MNK : nullptr;
+    qs.out = d.mind2;
+    qs.cloud = q.cloud;
+    qs.Q = MNK;
+    qs.n_points = q.n_points;
+    qs.n_qblocks = (int)((MNK + kQueriesPerBlock - 1) / kQueriesPerBlock);
+    qs.n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
+    qs.n_chunks = q.n_points > 0 ? chunks_for(qblocks, qs.n_tiles) : 0;
+    qs.block_base = blk;
+    blk += (int64_t)qs.n_qblocks * qs.n_chunks;
+  }
+  pl.total_samples = sb;
+  pl.total_rows = rb;
+  pl.total_blocks = blk;
+  pl.bytes = cur.off;
+}
+
+struct SelectPlan {
+  std::vector<DevSelect> sel;
+  std::vector<QuerySet> sets;
+  DevSelect* d_sel = nullptr;
+  QuerySet* d_sets = nullptr;
+  int64_t total_inst = 0, total_blocks = 0;
+  size_t bytes = 0;
+};
+
+void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* best,
+                 SelectPlan& pl) {
+  Cursor cur{ws};
+  pl.d_sel = cur.take<DevSelect>(n);
+  pl.d_sets = cur.take<QuerySet>(n);
+  pl.sel.assign(n, DevSelect{});
+  pl.sets.assign(n, QuerySet{});
+  int64_t qblocks = 0;
+  for (int b = 0; b < n; ++b)
+    if (h[b].n_points > 0)
+      qblocks += ((int64_t)h[b].M * h[b].N + kQueriesPerBlock - 1) / kQueriesPerBlock;
+  int64_t ib = 0, blk = 0;
+  for (int b = 0; b < n; ++b) {
+    const aero_problem& q = h[b];
+    DevSelect& d = pl.sel[b];
+    const int64_t MN = (int64_t)q.M * q.N;
+    d.cloud = q.cloud;
+    d.n_points = q.n_points;
+    d.M = q.M;
+    d.N = q.N;
+    memcpy(d.x0, q.x0, sizeof d.x0);
+    memcpy(d.pg, q.p_goal, sizeof d.pg);
+    memcpy(d.vg, q.v_goal, sizeof d.vg);
+    memcpy(d.qg, q.q_goal, sizeof d.qg);
+    d.u_nom = q.u_nom;
+    d.goal_cost = cur.take<double>(q.M);
+    d.pos = cur.take<float>(3 * MN);
+    d.mind2 = cur.take<unsigned>(MN);
+    d.S2 = S2 ? S2 + ib : nullptr;
+    d.best = best ? best + b : nullptr;
+    d.inst_base = ib;
+    ib += q.M;
+    QuerySet& qs = pl.sets[b];
+    qs.px = d.pos;
+    qs.py = d.pos ? d.pos + MN : nullptr;
+    qs.pz = d.pos ? d.pos + 2 * MN : nullptr;
+    qs.out = d.mind2;
+    qs.cloud = q.cloud;
+    qs.Q = MN;
+    qs.n_points = q.n_points;
+    qs.n_qblocks = (int)((MN + kQueriesPerBlock - 1) / kQueriesPerBlock);
+    qs.n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
+    qs.n_chunks = q.n_points > 0 ? qs.n_tiles : 0;  // one tile per block: tiny query sets
+    qs.block_base = blk;
+    blk += (int64_t)qs.n_qblocks * qs.n_chunks;
+  }
+  (void)qblocks;
+  pl.total_inst = ib;
+  pl.total_blocks = blk;
+  pl.bytes = cur.off;
+}
+
+inline int dev_status(hipError_t e) { return e == hipSuccess ? AERO_OK : AERO_ERR_DEVICE; }
+
+void table_angles(int32_t n_az, int32_t n_el, float* out) {
+  float* az_b = out;
+  float* el_b = az_b + 2 * n_az;
+  float* az_c = el_b + 2 * (n_el + 1);
+  float* el_c = az_c + 2 * n_az;
+  for (int i = 0; i < n_az; ++i) {
+    const double t = -M_PI + 2.0 * M_PI * (double)i / (double)n_az;
+    az_b[2 * i] = (float)cos(t);
+    az_b[2 * i + 1] = (float)sin(t);
+    const double tc = -M_PI + 2.0 * M_PI * ((double)i + 0.5) / (double)n_az;
+    az_c[2 * i] = (float)cos(tc);
+    az_c[2 * i + 1] = (float)sin(tc);
+  }
+  for (int j = 0; j <= n_el; ++j) {
+    const double t = -0.5 * M_PI + M_PI * (double)j / (double)n_el;
+    el_b[2 * j] = (float)cos(t);
+    el_b[2 * j + 1] = (float)sin(t);
+  }
+  for (int j = 0; j < n_el; ++j) {
+    const double t = -0.5 * M_PI + M_PI * ((double)j + 0.5) / (double)n_el;
+    el_c[2 * j] = (float)cos(t);
+    el_c[2 * j + 1] = (float)sin(t);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* aero_status_string(int status) {
+  switch (status) {
+    case AERO_OK: return "AERO_OK: success";
+    case AERO_ERR_NULL: return "AERO_ERR_NULL: a required pointer is NULL";
+    case AERO_ERR_SHAPE: return "AERO_ERR_SHAPE: a size is out of range";
+    case AERO_ERR_PARAM: return "AERO_ERR_PARAM: a parameter is non-finite or out of its domain";
+    case AERO_ERR_WORKSPACE: return "AERO_ERR_WORKSPACE: workspace missing or too small";
+    case AERO_ERR_DEVICE: return "AERO_ERR_DEVICE: the HIP runtime reported an error";
+    default: return "unknown aero_status";
+  }
+}
+
+size_t aero_partition_tables_size(int32_t n_az, int32_t n_el) {
+  if (n_az < 1 || n_el < 1) return 0;
+  return (size_t)2 * n_az + 2 * (n_el + 1) + 2 * n_az + 2 * n_el;
+}
+
+int aero_partition_tables(int32_t n_az, int32_t n_el, float* h_out, size_t n_floats) {
+  if (!h_out) return AERO_ERR_NULL;
+  if (n_az < 3 || n_el < 1 || n_az > AERO_GRID_MAX || n_el > AERO_GRID_MAX) return AERO_ERR_SHAPE;
+  if (n_floats < aero_partition_tables_size(n_az, n_el)) return AERO_ERR_SHAPE;
+  table_angles(n_az, n_el, h_out);
+  return AERO_OK;
+}
+
+size_t aero_workspace_size(int which, const aero_problem* h, int32_t n) {
+  if (!h || n < 1 || n > AERO_BATCH_MAX) return 0;
+  for (int b = 0; b < n; ++b)
+    if (h[b].M < 1 || h[b].K < 1 || h[b].N < 2 || h[b].n_points < 0) return 0;
+  if (which == AERO_CALL_MPPI_STEP) {
+    MppiPlan pl;
+    plan_mppi(h, n, nullptr, pl);
+    return pl.bytes;
+  }
+  if (which == AERO_CALL_SELECT_BEST) {
+    SelectPlan pl;
+    plan_select(h, n, nullptr, nullptr, nullptr, pl);
+    return pl.bytes;
+  }
+  return 0;
+}
+
+int aero_partition_anchors(const aero_partition_spec* spec, const float* d_cloud, int32_t n_points,
+                           const float* h_goal_dir, double* d_fine_key, int32_t* d_fine_idx,
+                           int32_t* d_coarse_best, int32_t* d_anchor_cell, int32_t* d_anchor_fine,
+                           float* d_anchors, void* stream) {
+  if (!spec || !h_goal_dir || !d_fine_key || !d_fine_idx || !d_coarse_best || !d_anchor_cell ||
+      !d_anchor_fine || !d_anchors || !spec->d_tables)
+    return AERO_ERR_NULL;
+  if (n_points < 0) return AERO_ERR_SHAPE;
+  if (n_points > 0 && !d_cloud) return AERO_ERR_NULL;
+  if (spec->n_az_c < 1 || spec->n_el_c < 1 || spec->f_a < 1 || spec->f_e < 1)
+    return AERO_ERR_SHAPE;
+  const int64_t n_az = (int64_t)spec->n_az_c * spec->f_a, n_el = (int64_t)spec->n_el_c * spec->f_e;
+  if (n_az < 3 || n_az > AERO_GRID_MAX || n_el > AERO_GRID_MAX) return AERO_ERR_SHAPE;
+  if (spec->M_h < 1 || spec->M_h > spec->n_az_c || spec->M_v < 1 || spec->M_v > spec->n_el_c ||
+      spec->M_h * spec->M_v > AERO_M_MAX)
+    return AERO_ERR_SHAPE;
+  if (!finite(spec->r_max) || !(spec->r_max > 0.f) || !finite(spec->ell)) return AERO_ERR_PARAM;
+  for (int i = 0; i < 3; ++i)
+    if (!finite(spec->p0[i]) || !finite(h_goal_dir[i])) return AERO_ERR_PARAM;
+  const hipStream_t s = (hipStream_t)stream;
+  return dev_status(timed(AERO_K_PARTITION, s, [&] {
+    return launch_partition(*spec, d_cloud, n_points, h_goal_dir, d_fine_key, d_fine_idx,
+                            d_coarse_best, d_anchor_cell, d_anchor_fine, d_anchors, s);
+  }));
+}
+
+int aero_build_guides(const float* h_p0, const float* h_v0, const float* h_a0,
+                      const float* d_anchors, const float* d_end_vel, const float* d_end_acc,
+                      float horizon_T, int32_t M, float* d_coef, void* stream) {
+  if (!h_p0 || !h_v0 || !h_a0 || !d_anchors || !d_coef) return AERO_ERR_NULL;
+  if (M < 1 || M > AERO_M_MAX) return AERO_ERR_SHAPE;
+  if (!finite(horizon_T) || !(horizon_T > 0.f)) return AERO_ERR_PARAM;
+  double p0[3], v0[3], a0[3];
+  for (int i = 0; i < 3; ++i) {
+    if (!finite(h_p0[i]) || !finite(h_v0[i]) || !finite(h_a0[i])) return AERO_ERR_PARAM;
+    p0[i] = h_p0[i];
+    v0[i] = h_v0[i];
+    a0[i] = h_a0[i];
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  return dev_status(timed(AERO_K_GUIDES, s, [&] {
+    return launch_guides(p0, v0, a0, d_anchors, d_end_vel, d_end_acc, (double)horizon_T, M, d_coef,
+                         s);
+  }));
+}
+
+int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, void* d_ws,
+                   size_t ws_bytes, void* stream) {
+  int e = check_params(h_prm);
+  if (e) return e;
+  e = check_problems(h, n, true);
+  if (e) return e;
+  MppiPlan pl;
+  plan_mppi(h, n, nullptr, pl);
+  if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
+  if (n * (sizeof(DevProblem) + sizeof(QuerySet)) + 2 * kAlign > kSlotBytes) return AERO_ERR_SHAPE;
+  plan_mppi(h, n, (char*)d_ws, pl);
+  const hipStream_t s = (hipStream_t)stream;
+  const DevParams prm = promote(*h_prm);
+  // One staged copy for both descriptor arrays (they are adjacent in the workspace).
+  std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_probs + n * sizeof(QuerySet));
+  memcpy(blob.data(), pl.probs.data(), n * sizeof(DevProblem));
+  memcpy(blob.data() + ((char*)pl.d_sets - (char*)pl.d_probs), pl.sets.data(),
+         n * sizeof(QuerySet));
+  hipError_t he = stage_copy(pl.d_probs, blob.data(), blob.size(), s);
+  if (he == hipSuccess)
+    he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, n, pl.total_samples, prm, s); });
+  if (he == hipSuccess && pl.total_blocks > 0)
+    he = timed(AERO_K_MIN_DIST, s, [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, s); });
+  if (he == hipSuccess)
+    he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, n, pl.total_samples, prm, s); });
+  if (he == hipSuccess)
+    he = timed(AERO_K_UPDATE, s, [&] { return launch_update(pl.d_probs, n, pl.total_rows, prm, s); });
+  return dev_status(he);
+}
+
+int aero_select_best(const aero_params* h_prm, const aero_problem* h, int32_t n, double* d_S2,
+                     int32_t* d_best, void* d_ws, size_t ws_bytes, void* stream) {
+  int e = check_params(h_prm);
+  if (e) return e;
+  e = check_problems(h, n, false);
+  if (e) return e;
+  if (!d_S2 || !d_best) return AERO_ERR_NULL;
+  SelectPlan pl;
+  plan_select(h, n, nullptr, nullptr, nullptr, pl);
+  if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
+  if (n * (sizeof(DevSelect) + sizeof(QuerySet)) + 2 * kAlign > kSlotBytes) return AERO_ERR_SHAPE;
+  plan_select(h, n, (char*)d_ws, d_S2, d_best, pl);
+  const hipStream_t s = (hipStream_t)stream;
+  const DevParams prm = promote(*h_prm);
+  std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_sel + n * sizeof(QuerySet));
+  memcpy(blob.data(), pl.sel.data(), n * sizeof(DevSelect));
+  memcpy(blob.data() + ((char*)pl.d_sets - (char*)pl.d_sel), pl.sets.data(), n * sizeof(QuerySet));
+  hipError_t he = stage_copy(pl.d_sel, blob.data(), blob.size(), s);
+  if (he == hipSuccess)
+    he = timed(AERO_K_SEL_ROLLOUT, s, [&] { return launch_select_rollout(pl.d_sel, n, pl.total_inst, prm, s); });
+  if (he == hipSuccess && pl.total_blocks > 0)
+    he = timed(AERO_K_SEL_MIN_DIST, s, [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, s); });
+  if (he == hipSuccess)
+    he = timed(AERO_K_SEL_FINAL, s, [&] { return launch_select_final(pl.d_sel, n, prm, s); });
+  return dev_status(he);
+}
+
+int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, float scale,
+                            float* d_grad_u_nom, float* d_grad_w, void* d_ws, size_t ws_bytes,
+                            void* stream) {
+  int e = check_params(h_prm);
+  if (e) return e;
+  e = check_problems(h, 1, true);
+  if (e) return e;
+  if (!d_grad_u_nom || !d_grad_w) return AERO_ERR_NULL;
+  if (!finite(scale)) return AERO_ERR_PARAM;
+  (void)d_ws;
+  (void)ws_bytes;
+  (void)stream;
+  return AERO_ERR_SHAPE;  // adjoint kernels not built yet
+}
+
+int aero_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing.on = on != 0;
+  return AERO_OK;
+}
+
+int aero_timing_read(int kernel, double* h_total_ms, int64_t* h_launches, int reset) {
+  if (!h_total_ms || !h_launches) return AERO_ERR_NULL;
+  if (kernel < 0 || kernel >= AERO_K_COUNT) return AERO_ERR_SHAPE;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& r : g_timing.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      return AERO_ERR_DEVICE;
+    g_timing.ms[r.kernel] += ms;
+    g_timing.n[r.kernel] += 1;
+    g_timing.pool.push_back(r.a);
+    g_timing.pool.push_back(r.b);
+  }
+  g_timing.pending.clear();
+  *h_total_ms = g_timing.ms[kernel];
+  *h_launches = g_timing.n[kernel];
+  if (reset)
+    for (int k = 0; k < AERO_K_COUNT; ++k) {
+      g_timing.ms[k] = 0.0;
+      g_timing.n[k] = 0;
+    }
+  return AERO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,340 @@
+// Stage I (Sec. III-B, IV-C) and Stage II (Sec. IV-C) kernels.
+//
+//   k_rollout      one lane per (problem, instance, sample): Philox noise, clip,
+//                  RK4 in binary64, smooth cost terms; writes the clipped
+//                  perturbations and float32 positions as sample-fastest planes
+//   k_min_dist     brute-force nearest squared distance of every rollout position
+//                  to the raw cloud: cloud tiles staged in LDS, read as wave-wide
+//                  broadcasts, kQueriesPerLane positions per lane in registers;
+//                  cloud chunks of one query block combine through atomicMin on
+//                  the float bit patterns (exact, order independent)
+//   k_finalize     J_col from the distances, S1 = smooth part + w_col J_col
+//   k_update       per (instance, step): rho, eta, and sum_k eps_k delta_eff_k
+//                  with fixed-order wave/block reductions in binary64
+//   k_sel_rollout  Stage II noise-free rollouts and J_goal
+//   k_sel_final    S2 and the argmin per problem
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "aero_device.h"
+#include "aero_internal.h"
+
+namespace aero {
+namespace {
+
+constexpr unsigned kInfBits = 0x7f800000u;
+constexpr float kFar = 1.0e18f;   // padding point: its squared distance stays finite
+
+__device__ inline void load_rg(const float* qg, double Rg[9]) {
+  const double w = qg[0], x = qg[1], y = qg[2], z = qg[3];
+  rotmat(w, x, y, z, Rg);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict__ probs, int n,
+                                                    int64_t total, DevParams prm) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= total) return;
+  const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.sample_base; });
+  const DevProblem& P = probs[b];
+  const int K = P.K, N = P.N;
+  const int64_t local = gid - P.sample_base;
+  const int m = (int)(local / K), k = (int)(local % K);
+  const int64_t MNK = (int64_t)P.M * N * K;
+
+  const Dyn dyn{1.0 / prm.mass, prm.gravity};
+  double x[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) x[i] = P.x0[i];
+  const double pg[3] = {P.pg[0], P.pg[1], P.pg[2]}, vg[3] = {P.vg[0], P.vg[1], P.vg[2]};
+  double Rg[9];
+  load_rg(P.qg, Rg);
+  double cf[3][6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cf[a][i] = P.coef[(m * 3 + a) * 6 + i];
+
+  double s_track = 0.0, s_vnorm = 0.0, s_u2 = 0.0, s_du2 = 0.0, s_goal = 0.0;
+  double up[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < N; ++t) {
+    double nz[4];
+    normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
+    double u[4];
+    const int64_t row = (int64_t)m * N + t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double un = P.u_nom[row * 4 + c];
+      const double v = un + prm.sigma[c] * nz[c];
+      u[c] = fmin(fmax(v, prm.u_min[c]), prm.u_max[c]);
+      P.deff[(row * 4 + c) * K + k] = (float)(u[c] - un);
+    }
+    rk4(x, u, prm.dt, dyn);
+    const int64_t qi = row * K + k;
+    P.pos[qi] = (float)x[0];
+    P.pos[MNK + qi] = (float)x[1];
+    P.pos[2 * MNK + qi] = (float)x[2];
+    P.mind2[qi] = kInfBits;
+    // guide position f((t+1) dt) by Horner
+    const double tau = (double)(t + 1) * prm.dt;
+    double e2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double f = cf[a][5];
+#pragma unroll
+      for (int i = 4; i >= 0; --i) f = f * tau + cf[a][i];
+      const double e = x[a] - f;
+      e2 += e * e;
+    }
+    s_track += sqrt(e2);
+    s_vnorm += x[7] * x[7] + x[8] * x[8] + x[9] * x[9];
+    if (t <= N - 2) {
+      s_u2 += u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+      if (t >= 1) {
+        const double d0 = u[0] - up[0], d1 = u[1] - up[1], d2 = u[2] - up[2], d3 = u[3] - up[3];
+        s_du2 += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+      }
+    }
+    s_goal += goal_term(x, pg, vg, Rg, prm);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) up[c] = u[c];
+  }
+  const double J_track = prm.Q_track * s_track;
+  const double J_vnorm = prm.Q_vnorm * s_vnorm;
+  const double J_ctrl = prm.Q_c * s_u2 + prm.Q_cdelta * s_du2;
+  P.S_smooth[(int64_t)m * K + k] =
+      prm.w[0] * J_track + prm.w[1] * J_vnorm + prm.w[2] * J_ctrl + prm.w[3] * s_goal;
+}
+
+// Brute-force nearest squared distance.  Block = (query block, cloud chunk).
+__global__ __launch_bounds__(kBlock) void k_min_dist(const QuerySet* __restrict__ sets,
+                                                     int n_sets) {
+  __shared__ float4 tile[kTilePts];
+  const int64_t bid = blockIdx.x;
+  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
+  const QuerySet S = sets[s];
+  const int64_t local = bid - S.block_base;
+  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
+  const int tid = threadIdx.x;
+
+  float px[kQueriesPerLane], py[kQueriesPerLane], pz[kQueriesPerLane], best[kQueriesPerLane];
+#pragma unroll
+  for (int r = 0; r < kQueriesPerLane; ++r) {
+    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    const bool ok = q < S.Q;
+    px[r] = ok ? S.px[q] : 0.0f;
+    py[r] = ok ? S.py[q] : 0.0f;
+    pz[r] = ok ? S.pz[q] : 0.0f;
+    best[r] = __uint_as_float(kInfBits);
+  }
+  const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunks);
+  const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunks);
+  for (int tl = t0; tl < t1; ++tl) {
+    const int64_t base = (int64_t)tl * kTilePts;
+#pragma unroll
+    for (int i = 0; i < kTilePts / kBlock; ++i) {
+      const int pt = i * kBlock + tid;
+      const int64_t g = base + pt;
+      float4 o;
+      if (g < S.n_points) {
+        o.x = S.cloud[3 * g];
+        o.y = S.cloud[3 * g + 1];
+        o.z = S.cloud[3 * g + 2];
+      } else {
+        o.x = kFar;
+        o.y = kFar;
+        o.z = kFar;
+      }
+      o.w = 0.0f;
+      tile[pt] = o;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int j = 0; j < kTilePts; j += 2) {
+      const float4 a = tile[j];
+      const float4 c = tile[j + 1];
+#pragma unroll
+      for (int r = 0; r < kQueriesPerLane; ++r) {
+        const float ax = px[r] - a.x, ay = py[r] - a.y, az = pz[r] - a.z;
+        const float cx = px[r] - c.x, cy = py[r] - c.y, cz = pz[r] - c.z;
+        const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
+        const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+        best[r] = fminf(best[r], fminf(da, dc));
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kQueriesPerLane; ++r) {
+    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    if (q < S.Q) atomicMin(S.out + q, __float_as_uint(best[r]));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const DevProblem* __restrict__ probs, int n,
+                                                     int64_t total, DevParams prm) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= total) return;
+  const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.sample_base; });
+  const DevProblem& P = probs[b];
+  const int K = P.K, N = P.N;
+  const int64_t local = gid - P.sample_base;
+  const int m = (int)(local / K), k = (int)(local % K);
+  double col = 0.0;
+  for (int t = 0; t < N; ++t) {
+    const float d2 = __uint_as_float(P.mind2[((int64_t)m * N + t) * K + k]);
+    col += collision_phi(sqrt((double)d2), prm);
+  }
+  const int64_t i = (int64_t)m * K + k;
+  P.S1[i] = P.S_smooth[i] + prm.w[4] * col;
+}
+
+// Block-wide reductions (4 waves) in a fixed order; every thread gets the result.
+__device__ inline double block_min(double v, double* sh) {
+  v = wave_min(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
+}
+
+__device__ inline void block_sum5(double v[5], double* sh) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[i] = wave_sum(v[i]);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sh[i * 4 + w] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[i] = ((sh[i * 4] + sh[i * 4 + 1]) + sh[i * 4 + 2]) + sh[i * 4 + 3];
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict__ probs, int n,
+                                                   DevParams prm) {
+  __shared__ double sh[20];
+  const int64_t gid = blockIdx.x;
+  const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.row_base; });
+  const DevProblem& P = probs[b];
+  const int K = P.K, N = P.N;
+  const int64_t row = gid - P.row_base;  // m * N + t
+  const int m = (int)(row / N);
+  const double* S = P.S1 + (int64_t)m * K;
+  double mn = INFINITY;
+  for (int k = threadIdx.x; k < K; k += kBlock) mn = fmin(mn, S[k]);
+  const double rho = block_min(mn, sh);
+  const double inv_lam = 1.0 / prm.lambda;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const float* D = P.deff + row * 4 * K;
+  for (int k = threadIdx.x; k < K; k += kBlock) {
+    const double e = exp(-(S[k] - rho) * inv_lam);
+    acc[0] += e;
+    acc[1] += e * (double)D[k];
+    acc[2] += e * (double)D[K + k];
+    acc[3] += e * (double)D[2 * K + k];
+    acc[4] += e * (double)D[3 * K + k];
+  }
+  block_sum5(acc, sh);
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    float* u = P.u_nom + row * 4 + c;
+    *u = (float)((double)*u + acc[1 + c] / acc[0]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_rollout(const DevSelect* __restrict__ sel, int n,
+                                                        int64_t total, DevParams prm) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= total) return;
+  const int b = find_owner(sel, n, gid, [](const DevSelect& p) { return p.inst_base; });
+  const DevSelect& P = sel[b];
+  const int m = (int)(gid - P.inst_base), N = P.N;
+  const int64_t MN = (int64_t)P.M * N;
+  const Dyn dyn{1.0 / prm.mass, prm.gravity};
+  double x[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) x[i] = P.x0[i];
+  const double pg[3] = {P.pg[0], P.pg[1], P.pg[2]}, vg[3] = {P.vg[0], P.vg[1], P.vg[2]};
+  double Rg[9];
+  load_rg(P.qg, Rg);
+  double s_goal = 0.0;
+  for (int t = 0; t < N; ++t) {
+    const int64_t row = (int64_t)m * N + t;
+    double u[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = P.u_nom[row * 4 + c];
+    rk4(x, u, prm.dt, dyn);
+    P.pos[row] = (float)x[0];
+    P.pos[MN + row] = (float)x[1];
+    P.pos[2 * MN + row] = (float)x[2];
+    P.mind2[row] = kInfBits;
+    s_goal += goal_term(x, pg, vg, Rg, prm);
+  }
+  P.goal_cost[m] = prm.w[3] * s_goal;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_final(const DevSelect* __restrict__ sel,
+                                                      DevParams prm) {
+  __shared__ double s2[AERO_M_MAX];
+  const DevSelect& P = sel[blockIdx.x];
+  const int M = P.M, N = P.N;
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    double col = 0.0;
+    for (int t = 0; t < N; ++t)
+      col += collision_phi(sqrt((double)__uint_as_float(P.mind2[(int64_t)m * N + t])), prm);
+    const double v = P.goal_cost[m] + prm.w[4] * col;
+    s2[m] = v;
+    P.S2[m] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int bi = 0;
+    for (int m = 1; m < M; ++m)
+      if (s2[m] < s2[bi]) bi = m;
+    *P.best = bi;
+  }
+}
+
+inline unsigned grid1d(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
+                          hipStream_t s) {
+  k_rollout<<<grid1d(total), kBlock, 0, s>>>(d_probs, n, total, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                           hipStream_t s) {
+  if (total_blocks > 0) k_min_dist<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
+                           hipStream_t s) {
+  k_finalize<<<grid1d(total), kBlock, 0, s>>>(d_probs, n, total, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
+                         const DevParams& prm, hipStream_t s) {
+  k_update<<<(unsigned)total_rows, kBlock, 0, s>>>(d_probs, n, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_rollout(const DevSelect* d_sel, int n, int64_t total_inst,
+                                 const DevParams& prm, hipStream_t s) {
+  k_sel_rollout<<<grid1d(total_inst), kBlock, 0, s>>>(d_sel, n, total_inst, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_final(const DevSelect* d_sel, int n, const DevParams& prm,
+                               hipStream_t s) {
+  k_sel_final<<<(unsigned)n, kBlock, 0, s>>>(d_sel, prm);
+  return hipGetLastError();
+}
+
+}  // namespace aero

@@ -1,0 +1,91 @@
+"""One planning step on the device: partition -> guides -> Stage I -> Stage II.
+
+`PlanStep` owns the device buffers of one problem and enqueues the four C-ABI
+calls on the current stream; it does no arithmetic of its own.
+"""
+import numpy as np
+import torch
+
+from . import (CALL_MPPI_STEP, CALL_SELECT_BEST, Problem, build_guides, mppi_step,
+               partition_anchors, partition_tables, select_best, workspace_size)
+
+
+class PlanStep:
+    """Device state of one planning problem given as a fixture dict.
+
+    The dict carries cloud, x0, p_goal, v_goal, q_goal, M, K, N, M_h, M_v,
+    partition (n_az_c, n_el_c, f_a, f_e, r_max, ell), params, u_nom, problem_id
+    and, optionally, `anchors` (then the partition is skipped and the given
+    anchors are used, as for a single straight-line guide).
+    """
+
+    def __init__(self, prob, device="cuda", keep_debug=False):
+        self.prob = prob
+        dev = torch.device(device)
+        self.dev = dev
+        self.M, self.K, self.N = prob["M"], prob["K"], prob["N"]
+        M, K, N = self.M, self.K, self.N
+        self.cloud = torch.from_numpy(np.ascontiguousarray(prob["cloud"], np.float32)).to(dev)
+        part = prob["partition"]
+        self.part = part
+        self.n_az = part["n_az_c"] * part["f_a"]
+        self.n_el = part["n_el_c"] * part["f_e"]
+        self.fixed_anchors = prob.get("anchors")
+        if self.fixed_anchors is None:
+            self.tables = torch.from_numpy(partition_tables(self.n_az, self.n_el)).to(dev)
+            nf = self.n_az * self.n_el
+            nc = part["n_az_c"] * part["n_el_c"]
+            self.fine_key = torch.empty(nf, dtype=torch.float64, device=dev)
+            self.fine_idx = torch.empty(nf, dtype=torch.int32, device=dev)
+            self.coarse_best = torch.empty(nc, dtype=torch.int32, device=dev)
+            self.anchor_cell = torch.empty(M, dtype=torch.int32, device=dev)
+            self.anchor_fine = torch.empty(M, dtype=torch.int32, device=dev)
+            self.anchors = torch.empty((M, 3), dtype=torch.float32, device=dev)
+        else:
+            self.anchors = torch.from_numpy(np.ascontiguousarray(self.fixed_anchors, np.float32)).to(dev)
+        self.coef = torch.empty((M, 3, 6), dtype=torch.float32, device=dev)
+        self.u_init = torch.from_numpy(np.ascontiguousarray(prob["u_nom"], np.float32)).to(dev)
+        self.u_nom = self.u_init.clone()
+        self.S1 = torch.empty((M, K), dtype=torch.float64, device=dev)
+        self.S2 = torch.empty(M, dtype=torch.float64, device=dev)
+        self.best = torch.empty(1, dtype=torch.int32, device=dev)
+        self.delta_eff = self.min_dist2 = None
+        if keep_debug:
+            self.delta_eff = torch.empty((M, N, 4, K), dtype=torch.float32, device=dev)
+            self.min_dist2 = torch.empty((M, N, K), dtype=torch.float32, device=dev)
+        self.problem = Problem(self.cloud, M, K, N, prob["x0"], prob["p_goal"], self.u_nom,
+                               coef=self.coef, v_goal=prob["v_goal"], q_goal=prob["q_goal"],
+                               S1=self.S1, delta_eff=self.delta_eff, min_dist2=self.min_dist2,
+                               problem_id=prob.get("problem_id", 0))
+        ws = max(workspace_size(CALL_MPPI_STEP, [self.problem]),
+                 workspace_size(CALL_SELECT_BEST, [self.problem]))
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
+        self.params = prob["params"]
+        x0 = np.asarray(prob["x0"], np.float32)
+        self.p0, self.v0 = x0[0:3].copy(), x0[7:10].copy()
+        self.a0 = np.zeros(3, np.float32)
+        self.T = float(np.float32(N * np.float32(self.params["dt"])))
+
+    def reset(self):
+        self.u_nom.copy_(self.u_init)
+
+    def front_end(self):
+        if self.fixed_anchors is None:
+            p = self.part
+            partition_anchors(p["n_az_c"], p["n_el_c"], p["f_a"], p["f_e"], self.prob["M_h"],
+                              self.prob["M_v"], p["r_max"], p["ell"], self.p0, self.tables,
+                              self.cloud, self.prob["goal_dir"], self.fine_key, self.fine_idx,
+                              self.coarse_best, self.anchor_cell, self.anchor_fine, self.anchors)
+        build_guides(self.p0, self.v0, self.a0, self.anchors, self.T, self.M, self.coef)
+
+    def stage1(self):
+        mppi_step(self.params, [self.problem], self.ws)
+
+    def stage2(self):
+        select_best(self.params, [self.problem], self.S2, self.best, self.ws)
+
+    def run(self):
+        """One full planning step (all enqueued on the current stream)."""
+        self.front_end()
+        self.stage1()
+        self.stage2()

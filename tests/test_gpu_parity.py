@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar:
+  * partition keys / indices / coarse argmax / anchor cells: bit-exact
+  * anchors, guide coefficients, clipped perturbations: <= 1e-6 relative
+  * nearest distances: |d_gpu - d_oracle| <= 1e-5 m
+  * S1, S2: |dS| <= 1e-4 |S| elementwise; samples with some step whose oracle
+    distance lies within 1e-5 m of d_max (the collision jump) are counted as
+    straddles and accepted under either branch
+  * u_nom: oracle weights fed the GPU's S1 (teacher forcing), |du| / |u| <= 1e-4
+    per instance; end to end reported with kappa = max |dS| / lambda
+  * best instance: identical unless the oracle's two lowest S2 are within 1e-6
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2509_17340_amd as aero  # noqa: E402
+from fixtures import make_ensemble_problem, make_plain_problem  # noqa: E402
+from oracle import guides as OG  # noqa: E402
+from oracle import mppi as OM  # noqa: E402
+from oracle import partition as OP  # noqa: E402
+from oracle import philox as OPh  # noqa: E402
+from oracle.cost import nearest  # noqa: E402
+from paper_2509_17340_amd.planner import PlanStep  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def sync():
+    torch.cuda.synchronize()
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+# ----------------------------------------------------------------------------
+# partition and anchors
+# ----------------------------------------------------------------------------
+def gpu_partition(cloud, part, M_h, M_v, goal, p0=(0.0, 0.0, 0.0)):
+    n_az, n_el = part["n_az_c"] * part["f_a"], part["n_el_c"] * part["f_e"]
+    tab = torch.from_numpy(aero.partition_tables(n_az, n_el)).to(DEV)
+    c = torch.from_numpy(np.ascontiguousarray(cloud, np.float32).reshape(-1, 3)).to(DEV)
+    M = M_h * M_v
+    out = dict(fine_key=torch.full((n_az * n_el,), -1.0, dtype=torch.float64, device=DEV),
+               fine_idx=torch.full((n_az * n_el,), -7, dtype=torch.int32, device=DEV),
+               coarse_best=torch.full((part["n_az_c"] * part["n_el_c"],), -7, dtype=torch.int32,
+                                      device=DEV),
+               anchor_cell=torch.empty(M, dtype=torch.int32, device=DEV),
+               anchor_fine=torch.empty(M, dtype=torch.int32, device=DEV),
+               anchors=torch.empty((M, 3), dtype=torch.float32, device=DEV))
+    aero.partition_anchors(part["n_az_c"], part["n_el_c"], part["f_a"], part["f_e"], M_h, M_v,
+                           part["r_max"], part["ell"], p0, tab, c, goal, **out)
+    sync()
+    return {k: np_(v) for k, v in out.items()}
+
+
+def check_partition(cloud, part, M_h, M_v, goal, p0=(0.0, 0.0, 0.0)):
+    g = gpu_partition(cloud, part, M_h, M_v, goal, p0)
+    o = OP.partition_anchors(cloud, goal, part["n_az_c"], part["n_el_c"], part["f_a"], part["f_e"],
+                             part["r_max"], part["ell"], M_h, M_v, p0=p0)
+    assert np.array_equal(g["fine_key"].view(np.uint64), o["fine_key"].view(np.uint64))
+    assert np.array_equal(g["fine_idx"], o["fine_idx"])
+    assert np.array_equal(g["coarse_best"], o["coarse_best"])
+    assert np.array_equal(g["anchor_cell"], o["anchor_cell"])
+    assert np.array_equal(g["anchor_fine"], o["anchor_fine"])
+    np.testing.assert_allclose(g["anchors"], o["anchors"], rtol=1e-6, atol=1e-6)
+    return g, o
+
+
+def test_partition_ensemble_forest_bit_exact():
+    prob = make_ensemble_problem()
+    print(f"partition: forest cloud {prob['cloud'].shape}", flush=True)
+    g, o = check_partition(prob["cloud"], prob["partition"], prob["M_h"], prob["M_v"],
+                           prob["goal_dir"])
+    assert (g["fine_idx"] >= 0).sum() > 500
+
+
+@pytest.mark.parametrize("case", ["empty", "single", "tiny_ragged", "origin_and_far", "zero_goal",
+                                  "paper_grid"])
+def test_partition_edge_cases(case):
+    rng = np.random.default_rng(7)
+    part = dict(n_az_c=32, n_el_c=8, f_a=4, f_e=4, r_max=30.0, ell=5.0)
+    Mh, Mv, goal = 4, 2, (18.0, 0.0, 0.0)
+    if case == "empty":
+        cloud = np.zeros((0, 3), np.float32)
+    elif case == "single":
+        cloud = np.float32([[3.0, -2.0, 0.5]])
+    elif case == "tiny_ragged":
+        cloud = (rng.normal(size=(77, 3)) * 5).astype(np.float32)
+        cloud[5] = cloud[2]
+    elif case == "origin_and_far":
+        cloud = (rng.normal(size=(1000, 3)) * 20).astype(np.float32)
+        cloud[:10] = 0.0
+        cloud[10:20] *= 10.0
+    elif case == "zero_goal":
+        cloud = (rng.normal(size=(3000, 3)) * 8).astype(np.float32)
+        goal = (0.0, 0.0, 0.0)
+    else:  # the paper's 3 deg grid: 120 x 60 fine, 20 x 10 coarse, 200k points, r_max 10 m
+        part = dict(n_az_c=20, n_el_c=10, f_a=6, f_e=6, r_max=10.0, ell=5.0)
+        Mh, Mv = 5, 3
+        cloud = (rng.normal(size=(200000, 3)) * 6).astype(np.float32)
+        goal = (30.0, 4.0, 2.0)
+    print(f"partition edge case {case}: {cloud.shape}", flush=True)
+    check_partition(cloud, part, Mh, Mv, goal, p0=(0.25, -0.5, 1.0))
+
+
+def test_guides_match_oracle():
+    rng = np.random.default_rng(3)
+    M = 13
+    anchors = (rng.normal(size=(M, 3)) * 5).astype(np.float32)
+    p0, v0, a0 = np.float32([0.5, -1, 2]), np.float32([3, 1, -0.5]), np.float32([0.2, 0, -1])
+    coef = torch.empty((M, 3, 6), dtype=torch.float32, device=DEV)
+    A = torch.from_numpy(anchors).to(DEV)
+    aero.build_guides(p0, v0, a0, A, 2.0, M, coef)
+    ev = torch.from_numpy((rng.normal(size=(M, 3))).astype(np.float32)).to(DEV)
+    coef2 = torch.empty_like(coef)
+    aero.build_guides(p0, v0, a0, A, 2.0, M, coef2, end_vel=ev, end_acc=ev)
+    sync()
+    o = OG.build_guides(p0, v0, a0, anchors, 2.0)
+    o2 = OG.build_guides(p0, v0, a0, anchors, 2.0, end_vel=np_(ev), end_acc=np_(ev))
+    scale = np.abs(o).max(-1, keepdims=True)
+    assert np.all(np.abs(np_(coef) - o) <= 1e-6 * scale + 1e-7)
+    assert np.all(np.abs(np_(coef2) - o2) <= 1e-6 * np.abs(o2).max(-1, keepdims=True) + 1e-7)
+
+
+# ----------------------------------------------------------------------------
+# Stage I
+# ----------------------------------------------------------------------------
+def run_stage1(prob):
+    ps = PlanStep(prob, keep_debug=True)
+    ps.front_end()
+    sync()
+    coef = np_(ps.coef)
+    ps.stage1()
+    sync()
+    return ps, dict(coef=coef, deff=np_(ps.delta_eff), md2=np_(ps.min_dist2), S1=np_(ps.S1),
+                    u_new=np_(ps.u_nom))
+
+
+def straddles(d, d_max, tol=1e-5):
+    return (np.abs(d - d_max) < tol).any(-1)
+
+
+def compare_stage1(prob, g, samples=None, nearest_fn=nearest):
+    """Oracle on the GPU's guide coefficients; optionally on a subset of samples."""
+    M, K, N = prob["M"], prob["K"], prob["N"]
+    prm = prob["params"]
+    normals = OPh.normals(prm["seed"], prob["problem_id"], M, K, N, prm["iter_base"])
+    coef = g["coef"].astype(np.float64)
+    # clipped perturbations, all samples
+    u, deff = OM.perturb(prob["u_nom"], normals, prm)
+    gdeff = np.transpose(g["deff"], (0, 3, 1, 2))           # (M,K,N,4)
+    np.testing.assert_allclose(gdeff, deff, rtol=1e-6, atol=1e-7)
+    # costs and distances on (a subset of) samples
+    sub = np.arange(K) if samples is None else np.asarray(samples)
+    p2 = dict(prob)
+    p2["K"] = len(sub)
+    st = OM.mppi_step(p2, coef, normals=normals[:, sub], nearest_fn=nearest_fn)
+    gd = np.sqrt(np.transpose(g["md2"], (0, 2, 1))[:, sub].astype(np.float64))
+    fin = np.isfinite(st["d"])
+    assert np.array_equal(fin, np.isfinite(gd))
+    assert np.abs(gd[fin] - st["d"][fin]).max(initial=0.0) <= 1e-5
+    strad = straddles(st["d"], float(np.float32(prm["d_max"])))
+    S_o, S_g = st["S1"], g["S1"][:, sub]
+    rel = np.abs(S_g - S_o) / np.abs(S_o)
+    ok = (rel <= 1e-4) | strad
+    assert ok.all(), f"S1 mismatch: max rel {rel[~strad].max()}"
+    # teacher-forced update over all samples
+    st_all_w = OM.mppi_weights(g["S1"], prm["lam"])
+    u_tf = OM.mppi_update(prob["u_nom"], st_all_w, deff)
+    num = np.linalg.norm((g["u_new"] - u_tf).reshape(M, -1), axis=1)
+    den = np.linalg.norm(u_tf.reshape(M, -1), axis=1)
+    assert (num / den).max() <= 1e-4, f"u_nom teacher-forced rel {num / den}"
+    kappa = np.abs(S_g - S_o)[~strad].max(initial=0.0) / prm["lam"]
+    return dict(straddles=int(strad.sum()), s1_rel=float(rel[~strad].max(initial=0.0)),
+                u_tf_rel=float((num / den).max()), kappa=float(kappa))
+
+
+def test_stage1_plain_cylinders_full():
+    prob = make_plain_problem()
+    print("stage1 plain K=256 N=20 P=5000", flush=True)
+    ps, g = run_stage1(prob)
+    rep = compare_stage1(prob, g)
+    print(rep)
+    # end to end: the oracle with its own costs
+    prm = prob["params"]
+    normals = OPh.normals(prm["seed"], 0, 1, 256, 20)
+    st = OM.mppi_step(prob, g["coef"].astype(np.float64), normals=normals)
+    e2e = np.linalg.norm(g["u_new"] - st["u_new"]) / np.linalg.norm(st["u_new"])
+    print(f"end-to-end u_nom rel {e2e:.3e} kappa {rep['kappa']:.3e}")
+    if rep["kappa"] <= 1e-3:
+        assert e2e <= 1e-4
+
+
+def test_stage1_ensemble_forest_sampled():
+    prob = make_ensemble_problem()
+    print("stage1 ensemble M=8 K=1024 N=40 P=50000 (sampled)", flush=True)
+    ps, g = run_stage1(prob)
+    rng = np.random.default_rng(0)
+    sub = np.sort(rng.choice(prob["K"], 24, replace=False))
+    sub[0] = 0
+    sub[-1] = prob["K"] - 1
+    rep = compare_stage1(prob, g, samples=sub)
+    print(rep)
+
+
+@pytest.mark.parametrize("M,K,N,P", [(1, 1, 2, 1), (3, 257, 7, 1025), (2, 100, 13, 0),
+                                     (5, 64, 3, 2048), (1, 513, 25, 77)])
+def test_stage1_ragged_shapes(M, K, N, P):
+    rng = np.random.default_rng(M * 1000 + K)
+    prob = dict(make_plain_problem())
+    prob.update(M=M, K=K, N=N, M_h=M, M_v=1)
+    prob["cloud"] = (rng.normal(size=(P, 3)) * 3 + np.float32([4, 0, 0])).astype(np.float32)
+    prob["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(M, N, 4)) * 0.3).astype(np.float32)
+    prob["anchors"] = (rng.normal(size=(M, 3)) * 3).astype(np.float32)
+    prob["problem_id"] = 3
+    print(f"stage1 ragged M={M} K={K} N={N} P={P}", flush=True)
+    ps, g = run_stage1(prob)
+    compare_stage1(prob, g)
+
+
+def test_stage1_zero_noise_returns_nominal():
+    prob = dict(make_plain_problem())
+    prm = dict(prob["params"])
+    prm["sigma"] = np.zeros(4, np.float32)
+    prob["params"] = prm
+    ps, g = run_stage1(prob)
+    assert np.all(g["S1"] == g["S1"][:, :1])
+    assert np.array_equal(g["u_new"], prob["u_nom"])
+    assert np.all(g["deff"] == 0.0)
+
+
+def test_stage1_deterministic_and_batched_equals_plain():
+    rng = np.random.default_rng(11)
+    probs = []
+    for b, (M, K, N, P) in enumerate([(2, 300, 9, 3000), (4, 128, 20, 1500), (1, 1000, 5, 0)]):
+        p = dict(make_plain_problem())
+        p.update(M=M, K=K, N=N, M_h=M, M_v=1, problem_id=b)
+        p["cloud"] = (rng.normal(size=(P, 3)) * 4).astype(np.float32)
+        p["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(M, N, 4)) * 0.2).astype(np.float32)
+        p["anchors"] = (rng.normal(size=(M, 3)) * 3).astype(np.float32)
+        probs.append(p)
+    steps = [PlanStep(p, keep_debug=True) for p in probs]
+    for s in steps:
+        s.front_end()
+    # plain, twice
+    outs = []
+    for rep in range(2):
+        for s in steps:
+            s.reset()
+            s.stage1()
+        sync()
+        outs.append([(np_(s.S1), np_(s.u_nom), np_(s.min_dist2)) for s in steps])
+    for a, b in zip(outs[0], outs[1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    # batched: one call for all three problems
+    for s in steps:
+        s.reset()
+    pr = [s.problem for s in steps]
+    ws = torch.empty(aero.workspace_size(aero.CALL_MPPI_STEP, pr), dtype=torch.uint8, device=DEV)
+    aero.mppi_step(probs[0]["params"], pr, ws)
+    sync()
+    for s, ref in zip(steps, outs[0]):
+        assert np.array_equal(np_(s.S1), ref[0])
+        assert np.array_equal(np_(s.u_nom), ref[1])
+        assert np.array_equal(np_(s.min_dist2), ref[2])
+
+
+# ----------------------------------------------------------------------------
+# Stage II
+# ----------------------------------------------------------------------------
+def test_stage2_select_matches_oracle():
+    prob = make_ensemble_problem()
+    ps = PlanStep(prob)
+    ps.run()
+    sync()
+    u = np_(ps.u_nom)
+    o = OM.select_best(prob, u)
+    S2 = np_(ps.S2)
+    assert np.all(np.abs(S2 - o["S2"]) <= 1e-4 * np.abs(o["S2"]))
+    srt = np.sort(o["S2"])
+    near_tie = (srt[1] - srt[0]) <= 1e-6 * abs(srt[0])
+    if not near_tie:
+        assert int(np_(ps.best)[0]) == o["best"]
+    print(f"S2 {S2} best {int(np_(ps.best)[0])} oracle {o['best']}")
+
+
+def test_stage2_rejects_instance_through_obstacle():
+    rng = np.random.default_rng(0)
+    th = rng.uniform(-np.pi, np.pi, 4000)
+    z = rng.uniform(-2, 6, 4000)
+    prob = dict(make_plain_problem())
+    prob["cloud"] = np.stack([3.0 + 0.3 * np.cos(th), 0.3 * np.sin(th), z], 1).astype(np.float32)
+    prob["x0"] = np.float32([0, 0, 0, 1, 0, 0, 0, 4.0, 0, 0])
+    N = 40
+    u = np.zeros((2, N, 4), np.float32)
+    u[:, :, 0] = 9.81
+    u[1, :10, 1] = -0.5
+    prob.update(M=2, N=N, u_nom=u, M_h=2, M_v=1,
+                anchors=np.float32([[5, 0, 0], [5, 1, 0]]))
+    ps = PlanStep(prob)
+    ps.stage2()
+    sync()
+    o = OM.select_best(prob, u)
+    assert o["best"] == 1 and int(np_(ps.best)[0]) == 1
+    assert np_(ps.S2)[0] >= 1e6
