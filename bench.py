@@ -63,12 +63,55 @@ def cpu_baseline(prob, samples_per_instance=32):
     }
 
 
+def bench_batched(n_steps):
+    """64 uneven problems: 64 plain per-problem calls vs one batched call."""
+    import numpy as np
+    import torch
+
+    from fixtures import make_batched_problems
+    from paper_2509_17340_amd.planner import BatchPlan
+
+    t0 = time.perf_counter()
+    probs = make_batched_problems()
+    print(f"# batched fixtures: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    bp = BatchPlan(probs)
+    res = {}
+    outs = {}
+    for mode in ("plain", "batched"):
+        run = bp.run_plain if mode == "plain" else bp.run_batched
+        bp.reset()
+        run()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(n_steps):
+            bp.reset()
+            run()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / n_steps
+        res[mode] = {"ms_per_step": ms, "rollout_steps_per_s": bp.rollout_steps / (ms * 1e-3)}
+        outs[mode] = [(s.u_nom.cpu().numpy().copy(), s.S1.cpu().numpy().copy()) for s in bp.steps]
+        print(f"# batched workload {mode}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+               for a, b in zip(outs["plain"], outs["batched"]))
+    res.update(problems=len(probs), rollout_steps=bp.rollout_steps, pairs=bp.pairs,
+               speedup=res["plain"]["ms_per_step"] / res["batched"]["ms_per_step"],
+               batched_equals_plain_bitwise=bool(same), steps=n_steps,
+               workload="64 uneven problems: forest / verticals+wall / incline scenes, "
+                        "P ~ LogNormal(ln 5e4, 0.5) in [1e4, 2e5], M ~ U{4..16}, "
+                        "K ~ U{512..4096}, N ~ U{30, 40, 60}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="also time the 64-problem uneven batch (plain vs batched), N steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -111,6 +154,7 @@ def main():
     md_avg = md_ms / max(md_n, 1)
     flop = FLOP_PER_PAIR * (M * K * N) * P
     achieved = flop / (md_avg * 1e-3) / 1e12
+    dist_ms = (kt["min_dist"][0] + kt["flag"][0] + kt["min_dist_exact"][0]) / args.steps
     out = {
         "metric": METRIC,
         "value": steps_per_plan / (ms * 1e-3),
@@ -128,12 +172,18 @@ def main():
                                f"(partition 32x8 coarse x 4x4, M={M}, K={K}, N={N}, dt=0.05, "
                                f"{P}-point LiDAR cloud, Stage I + Stage II)",
                    "M": M, "K": K, "N": N, "points": P, "collision_set": "raw cloud"},
-        "roofline": {"bound": "alu", "kernel": "k_min_dist (Stage I nearest distance)",
+        "roofline": {"bound": "alu",
+                     "kernel": "k_min_dist_approx (Stage I nearest distance, pass A over every "
+                               "rollout position)",
                      "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "flop_per_launch": flop, "avg_launch_ms": md_avg},
+                     "flop_per_launch": flop, "avg_launch_ms": md_avg,
+                     "distance_all_passes_ms": dist_ms,
+                     "distance_all_passes_tflops": flop / (dist_ms * 1e-3) / 1e12},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
     }
+    if args.batched:
+        out["batched"] = bench_batched(args.batched)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

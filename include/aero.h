@@ -209,13 +209,15 @@ typedef enum aero_kernel {
   AERO_K_PARTITION = 0,    /* the four partition/anchor kernels of one call         */
   AERO_K_GUIDES = 1,
   AERO_K_ROLLOUT = 2,      /* Stage-I noise + RK4 rollout                           */
-  AERO_K_MIN_DIST = 3,     /* Stage-I brute-force nearest distance                  */
+  AERO_K_MIN_DIST = 3,     /* Stage-I nearest distance, pass A (every position)      */
   AERO_K_FINALIZE = 4,     /* Stage-I J_col and S1                                  */
   AERO_K_UPDATE = 5,       /* softmax weights and control update                    */
   AERO_K_SEL_ROLLOUT = 6,  /* Stage-II rollout                                      */
   AERO_K_SEL_MIN_DIST = 7, /* Stage-II nearest distance                             */
   AERO_K_SEL_FINAL = 8,    /* Stage-II S2 and argmin                                */
-  AERO_K_COUNT = 9
+  AERO_K_FLAG = 9,         /* Stage-I compaction of positions near the cloud        */
+  AERO_K_MIN_DIST_EXACT = 10, /* Stage-I nearest distance, pass B (flagged only)    */
+  AERO_K_COUNT = 11
 } aero_kernel;
 
 /* on != 0: from now on every launch of the kernels above is bracketed by two HIP

@@ -82,7 +82,7 @@ _SIGS = {
 }
 
 KERNELS = ("partition", "guides", "rollout", "min_dist", "finalize", "update", "sel_rollout",
-           "sel_min_dist", "sel_final")
+           "sel_min_dist", "sel_final", "flag", "min_dist_exact")
 
 
 def _load():

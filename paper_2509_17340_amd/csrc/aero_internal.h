@@ -30,7 +30,13 @@ struct DevProblem {
   int64_t row_base;      // prefix of M*N over problems
 };
 
-// One set of query positions scored against one cloud by the distance kernel.
+// One set of query positions scored against one cloud by the distance kernels.
+//
+// Exact sets (list == nullptr) run the direct-form kernel over every query.
+// Two-pass sets run the recentred expanded form over every query (pass A), flag
+// the queries whose approximate squared distance is below a per-block bound
+// (`thresh`, derived from the rounding error of pass A), and rerun the direct
+// form on the flagged list only (pass B).
 struct QuerySet {
   const float* px;
   const float* py;
@@ -40,9 +46,16 @@ struct QuerySet {
   int64_t Q;             // queries
   int32_t n_points;
   int32_t n_qblocks;     // ceil(Q / kQueriesPerBlock)
-  int32_t n_chunks;      // splits of the cloud, each a whole number of tiles
+  int32_t n_chunks;      // cloud splits for the full pass, each a whole number of tiles
   int32_t n_tiles;       // ceil(n_points / kTilePts)
   int64_t block_base;    // prefix of n_qblocks * n_chunks over sets
+  // two-pass extension
+  float* thresh;         // [n_qblocks] flag bound on the pass-A squared distance
+  int32_t* list;         // [Q] flagged query indices (nullptr: exact set)
+  int32_t* count;        // flagged count
+  int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
+  int32_t n_chunksB;
+  float d_max;
 };
 
 // Parameters promoted once on the host.
@@ -81,6 +94,11 @@ hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_sample
                           const DevParams& prm, hipStream_t s);
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                            hipStream_t s);
+hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                                  hipStream_t s);
+hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
+hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                                  hipStream_t s);
 hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_samples,
                            const DevParams& prm, hipStream_t s);
 hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,

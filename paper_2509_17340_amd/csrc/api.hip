@@ -219,11 +219,11 @@ struct MppiPlan {
   std::vector<QuerySet> sets;
   DevProblem* d_probs = nullptr;
   QuerySet* d_sets = nullptr;
-  int64_t total_samples = 0, total_rows = 0, total_blocks = 0;
+  int64_t total_samples = 0, total_rows = 0, total_blocks = 0, flag_blocks = 0, listed_items = 0;
   size_t bytes = 0;
 };
 
-void plan_mppi(const aero_problem* h, int n, char* ws, MppiPlan& pl) {
+void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl) {
   Cursor cur{ws};
   pl.d_probs = cur.take<DevProblem>(n);
   pl.d_sets = cur.take<QuerySet>(n);
@@ -234,7 +234,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, MppiPlan& pl) {
     const int64_t Q = (int64_t)h[b].M * h[b].N * h[b].K;
     if (h[b].n_points > 0) qblocks += (Q + kQueriesPerBlock - 1) / kQueriesPerBlock;
   }
-  int64_t sb = 0, rb = 0, blk = 0;
+  int64_t sb = 0, rb = 0, blk = 0, fb = 0, items = 0;
   for (int b = 0; b < n; ++b) {
     const aero_problem& q = h[b];
     DevProblem& d = pl.probs[b];
@@ -277,10 +277,26 @@ void plan_mppi(const aero_problem* h, int n, char* ws, MppiPlan& pl) {
     qs.n_chunks = q.n_points > 0 ? chunks_for(qblocks, qs.n_tiles) : 0;
     qs.block_base = blk;
     blk += (int64_t)qs.n_qblocks * qs.n_chunks;
+    qs.d_max = d_max;
+    const bool two_pass = q.n_points > 0;
+    qs.thresh = cur.take<float>(two_pass ? qs.n_qblocks : 0);
+    qs.list = cur.take<int32_t>(two_pass ? MNK : 0);
+    qs.count = cur.take<int32_t>(two_pass ? 1 : 0);
+    if (!two_pass) {
+      qs.thresh = nullptr;
+      qs.list = nullptr;
+      qs.count = nullptr;
+    }
+    qs.query_base = fb;
+    fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
+    qs.n_chunksB = two_pass ? qs.n_tiles : 0;
+    items += two_pass ? (int64_t)qs.n_qblocks * qs.n_chunksB : 0;
   }
   pl.total_samples = sb;
   pl.total_rows = rb;
   pl.total_blocks = blk;
+  pl.flag_blocks = fb;
+  pl.listed_items = items;
   pl.bytes = cur.off;
 }
 
@@ -407,7 +423,7 @@ size_t aero_workspace_size(int which, const aero_problem* h, int32_t n) {
     if (h[b].M < 1 || h[b].K < 1 || h[b].N < 2 || h[b].n_points < 0) return 0;
   if (which == AERO_CALL_MPPI_STEP) {
     MppiPlan pl;
-    plan_mppi(h, n, nullptr, pl);
+    plan_mppi(h, n, nullptr, 1.0f, pl);
     return pl.bytes;
   }
   if (which == AERO_CALL_SELECT_BEST) {
@@ -471,10 +487,10 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   e = check_problems(h, n, true);
   if (e) return e;
   MppiPlan pl;
-  plan_mppi(h, n, nullptr, pl);
+  plan_mppi(h, n, nullptr, h_prm->d_max, pl);
   if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
   if (n * (sizeof(DevProblem) + sizeof(QuerySet)) + 2 * kAlign > kSlotBytes) return AERO_ERR_SHAPE;
-  plan_mppi(h, n, (char*)d_ws, pl);
+  plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl);
   const hipStream_t s = (hipStream_t)stream;
   const DevParams prm = promote(*h_prm);
   // One staged copy for both descriptor arrays (they are adjacent in the workspace).
@@ -486,7 +502,13 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, n, pl.total_samples, prm, s); });
   if (he == hipSuccess && pl.total_blocks > 0)
-    he = timed(AERO_K_MIN_DIST, s, [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, s); });
+    he = timed(AERO_K_MIN_DIST, s,
+               [&] { return launch_min_dist_approx(pl.d_sets, n, pl.total_blocks, s); });
+  if (he == hipSuccess && pl.flag_blocks > 0)
+    he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, n, pl.flag_blocks, s); });
+  if (he == hipSuccess && pl.listed_items > 0)
+    he = timed(AERO_K_MIN_DIST_EXACT, s,
+               [&] { return launch_min_dist_listed(pl.d_sets, n, pl.listed_items, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, n, pl.total_samples, prm, s); });
   if (he == hipSuccess)

@@ -1,0 +1,344 @@
+// Brute-force nearest squared distance from rollout positions to the raw cloud
+// (the d_t of the collision cost, Sec. IV-C).
+//
+//   k_min_dist_exact   direct form (p - o)^2 per pair; cloud tiles staged in LDS
+//                      and read as wave-wide broadcasts, kQueriesPerLane queries
+//                      per lane in registers.  Over every query of a set, or (pass
+//                      B) over a flagged list with a persistent grid.
+//   k_min_dist_approx  pass A: the expanded form |o'|^2 - 2 p'.o' with query and
+//                      cloud recentred on the query block's bounding-box centre:
+//                      three FMAs and half a min3 per pair.  Also writes, per query
+//                      block, the bound below which the approximate value may hide
+//                      a true distance under d_max (from its rounding-error bound).
+//   k_flag             compacts the queries under that bound into a list and resets
+//                      them for pass B.
+//
+// Chunks of the cloud combine through atomicMin on the float bit patterns of the
+// non-negative squared distances (exact and order independent), so every result
+// is bitwise reproducible.  Queries left unflagged keep their pass-A value, which
+// is then provably >= d_max^2: there the collision penalty is 0 whatever the exact
+// distance.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "aero_device.h"
+#include "aero_internal.h"
+
+namespace aero {
+namespace {
+
+constexpr unsigned kInfBits = 0x7f800000u;
+constexpr float kFar = 1.0e18f;  // padding point of the direct form: d^2 stays finite
+constexpr float kFarT = 1.0e30f;  // padding of the expanded form
+constexpr int kPersistBlocks = 2048;
+
+// min(a, b, c) as one VALU instruction (the compiler otherwise pairs two mins).
+__device__ __forceinline__ float min3f(float a, float b, float c) {
+  float r;
+  asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// Direct-form min over the tiles [t0, t1) of the cloud for R queries per lane.
+template <int R>
+__device__ inline void direct_tiles(const QuerySet& S, int t0, int t1, float4* tile,
+                                    const float* px, const float* py, const float* pz,
+                                    float* best) {
+  const int tid = threadIdx.x;
+  for (int tl = t0; tl < t1; ++tl) {
+    const int64_t base = (int64_t)tl * kTilePts;
+#pragma unroll
+    for (int i = 0; i < kTilePts / kBlock; ++i) {
+      const int pt = i * kBlock + tid;
+      const int64_t g = base + pt;
+      const bool in = g < S.n_points;
+      const int64_t gg = in ? g : 0;  // always a valid address
+      const float x = S.cloud[3 * gg], y = S.cloud[3 * gg + 1], z = S.cloud[3 * gg + 2];
+      tile[pt] = in ? make_float4(x, y, z, 0.0f) : make_float4(kFar, kFar, kFar, 0.0f);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int j = 0; j < kTilePts; j += 2) {
+      const float4 a = tile[j];
+      const float4 c = tile[j + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float ax = px[r] - a.x, ay = py[r] - a.y, az = pz[r] - a.z;
+        const float cx = px[r] - c.x, cy = py[r] - c.y, cz = pz[r] - c.z;
+        const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
+        const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+        best[r] = min3f(best[r], da, dc);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Every query of an exact set.  Block = (query block, cloud chunk).
+__global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __restrict__ sets,
+                                                           int n_sets) {
+  __shared__ float4 tile[kTilePts];
+  const int64_t bid = blockIdx.x;
+  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
+  const QuerySet S = sets[s];
+  const int64_t local = bid - S.block_base;
+  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
+  const int tid = threadIdx.x;
+  constexpr int R = kQueriesPerLane;
+  float px[R], py[R], pz[R], best[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    const int64_t qq = q < S.Q ? q : 0;  // out-of-range lanes read query 0, never stored
+    px[r] = S.px[qq];
+    py[r] = S.py[qq];
+    pz[r] = S.pz[qq];
+    best[r] = __uint_as_float(kInfBits);
+  }
+  const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunks);
+  const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunks);
+  direct_tiles<R>(S, t0, t1, tile, px, py, pz, best);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    if (q < S.Q) atomicMin(S.out + q, __float_as_uint(best[r]));
+  }
+}
+
+// Pass B: the flagged list of every two-pass set, persistent grid.  Work item =
+// (set, list block, tile chunk); the list lengths are read on the device.
+__global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __restrict__ sets,
+                                                            int n_sets) {
+  __shared__ float4 tile[kTilePts];
+  const int tid = threadIdx.x;
+  constexpr int R = kQueriesPerLane;
+  // Walk the sets; within a set, items = ceil(count / QPB) * n_chunksB.
+  int64_t item_base = 0;
+  for (int s = 0; s < n_sets; ++s) {
+    const QuerySet& Sref = sets[s];
+    if (!Sref.list || Sref.n_points <= 0) continue;
+    const int cnt = *Sref.count;
+    const int nlb = (cnt + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    const int64_t items = (int64_t)nlb * Sref.n_chunksB;
+    // items of this set handled by this block: global item id = item_base + i
+    int64_t first = ((int64_t)blockIdx.x - item_base) % gridDim.x;
+    if (first < 0) first += gridDim.x;
+    if (items > 0) {
+      const QuerySet S = Sref;
+      for (int64_t it = first; it < items; it += gridDim.x) {
+        const int lb = (int)(it / S.n_chunksB), ch = (int)(it % S.n_chunksB);
+        float px[R], py[R], pz[R], best[R];
+        int32_t qi[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int idx = lb * kQueriesPerBlock + r * kBlock + tid;
+          const bool ok = idx < cnt;
+          const int32_t q = S.list[ok ? idx : 0];  // cnt >= 1 here: entry 0 exists
+          qi[r] = ok ? q : -1;
+          px[r] = S.px[q];
+          py[r] = S.py[q];
+          pz[r] = S.pz[q];
+          best[r] = __uint_as_float(kInfBits);
+        }
+        const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunksB);
+        const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunksB);
+        direct_tiles<R>(S, t0, t1, tile, px, py, pz, best);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (qi[r] >= 0) atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+      }
+    }
+    item_base += items;
+  }
+}
+
+__device__ inline float wave_minf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline float wave_maxf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Pass A.  Block = (query block, cloud chunk) of a two-pass set.
+__global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __restrict__ sets,
+                                                            int n_sets) {
+  __shared__ float4 tile[kTilePts];
+  __shared__ float red[7][4];
+  const int64_t bid = blockIdx.x;
+  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
+  const QuerySet S = sets[s];
+  const int64_t local = bid - S.block_base;
+  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int R = kQueriesPerLane;
+  float px[R], py[R], pz[R];
+  bool ok[R];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    ok[r] = q < S.Q;
+    const int64_t qq = ok[r] ? q : 0;
+    px[r] = S.px[qq];
+    py[r] = S.py[qq];
+    pz[r] = S.pz[qq];
+    if (ok[r]) {
+      lo[0] = fminf(lo[0], px[r]);
+      lo[1] = fminf(lo[1], py[r]);
+      lo[2] = fminf(lo[2], pz[r]);
+      hi[0] = fmaxf(hi[0], px[r]);
+      hi[1] = fmaxf(hi[1], py[r]);
+      hi[2] = fmaxf(hi[2], pz[r]);
+    }
+  }
+  // Bounding-box centre of the block's queries (exact min/max, order independent).
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_minf(lo[a]);
+    hi[a] = wave_maxf(hi[a]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      red[a][w] = lo[a];
+      red[3 + a][w] = hi[a];
+    }
+  }
+  __syncthreads();
+  float c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float l = fminf(fminf(red[a][0], red[a][1]), fminf(red[a][2], red[a][3]));
+    const float h = fmaxf(fmaxf(red[3 + a][0], red[3 + a][1]), fmaxf(red[3 + a][2], red[3 + a][3]));
+    c[a] = 0.5f * l + 0.5f * h;
+  }
+  float pp[R], tmin[R], rr = 0.0f;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    px[r] -= c[0];
+    py[r] -= c[1];
+    pz[r] -= c[2];
+    pp[r] = fmaf(pz[r], pz[r], fmaf(py[r], py[r], px[r] * px[r]));
+    if (ok[r]) rr = fmaxf(rr, pp[r]);
+    tmin[r] = kFarT;
+  }
+  const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunks);
+  const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunks);
+  for (int tl = t0; tl < t1; ++tl) {
+    const int64_t base = (int64_t)tl * kTilePts;
+#pragma unroll
+    for (int i = 0; i < kTilePts / kBlock; ++i) {
+      const int pt = i * kBlock + tid;
+      const int64_t g = base + pt;
+      const bool in = g < S.n_points;
+      const int64_t gg = in ? g : 0;
+      const float ox = S.cloud[3 * gg] - c[0];
+      const float oy = S.cloud[3 * gg + 1] - c[1];
+      const float oz = S.cloud[3 * gg + 2] - c[2];
+      tile[pt] = in ? make_float4(-2.0f * ox, -2.0f * oy, -2.0f * oz,
+                                  fmaf(oz, oz, fmaf(oy, oy, ox * ox)))
+                    : make_float4(0.0f, 0.0f, 0.0f, kFarT);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < kTilePts; j += 2) {
+      const float4 a = tile[j];
+      const float4 b = tile[j + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float ta = fmaf(px[r], a.x, fmaf(py[r], a.y, fmaf(pz[r], a.z, a.w)));
+        const float tb = fmaf(px[r], b.x, fmaf(py[r], b.y, fmaf(pz[r], b.z, b.w)));
+        tmin[r] = min3f(tmin[r], ta, tb);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    if (ok[r]) atomicMin(S.out + q, __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
+  }
+  if (ch == 0) {
+    // Rounding-error bound of the pass-A value of any pair within d_max:
+    // about 26 u (R + d_max)^2 with u = 2^-24; flag with a 5x margin.
+    rr = wave_maxf(rr);
+    __syncthreads();
+    if (lane == 0) red[6][w] = rr;
+    __syncthreads();
+    if (tid == 0) {
+      const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
+      const float span = sqrtf(R2) * 1.001f + S.d_max;
+      S.thresh[qb] = S.d_max * S.d_max + 0x1p-17f * span * span + 1e-6f;
+      if (qb == 0) *S.count = 0;
+    }
+  }
+}
+
+// Compact the queries of two-pass sets whose pass-A value is under the bound.
+// Block = 256 consecutive queries of one set; one atomic per block.
+__global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ sets, int n_sets) {
+  __shared__ int wave_cnt[4];
+  __shared__ int base;
+  const int64_t bid = blockIdx.x;
+  // query_base holds the prefix of ceil(Q / kBlock) blocks over sets
+  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.query_base; });
+  const QuerySet& S = sets[s];
+  const int64_t q = (bid - S.query_base) * kBlock + threadIdx.x;
+  bool flag = false;
+  if (q < S.Q) {
+    const float d2 = __uint_as_float(S.out[q]);
+    flag = d2 < S.thresh[q / kQueriesPerBlock];
+  }
+  const uint64_t mask = __ballot(flag);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int before = __popcll(mask & ((1ull << lane) - 1ull));
+  if (lane == 0) wave_cnt[w] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+    base = tot ? atomicAdd(S.count, tot) : 0;
+  }
+  __syncthreads();
+  if (flag) {
+    int off = base + before;
+    for (int i = 0; i < w; ++i) off += wave_cnt[i];
+    S.list[off] = (int32_t)q;
+    S.out[q] = kInfBits;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                           hipStream_t s) {
+  if (total_blocks > 0) k_min_dist_exact<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                                  hipStream_t s) {
+  if (total_blocks > 0)
+    k_min_dist_approx<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks > 0) k_flag<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t max_items,
+                                  hipStream_t s) {
+  if (max_items > 0) {
+    const unsigned grid = (unsigned)(max_items < kPersistBlocks ? max_items : kPersistBlocks);
+    k_min_dist_listed<<<grid, kBlock, 0, s>>>(d_sets, n_sets);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace aero

@@ -3,11 +3,7 @@
 //   k_rollout      one lane per (problem, instance, sample): Philox noise, clip,
 //                  RK4 in binary64, smooth cost terms; writes the clipped
 //                  perturbations and float32 positions as sample-fastest planes
-//   k_min_dist     brute-force nearest squared distance of every rollout position
-//                  to the raw cloud: cloud tiles staged in LDS, read as wave-wide
-//                  broadcasts, kQueriesPerLane positions per lane in registers;
-//                  cloud chunks of one query block combine through atomicMin on
-//                  the float bit patterns (exact, order independent)
+//   (the nearest-distance kernels live in distance.hip)
 //   k_finalize     J_col from the distances, S1 = smooth part + w_col J_col
 //   k_update       per (instance, step): rho, eta, and sum_k eps_k delta_eff_k
 //                  with fixed-order wave/block reductions in binary64
@@ -24,7 +20,6 @@ namespace aero {
 namespace {
 
 constexpr unsigned kInfBits = 0x7f800000u;
-constexpr float kFar = 1.0e18f;   // padding point: its squared distance stays finite
 
 __device__ inline void load_rg(const float* qg, double Rg[9]) {
   const double w = qg[0], x = qg[1], y = qg[2], z = qg[3];
@@ -104,71 +99,6 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
   const double J_ctrl = prm.Q_c * s_u2 + prm.Q_cdelta * s_du2;
   P.S_smooth[(int64_t)m * K + k] =
       prm.w[0] * J_track + prm.w[1] * J_vnorm + prm.w[2] * J_ctrl + prm.w[3] * s_goal;
-}
-
-// Brute-force nearest squared distance.  Block = (query block, cloud chunk).
-__global__ __launch_bounds__(kBlock) void k_min_dist(const QuerySet* __restrict__ sets,
-                                                     int n_sets) {
-  __shared__ float4 tile[kTilePts];
-  const int64_t bid = blockIdx.x;
-  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
-  const QuerySet S = sets[s];
-  const int64_t local = bid - S.block_base;
-  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
-  const int tid = threadIdx.x;
-
-  float px[kQueriesPerLane], py[kQueriesPerLane], pz[kQueriesPerLane], best[kQueriesPerLane];
-#pragma unroll
-  for (int r = 0; r < kQueriesPerLane; ++r) {
-    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
-    const bool ok = q < S.Q;
-    px[r] = ok ? S.px[q] : 0.0f;
-    py[r] = ok ? S.py[q] : 0.0f;
-    pz[r] = ok ? S.pz[q] : 0.0f;
-    best[r] = __uint_as_float(kInfBits);
-  }
-  const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunks);
-  const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunks);
-  for (int tl = t0; tl < t1; ++tl) {
-    const int64_t base = (int64_t)tl * kTilePts;
-#pragma unroll
-    for (int i = 0; i < kTilePts / kBlock; ++i) {
-      const int pt = i * kBlock + tid;
-      const int64_t g = base + pt;
-      float4 o;
-      if (g < S.n_points) {
-        o.x = S.cloud[3 * g];
-        o.y = S.cloud[3 * g + 1];
-        o.z = S.cloud[3 * g + 2];
-      } else {
-        o.x = kFar;
-        o.y = kFar;
-        o.z = kFar;
-      }
-      o.w = 0.0f;
-      tile[pt] = o;
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int j = 0; j < kTilePts; j += 2) {
-      const float4 a = tile[j];
-      const float4 c = tile[j + 1];
-#pragma unroll
-      for (int r = 0; r < kQueriesPerLane; ++r) {
-        const float ax = px[r] - a.x, ay = py[r] - a.y, az = pz[r] - a.z;
-        const float cx = px[r] - c.x, cy = py[r] - c.y, cz = pz[r] - c.z;
-        const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
-        const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-        best[r] = fminf(best[r], fminf(da, dc));
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < kQueriesPerLane; ++r) {
-    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
-    if (q < S.Q) atomicMin(S.out + q, __float_as_uint(best[r]));
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const DevProblem* __restrict__ probs, int n,
@@ -304,12 +234,6 @@ inline unsigned grid1d(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock)
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
                           hipStream_t s) {
   k_rollout<<<grid1d(total), kBlock, 0, s>>>(d_probs, n, total, prm);
-  return hipGetLastError();
-}
-
-hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                           hipStream_t s) {
-  if (total_blocks > 0) k_min_dist<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
   return hipGetLastError();
 }
 

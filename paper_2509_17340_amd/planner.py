@@ -89,3 +89,44 @@ class PlanStep:
         self.front_end()
         self.stage1()
         self.stage2()
+
+
+class BatchPlan:
+    """Many independent planning problems: per-problem calls or one batched call.
+
+    Both modes run the same partition/guide calls per problem; Stage I and Stage
+    II are either 2 x n_problems plain calls or 2 batched calls.
+    """
+
+    def __init__(self, probs, device="cuda"):
+        self.steps = [PlanStep(p, device=device) for p in probs]
+        self.problems = [s.problem for s in self.steps]
+        self.params = probs[0]["params"]
+        dev = torch.device(device)
+        ws = max(workspace_size(CALL_MPPI_STEP, self.problems),
+                 workspace_size(CALL_SELECT_BEST, self.problems))
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
+        self.S2 = torch.empty(sum(s.M for s in self.steps), dtype=torch.float64, device=dev)
+        self.best = torch.empty(len(self.steps), dtype=torch.int32, device=dev)
+        self.rollout_steps = sum(s.M * s.K * s.N + s.M * s.N for s in self.steps)
+        self.pairs = sum(s.M * s.K * s.N * int(s.cloud.shape[0]) for s in self.steps)
+
+    def reset(self):
+        for s in self.steps:
+            s.reset()
+
+    def front_end(self):
+        for s in self.steps:
+            s.front_end()
+
+    def run_plain(self):
+        self.front_end()
+        for s in self.steps:
+            s.stage1()
+        for s in self.steps:
+            s.stage2()
+
+    def run_batched(self):
+        self.front_end()
+        mppi_step(self.params, self.problems, self.ws)
+        select_best(self.params, self.problems, self.S2, self.best, self.ws)

@@ -163,7 +163,14 @@ def compare_stage1(prob, g, samples=None, nearest_fn=nearest):
     gd = np.sqrt(np.transpose(g["md2"], (0, 2, 1))[:, sub].astype(np.float64))
     fin = np.isfinite(st["d"])
     assert np.array_equal(fin, np.isfinite(gd))
-    assert np.abs(gd[fin] - st["d"][fin]).max(initial=0.0) <= 1e-5
+    d_max = float(np.float32(prm["d_max"]))
+    # exact wherever the collision penalty depends on d; beyond, the first-pass
+    # value is only required to stay on the same (zero-penalty) side of d_max
+    near = fin & (st["d"] < 1.2 * d_max)
+    far = fin & ~near
+    assert np.abs(gd[near] - st["d"][near]).max(initial=0.0) <= 1e-5
+    assert np.all(gd[far] >= d_max)
+    assert (np.abs(gd[far] ** 2 - st["d"][far] ** 2) / st["d"][far] ** 2).max(initial=0.0) <= 2e-3
     strad = straddles(st["d"], float(np.float32(prm["d_max"])))
     S_o, S_g = st["S1"], g["S1"][:, sub]
     rel = np.abs(S_g - S_o) / np.abs(S_o)
