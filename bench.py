@@ -63,6 +63,46 @@ def cpu_baseline(prob, samples_per_instance=32):
     }
 
 
+def bench_adjoint(prob, iters=20):
+    """Forward (one Stage-I call) vs backward (aero_mppi_step_backward), same GPU."""
+    import torch
+
+    import paper_2509_17340_amd as aero
+    from paper_2509_17340_amd.planner import PlanStep
+
+    ps = PlanStep(prob)
+    ps.front_end()
+    M, K, N = prob["M"], prob["K"], prob["N"]
+    pr = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], ps.u_nom, coef=ps.coef,
+                      v_goal=prob["v_goal"], q_goal=prob["q_goal"])
+    ws = torch.empty(aero.workspace_size(aero.CALL_BACKWARD, [pr]), dtype=torch.uint8,
+                     device="cuda")
+    gu = torch.empty((M, N, 4), dtype=torch.float32, device="cuda")
+    gw = torch.empty(5, dtype=torch.float32, device="cuda")
+    res = {}
+    for name in ("forward", "backward"):
+        def once():
+            if name == "forward":
+                ps.reset()
+                ps.stage1()
+            else:
+                aero.mppi_step_backward(prob["params"], pr, 1.0, gu, gw, ws)
+        for _ in range(3):
+            once()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            once()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = e0.elapsed_time(e1) / iters
+    res["backward_over_forward"] = res["backward_ms"] / res["forward_ms"]
+    res["workload"] = (f"gradient of sum S1 w.r.t. u_nom [{M}][{N}][4] and the 5 weights, "
+                       f"same inputs as the headline step (checkpoints every 8 steps)")
+    return res
+
+
 def bench_batched(n_steps):
     """64 uneven problems: 64 plain per-problem calls vs one batched call."""
     import numpy as np
@@ -136,15 +176,16 @@ def main():
 
     aero.timing_enable(True)
     aero.timing_read(reset=True)
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         ps.reset()
         ps.run()
-    end.record()
+        evs[i + 1].record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
+    ms = evs[0].elapsed_time(evs[-1]) / args.steps
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
     kt = aero.timing_read(reset=True)
     aero.timing_enable(False)
     print(f"# timed {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
@@ -163,6 +204,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "plan_step_ms_p50": per_step[len(per_step) // 2],
+        "plan_step_ms_p99": per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -182,6 +225,7 @@ def main():
                      "distance_all_passes_tflops": flop / (dist_ms * 1e-3) / 1e12},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
     }
+    out["adjoint"] = bench_adjoint(prob)
     if args.batched:
         out["batched"] = bench_batched(args.batched)
     if not args.no_cpu_baseline:

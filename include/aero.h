@@ -88,7 +88,12 @@ typedef struct aero_problem {
   float* u_nom;         /* device [M][N][4] nominal controls; updated in place      */
   double* S1;           /* optional device [M][K]: Stage-I cost of every sample     */
   float* delta_eff;     /* optional device [M][N][4][K]: clipped perturbations      */
-  float* min_dist2;     /* optional device [M][N][K]: squared nearest distance      */
+  float* min_dist2;     /* optional device [M][N][K]: squared nearest distance; exact  *
+                         * wherever it is below about d_max^2, elsewhere only a value *
+                         * known to be >= d_max^2                                     */
+  int32_t* nearest_idx; /* optional device [M][N][K], aero_mppi_step_backward only:   *
+                         * nearest cloud point (lowest index on ties) of positions    *
+                         * within reach of d_max, -1 elsewhere                        */
 } aero_problem;
 
 /* Angular grid of the multi-resolution partition (Sec. IV-A). */
@@ -217,7 +222,10 @@ typedef enum aero_kernel {
   AERO_K_SEL_FINAL = 8,    /* Stage-II S2 and argmin                                */
   AERO_K_FLAG = 9,         /* Stage-I compaction of positions near the cloud        */
   AERO_K_MIN_DIST_EXACT = 10, /* Stage-I nearest distance, pass B (flagged only)    */
-  AERO_K_COUNT = 11
+  AERO_K_NEAREST = 11,     /* backward: nearest indices of flagged positions         */
+  AERO_K_ADJOINT = 12,     /* backward: per-sample reverse sweep                     */
+  AERO_K_GRAD_REDUCE = 13, /* backward: sums over samples                            */
+  AERO_K_COUNT = 14
 } aero_kernel;
 
 /* on != 0: from now on every launch of the kernels above is bracketed by two HIP

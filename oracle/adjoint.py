@@ -45,10 +45,13 @@ def active_set(prob, coef, u_nom=None, normals=None, nearest_fn=nearest, nearest
         d, idx = d.reshape(M, K, N), idx.reshape(M, K, N)
     else:
         idx = np.asarray(nearest_idx, np.int64)
-        d = np.where(idx >= 0, np.linalg.norm(pos - cloud[np.maximum(idx, 0)], axis=-1), np.inf)
+    # an empty collision set has no nearest point: d = +inf (zero penalty)
+    pad = np.concatenate([cloud, np.zeros((1, 3))])          # row -1 (= last) is a dummy
+    o_star = np.where((idx >= 0)[..., None], pad[np.where(idx >= 0, idx, -1)], 0.0)
+    if nearest_idx is not None:
+        d = np.where(idx >= 0, np.linalg.norm(pos - o_star, axis=-1), np.inf)
     d_min, d_max = f64(prm["d_min"]), f64(prm["d_max"])
     branch = np.where(d < d_min, 0, np.where(d < d_max, 1, 2))
-    o_star = np.where((idx >= 0)[..., None], cloud[np.maximum(idx, 0)], 0.0)
     return dict(mask=mask, clipped=u, normals=np.asarray(normals, np.float64), branch=branch,
                 o_star=o_star, d=d, idx=idx)
 

@@ -51,6 +51,7 @@ class ProblemStruct(ctypes.Structure):
         ("v_goal", ctypes.c_float * 3), ("q_goal", ctypes.c_float * 4),
         ("coef", ctypes.c_void_p), ("u_nom", ctypes.c_void_p), ("S1", ctypes.c_void_p),
         ("delta_eff", ctypes.c_void_p), ("min_dist2", ctypes.c_void_p),
+        ("nearest_idx", ctypes.c_void_p),
     ]
 
 
@@ -82,7 +83,8 @@ _SIGS = {
 }
 
 KERNELS = ("partition", "guides", "rollout", "min_dist", "finalize", "update", "sel_rollout",
-           "sel_min_dist", "sel_final", "flag", "min_dist_exact")
+           "sel_min_dist", "sel_final", "flag", "min_dist_exact", "nearest", "adjoint",
+           "grad_reduce")
 
 
 def _load():
@@ -150,7 +152,7 @@ class Problem:
 
     def __init__(self, cloud, M, K, N, x0, p_goal, u_nom, coef=None, v_goal=(0, 0, 0),
                  q_goal=(1, 0, 0, 0), S1=None, delta_eff=None, min_dist2=None, problem_id=0,
-                 n_points=None):
+                 n_points=None, nearest_idx=None):
         self.cloud, self.M, self.K, self.N = cloud, int(M), int(K), int(N)
         self.n_points = int(cloud.shape[0]) if n_points is None else int(n_points)
         self.x0 = np.asarray(x0, np.float32)
@@ -159,6 +161,7 @@ class Problem:
         self.q_goal = np.asarray(q_goal, np.float32)
         self.u_nom, self.coef = u_nom, coef
         self.S1, self.delta_eff, self.min_dist2 = S1, delta_eff, min_dist2
+        self.nearest_idx = nearest_idx
         self.problem_id = int(problem_id)
 
     def struct(self):
@@ -172,6 +175,7 @@ class Problem:
         s.q_goal[:] = [float(v) for v in self.q_goal]
         s.coef, s.u_nom = _ptr(self.coef), _ptr(self.u_nom)
         s.S1, s.delta_eff, s.min_dist2 = _ptr(self.S1), _ptr(self.delta_eff), _ptr(self.min_dist2)
+        s.nearest_idx = _ptr(self.nearest_idx)
         return s
 
 

@@ -1,0 +1,63 @@
+"""torch.autograd.Function over the Stage-I cost of one planning problem.
+
+    L = StageOneCost.apply(u_nom, w, step)    # L = sum_{m,k} S1[m,k]
+
+forward runs aero_mppi_step on a copy of u_nom (the input is not modified) and
+returns the summed cost; backward runs aero_mppi_step_backward with the upstream
+gradient as `scale` and returns dL/du_nom and dL/dw.  Both directions are single
+library calls; this module only moves pointers and scalars.
+"""
+import numpy as np
+import torch
+
+from . import CALL_BACKWARD, CALL_MPPI_STEP, Problem, mppi_step, mppi_step_backward, workspace_size
+
+
+class StageOneContext:
+    """Device inputs of one problem that the cost depends on besides u_nom, w."""
+
+    def __init__(self, cloud, coef, M, K, N, x0, p_goal, params, v_goal=(0, 0, 0),
+                 q_goal=(1, 0, 0, 0), problem_id=0):
+        self.cloud, self.coef = cloud, coef
+        self.M, self.K, self.N = M, K, N
+        self.x0, self.p_goal, self.v_goal, self.q_goal = x0, p_goal, v_goal, q_goal
+        self.params = dict(params)
+        self.problem_id = problem_id
+        dev = cloud.device
+        self.S1 = torch.empty((M, K), dtype=torch.float64, device=dev)
+        self.nearest_idx = torch.empty((M, N, K), dtype=torch.int32, device=dev)
+        p = self._problem(torch.empty((M, N, 4), dtype=torch.float32, device=dev))
+        ws = max(workspace_size(CALL_MPPI_STEP, [p]), workspace_size(CALL_BACKWARD, [p]))
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
+
+    def _problem(self, u, with_idx=False):
+        return Problem(self.cloud, self.M, self.K, self.N, self.x0, self.p_goal, u, coef=self.coef,
+                       v_goal=self.v_goal, q_goal=self.q_goal, S1=self.S1,
+                       nearest_idx=self.nearest_idx if with_idx else None,
+                       problem_id=self.problem_id)
+
+    def params_with(self, w):
+        prm = dict(self.params)
+        prm["w"] = np.asarray(w.detach().cpu().numpy(), np.float32)
+        return prm
+
+
+class StageOneCost(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u_nom, w, sc):
+        u = u_nom.detach().to(torch.float32).contiguous().clone()
+        prm = sc.params_with(w)
+        mppi_step(prm, [sc._problem(u)], sc.ws)
+        ctx.save_for_backward(u_nom.detach().to(torch.float32).contiguous(), w.detach())
+        ctx.sc = sc
+        return sc.S1.sum()
+
+    @staticmethod
+    def backward(ctx, gL):
+        u_nom, w = ctx.saved_tensors
+        sc = ctx.sc
+        gu = torch.empty_like(u_nom)
+        gw = torch.empty(5, dtype=torch.float32, device=u_nom.device)
+        mppi_step_backward(sc.params_with(w), sc._problem(u_nom, with_idx=True), float(gL), gu, gw,
+                           sc.ws)
+        return gu, gw.to(w.dtype), None

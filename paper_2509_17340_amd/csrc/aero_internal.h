@@ -28,6 +28,8 @@ struct DevProblem {
   unsigned* mind2;       // [M][N][K] float bits of the squared nearest distance
   int64_t sample_base;   // prefix of M*K over problems
   int64_t row_base;      // prefix of M*N over problems
+  double* J;             // optional [5][M*K] unweighted terms (track, vnorm, ctrl, goal, col)
+  int32_t* nidx;         // optional [M][N][K] nearest point index (-1: none within reach)
 };
 
 // One set of query positions scored against one cloud by the distance kernels.
@@ -56,6 +58,9 @@ struct QuerySet {
   int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
   int32_t n_chunksB;
   float d_max;
+  unsigned long long* nn;  // optional [Q]: pass B also keeps (d^2 bits << 32 | index),
+                           // indexed by list position (lowest index on ties)
+  int32_t* nidx;           // with nn: [Q] nearest index per query (-1 where not flagged)
 };
 
 // Parameters promoted once on the host.
@@ -99,6 +104,12 @@ hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t to
 hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                   hipStream_t s);
+hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);
+hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
+                          double* ckpt, double* seg, double* gsamp, hipStream_t s);
+hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, int64_t rows,
+                              const double* gsamp, double scale, float* grad_u, float* grad_w,
+                              hipStream_t s);
 hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_samples,
                            const DevParams& prm, hipStream_t s);
 hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,

@@ -300,6 +300,44 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   pl.bytes = cur.off;
 }
 
+struct BackwardPlan {
+  MppiPlan fwd;
+  double* J = nullptr;
+  int32_t* nidx = nullptr;
+  unsigned long long* nn = nullptr;
+  double* ckpt = nullptr;
+  double* seg = nullptr;
+  double* gsamp = nullptr;
+  size_t bytes = 0;
+};
+
+void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& bp) {
+  plan_mppi(h, 1, ws, d_max, bp.fwd);
+  Cursor cur{ws};
+  cur.off = bp.fwd.bytes;
+  const aero_problem& q = h[0];
+  const int64_t MK = (int64_t)q.M * q.K, MNK = MK * q.N;
+  const int64_t n_seg = (q.N + 7) / 8;
+  bp.J = cur.take<double>(5 * MK);
+  int32_t* ni = cur.take<int32_t>(q.nearest_idx ? 0 : MNK);
+  bp.nidx = q.nearest_idx ? q.nearest_idx : ni;
+  bp.nn = cur.take<unsigned long long>(q.n_points > 0 ? MNK : 0);
+  bp.ckpt = cur.take<double>(n_seg * 10 * MK);
+  bp.seg = cur.take<double>(8 * 10 * MK);
+  bp.gsamp = cur.take<double>(MNK * 4);
+  bp.bytes = cur.off;
+  if (ws) {
+    DevProblem& d = bp.fwd.probs[0];
+    d.J = bp.J;
+    d.nidx = bp.nidx;
+    QuerySet& qs = bp.fwd.sets[0];
+    if (q.n_points > 0) {
+      qs.nn = bp.nn;
+      qs.nidx = bp.nidx;
+    }
+  }
+}
+
 struct SelectPlan {
   std::vector<DevSelect> sel;
   std::vector<QuerySet> sets;
@@ -425,6 +463,12 @@ size_t aero_workspace_size(int which, const aero_problem* h, int32_t n) {
     MppiPlan pl;
     plan_mppi(h, n, nullptr, 1.0f, pl);
     return pl.bytes;
+  }
+  if (which == AERO_CALL_BACKWARD) {
+    if (n != 1) return 0;
+    BackwardPlan bp;
+    plan_backward(h, nullptr, 1.0f, bp);
+    return bp.bytes;
   }
   if (which == AERO_CALL_SELECT_BEST) {
     SelectPlan pl;
@@ -552,10 +596,43 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   if (e) return e;
   if (!d_grad_u_nom || !d_grad_w) return AERO_ERR_NULL;
   if (!finite(scale)) return AERO_ERR_PARAM;
-  (void)d_ws;
-  (void)ws_bytes;
-  (void)stream;
-  return AERO_ERR_SHAPE;  // adjoint kernels not built yet
+  BackwardPlan bp;
+  plan_backward(h, nullptr, h_prm->d_max, bp);
+  if (!d_ws || ws_bytes < bp.bytes) return AERO_ERR_WORKSPACE;
+  plan_backward(h, (char*)d_ws, h_prm->d_max, bp);
+  MppiPlan& pl = bp.fwd;
+  const hipStream_t s = (hipStream_t)stream;
+  const DevParams prm = promote(*h_prm);
+  std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_probs + sizeof(QuerySet));
+  memcpy(blob.data(), pl.probs.data(), sizeof(DevProblem));
+  memcpy(blob.data() + ((char*)pl.d_sets - (char*)pl.d_probs), pl.sets.data(), sizeof(QuerySet));
+  const aero_problem& q = h[0];
+  const int64_t MK = (int64_t)q.M * q.K, MN = (int64_t)q.M * q.N;
+  hipError_t he = stage_copy(pl.d_probs, blob.data(), blob.size(), s);
+  if (he == hipSuccess)
+    he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, 1, pl.total_samples, prm, s); });
+  if (he == hipSuccess && pl.total_blocks > 0)
+    he = timed(AERO_K_MIN_DIST, s,
+               [&] { return launch_min_dist_approx(pl.d_sets, 1, pl.total_blocks, s); });
+  if (he == hipSuccess && pl.flag_blocks > 0)
+    he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, 1, pl.flag_blocks, s); });
+  if (he == hipSuccess && pl.listed_items > 0)
+    he = timed(AERO_K_MIN_DIST_EXACT, s,
+               [&] { return launch_min_dist_listed(pl.d_sets, 1, pl.listed_items, s); });
+  if (he == hipSuccess && q.n_points > 0)
+    he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, 1, s); });
+  if (he == hipSuccess)
+    he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, 1, MK, prm, s); });
+  if (he == hipSuccess)
+    he = timed(AERO_K_ADJOINT, s, [&] {
+      return launch_adjoint(pl.d_probs, prm, MK, bp.ckpt, bp.seg, bp.gsamp, s);
+    });
+  if (he == hipSuccess)
+    he = timed(AERO_K_GRAD_REDUCE, s, [&] {
+      return launch_grad_reduce(pl.d_probs, prm, MN, bp.gsamp, (double)scale, d_grad_u_nom,
+                                d_grad_w, s);
+    });
+  return dev_status(he);
 }
 
 int aero_timing_enable(int on) {

@@ -40,11 +40,13 @@ __device__ __forceinline__ float min3f(float a, float b, float c) {
   return r;
 }
 
-// Direct-form min over the tiles [t0, t1) of the cloud for R queries per lane.
-template <int R>
+// Direct-form min over the tiles [t0, t1) of the cloud for R queries per lane;
+// with kIdx also the lowest point index attaining it (points are visited in
+// increasing index order within a lane and ties never replace).
+template <int R, bool kIdx>
 __device__ inline void direct_tiles(const QuerySet& S, int t0, int t1, float4* tile,
                                     const float* px, const float* py, const float* pz,
-                                    float* best) {
+                                    float* best, int32_t* bidx) {
   const int tid = threadIdx.x;
   for (int tl = t0; tl < t1; ++tl) {
     const int64_t base = (int64_t)tl * kTilePts;
@@ -68,7 +70,19 @@ __device__ inline void direct_tiles(const QuerySet& S, int t0, int t1, float4* t
         const float cx = px[r] - c.x, cy = py[r] - c.y, cz = pz[r] - c.z;
         const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
         const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-        best[r] = min3f(best[r], da, dc);
+        if constexpr (kIdx) {
+          const int ia = (int)(base + j);
+          if (da < best[r]) {
+            best[r] = da;
+            bidx[r] = ia;
+          }
+          if (dc < best[r]) {
+            best[r] = dc;
+            bidx[r] = ia + 1;
+          }
+        } else {
+          best[r] = min3f(best[r], da, dc);
+        }
       }
     }
     __syncthreads();
@@ -98,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
   }
   const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunks);
   const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunks);
-  direct_tiles<R>(S, t0, t1, tile, px, py, pz, best);
+  direct_tiles<R, false>(S, t0, t1, tile, px, py, pz, best, nullptr);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
@@ -143,10 +157,25 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
         }
         const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunksB);
         const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunksB);
-        direct_tiles<R>(S, t0, t1, tile, px, py, pz, best);
+        if (S.nn) {
+          int32_t bidx[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (qi[r] >= 0) atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+          for (int r = 0; r < R; ++r) bidx[r] = 0x7fffffff;
+          direct_tiles<R, true>(S, t0, t1, tile, px, py, pz, best, bidx);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (qi[r] >= 0) {
+              const int idx = lb * kQueriesPerBlock + r * kBlock + tid;
+              atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+              atomicMin(S.nn + idx, ((unsigned long long)__float_as_uint(best[r]) << 32) |
+                                        (unsigned long long)(unsigned)bidx[r]);
+            }
+        } else {
+          direct_tiles<R, false>(S, t0, t1, tile, px, py, pz, best, nullptr);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (qi[r] >= 0) atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+        }
       }
     }
     item_base += items;
@@ -309,6 +338,22 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
     for (int i = 0; i < w; ++i) off += wave_cnt[i];
     S.list[off] = (int32_t)q;
     S.out[q] = kInfBits;
+    if (S.nn) S.nn[off] = ~0ull;
+  }
+}
+
+// Nearest indices of the flagged queries (sets with nn), persistent grid.
+__global__ __launch_bounds__(kBlock) void k_scatter_nearest(const QuerySet* __restrict__ sets,
+                                                            int n_sets) {
+  for (int s = 0; s < n_sets; ++s) {
+    const QuerySet& S = sets[s];
+    if (!S.nn || !S.list) continue;
+    const int cnt = *S.count;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+      const unsigned long long v = S.nn[i];
+      const unsigned idx = (unsigned)(v & 0xffffffffull);
+      S.nidx[S.list[i]] = (v == ~0ull || idx >= (unsigned)S.n_points) ? -1 : (int32_t)idx;
+    }
   }
 }
 
@@ -329,6 +374,11 @@ hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t to
 
 hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_blocks, hipStream_t s) {
   if (total_blocks > 0) k_flag<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_t s) {
+  k_scatter_nearest<<<256, kBlock, 0, s>>>(d_sets, n_sets);
   return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
     P.pos[MNK + qi] = (float)x[1];
     P.pos[2 * MNK + qi] = (float)x[2];
     P.mind2[qi] = kInfBits;
+    if (P.nidx) P.nidx[qi] = -1;
     // guide position f((t+1) dt) by Horner
     const double tau = (double)(t + 1) * prm.dt;
     double e2 = 0.0;
@@ -97,8 +98,15 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
   const double J_track = prm.Q_track * s_track;
   const double J_vnorm = prm.Q_vnorm * s_vnorm;
   const double J_ctrl = prm.Q_c * s_u2 + prm.Q_cdelta * s_du2;
-  P.S_smooth[(int64_t)m * K + k] =
-      prm.w[0] * J_track + prm.w[1] * J_vnorm + prm.w[2] * J_ctrl + prm.w[3] * s_goal;
+  const int64_t i = (int64_t)m * K + k;
+  P.S_smooth[i] = prm.w[0] * J_track + prm.w[1] * J_vnorm + prm.w[2] * J_ctrl + prm.w[3] * s_goal;
+  if (P.J) {
+    const int64_t MK = (int64_t)P.M * K;
+    P.J[i] = J_track;
+    P.J[MK + i] = J_vnorm;
+    P.J[2 * MK + i] = J_ctrl;
+    P.J[3 * MK + i] = s_goal;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const DevProblem* __restrict__ probs, int n,
@@ -117,6 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const DevProblem* __restric
   }
   const int64_t i = (int64_t)m * K + k;
   P.S1[i] = P.S_smooth[i] + prm.w[4] * col;
+  if (P.J) P.J[4 * (int64_t)P.M * K + i] = col;
 }
 
 // Block-wide reductions (4 waves) in a fixed order; every thread gets the result.

@@ -93,3 +93,17 @@ def test_collision_gradient_points_away_from_obstacle():
     gu, _, _ = A.grad(prob, coef, act)
     # more thrust moves the drone up, closer to the point: cost increases
     assert np.all(gu[0, :-1, 0] > 0)
+
+
+def test_empty_cloud_has_no_collision_gradient():
+    prob, coef = small_problem(K=8, N=5, M=1)
+    prob["cloud"] = np.zeros((0, 3), np.float32)
+    act = A.active_set(prob, coef)
+    assert np.all(act["branch"] == 2) and np.all(act["idx"] == -1)
+    act2 = A.active_set(prob, coef, nearest_idx=np.full((1, 8, 5), -1))
+    assert np.all(act2["branch"] == 2)
+    prm = dict(prob["params"])
+    prm["w"] = np.float32([0, 0, 0, 0, 1])
+    prob["params"] = prm
+    gu, gw, L = A.grad(prob, coef, act)
+    assert L == 0.0 and np.all(gu == 0.0)
