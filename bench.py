@@ -103,6 +103,40 @@ def bench_adjoint(prob, iters=20):
     return res
 
 
+def bench_paper_point(steps=200):
+    """The paper's operating point (M=15, K=128, N=25, 120x60 partition, 200k-point
+    cloud, P_f collision set), replayed from a HIP graph: planning rate on one GPU."""
+    import torch
+
+    from fixtures import make_paper_point_problem
+    from paper_2509_17340_amd.planner import GraphStep, PlanStep
+
+    prob = make_paper_point_problem()
+    ps = PlanStep(prob)
+    g = GraphStep(ps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(steps):
+        g.replay()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    ms = ev[0].elapsed_time(ev[-1]) / steps
+    M, K, N = prob["M"], prob["K"], prob["N"]
+    tensors = [ps.cloud, ps.tables, ps.fine_key, ps.fine_idx, ps.coarse_best, ps.anchor_cell,
+               ps.anchor_fine, ps.anchors, ps.pf, ps.coef, ps.u_init, ps.u_nom, ps.S1, ps.S2,
+               ps.best, ps.ws]
+    mem = sum(t.numel() * t.element_size() for t in tensors)
+    return {"ms_per_step": ms, "p50_ms": per[steps // 2], "p99_ms": per[int(0.99 * steps)],
+            "plans_per_s": 1e3 / ms, "rollout_steps_per_s": (M * K * N + M * N) / (ms * 1e-3),
+            "device_bytes": mem,
+            "workload": f"M={M} (5x3), K={K}, N={N}, dt=0.05, 200k-point cloud within 10 m, "
+                        "120x60 fine / 20x10 coarse partition, collision set P_f",
+            "paper_context": "500 Hz on GeForce RTX 4080 SUPER at K=128-256, N=25; "
+                             "<600 MB at N=25, K=256 (Sec. V-B-1)"}
+
+
 def bench_batched(n_steps):
     """64 uneven problems: 64 plain per-problem calls vs one batched call."""
     import numpy as np
@@ -188,7 +222,21 @@ def main():
     per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
     kt = aero.timing_read(reset=True)
     aero.timing_enable(False)
-    print(f"# timed {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"# timed {args.steps} eager steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # the same step captured once as a HIP graph and replayed
+    from paper_2509_17340_amd.planner import GraphStep
+    g = GraphStep(ps)
+    gev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    gev[0].record()
+    for i in range(args.steps):
+        g.replay()
+        gev[i + 1].record()
+    torch.cuda.synchronize()
+    gms = gev[0].elapsed_time(gev[-1]) / args.steps
+    g_steps = sorted(gev[i].elapsed_time(gev[i + 1]) for i in range(args.steps))
+    print(f"# timed {args.steps} graph replays: {gms:.3f} ms/step", file=sys.stderr, flush=True)
 
     steps_per_plan = M * K * N + M * N
     md_ms, md_n = kt["min_dist"]
@@ -196,16 +244,21 @@ def main():
     flop = FLOP_PER_PAIR * (M * K * N) * P
     achieved = flop / (md_avg * 1e-3) / 1e12
     dist_ms = (kt["min_dist"][0] + kt["flag"][0] + kt["min_dist_exact"][0]) / args.steps
+    best_ms = min(ms, gms)
     out = {
         "metric": METRIC,
-        "value": steps_per_plan / (ms * 1e-3),
+        "value": steps_per_plan / (best_ms * 1e-3),
         "unit": "rollout-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
-        "plan_step_ms_p50": per_step[len(per_step) // 2],
-        "plan_step_ms_p99": per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))],
+        "ms_per_step": best_ms,
+        "launch_mode": "hip_graph" if gms <= ms else "eager",
+        "eager_ms_per_step": ms,
+        "graph_ms_per_step": gms,
+        "plan_step_ms_p50": (g_steps if gms <= ms else per_step)[args.steps // 2],
+        "plan_step_ms_p99": (g_steps if gms <= ms else per_step)[
+            min(args.steps - 1, int(0.99 * args.steps))],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -226,6 +279,7 @@ def main():
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
     }
     out["adjoint"] = bench_adjoint(prob)
+    out["paper_operating_point"] = bench_paper_point()
     if args.batched:
         out["batched"] = bench_batched(args.batched)
     if not args.no_cpu_baseline:

@@ -11,5 +11,5 @@ from .scenes import (  # noqa: F401
 )
 from .configs import (  # noqa: F401
     table1_params, make_plain_problem, make_ensemble_problem,
-    make_batched_problems, make_loop_step, split_instances, hover_controls,
+    make_batched_problems, make_loop_step, make_paper_point_problem, split_instances, hover_controls,
 )

@@ -134,6 +134,33 @@ def make_ensemble_problem(seed=2, n_points=50000, K=1024, N=40, M=8):
                     name=f"ensemble-forest-{n_points // 1000}k")
 
 
+def make_paper_point_problem(seed=6, n_points=200000, K=128, N=25, M=15):
+    """The paper's own operating point (Sec. IV-A, Sec. V-A, Table I).
+
+    An accumulated LiDAR cloud of 200,000 points within r_max = 10 m (Livox-like
+    vertical field of view -7..52 deg) in a dense "Verticals" scene (0.625 per m^2,
+    radii 0.4-1.1 m, 6 m tall); 3 deg partition, 120 x 60 fine cells pooled 6 x 6
+    into 20 x 10 coarse cells; M = 15 (5 x 3) instances, K = 128, N = 25,
+    dt = 0.05; the collision set is the filtered cloud P_f.
+    """
+    s = seed
+    n_az = 4000
+    while True:
+        rng = np.random.Generator(np.random.PCG64(s))
+        cyl, boxes = verticals_scene(rng, half=16.0, wall=False)
+        pts = lidar_sweep(rng, cyl, boxes, (0.0, 0.0, 1.5), n_az,
+                          np.linspace(-7.0, 52.0, 96), 10.0, 0.02)
+        if len(pts) >= n_points:
+            break
+        n_az = int(n_az * 1.5)
+    cloud = _subsample(rng, pts, n_points)
+    prob = _problem(cloud, M, K, N, table1_params(), (18.0, 0.0, 0.0),
+                    partition=dict(n_az_c=20, n_el_c=10, f_a=6, f_e=6, r_max=10.0, ell=5.0),
+                    name=f"paper-point-verticals-{n_points // 1000}k")
+    prob["collision"] = "filtered"
+    return prob
+
+
 @functools.lru_cache(maxsize=4)
 def _batched_cached(seed, n_problems):
     rng = np.random.Generator(np.random.PCG64(seed))

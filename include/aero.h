@@ -160,6 +160,18 @@ int aero_partition_anchors(const aero_partition_spec* h_spec, const float* d_clo
                            int32_t* d_fine_idx, int32_t* d_coarse_best, int32_t* d_anchor_cell,
                            int32_t* d_anchor_fine, float* d_anchors, void* stream);
 
+/* Filtered collision set P_f of the collision cost (Sec. IV-C: the closest point of
+ * every fine cone of the partition).  out[c] = cloud[fine_idx[c]] in cone order
+ * c = 0 .. n_fine-1; a cone without a point holds the sentinel (1e18, 1e18, 1e18),
+ * which is never the nearest point of any position, so P_f can be passed to
+ * aero_mppi_step / aero_select_best as a cloud of exactly n_fine points.
+ *   d_cloud     [n_points][3] float32 (the cloud the partition was built on)
+ *   d_fine_idx  [n_fine] int32 from aero_partition_anchors (-1 = empty cone)
+ *   d_out       [n_fine][3] float32
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (n_fine < 1, n_points < 0), AERO_ERR_DEVICE. */
+int aero_filtered_cloud(const float* d_cloud, int32_t n_points, const int32_t* d_fine_idx,
+                        int32_t n_fine, float* d_out, void* stream);
+
 /* Quintic guides (Sec. IV-B-3, eq. (polynomial)): per anchor m and axis mu, the six
  * coefficients of f(t) = sum_i a_i t^i on [0, T] meeting position, velocity and
  * acceleration at both ends.  Start (h_p0, h_v0, h_a0) (host [3] each); end

@@ -12,7 +12,7 @@ import numpy as np
 
 __all__ = [
     "AeroError", "lib", "params_struct", "Problem", "partition_tables", "partition_anchors",
-    "build_guides", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
+    "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
     "KERNELS",
 ]
@@ -79,6 +79,7 @@ _SIGS = {
     "aero_mppi_step_backward": (ctypes.c_int, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_size_t,
                                                _P]),
     "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "aero_filtered_cloud": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "aero_timing_read": (ctypes.c_int, [ctypes.c_int, _P, _P, ctypes.c_int]),
 }
 
@@ -87,10 +88,10 @@ KERNELS = ("partition", "guides", "rollout", "min_dist", "finalize", "update", "
            "grad_reduce")
 
 
-def _load():
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2509_17340_amd/build.py`")
-    lib_ = ctypes.CDLL(LIB_PATH)
+def _load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python paper_2509_17340_amd/build.py`")
+    lib_ = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib_, name)
         fn.restype = res
@@ -102,6 +103,13 @@ _lib = _load()
 
 
 def lib():
+    return _lib
+
+
+def use_library(path):
+    """Load another build of libaero.so (for example a tuning variant) for all calls."""
+    global _lib
+    _lib = _load(path)
     return _lib
 
 
@@ -207,6 +215,14 @@ def partition_anchors(n_az_c, n_el_c, f_a, f_e, M_h, M_v, r_max, ell, p0, d_tabl
         ctypes.byref(spec), _ptr(cloud) if n > 0 else None, n, g.ctypes.data, _ptr(fine_key),
         _ptr(fine_idx), _ptr(coarse_best), _ptr(anchor_cell), _ptr(anchor_fine), _ptr(anchors),
         _stream(stream)), "aero_partition_anchors")
+
+
+def filtered_cloud(cloud, fine_idx, out, n_points=None, stream=None):
+    """P_f (closest point of every fine cone, cone order, sentinel for empty cones)."""
+    n = int(cloud.shape[0]) if n_points is None else int(n_points)
+    _check(_lib.aero_filtered_cloud(_ptr(cloud) if n > 0 else None, n, _ptr(fine_idx),
+                                    int(fine_idx.shape[0]), _ptr(out), _stream(stream)),
+           "aero_filtered_cloud")
 
 
 def build_guides(p0, v0, a0, anchors, horizon_T, M, coef, end_vel=None, end_acc=None,

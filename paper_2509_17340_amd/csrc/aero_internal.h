@@ -7,9 +7,16 @@
 
 namespace aero {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
-constexpr int kTilePts = 1024;       // cloud points staged in LDS per tile
-constexpr int kQueriesPerLane = 8;   // rollout positions held in registers per lane
+#ifndef AERO_TILE_PTS
+#define AERO_TILE_PTS 1024
+#endif
+#ifndef AERO_QUERIES_PER_LANE
+#define AERO_QUERIES_PER_LANE 8
+#endif
+
+constexpr int kBlock = 256;                              // threads per workgroup (4 wave64)
+constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points staged in LDS per tile
+constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
 constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
 
 // Per-problem record, built on the host and copied into the workspace.
@@ -48,15 +55,16 @@ struct QuerySet {
   int64_t Q;             // queries
   int32_t n_points;
   int32_t n_qblocks;     // ceil(Q / kQueriesPerBlock)
-  int32_t n_chunks;      // cloud splits for the full pass, each a whole number of tiles
-  int32_t n_tiles;       // ceil(n_points / kTilePts)
+  int32_t n_chunks;      // cloud splits of the full pass: chunk c covers points
+  int32_t chunk_pts;     //   [c chunk_pts, min((c+1) chunk_pts, n_points))
   int64_t block_base;    // prefix of n_qblocks * n_chunks over sets
   // two-pass extension
   float* thresh;         // [n_qblocks] flag bound on the pass-A squared distance
   int32_t* list;         // [Q] flagged query indices (nullptr: exact set)
   int32_t* count;        // flagged count
   int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
-  int32_t n_chunksB;
+  int32_t n_chunksB;     // cloud splits of pass B (chunk_ptsB points each)
+  int32_t chunk_ptsB;
   float d_max;
   unsigned long long* nn;  // optional [Q]: pass B also keeps (d^2 bits << 32 | index),
                            // indexed by list position (lowest index on ties)
@@ -88,10 +96,13 @@ struct DevSelect {
 };
 
 // Kernel launchers (defined in the .hip files).
+hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_partition(const aero_partition_spec& spec, const float* cloud, int n_points,
                             const float goal[3], double* fine_key, int32_t* fine_idx,
                             int32_t* coarse_best, int32_t* anchor_cell, int32_t* anchor_fine,
                             float* anchors, hipStream_t s);
+hipError_t launch_filter_cloud(const float* cloud, int n_points, const int32_t* fine_idx,
+                               int n_fine, float* out, hipStream_t s);
 hipError_t launch_guides(const double p0[3], const double v0[3], const double a0[3],
                          const float* anchors, const float* end_vel, const float* end_acc,
                          double T, int M, float* coef, hipStream_t s);

@@ -20,59 +20,13 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 inline bool finite(float v) { return std::isfinite(v); }
 
 // ---------------------------------------------------------------------------
-// Descriptor staging: per-device pinned host ring; a slot is reused only after
-// the copy that read it has completed on its stream.
+// Descriptors reach the workspace through kernel arguments (launch_put_bytes),
+// so every call enqueues kernels only: no host staging memory, no host-side
+// synchronisation, and the calls can be captured into a graph by the caller.
 // ---------------------------------------------------------------------------
-constexpr int kSlots = 16;
-constexpr size_t kSlotBytes = size_t(1) << 20;
-
-struct Staging {
-  char* host = nullptr;
-  hipEvent_t ev[kSlots];
-  bool used[kSlots] = {};
-  int next = 0;
-};
-
-std::mutex g_mu;
-std::vector<Staging*> g_stage;
-
 hipError_t stage_copy(void* d_dst, const void* src, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return hipSuccess;
-  if (bytes > kSlotBytes) return hipErrorInvalidValue;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(g_mu);
-  if ((int)g_stage.size() <= dev) g_stage.resize(dev + 1, nullptr);
-  Staging*& st = g_stage[dev];
-  if (!st) {
-    st = new Staging();
-    e = hipHostMalloc((void**)&st->host, kSlotBytes * kSlots, hipHostMallocDefault);
-    if (e != hipSuccess) {
-      delete st;
-      st = nullptr;
-      return e;
-    }
-    for (int i = 0; i < kSlots; ++i) {
-      e = hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming);
-      if (e != hipSuccess) return e;
-    }
-  }
-  const int slot = st->next;
-  st->next = (st->next + 1) % kSlots;
-  if (st->used[slot]) {
-    e = hipEventSynchronize(st->ev[slot]);
-    if (e != hipSuccess) return e;
-  }
-  char* h = st->host + slot * kSlotBytes;
-  memcpy(h, src, bytes);
-  e = hipMemcpyAsync(d_dst, h, bytes, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(st->ev[slot], s);
-  st->used[slot] = true;
-  return e;
+  return launch_put_bytes(d_dst, src, bytes, s);
 }
-
 
 // ---------------------------------------------------------------------------
 // Optional per-kernel event timing.
@@ -214,6 +168,19 @@ int chunks_for(int64_t total_qblocks, int n_tiles) {
   return (int)std::min<int64_t>(std::max<int64_t>(c, 1), std::max(n_tiles, 1));
 }
 
+// Split P points into about `want` chunks of a multiple of 64 points.
+void set_chunks(int64_t P, int64_t want, int32_t& n_chunks, int32_t& chunk_pts) {
+  if (P <= 0) {
+    n_chunks = 0;
+    chunk_pts = 0;
+    return;
+  }
+  want = std::min<int64_t>(std::max<int64_t>(want, 1), (P + 63) / 64);
+  const int64_t per = (P + want - 1) / want;
+  chunk_pts = (int32_t)((per + 63) / 64 * 64);
+  n_chunks = (int32_t)((P + chunk_pts - 1) / chunk_pts);
+}
+
 struct MppiPlan {
   std::vector<DevProblem> probs;
   std::vector<QuerySet> sets;
@@ -273,8 +240,9 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.Q = MNK;
     qs.n_points = q.n_points;
     qs.n_qblocks = (int)((MNK + kQueriesPerBlock - 1) / kQueriesPerBlock);
-    qs.n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
-    qs.n_chunks = q.n_points > 0 ? chunks_for(qblocks, qs.n_tiles) : 0;
+    const int n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
+    set_chunks(q.n_points, q.n_points > 0 ? chunks_for(qblocks, n_tiles) : 0, qs.n_chunks,
+               qs.chunk_pts);
     qs.block_base = blk;
     blk += (int64_t)qs.n_qblocks * qs.n_chunks;
     qs.d_max = d_max;
@@ -289,7 +257,8 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     }
     qs.query_base = fb;
     fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
-    qs.n_chunksB = two_pass ? qs.n_tiles : 0;
+    qs.chunk_ptsB = two_pass ? kTilePts : 0;
+    qs.n_chunksB = two_pass ? n_tiles : 0;
     items += two_pass ? (int64_t)qs.n_qblocks * qs.n_chunksB : 0;
   }
   pl.total_samples = sb;
@@ -388,8 +357,9 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     qs.Q = MN;
     qs.n_points = q.n_points;
     qs.n_qblocks = (int)((MN + kQueriesPerBlock - 1) / kQueriesPerBlock);
-    qs.n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
-    qs.n_chunks = q.n_points > 0 ? qs.n_tiles : 0;  // one tile per block: tiny query sets
+    // few queries: split the cloud finely so that the chip fills (about 512 blocks)
+    set_chunks(q.n_points, (512 + qblocks - 1) / std::max<int64_t>(qblocks, 1), qs.n_chunks,
+               qs.chunk_pts);
     qs.block_base = blk;
     blk += (int64_t)qs.n_qblocks * qs.n_chunks;
   }
@@ -504,6 +474,17 @@ int aero_partition_anchors(const aero_partition_spec* spec, const float* d_cloud
   }));
 }
 
+int aero_filtered_cloud(const float* d_cloud, int32_t n_points, const int32_t* d_fine_idx,
+                        int32_t n_fine, float* d_out, void* stream) {
+  if (!d_fine_idx || !d_out) return AERO_ERR_NULL;
+  if (n_points < 0 || n_fine < 1) return AERO_ERR_SHAPE;
+  if (n_points > 0 && !d_cloud) return AERO_ERR_NULL;
+  const hipStream_t s = (hipStream_t)stream;
+  return dev_status(timed(AERO_K_PARTITION, s, [&] {
+    return launch_filter_cloud(d_cloud, n_points, d_fine_idx, n_fine, d_out, s);
+  }));
+}
+
 int aero_build_guides(const float* h_p0, const float* h_v0, const float* h_a0,
                       const float* d_anchors, const float* d_end_vel, const float* d_end_acc,
                       float horizon_T, int32_t M, float* d_coef, void* stream) {
@@ -533,7 +514,6 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   MppiPlan pl;
   plan_mppi(h, n, nullptr, h_prm->d_max, pl);
   if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
-  if (n * (sizeof(DevProblem) + sizeof(QuerySet)) + 2 * kAlign > kSlotBytes) return AERO_ERR_SHAPE;
   plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl);
   const hipStream_t s = (hipStream_t)stream;
   const DevParams prm = promote(*h_prm);
@@ -570,7 +550,6 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h, int32_t n,
   SelectPlan pl;
   plan_select(h, n, nullptr, nullptr, nullptr, pl);
   if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
-  if (n * (sizeof(DevSelect) + sizeof(QuerySet)) + 2 * kAlign > kSlotBytes) return AERO_ERR_SHAPE;
   plan_select(h, n, (char*)d_ws, d_S2, d_best, pl);
   const hipStream_t s = (hipStream_t)stream;
   const DevParams prm = promote(*h_prm);

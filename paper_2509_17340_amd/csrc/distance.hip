@@ -40,28 +40,27 @@ __device__ __forceinline__ float min3f(float a, float b, float c) {
   return r;
 }
 
-// Direct-form min over the tiles [t0, t1) of the cloud for R queries per lane;
-// with kIdx also the lowest point index attaining it (points are visited in
+// Direct-form min over the cloud points [g0, g1) for R queries per lane; with
+// kIdx also the lowest point index attaining it (points are visited in
 // increasing index order within a lane and ties never replace).
 template <int R, bool kIdx>
-__device__ inline void direct_tiles(const QuerySet& S, int t0, int t1, float4* tile,
+__device__ inline void direct_range(const QuerySet& S, int64_t g0, int64_t g1, float4* tile,
                                     const float* px, const float* py, const float* pz,
                                     float* best, int32_t* bidx) {
   const int tid = threadIdx.x;
-  for (int tl = t0; tl < t1; ++tl) {
-    const int64_t base = (int64_t)tl * kTilePts;
-#pragma unroll
-    for (int i = 0; i < kTilePts / kBlock; ++i) {
-      const int pt = i * kBlock + tid;
+  for (int64_t base = g0; base < g1; base += kTilePts) {
+    const int cnt = (int)min<int64_t>(kTilePts, g1 - base);
+    const int cnt2 = (cnt + 1) & ~1;  // even: the loop takes points in pairs
+    for (int pt = tid; pt < cnt2; pt += kBlock) {
       const int64_t g = base + pt;
-      const bool in = g < S.n_points;
-      const int64_t gg = in ? g : 0;  // always a valid address
+      const bool in = pt < cnt;
+      const int64_t gg = in ? g : base;  // always a valid address
       const float x = S.cloud[3 * gg], y = S.cloud[3 * gg + 1], z = S.cloud[3 * gg + 2];
       tile[pt] = in ? make_float4(x, y, z, 0.0f) : make_float4(kFar, kFar, kFar, 0.0f);
     }
     __syncthreads();
 #pragma unroll 2
-    for (int j = 0; j < kTilePts; j += 2) {
+    for (int j = 0; j < cnt2; j += 2) {
       const float4 a = tile[j];
       const float4 c = tile[j + 1];
 #pragma unroll
@@ -110,9 +109,9 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
     pz[r] = S.pz[qq];
     best[r] = __uint_as_float(kInfBits);
   }
-  const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunks);
-  const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunks);
-  direct_tiles<R, false>(S, t0, t1, tile, px, py, pz, best, nullptr);
+  const int64_t g0 = (int64_t)ch * S.chunk_pts;
+  const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
+  direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
@@ -155,13 +154,13 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
           pz[r] = S.pz[q];
           best[r] = __uint_as_float(kInfBits);
         }
-        const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunksB);
-        const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunksB);
+        const int64_t g0 = (int64_t)ch * S.chunk_ptsB;
+        const int64_t g1 = min<int64_t>(g0 + S.chunk_ptsB, S.n_points);
         if (S.nn) {
           int32_t bidx[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) bidx[r] = 0x7fffffff;
-          direct_tiles<R, true>(S, t0, t1, tile, px, py, pz, best, bidx);
+          direct_range<R, true>(S, g0, g1, tile, px, py, pz, best, bidx);
 #pragma unroll
           for (int r = 0; r < R; ++r)
             if (qi[r] >= 0) {
@@ -171,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
                                         (unsigned long long)(unsigned)bidx[r]);
             }
         } else {
-          direct_tiles<R, false>(S, t0, t1, tile, px, py, pz, best, nullptr);
+          direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
 #pragma unroll
           for (int r = 0; r < R; ++r)
             if (qi[r] >= 0) atomicMin(S.out + qi[r], __float_as_uint(best[r]));
@@ -256,16 +255,14 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
     if (ok[r]) rr = fmaxf(rr, pp[r]);
     tmin[r] = kFarT;
   }
-  const int t0 = (int)((int64_t)ch * S.n_tiles / S.n_chunks);
-  const int t1 = (int)((int64_t)(ch + 1) * S.n_tiles / S.n_chunks);
-  for (int tl = t0; tl < t1; ++tl) {
-    const int64_t base = (int64_t)tl * kTilePts;
-#pragma unroll
-    for (int i = 0; i < kTilePts / kBlock; ++i) {
-      const int pt = i * kBlock + tid;
-      const int64_t g = base + pt;
-      const bool in = g < S.n_points;
-      const int64_t gg = in ? g : 0;
+  const int64_t g0 = (int64_t)ch * S.chunk_pts;
+  const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
+  for (int64_t base = g0; base < g1; base += kTilePts) {
+    const int cnt = (int)min<int64_t>(kTilePts, g1 - base);
+    const int cnt2 = (cnt + 1) & ~1;
+    for (int pt = tid; pt < cnt2; pt += kBlock) {
+      const bool in = pt < cnt;
+      const int64_t gg = in ? base + pt : base;
       const float ox = S.cloud[3 * gg] - c[0];
       const float oy = S.cloud[3 * gg + 1] - c[1];
       const float oz = S.cloud[3 * gg + 2] - c[2];
@@ -275,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
     }
     __syncthreads();
 #pragma unroll 4
-    for (int j = 0; j < kTilePts; j += 2) {
+    for (int j = 0; j < cnt2; j += 2) {
       const float4 a = tile[j];
       const float4 b = tile[j + 1];
 #pragma unroll

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "aero_device.h"
 #include "aero_internal.h"
@@ -238,7 +239,34 @@ __global__ __launch_bounds__(kBlock) void k_sel_final(const DevSelect* __restric
 
 inline unsigned grid1d(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Host bytes carried in the kernel arguments and written to device memory.
+constexpr int kPutBytes = 2048;
+struct PutBlob {
+  uint32_t n;
+  uint32_t pad;
+  unsigned char b[kPutBytes];
+};
+
+__global__ void k_put_bytes(unsigned char* dst, PutBlob blob) {
+  for (uint32_t i = threadIdx.x; i < blob.n; i += blockDim.x) dst[i] = blob.b[i];
+}
+
 }  // namespace
+
+hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const unsigned char* p = static_cast<const unsigned char*>(src);
+  unsigned char* d = static_cast<unsigned char*>(dst);
+  for (size_t off = 0; off < bytes; off += kPutBytes) {
+    PutBlob blob;
+    blob.n = (uint32_t)(bytes - off < (size_t)kPutBytes ? bytes - off : (size_t)kPutBytes);
+    blob.pad = 0;
+    memcpy(blob.b, p + off, blob.n);
+    k_put_bytes<<<1, 256, 0, s>>>(d + off, blob);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
                           hipStream_t s) {

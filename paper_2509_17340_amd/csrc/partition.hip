@@ -222,7 +222,31 @@ __global__ void k_guides(double p0x, double p0y, double p0z, double v0x, double 
   c[5] = (float)((6.0 * dP - 3.0 * dV + 0.5 * dA) / T5);
 }
 
+// P_f: the closest point of every fine cone, in cone order, sentinel when empty.
+__global__ void k_filter_cloud(const float* __restrict__ cloud, const int32_t* __restrict__ idx,
+                               int n_fine, int n_points, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_fine) return;
+  const int i = idx[c];
+  if (n_points <= 0 || i < 0 || i >= n_points) {
+    out[3 * c] = 1.0e18f;
+    out[3 * c + 1] = 1.0e18f;
+    out[3 * c + 2] = 1.0e18f;
+    return;
+  }
+  out[3 * c] = cloud[3 * (int64_t)i];
+  out[3 * c + 1] = cloud[3 * (int64_t)i + 1];
+  out[3 * c + 2] = cloud[3 * (int64_t)i + 2];
+}
+
 }  // namespace
+
+hipError_t launch_filter_cloud(const float* cloud, int n_points, const int32_t* fine_idx,
+                               int n_fine, float* out, hipStream_t s) {
+  k_filter_cloud<<<(n_fine + kBlock - 1) / kBlock, kBlock, 0, s>>>(
+      n_points > 0 ? cloud : nullptr, fine_idx, n_fine, n_points, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_partition(const aero_partition_spec& spec, const float* cloud, int n_points,
                             const float goal[3], double* fine_key, int32_t* fine_idx,

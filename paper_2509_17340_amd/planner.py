@@ -6,8 +6,8 @@ calls on the current stream; it does no arithmetic of its own.
 import numpy as np
 import torch
 
-from . import (CALL_MPPI_STEP, CALL_SELECT_BEST, Problem, build_guides, mppi_step,
-               partition_anchors, partition_tables, select_best, workspace_size)
+from . import (CALL_MPPI_STEP, CALL_SELECT_BEST, Problem, build_guides, filtered_cloud,
+               mppi_step, partition_anchors, partition_tables, select_best, workspace_size)
 
 
 class PlanStep:
@@ -16,7 +16,9 @@ class PlanStep:
     The dict carries cloud, x0, p_goal, v_goal, q_goal, M, K, N, M_h, M_v,
     partition (n_az_c, n_el_c, f_a, f_e, r_max, ell), params, u_nom, problem_id
     and, optionally, `anchors` (then the partition is skipped and the given
-    anchors are used, as for a single straight-line guide).
+    anchors are used, as for a single straight-line guide) and `collision`
+    ("raw": the whole cloud, default; "filtered": P_f, the closest point of every
+    fine cone).
     """
 
     def __init__(self, prob, device="cuda", keep_debug=False):
@@ -43,6 +45,13 @@ class PlanStep:
             self.anchors = torch.empty((M, 3), dtype=torch.float32, device=dev)
         else:
             self.anchors = torch.from_numpy(np.ascontiguousarray(self.fixed_anchors, np.float32)).to(dev)
+        self.collision = prob.get("collision", "raw")
+        self.pf = None
+        mppi_cloud = self.cloud
+        if self.collision == "filtered":
+            assert self.fixed_anchors is None, "P_f needs the partition"
+            self.pf = torch.empty((self.n_az * self.n_el, 3), dtype=torch.float32, device=dev)
+            mppi_cloud = self.pf
         self.coef = torch.empty((M, 3, 6), dtype=torch.float32, device=dev)
         self.u_init = torch.from_numpy(np.ascontiguousarray(prob["u_nom"], np.float32)).to(dev)
         self.u_nom = self.u_init.clone()
@@ -53,7 +62,7 @@ class PlanStep:
         if keep_debug:
             self.delta_eff = torch.empty((M, N, 4, K), dtype=torch.float32, device=dev)
             self.min_dist2 = torch.empty((M, N, K), dtype=torch.float32, device=dev)
-        self.problem = Problem(self.cloud, M, K, N, prob["x0"], prob["p_goal"], self.u_nom,
+        self.problem = Problem(mppi_cloud, M, K, N, prob["x0"], prob["p_goal"], self.u_nom,
                                coef=self.coef, v_goal=prob["v_goal"], q_goal=prob["q_goal"],
                                S1=self.S1, delta_eff=self.delta_eff, min_dist2=self.min_dist2,
                                problem_id=prob.get("problem_id", 0))
@@ -76,6 +85,8 @@ class PlanStep:
                               self.prob["M_v"], p["r_max"], p["ell"], self.p0, self.tables,
                               self.cloud, self.prob["goal_dir"], self.fine_key, self.fine_idx,
                               self.coarse_best, self.anchor_cell, self.anchor_fine, self.anchors)
+            if self.pf is not None:
+                filtered_cloud(self.cloud, self.fine_idx, self.pf)
         build_guides(self.p0, self.v0, self.a0, self.anchors, self.T, self.M, self.coef)
 
     def stage1(self):
@@ -130,3 +141,28 @@ class BatchPlan:
         self.front_end()
         mppi_step(self.params, self.problems, self.ws)
         select_best(self.params, self.problems, self.S2, self.best, self.ws)
+
+
+class GraphStep:
+    """A PlanStep captured once into a HIP graph (torch.cuda.CUDAGraph) and
+    replayed: reset of u_nom followed by the four library calls.  Valid while the
+    step's buffers and host inputs stay unchanged."""
+
+    def __init__(self, step, warmup=2):
+        self.step = step
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                step.reset()
+                step.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            step.reset()
+            step.run()
+        torch.cuda.synchronize()
+
+    def replay(self):
+        self.graph.replay()

@@ -316,3 +316,38 @@ def test_stage2_rejects_instance_through_obstacle():
     o = OM.select_best(prob, u)
     assert o["best"] == 1 and int(np_(ps.best)[0]) == 1
     assert np_(ps.S2)[0] >= 1e6
+
+
+# ----------------------------------------------------------------------------
+# the paper's operating point: 120 x 60 partition, 200k-point cloud, P_f collision set
+# ----------------------------------------------------------------------------
+def test_paper_point_filtered_collision_set():
+    from fixtures import make_paper_point_problem
+    prob = make_paper_point_problem()
+    print("paper point: partition 120x60, 200k points, P_f", flush=True)
+    ps = PlanStep(prob, keep_debug=True)
+    ps.front_end()
+    sync()
+    part = prob["partition"]
+    o = OP.partition_anchors(prob["cloud"], prob["goal_dir"], part["n_az_c"], part["n_el_c"],
+                             part["f_a"], part["f_e"], part["r_max"], part["ell"],
+                             prob["M_h"], prob["M_v"])
+    assert np.array_equal(np_(ps.fine_idx), o["fine_idx"])
+    assert np.array_equal(np_(ps.anchor_fine), o["anchor_fine"])
+    pf = np_(ps.pf)
+    has = o["fine_idx"] >= 0
+    assert np.array_equal(pf[has], prob["cloud"][o["fine_idx"][has]])
+    assert np.all(pf[~has] == np.float32(1e18))
+    ps.stage1()
+    sync()
+    g = dict(coef=np_(ps.coef), deff=np_(ps.delta_eff), md2=np_(ps.min_dist2), S1=np_(ps.S1),
+             u_new=np_(ps.u_nom))
+    # the oracle scores against P_f itself (the closest point of every non-empty cone)
+    p2 = dict(prob)
+    p2["cloud"] = prob["cloud"][o["fine_idx"][has]]
+    rep = compare_stage1(p2, g)
+    print(rep)
+    ps.stage2()
+    sync()
+    sel = OM.select_best(p2, g["u_new"])
+    assert np.all(np.abs(np_(ps.S2) - sel["S2"]) <= 1e-4 * np.abs(sel["S2"]))
