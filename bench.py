@@ -23,6 +23,29 @@ FP32_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
 FLOP_PER_PAIR = 8             # 3 sub + 3 mul + 2 add per (position, point) pair
 
 
+def measured_traffic(kernel="k_min_dist_approx"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_ensemble_forest_50k.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and line.startswith("    "):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or "kernel_source" not in kv:
+        return None
+    src = os.path.join(ROOT, kv["kernel_source"])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return int(kv["traffic_bytes_per_launch"]) if sha == kv.get("kernel_source_sha256") else None
+
+
+def steps_per_plan_of(prob):
+    return prob["M"] * prob["K"] * prob["N"] + prob["M"] * prob["N"]
+
+
 def cpu_baseline(prob, samples_per_instance=32):
     """The oracle as it is, on a bounded sample of the same planning step."""
     import numpy as np
@@ -184,6 +207,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lean", action="store_true",
+                    help="headline step only (no graph, adjoint, paper-point or CPU legs)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the 64-problem uneven batch (plain vs batched), N steps")
     args = ap.parse_args()
@@ -224,6 +249,11 @@ def main():
     aero.timing_enable(False)
     print(f"# timed {args.steps} eager steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
 
+    if args.lean:
+        print(json.dumps({"metric": METRIC, "value": steps_per_plan_of(prob) / (ms * 1e-3),
+                          "ms_per_step": ms, "kernels_ms_per_step":
+                          {k: v[0] / args.steps for k, v in kt.items()}}))
+        return
     # the same step captured once as a HIP graph and replayed
     from paper_2509_17340_amd.planner import GraphStep
     g = GraphStep(ps)
@@ -272,7 +302,9 @@ def main():
                      "kernel": "k_min_dist_approx (Stage I nearest distance, pass A over every "
                                "rollout position)",
                      "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "flop_per_launch": flop, "avg_launch_ms": md_avg,
                      "distance_all_passes_ms": dist_ms,
                      "distance_all_passes_tflops": flop / (dist_ms * 1e-3) / 1e12},
