@@ -219,6 +219,23 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h_prob
                             float scale, float* d_grad_u_nom, float* d_grad_w, void* d_ws,
                             size_t ws_bytes, void* stream);
 
+/* ---- kernel-variant selection --------------------------------------------------- */
+
+/* The first, approximate pass of the nearest-distance computation has two
+ * implementations: 0 = VALU FMAs, 1 = matrix-core MFMA.  By default (-1) the
+ * library autotunes per call shape (sum of M N K, sum of cloud sizes, problem count):
+ * the first two calls of a shape each time one variant with HIP events on the
+ * call's stream, the third call keeps the faster one for that shape.  Costs, controls
+ * and selections are bitwise identical for both variants; only min_dist2 entries far
+ * beyond d_max may differ.  While the stream is being captured into a graph an
+ * unsettled shape uses variant 0 and records nothing.
+ * aero_set_pass_a_variant forces a variant for all later calls (-1 = autotune);
+ * errors: AERO_ERR_PARAM for other values. */
+int aero_set_pass_a_variant(int variant);
+
+/* The variant in use for this call shape: 0 or 1, or -1 while still being tuned. */
+int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems);
+
 /* ---- per-kernel timing (profiling aid) ---------------------------------------- */
 
 /* Kernel identifiers for aero_timing_read. */

@@ -79,6 +79,8 @@ _SIGS = {
     "aero_mppi_step_backward": (ctypes.c_int, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_size_t,
                                                _P]),
     "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "aero_set_pass_a_variant": (ctypes.c_int, [ctypes.c_int]),
+    "aero_pass_a_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
     "aero_filtered_cloud": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "aero_timing_read": (ctypes.c_int, [ctypes.c_int, _P, _P, ctypes.c_int]),
 }
@@ -255,6 +257,16 @@ def select_best(prm, problems, S2, best, ws, ws_bytes=None, stream=None):
     _check(_lib.aero_select_best(ctypes.byref(p), ctypes.cast(arr, ctypes.c_void_p), len(problems),
                                  _ptr(S2), _ptr(best), _ptr(ws), nbytes, _stream(stream)),
            "aero_select_best")
+
+
+def set_pass_a_variant(variant):
+    """Force the first distance pass: 0 = VALU, 1 = MFMA, -1 = autotune (default)."""
+    _check(_lib.aero_set_pass_a_variant(int(variant)), "aero_set_pass_a_variant")
+
+
+def pass_a_variant(problems):
+    arr = _problem_array(problems)
+    return int(_lib.aero_pass_a_variant(ctypes.cast(arr, ctypes.c_void_p), len(problems)))
 
 
 def timing_enable(on=True):

@@ -19,6 +19,11 @@ constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points staged 
 constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
 constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
 
+// Pass-A variants (the expanded-form first pass of the distance computation).
+constexpr int kPassAValu = 0;   // VALU FMAs, kQueriesPerBlock positions per block
+constexpr int kPassAMfma = 1;   // matrix-core MFMA, 512 positions per block
+constexpr int kPassAQPB[2] = {kQueriesPerBlock, 512};
+
 // Per-problem record, built on the host and copied into the workspace.
 struct DevProblem {
   const float* cloud;
@@ -63,6 +68,7 @@ struct QuerySet {
   int32_t* list;         // [Q] flagged query indices (nullptr: exact set)
   int32_t* count;        // flagged count
   int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
+  int32_t qpbA;          // positions per pass-A block (the variant's block size)
   int32_t n_chunksB;     // cloud splits of pass B (chunk_ptsB points each)
   int32_t chunk_ptsB;
   float d_max;
@@ -111,7 +117,7 @@ hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_sample
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                            hipStream_t s);
 hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                                  hipStream_t s);
+                                  int variant, hipStream_t s);
 hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                   hipStream_t s);

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -69,6 +70,68 @@ hipError_t timed(int kernel, hipStream_t s, F&& launch) {
   e = hipEventRecord(b, s);
   g_timing.pending.push_back({kernel, a, b});
   return e;
+}
+
+// ---------------------------------------------------------------------------
+// Online autotuner of the pass-A variant, keyed by the call's shape.  The first
+// two calls of a shape time one variant each with HIP events; the third reads
+// both and keeps the faster.  Every variant yields bitwise-identical costs and
+// controls, so tuning never changes results.  While a stream is being captured
+// into a graph no events are recorded and an unsettled shape uses the VALU pass.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+  int64_t q, p;
+  int n;
+  bool operator<(const TuneKey& o) const {
+    return q != o.q ? q < o.q : p != o.p ? p < o.p : n < o.n;
+  }
+};
+struct TuneState {
+  int trials = 0;
+  int choice = -1;
+  hipEvent_t ev[2][2] = {};
+  float ms[2] = {0.f, 0.f};
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneState> g_tune;
+int g_forced_variant = -1;
+
+TuneKey tune_key(const aero_problem* h, int n) {
+  TuneKey k{0, 0, n};
+  for (int b = 0; b < n; ++b) {
+    k.q += (int64_t)h[b].M * h[b].N * h[b].K;
+    k.p += h[b].n_points;
+  }
+  return k;
+}
+
+// Variant for this call; *ev receives the event pair to record around pass A (or null).
+int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
+  *ev = nullptr;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_forced_variant >= 0) return g_forced_variant;
+  TuneState& st = g_tune[key];
+  if (st.choice >= 0) return st.choice;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return kPassAValu;
+  if (st.trials < 2) {
+    const int v = st.trials;
+    if (hipEventCreate(&st.ev[v][0]) != hipSuccess || hipEventCreate(&st.ev[v][1]) != hipSuccess)
+      return kPassAValu;
+    st.trials++;
+    *ev = st.ev[v];
+    return v;
+  }
+  for (int v = 0; v < 2; ++v) {
+    if (hipEventSynchronize(st.ev[v][1]) != hipSuccess ||
+        hipEventElapsedTime(&st.ms[v], st.ev[v][0], st.ev[v][1]) != hipSuccess)
+      st.ms[v] = 1e30f;
+    hipEventDestroy(st.ev[v][0]);
+    hipEventDestroy(st.ev[v][1]);
+  }
+  st.choice = st.ms[kPassAMfma] < st.ms[kPassAValu] ? kPassAMfma : kPassAValu;
+  return st.choice;
 }
 
 // ---------------------------------------------------------------------------
@@ -190,16 +253,18 @@ struct MppiPlan {
   size_t bytes = 0;
 };
 
-void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl) {
+void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl,
+               int variant = kPassAValu) {
   Cursor cur{ws};
   pl.d_probs = cur.take<DevProblem>(n);
   pl.d_sets = cur.take<QuerySet>(n);
   pl.probs.assign(n, DevProblem{});
   pl.sets.assign(n, QuerySet{});
+  const int qpbA = kPassAQPB[variant];
   int64_t qblocks = 0;
   for (int b = 0; b < n; ++b) {
     const int64_t Q = (int64_t)h[b].M * h[b].N * h[b].K;
-    if (h[b].n_points > 0) qblocks += (Q + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    if (h[b].n_points > 0) qblocks += (Q + qpbA - 1) / qpbA;
   }
   int64_t sb = 0, rb = 0, blk = 0, fb = 0, items = 0;
   for (int b = 0; b < n; ++b) {
@@ -239,7 +304,8 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.cloud = q.cloud;
     qs.Q = MNK;
     qs.n_points = q.n_points;
-    qs.n_qblocks = (int)((MNK + kQueriesPerBlock - 1) / kQueriesPerBlock);
+    qs.qpbA = qpbA;
+    qs.n_qblocks = (int)((MNK + qpbA - 1) / qpbA);
     const int n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
     set_chunks(q.n_points, q.n_points > 0 ? chunks_for(qblocks, n_tiles) : 0, qs.n_chunks,
                qs.chunk_pts);
@@ -247,7 +313,9 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     blk += (int64_t)qs.n_qblocks * qs.n_chunks;
     qs.d_max = d_max;
     const bool two_pass = q.n_points > 0;
-    qs.thresh = cur.take<float>(two_pass ? qs.n_qblocks : 0);
+    // sized for the smallest pass-A block of any variant: the layout does not depend on it
+    const int64_t min_qpb = std::min(kPassAQPB[0], kPassAQPB[1]);
+    qs.thresh = cur.take<float>(two_pass ? (MNK + min_qpb - 1) / min_qpb : 0);
     qs.list = cur.take<int32_t>(two_pass ? MNK : 0);
     qs.count = cur.take<int32_t>(two_pass ? 1 : 0);
     if (!two_pass) {
@@ -259,7 +327,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
     qs.chunk_ptsB = two_pass ? kTilePts : 0;
     qs.n_chunksB = two_pass ? n_tiles : 0;
-    items += two_pass ? (int64_t)qs.n_qblocks * qs.n_chunksB : 0;
+    items += two_pass ? (MNK + kQueriesPerBlock - 1) / kQueriesPerBlock * qs.n_chunksB : 0;
   }
   pl.total_samples = sb;
   pl.total_rows = rb;
@@ -514,8 +582,10 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   MppiPlan pl;
   plan_mppi(h, n, nullptr, h_prm->d_max, pl);
   if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
-  plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl);
   const hipStream_t s = (hipStream_t)stream;
+  hipEvent_t* tev = nullptr;
+  const int variant = pick_variant(tune_key(h, n), s, &tev);
+  plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl, variant);
   const DevParams prm = promote(*h_prm);
   // One staged copy for both descriptor arrays (they are adjacent in the workspace).
   std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_probs + n * sizeof(QuerySet));
@@ -525,9 +595,12 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   hipError_t he = stage_copy(pl.d_probs, blob.data(), blob.size(), s);
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, n, pl.total_samples, prm, s); });
+  if (he == hipSuccess && tev) he = hipEventRecord(tev[0], s);
   if (he == hipSuccess && pl.total_blocks > 0)
-    he = timed(AERO_K_MIN_DIST, s,
-               [&] { return launch_min_dist_approx(pl.d_sets, n, pl.total_blocks, s); });
+    he = timed(AERO_K_MIN_DIST, s, [&] {
+      return launch_min_dist_approx(pl.d_sets, n, pl.total_blocks, variant, s);
+    });
+  if (he == hipSuccess && tev) he = hipEventRecord(tev[1], s);
   if (he == hipSuccess && pl.flag_blocks > 0)
     he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, n, pl.flag_blocks, s); });
   if (he == hipSuccess && pl.listed_items > 0)
@@ -591,8 +664,9 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, 1, pl.total_samples, prm, s); });
   if (he == hipSuccess && pl.total_blocks > 0)
-    he = timed(AERO_K_MIN_DIST, s,
-               [&] { return launch_min_dist_approx(pl.d_sets, 1, pl.total_blocks, s); });
+    he = timed(AERO_K_MIN_DIST, s, [&] {
+      return launch_min_dist_approx(pl.d_sets, 1, pl.total_blocks, kPassAValu, s);
+    });
   if (he == hipSuccess && pl.flag_blocks > 0)
     he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, 1, pl.flag_blocks, s); });
   if (he == hipSuccess && pl.listed_items > 0)
@@ -612,6 +686,21 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
                                 d_grad_w, s);
     });
   return dev_status(he);
+}
+
+int aero_set_pass_a_variant(int variant) {
+  if (variant < -1 || variant > 1) return AERO_ERR_PARAM;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_forced_variant = variant;
+  return AERO_OK;
+}
+
+int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems) {
+  if (!h_problems || n_problems < 1) return -1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_forced_variant >= 0) return g_forced_variant;
+  auto it = g_tune.find(tune_key(h_problems, n_problems));
+  return it == g_tune.end() ? -1 : it->second.choice;
 }
 
 int aero_timing_enable(int on) {

@@ -187,7 +187,15 @@ def compare_stage1(prob, g, samples=None, nearest_fn=nearest):
                 u_tf_rel=float((num / den).max()), kappa=float(kappa))
 
 
-def test_stage1_plain_cylinders_full():
+@pytest.fixture(params=[0, 1], ids=["valu", "mfma"])
+def pass_a(request):
+    """Run the test with the first distance pass forced to one variant."""
+    aero.set_pass_a_variant(request.param)
+    yield request.param
+    aero.set_pass_a_variant(-1)
+
+
+def test_stage1_plain_cylinders_full(pass_a):
     prob = make_plain_problem()
     print("stage1 plain K=256 N=20 P=5000", flush=True)
     ps, g = run_stage1(prob)
@@ -203,7 +211,7 @@ def test_stage1_plain_cylinders_full():
         assert e2e <= 1e-4
 
 
-def test_stage1_ensemble_forest_sampled():
+def test_stage1_ensemble_forest_sampled(pass_a):
     prob = make_ensemble_problem()
     print("stage1 ensemble M=8 K=1024 N=40 P=50000 (sampled)", flush=True)
     ps, g = run_stage1(prob)
@@ -217,7 +225,7 @@ def test_stage1_ensemble_forest_sampled():
 
 @pytest.mark.parametrize("M,K,N,P", [(1, 1, 2, 1), (3, 257, 7, 1025), (2, 100, 13, 0),
                                      (5, 64, 3, 2048), (1, 513, 25, 77)])
-def test_stage1_ragged_shapes(M, K, N, P):
+def test_stage1_ragged_shapes(M, K, N, P, pass_a):
     rng = np.random.default_rng(M * 1000 + K)
     prob = dict(make_plain_problem())
     prob.update(M=M, K=K, N=N, M_h=M, M_v=1)
@@ -241,7 +249,7 @@ def test_stage1_zero_noise_returns_nominal():
     assert np.all(g["deff"] == 0.0)
 
 
-def test_stage1_deterministic_and_batched_equals_plain():
+def test_stage1_deterministic_and_batched_equals_plain(pass_a):
     rng = np.random.default_rng(11)
     probs = []
     for b, (M, K, N, P) in enumerate([(2, 300, 9, 3000), (4, 128, 20, 1500), (1, 1000, 5, 0)]):
@@ -276,6 +284,43 @@ def test_stage1_deterministic_and_batched_equals_plain():
         assert np.array_equal(np_(s.S1), ref[0])
         assert np.array_equal(np_(s.u_nom), ref[1])
         assert np.array_equal(np_(s.min_dist2), ref[2])
+
+
+def test_pass_a_variants_give_identical_costs():
+    """Both first-pass variants yield bitwise-identical S1, u_nom and exact distances
+    below d_max (they may differ only in first-pass values far beyond d_max)."""
+    prob = make_ensemble_problem()
+    outs = []
+    for v in (0, 1):
+        aero.set_pass_a_variant(v)
+        ps, g = run_stage1(prob)
+        outs.append(g)
+    aero.set_pass_a_variant(-1)
+    a, b = outs
+    assert np.array_equal(a["S1"], b["S1"])
+    assert np.array_equal(a["u_new"], b["u_new"])
+    d_max2 = np.float32(prob["params"]["d_max"]) ** 2
+    near = (a["md2"] < d_max2) | (b["md2"] < d_max2)
+    assert np.array_equal(a["md2"][near], b["md2"][near])
+    assert near.sum() > 1000
+
+
+def test_autotuner_settles_and_keeps_results():
+    prob = make_plain_problem()
+    aero.set_pass_a_variant(-1)
+    ps = PlanStep(prob)
+    ps.front_end()
+    res = []
+    for i in range(4):
+        ps.reset()
+        ps.stage1()
+        sync()
+        res.append((np_(ps.S1), np_(ps.u_nom)))
+    v = aero.pass_a_variant([ps.problem])
+    print(f"autotuned pass-A variant: {v}")
+    assert v in (0, 1)
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0]) and np.array_equal(r[1], res[0][1])
 
 
 # ----------------------------------------------------------------------------
