@@ -160,6 +160,45 @@ def bench_paper_point(steps=200):
                              "<600 MB at N=25, K=256 (Sec. V-B-1)"}
 
 
+def bench_loop(n_steps, stride=40):
+    """Closed loop over replayed poses of the incline flight (7 m/s): M=16, K=8192,
+    N=60, dt=0.04, 1,000,000-point cloud per step, plus one adjoint refinement of
+    the selected plan and the warm start.  Cloud upload excluded from the timing."""
+    import torch
+
+    from fixtures import make_loop_step
+    from paper_2509_17340_amd.planner import LoopRunner
+
+    poses = [i * stride for i in range(n_steps)]
+    t0 = time.perf_counter()
+    probs = [make_loop_step(s) for s in poses]
+    print(f"# loop fixtures: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    lr = LoopRunner(probs[0])
+    lr.load(probs[0])
+    lr.step()                           # warm-up (and the autotuner's first trial)
+    torch.cuda.synchronize()
+    times = []
+    for p in probs:
+        lr.load(p)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lr.step()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        print(f"# loop pose {len(times)}: {times[-1]:.1f} ms", file=sys.stderr, flush=True)
+    ps = lr.ps
+    steps = ps.M * ps.K * ps.N + ps.M * ps.N
+    srt = sorted(times)
+    return {"poses": poses, "ms": times, "p50_ms": srt[len(srt) // 2], "p99_ms": srt[-1],
+            "rollout_steps_per_s": steps / (sum(times) / len(times) * 1e-3),
+            "pairs_per_step": ps.M * ps.K * ps.N * int(ps.cloud.shape[0]),
+            "workload": "incline corridor, 7 m/s replayed poses, M=16 (8x2), K=8192, N=60, "
+                        "dt=0.04, 1e6-point cloud, + adjoint refinement of the selected plan "
+                        "(4 step candidates) and warm start; p99 over the timed poses"}
+
+
 def bench_batched(n_steps):
     """64 uneven problems: 64 plain per-problem calls vs one batched call."""
     import numpy as np
@@ -207,6 +246,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--loop", type=int, default=5,
+                    help="closed-loop leg: number of replayed poses (0 = skip)")
     ap.add_argument("--lean", action="store_true",
                     help="headline step only (no graph, adjoint, paper-point or CPU legs)")
     ap.add_argument("--batched", type=int, default=0,
@@ -314,6 +355,8 @@ def main():
     out["paper_operating_point"] = bench_paper_point()
     if args.batched:
         out["batched"] = bench_batched(args.batched)
+    if args.loop:
+        out["closed_loop"] = bench_loop(args.loop)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

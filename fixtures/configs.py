@@ -210,15 +210,16 @@ def make_loop_step(step, seed=5, n_points=1_000_000):
     """One replayed pose of the closed-loop incline flight.
 
     Pose p_s = (0.28 s, 0, 2.0), v = (7, 0, 0), q = identity; the cloud is
-    8 sweeps of 1024 x 128 beams (el +-15 deg, 40 m, 2 cm noise) with
-    azimuth jitter, truncated to `n_points`; M = 16 (8 x 2), K = 8192,
+    sweeps of 1024 x 128 beams (el +-15 deg, 40 m, 2 cm noise) with azimuth
+    jitter, accumulated until there are `n_points` hits (8 sweeps nominally)
+    and truncated to exactly that; M = 16 (8 x 2), K = 8192,
     N = 60, dt = 0.04.  Expressed in the drone-centred frame.
     """
     scene = _loop_scene(seed)
     rng = np.random.Generator(np.random.PCG64(seed * 100000 + step))
     pose = np.array([0.28 * step, 0.0, 2.0])
     chunks, have = [], 0
-    for _ in range(8):
+    for _ in range(16):
         pts = lidar_sweep(rng, scene, _empty_boxes(), pose, 1024,
                           np.linspace(-15.0, 15.0, 128), 40.0, 0.02,
                           az_jitter=math.pi / 1024)

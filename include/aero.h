@@ -219,6 +219,28 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h_prob
                             float scale, float* d_grad_u_nom, float* d_grad_w, void* d_ws,
                             size_t ws_bytes, void* stream);
 
+/* ---- receding horizon ----------------------------------------------------------- */
+
+/* Warm start for the next planning step (receding-horizon execution, Sec. III-B):
+ * dst[m][t][c] = src[i][min(t + shift, N - 1)][c] for every m < M_dst, where
+ * i = *d_index clamped to [0, M_src) (d_index is device memory, e.g. the d_best
+ * output of aero_select_best, so no host synchronisation is needed).
+ *   d_src [M_src][N][4], d_dst [M_dst][N][4] float32 (must not overlap)
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (M_src, M_dst < 1, N < 1, shift < 0),
+ * AERO_ERR_DEVICE. */
+int aero_shift_controls(const float* d_src, int32_t M_src, int32_t N, const int32_t* d_index,
+                        int32_t shift, float* d_dst, int32_t M_dst, void* stream);
+
+/* Candidates of a gradient step on one control sequence (adjoint refinement of
+ * the selected plan; scored afterwards with aero_select_best):
+ *   out[0] = u,  out[i] = clip(u - s_i g / max|g|, u_min, u_max),
+ *   s_i = s0 beta^(i-1), i = 1 .. n_candidates-1 (g = 0 gives copies of u).
+ *   d_u, d_g [N][4]; d_out [n_candidates][N][4]; clip box from h_prm.
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (N < 1, n_candidates < 1 or > AERO_M_MAX),
+ * AERO_ERR_PARAM (s0 or beta non-finite or negative), AERO_ERR_DEVICE. */
+int aero_step_candidates(const aero_params* h_prm, const float* d_u, const float* d_g, int32_t N,
+                         float s0, float beta, int32_t n_candidates, float* d_out, void* stream);
+
 /* ---- kernel-variant selection --------------------------------------------------- */
 
 /* The first, approximate pass of the nearest-distance computation has two

@@ -14,7 +14,8 @@ __all__ = [
     "AeroError", "lib", "params_struct", "Problem", "partition_tables", "partition_anchors",
     "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
-    "KERNELS",
+    "KERNELS", "shift_controls", "step_candidates", "set_pass_a_variant", "pass_a_variant",
+    "use_library",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -80,6 +81,10 @@ _SIGS = {
                                                _P]),
     "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "aero_set_pass_a_variant": (ctypes.c_int, [ctypes.c_int]),
+    "aero_shift_controls": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                                           _P, ctypes.c_int32, _P]),
+    "aero_step_candidates": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_int32, _P, _P]),
     "aero_pass_a_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
     "aero_filtered_cloud": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "aero_timing_read": (ctypes.c_int, [ctypes.c_int, _P, _P, ctypes.c_int]),
@@ -257,6 +262,21 @@ def select_best(prm, problems, S2, best, ws, ws_bytes=None, stream=None):
     _check(_lib.aero_select_best(ctypes.byref(p), ctypes.cast(arr, ctypes.c_void_p), len(problems),
                                  _ptr(S2), _ptr(best), _ptr(ws), nbytes, _stream(stream)),
            "aero_select_best")
+
+
+def shift_controls(src, index, shift, dst, stream=None):
+    """dst[m] = src[index][t + shift] (last control held); index is a device int32."""
+    M_src, N = int(src.shape[0]), int(src.shape[1])
+    _check(_lib.aero_shift_controls(_ptr(src), M_src, N, _ptr(index), int(shift), _ptr(dst),
+                                    int(dst.shape[0]), _stream(stream)), "aero_shift_controls")
+
+
+def step_candidates(prm, u, g, s0, beta, out, stream=None):
+    """out[0] = u, out[i] = clip(u - s0 beta^(i-1) g / max|g|)."""
+    p = params_struct(prm) if isinstance(prm, dict) else prm
+    _check(_lib.aero_step_candidates(ctypes.byref(p), _ptr(u), _ptr(g), int(u.shape[-2]),
+                                     float(s0), float(beta), int(out.shape[0]), _ptr(out),
+                                     _stream(stream)), "aero_step_candidates")
 
 
 def set_pass_a_variant(variant):

@@ -103,6 +103,10 @@ struct DevSelect {
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_shift_controls(const float* src, int M_src, int N, const int32_t* index,
+                                 int shift, float* dst, int M_dst, hipStream_t s);
+hipError_t launch_step_candidates(const float* u, const float* g, int N, float s0, float beta,
+                                  int n, const DevParams& prm, float* out, hipStream_t s);
 hipError_t launch_partition(const aero_partition_spec& spec, const float* cloud, int n_points,
                             const float goal[3], double* fine_key, int32_t* fine_idx,
                             int32_t* coarse_best, int32_t* anchor_cell, int32_t* anchor_fine,

@@ -688,6 +688,25 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   return dev_status(he);
 }
 
+int aero_shift_controls(const float* d_src, int32_t M_src, int32_t N, const int32_t* d_index,
+                        int32_t shift, float* d_dst, int32_t M_dst, void* stream) {
+  if (!d_src || !d_index || !d_dst) return AERO_ERR_NULL;
+  if (M_src < 1 || M_dst < 1 || N < 1 || shift < 0) return AERO_ERR_SHAPE;
+  return dev_status(
+      launch_shift_controls(d_src, M_src, N, d_index, shift, d_dst, M_dst, (hipStream_t)stream));
+}
+
+int aero_step_candidates(const aero_params* h_prm, const float* d_u, const float* d_g, int32_t N,
+                         float s0, float beta, int32_t n_candidates, float* d_out, void* stream) {
+  int e = check_params(h_prm);
+  if (e) return e;
+  if (!d_u || !d_g || !d_out) return AERO_ERR_NULL;
+  if (N < 1 || n_candidates < 1 || n_candidates > AERO_M_MAX) return AERO_ERR_SHAPE;
+  if (!finite(s0) || !finite(beta) || s0 < 0.f || beta < 0.f) return AERO_ERR_PARAM;
+  return dev_status(launch_step_candidates(d_u, d_g, N, s0, beta, n_candidates, promote(*h_prm),
+                                           d_out, (hipStream_t)stream));
+}
+
 int aero_set_pass_a_variant(int variant) {
   if (variant < -1 || variant > 1) return AERO_ERR_PARAM;
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -239,6 +239,47 @@ __global__ __launch_bounds__(kBlock) void k_sel_final(const DevSelect* __restric
 
 inline unsigned grid1d(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Receding-horizon warm start: every destination instance gets the selected
+// source sequence advanced by `shift` steps (last control held).
+__global__ void k_shift_controls(const float* __restrict__ src, int M_src, int N,
+                                 const int32_t* __restrict__ index, int shift,
+                                 float* __restrict__ dst, int M_dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M_dst * N * 4) return;
+  int sel = *index;
+  sel = sel < 0 ? 0 : (sel >= M_src ? M_src - 1 : sel);
+  const int c = (int)(i % 4), t = (int)((i / 4) % N);
+  const int ts = t + shift < N ? t + shift : N - 1;
+  dst[i] = src[((int64_t)sel * N + ts) * 4 + c];
+}
+
+// Step candidates: out[0] = u, out[j] = clip(u - s_j g / max|g|).  One block.
+__global__ void k_step_candidates(const float* __restrict__ u, const float* __restrict__ g,
+                                  int N, float s0, float beta, int n, DevParams prm,
+                                  float* __restrict__ out) {
+  __shared__ float red[kBlock];
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < N * 4; i += blockDim.x) m = fmaxf(m, fabsf(g[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const float gmax = red[0];
+  for (int i = threadIdx.x; i < n * N * 4; i += blockDim.x) {
+    const int j = i / (N * 4), e = i % (N * 4), c = e % 4;
+    if (j == 0 || !(gmax > 0.0f)) {
+      out[i] = u[e];
+      continue;
+    }
+    double s = (double)s0;
+    for (int k = 1; k < j; ++k) s *= (double)beta;
+    const double v = (double)u[e] - s * (double)g[e] / (double)gmax;
+    out[i] = (float)fmin(fmax(v, prm.u_min[c]), prm.u_max[c]);
+  }
+}
+
 // Host bytes carried in the kernel arguments and written to device memory.
 constexpr int kPutBytes = 2048;
 struct PutBlob {
@@ -252,6 +293,19 @@ __global__ void k_put_bytes(unsigned char* dst, PutBlob blob) {
 }
 
 }  // namespace
+
+hipError_t launch_shift_controls(const float* src, int M_src, int N, const int32_t* index,
+                                 int shift, float* dst, int M_dst, hipStream_t s) {
+  k_shift_controls<<<grid1d((int64_t)M_dst * N * 4), kBlock, 0, s>>>(src, M_src, N, index, shift,
+                                                                     dst, M_dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_candidates(const float* u, const float* g, int N, float s0, float beta,
+                                  int n, const DevParams& prm, float* out, hipStream_t s) {
+  k_step_candidates<<<1, kBlock, 0, s>>>(u, g, N, s0, beta, n, prm, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const unsigned char* p = static_cast<const unsigned char*>(src);

@@ -166,3 +166,57 @@ class GraphStep:
 
     def replay(self):
         self.graph.replay()
+
+
+class LoopRunner:
+    """Closed loop over replayed poses: each step runs a full planning step, refines
+    the selected sequence once by a gradient step on its Stage-II cost (the adjoint
+    of a single noise-free rollout with weights (0, 0, 0, w_goal, w_col), step
+    length picked among `n_cand` candidates by Stage II), and warm-starts every
+    instance from the refined sequence advanced by one step."""
+
+    def __init__(self, prob, n_cand=4, s0=0.5, beta=0.5, device="cuda"):
+        from . import (CALL_BACKWARD, mppi_step_backward, shift_controls, step_candidates)
+        self._bwd, self._shift, self._cand = mppi_step_backward, shift_controls, step_candidates
+        self.ps = PlanStep(prob, device=device)
+        ps = self.ps
+        dev = ps.dev
+        N = ps.N
+        self.s0, self.beta, self.n_cand = s0, beta, n_cand
+        self.u_sel = torch.empty((1, N, 4), dtype=torch.float32, device=dev)
+        self.grad = torch.empty((1, N, 4), dtype=torch.float32, device=dev)
+        self.grad_w = torch.empty(5, dtype=torch.float32, device=dev)
+        self.cands = torch.empty((n_cand, N, 4), dtype=torch.float32, device=dev)
+        self.cS2 = torch.empty(n_cand, dtype=torch.float64, device=dev)
+        self.cbest = torch.empty(1, dtype=torch.int32, device=dev)
+        prm = dict(ps.params)
+        prm["sigma"] = np.zeros(4, np.float32)
+        w = np.asarray(prm["w"], np.float32)
+        prm["w"] = np.float32([0.0, 0.0, 0.0, w[3], w[4]])
+        self.refine_params = prm
+        self.ref_problem = Problem(ps.cloud, 1, 1, N, prob["x0"], prob["p_goal"], self.u_sel,
+                                   coef=ps.coef, v_goal=prob["v_goal"], q_goal=prob["q_goal"])
+        self.cand_problem = Problem(ps.cloud, n_cand, 1, N, prob["x0"], prob["p_goal"], self.cands,
+                                    coef=ps.coef, v_goal=prob["v_goal"], q_goal=prob["q_goal"])
+        self.ws_b = torch.empty(workspace_size(CALL_BACKWARD, [self.ref_problem]),
+                                dtype=torch.uint8, device=dev)
+        self.ws_c = torch.empty(workspace_size(CALL_SELECT_BEST, [self.cand_problem]),
+                                dtype=torch.uint8, device=dev)
+
+    def load(self, prob):
+        """Next replayed pose: new cloud (same size) and goal; outside the timed step."""
+        ps = self.ps
+        ps.cloud.copy_(torch.from_numpy(np.ascontiguousarray(prob["cloud"], np.float32)))
+        ps.prob = prob
+        for p in (ps.problem, self.ref_problem, self.cand_problem):
+            p.p_goal = np.asarray(prob["p_goal"], np.float32)
+            p.x0 = np.asarray(prob["x0"], np.float32)
+
+    def step(self):
+        ps = self.ps
+        ps.run()
+        self._shift(ps.u_nom, ps.best, 0, self.u_sel)
+        self._bwd(self.refine_params, self.ref_problem, 1.0, self.grad, self.grad_w, self.ws_b)
+        self._cand(ps.params, self.u_sel[0], self.grad[0], self.s0, self.beta, self.cands)
+        select_best(ps.params, [self.cand_problem], self.cS2, self.cbest, self.ws_c)
+        self._shift(self.cands, self.cbest, 1, ps.u_nom)
