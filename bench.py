@@ -174,8 +174,9 @@ def bench_loop(n_steps, stride=40):
     probs = [make_loop_step(s) for s in poses]
     print(f"# loop fixtures: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     lr = LoopRunner(probs[0])
-    lr.load(probs[0])
-    lr.step()                           # warm-up (and the autotuner's first trial)
+    for _ in range(2):                  # warm-up: the autotuner's two timing trials
+        lr.load(probs[0])
+        lr.step()
     torch.cuda.synchronize()
     times = []
     for p in probs:
