@@ -92,6 +92,18 @@ def select_best(prob, u_nom, nearest_fn=nearest):
     return dict(S2=S2, best=int(np.argmin(S2)), states=states, d=d.reshape(M, N), terms=terms)
 
 
+def mppi_iterations(prob, coef, n_iter, nearest_fn=nearest):
+    """Several Stage-I iterations in a row (Sec. III-B iterates sampling and update;
+    iteration i draws its noise at counter word iter_base + i and starts from the
+    previous iteration's u_nom).  Returns the list of per-iteration results."""
+    out, u = [], prob["u_nom"]
+    for i in range(int(n_iter)):
+        st = mppi_step(prob, coef, u_nom=u, nearest_fn=nearest_fn, iteration=i)
+        out.append(st)
+        u = st["u_new"]
+    return out
+
+
 def plan_step(prob, nearest_fn=nearest):
     """Partition -> anchors -> guides -> Stage I -> Stage II for one problem."""
     from .guides import build_guides
@@ -103,6 +115,6 @@ def plan_step(prob, nearest_fn=nearest):
     T = np.float32(prob["N"] * np.float32(prob["params"]["dt"]))
     coef = build_guides(prob["x0"][:3], prob["x0"][7:10], np.zeros(3, np.float32),
                         pa["anchors"].astype(np.float32), T)
-    st = mppi_step(prob, coef, nearest_fn=nearest_fn)
-    sel = select_best(prob, st["u_new"], nearest_fn=nearest_fn)
-    return dict(partition=pa, coef=coef, stage1=st, stage2=sel)
+    its = mppi_iterations(prob, coef, prob.get("n_iter", 1), nearest_fn=nearest_fn)
+    sel = select_best(prob, its[-1]["u_new"], nearest_fn=nearest_fn)
+    return dict(partition=pa, coef=coef, stage1=its[-1], iterations=its, stage2=sel)

@@ -18,7 +18,8 @@ class PlanStep:
     and, optionally, `anchors` (then the partition is skipped and the given
     anchors are used, as for a single straight-line guide) and `collision`
     ("raw": the whole cloud, default; "filtered": P_f, the closest point of every
-    fine cone).
+    fine cone) and `n_iter` (MPPI iterations per planning step, default 1;
+    iteration i draws its noise at counter word iter_base + i).
     """
 
     def __init__(self, prob, device="cuda", keep_debug=False):
@@ -70,6 +71,11 @@ class PlanStep:
                  workspace_size(CALL_SELECT_BEST, [self.problem]))
         self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
         self.params = prob["params"]
+        self.n_iter = int(prob.get("n_iter", 1))
+        if self.n_iter < 1:
+            raise ValueError("n_iter must be at least 1")
+        base = int(self.params.get("iter_base", 0))
+        self.iter_params = [dict(self.params, iter_base=base + i) for i in range(self.n_iter)]
         x0 = np.asarray(prob["x0"], np.float32)
         self.p0, self.v0 = x0[0:3].copy(), x0[7:10].copy()
         self.a0 = np.zeros(3, np.float32)
@@ -90,7 +96,12 @@ class PlanStep:
         build_guides(self.p0, self.v0, self.a0, self.anchors, self.T, self.M, self.coef)
 
     def stage1(self):
-        mppi_step(self.params, [self.problem], self.ws)
+        for prm in self.iter_params:
+            mppi_step(prm, [self.problem], self.ws)
+
+    def stage1_iteration(self, i):
+        """Only iteration i of Stage I (u_nom is read and updated in place)."""
+        mppi_step(self.iter_params[i], [self.problem], self.ws)
 
     def stage2(self):
         select_best(self.params, [self.problem], self.S2, self.best, self.ws)

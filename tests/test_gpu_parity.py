@@ -238,6 +238,33 @@ def test_stage1_ragged_shapes(M, K, N, P, pass_a):
     compare_stage1(prob, g)
 
 
+def test_stage1_iterations_teacher_forced():
+    """Three MPPI iterations in one planning step: each iteration against the oracle
+    started from the GPU's u_nom before it; the fused loop equals the single calls."""
+    prob = dict(make_plain_problem())
+    prm = dict(prob["params"], iter_base=2)
+    prob.update(params=prm, n_iter=3)
+    print("stage1 plain K=256 N=20, 3 iterations", flush=True)
+    ps = PlanStep(prob, keep_debug=True)
+    ps.front_end()
+    sync()
+    coef = np_(ps.coef)
+    for i in range(3):
+        u_before = np_(ps.u_nom)
+        ps.stage1_iteration(i)
+        sync()
+        g = dict(coef=coef, deff=np_(ps.delta_eff), md2=np_(ps.min_dist2), S1=np_(ps.S1),
+                 u_new=np_(ps.u_nom))
+        pi = dict(prob, u_nom=u_before, params=dict(prm, iter_base=2 + i))
+        print(i, compare_stage1(pi, g))
+        assert not np.array_equal(g["u_new"], u_before)
+    ps2 = PlanStep(prob)
+    ps2.front_end()
+    ps2.stage1()
+    sync()
+    assert np.array_equal(np_(ps2.u_nom), np_(ps.u_nom))
+
+
 def test_stage1_zero_noise_returns_nominal():
     prob = dict(make_plain_problem())
     prm = dict(prob["params"])

@@ -256,3 +256,31 @@ def test_stage1_terms_on_exact_parabola():
     st2 = MP.mppi_step(prob, coef)
     tot = sum(float(w[i]) * st2["terms"][n][0, 0] for i, n in enumerate(C.TERMS))
     assert st2["S1"][0, 0] == pytest.approx(tot, rel=1e-14)
+
+
+def test_iterations_chain_noise_and_controls():
+    """Several iterations per step: with K = 1 each iteration is u <- clip(u + sigma n_i)
+    with n_i drawn at counter word iter_base + i, u_nom held in float32 between
+    iterations; sigma = 0 leaves u unchanged."""
+    prob = dict(make_plain_problem())
+    prob.update(K=1, N=12)
+    prob["u_nom"] = prob["u_nom"][:, :12].copy()
+    prm = dict(prob["params"])
+    prm["iter_base"] = 5
+    prob["params"] = prm
+    coef = build_guides(prob["x0"][:3], prob["x0"][7:10], np.zeros(3), prob["anchors"], 0.6)
+    its = MP.mppi_iterations(prob, coef, 3)
+    lo, hi = prm["u_min"].astype(np.float64), prm["u_max"].astype(np.float64)
+    u = prob["u_nom"].astype(np.float64)
+    for i, st in enumerate(its):
+        n = PH.normals(prm["seed"], prob["problem_id"], 1, 1, 12, iteration=5 + i)
+        u = u.astype(np.float32).astype(np.float64)
+        u = np.clip(u + prm["sigma"].astype(np.float64) * n[:, 0], lo, hi)
+        np.testing.assert_allclose(st["u_new"], u, atol=1e-13)
+    assert not np.allclose(its[0]["u_new"] - prob["u_nom"], its[1]["u_new"] - its[0]["u_new"])
+    prm0 = dict(prm)
+    prm0["sigma"] = np.zeros(4, np.float32)
+    prob["params"] = prm0
+    prob["K"] = 6
+    its = MP.mppi_iterations(prob, coef, 4)
+    assert np.array_equal(its[-1]["u_new"], prob["u_nom"].astype(np.float64))
