@@ -54,6 +54,7 @@ typedef enum aero_status {
 #define AERO_K_MAX (1 << 20)  /* most samples per instance                        */
 #define AERO_BATCH_MAX 2048   /* most problems per call                           */
 #define AERO_GRID_MAX 8192    /* most fine cells along one angular axis           */
+#define AERO_FRAMES_MAX 256   /* most LiDAR frames per accumulated cloud          */
 
 /* Table I parameters shared by all problems of a call (float32 values). */
 typedef struct aero_params {
@@ -240,6 +241,45 @@ int aero_shift_controls(const float* d_src, int32_t M_src, int32_t N, const int3
  * AERO_ERR_PARAM (s0 or beta non-finite or negative), AERO_ERR_DEVICE. */
 int aero_step_candidates(const aero_params* h_prm, const float* d_u, const float* d_g, int32_t N,
                          float s0, float beta, int32_t n_candidates, float* d_out, void* stream);
+
+/* ---- closed loop: cloud accumulation and the vehicle step ----------------------- */
+
+/* Accumulated cloud in the drone-centred frame (Sec. IV-A builds the planner's
+ * cloud from several recent LiDAR frames; the partition reads it with world axes
+ * and the origin at the current position).  Frames sit in a ring of recorded
+ * points; frame f has n_f = offsets[f+1] - offsets[f] points from ring row
+ * start[f] on, in that frame's sensor coordinates.  Output rows
+ * offsets[f] .. offsets[f+1]-1 receive them in order, mapped as
+ *   out = (R(q_f / |q_f|) x + p_f) - origin,
+ * evaluated in binary64 and rounded once to float32.
+ *   d_ring            [ring_points][3] float32
+ *   d_frame_start     [n_frames] int32 ring row of each frame's first point
+ *   d_frame_offsets   [n_frames + 1] int32, non-decreasing from 0; offsets[n_frames]
+ *                     should equal n_points
+ *   d_poses           [n_frames][7] float32: p_f (world), then q_f (w, x, y, z),
+ *                     sensor to world, non-zero
+ *   d_origin          [3] float32 world position of the drone (e.g. p of its state)
+ *   d_out             [n_points][3] float32, must not overlap the ring
+ * All device memory, owned by the caller.  Starts and offsets are not validated on
+ * the host: inconsistent ones give wrong points, but every read is clamped into the
+ * ring and exactly n_points rows are written.
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (n_frames < 1 or > AERO_FRAMES_MAX,
+ * n_points < 0, ring_points < 0, or ring_points = 0 with n_points > 0),
+ * AERO_ERR_DEVICE.  n_points = 0 enqueues nothing. */
+int aero_accumulate_cloud(const float* d_ring, int32_t ring_points, const int32_t* d_frame_start,
+                          const int32_t* d_frame_offsets, int32_t n_frames, int32_t n_points,
+                          const float* d_poses, const float* d_origin, float* d_out,
+                          void* stream);
+
+/* One control period of the vehicle under the first control of the executed plan
+ * (Sec. III-A model, Sec. III-B RK4 step with the control held and the quaternion
+ * renormalised):  x1 = RK4(x0, u[i][0], dt),  i = *d_index clamped to [0, M).
+ *   d_x0, d_x1 [10] float32 (may alias), d_u [M][N][4] float32, d_index int32 (device,
+ *   e.g. the d_best output of aero_select_best); dt, mass, gravity from h_prm.
+ * Errors: as aero_step_candidates' parameter checks; AERO_ERR_NULL, AERO_ERR_SHAPE
+ * (M < 1 or > AERO_M_MAX, N < 1), AERO_ERR_DEVICE. */
+int aero_advance_state(const aero_params* h_prm, const float* d_x0, const float* d_u, int32_t M,
+                       int32_t N, const int32_t* d_index, float* d_x1, void* stream);
 
 /* ---- kernel-variant selection --------------------------------------------------- */
 

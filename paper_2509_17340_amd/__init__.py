@@ -15,7 +15,7 @@ __all__ = [
     "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
     "KERNELS", "shift_controls", "step_candidates", "set_pass_a_variant", "pass_a_variant",
-    "use_library",
+    "use_library", "accumulate_cloud", "advance_state",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -86,6 +86,9 @@ _SIGS = {
     "aero_step_candidates": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_int32, _P, _P]),
     "aero_pass_a_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "aero_accumulate_cloud": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32,
+                                             ctypes.c_int32, _P, _P, _P, _P]),
+    "aero_advance_state": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "aero_filtered_cloud": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "aero_timing_read": (ctypes.c_int, [ctypes.c_int, _P, _P, ctypes.c_int]),
 }
@@ -136,6 +139,24 @@ def _ptr(t):
     return int(t)
 
 
+_DT = {"f32": "torch.float32", "f64": "torch.float64", "i32": "torch.int32", "u8": "torch.uint8"}
+
+
+def _need(t, numel, kind, name):
+    """Host check that a device tensor can hold what the kernels will touch:
+    contiguous, of the expected element type and with at least `numel` elements."""
+    if t is None:
+        return
+    if not hasattr(t, "data_ptr") or not hasattr(t, "is_contiguous"):
+        return
+    if str(t.dtype) != _DT[kind]:
+        raise TypeError(f"{name}: expected {_DT[kind]}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, the call needs {numel}")
+
+
 def _stream(stream=None):
     if stream is not None:
         return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
@@ -179,7 +200,18 @@ class Problem:
         self.nearest_idx = nearest_idx
         self.problem_id = int(problem_id)
 
+    def check(self):
+        M, K, N = self.M, self.K, self.N
+        _need(self.cloud, 3 * self.n_points, "f32", "cloud")
+        _need(self.u_nom, M * N * 4, "f32", "u_nom")
+        _need(self.coef, M * 18, "f32", "coef")
+        _need(self.S1, M * K, "f64", "S1")
+        _need(self.delta_eff, M * N * 4 * K, "f32", "delta_eff")
+        _need(self.min_dist2, M * N * K, "f32", "min_dist2")
+        _need(self.nearest_idx, M * N * K, "i32", "nearest_idx")
+
     def struct(self):
+        self.check()
         s = ProblemStruct()
         s.cloud = _ptr(self.cloud) if self.n_points > 0 else None
         s.n_points, s.M, s.K, s.N = self.n_points, self.M, self.K, self.N
@@ -267,6 +299,9 @@ def select_best(prm, problems, S2, best, ws, ws_bytes=None, stream=None):
 def shift_controls(src, index, shift, dst, stream=None):
     """dst[m] = src[index][t + shift] (last control held); index is a device int32."""
     M_src, N = int(src.shape[0]), int(src.shape[1])
+    _need(src, M_src * N * 4, "f32", "src")
+    _need(index, 1, "i32", "index")
+    _need(dst, int(dst.shape[0]) * N * 4, "f32", "dst")
     _check(_lib.aero_shift_controls(_ptr(src), M_src, N, _ptr(index), int(shift), _ptr(dst),
                                     int(dst.shape[0]), _stream(stream)), "aero_shift_controls")
 
@@ -274,9 +309,46 @@ def shift_controls(src, index, shift, dst, stream=None):
 def step_candidates(prm, u, g, s0, beta, out, stream=None):
     """out[0] = u, out[i] = clip(u - s0 beta^(i-1) g / max|g|)."""
     p = params_struct(prm) if isinstance(prm, dict) else prm
+    N = int(u.shape[-2])
+    _need(u, N * 4, "f32", "u")
+    _need(g, N * 4, "f32", "g")
+    _need(out, int(out.shape[0]) * N * 4, "f32", "out")
     _check(_lib.aero_step_candidates(ctypes.byref(p), _ptr(u), _ptr(g), int(u.shape[-2]),
                                      float(s0), float(beta), int(out.shape[0]), _ptr(out),
                                      _stream(stream)), "aero_step_candidates")
+
+
+def accumulate_cloud(ring, frame_start, frame_offsets, poses, origin, out, n_points=None,
+                     stream=None):
+    """out rows offsets[f]..offsets[f+1] = (R(q_f) x + p_f) - origin for the points of
+    frame f read from ring rows start[f].. (see aero_accumulate_cloud).
+
+    ring (R, 3) float32, frame_start (F,) int32, frame_offsets (F+1,) int32,
+    poses (F, 7) float32, origin (>= 3,) float32, out (>= n_points, 3) float32 --
+    all device tensors; n_points defaults to out's row count."""
+    R, F = int(ring.shape[0]), int(poses.shape[0])
+    P = int(out.shape[0]) if n_points is None else int(n_points)
+    _need(ring, 3 * R, "f32", "ring")
+    _need(out, 3 * P, "f32", "out")
+    _need(frame_start, F, "i32", "frame_start")
+    _need(frame_offsets, F + 1, "i32", "frame_offsets")
+    _need(poses, 7 * F, "f32", "poses")
+    _need(origin, 3, "f32", "origin")
+    _check(_lib.aero_accumulate_cloud(_ptr(ring), R, _ptr(frame_start), _ptr(frame_offsets), F, P,
+                                      _ptr(poses), _ptr(origin), _ptr(out), _stream(stream)),
+           "aero_accumulate_cloud")
+
+
+def advance_state(prm, x0, u, index, x1, stream=None):
+    """x1 = RK4(x0, u[index][0], dt) (see aero_advance_state); u (M, N, 4)."""
+    p = params_struct(prm) if isinstance(prm, dict) else prm
+    M, N = int(u.shape[0]), int(u.shape[1])
+    _need(x0, 10, "f32", "x0")
+    _need(x1, 10, "f32", "x1")
+    _need(u, M * N * 4, "f32", "u")
+    _need(index, 1, "i32", "index")
+    _check(_lib.aero_advance_state(ctypes.byref(p), _ptr(x0), _ptr(u), M, N, _ptr(index), _ptr(x1),
+                                   _stream(stream)), "aero_advance_state")
 
 
 def set_pass_a_variant(variant):

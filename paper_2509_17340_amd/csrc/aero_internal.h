@@ -103,6 +103,13 @@ struct DevSelect {
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_accumulate_cloud(const float* ring, int64_t ring_points, const int32_t* start,
+                                   const int32_t* offsets, int F, int64_t n_points,
+                                   const float* poses, const float* origin, float* out,
+                                   hipStream_t s);
+hipError_t launch_advance_state(const float* x0, const float* u, int M, int N,
+                                const int32_t* index, const DevParams& prm, float* x1,
+                                hipStream_t s);
 hipError_t launch_shift_controls(const float* src, int M_src, int N, const int32_t* index,
                                  int shift, float* dst, int M_dst, hipStream_t s);
 hipError_t launch_step_candidates(const float* u, const float* g, int N, float s0, float beta,

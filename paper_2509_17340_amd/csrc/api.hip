@@ -707,6 +707,31 @@ int aero_step_candidates(const aero_params* h_prm, const float* d_u, const float
                                            d_out, (hipStream_t)stream));
 }
 
+int aero_accumulate_cloud(const float* d_ring, int32_t ring_points, const int32_t* d_frame_start,
+                          const int32_t* d_frame_offsets, int32_t n_frames, int32_t n_points,
+                          const float* d_poses, const float* d_origin, float* d_out,
+                          void* stream) {
+  if (!d_frame_start || !d_frame_offsets || !d_poses || !d_origin) return AERO_ERR_NULL;
+  if (n_frames < 1 || n_frames > AERO_FRAMES_MAX || n_points < 0 || ring_points < 0)
+    return AERO_ERR_SHAPE;
+  if (n_points == 0) return AERO_OK;
+  if (ring_points == 0) return AERO_ERR_SHAPE;
+  if (!d_ring || !d_out) return AERO_ERR_NULL;
+  return dev_status(launch_accumulate_cloud(d_ring, ring_points, d_frame_start, d_frame_offsets,
+                                            n_frames, n_points, d_poses, d_origin, d_out,
+                                            (hipStream_t)stream));
+}
+
+int aero_advance_state(const aero_params* h_prm, const float* d_x0, const float* d_u, int32_t M,
+                       int32_t N, const int32_t* d_index, float* d_x1, void* stream) {
+  int e = check_params(h_prm);
+  if (e) return e;
+  if (!d_x0 || !d_u || !d_index || !d_x1) return AERO_ERR_NULL;
+  if (M < 1 || M > AERO_M_MAX || N < 1) return AERO_ERR_SHAPE;
+  return dev_status(
+      launch_advance_state(d_x0, d_u, M, N, d_index, promote(*h_prm), d_x1, (hipStream_t)stream));
+}
+
 int aero_set_pass_a_variant(int variant) {
   if (variant < -1 || variant > 1) return AERO_ERR_PARAM;
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -179,3 +179,38 @@ def test_partition_and_guides_validation_without_device():
     expect_status(3, aero.build_guides, (np.nan, 0, 0), z, z, FakeTensor((1, 3)), 2.0, 1,
                   FakeTensor((1,)))
     expect_status(1, aero.build_guides, z, z, z, None, 2.0, 1, FakeTensor((1,)))
+
+
+def test_loop_calls_validation_without_device():
+    ring, st, off = FakeTensor((10, 3)), FakeTensor((2,)), FakeTensor((3,))
+    poses, org, out = FakeTensor((2, 7)), FakeTensor((3,)), FakeTensor((10, 3))
+    expect_status(1, aero.accumulate_cloud, ring, st, None, poses, org, out)
+    expect_status(2, aero.accumulate_cloud, ring, st, FakeTensor((1,)), FakeTensor((0, 7)), org, out)
+    expect_status(2, aero.accumulate_cloud, ring, FakeTensor((257,)), FakeTensor((258,)),
+                  FakeTensor((257, 7)), org, out)
+    expect_status(2, aero.accumulate_cloud, FakeTensor((0, 3)), st, off, poses, org, out)
+    aero.accumulate_cloud(ring, st, off, poses, org, FakeTensor((0, 3)))  # nothing enqueued
+    x, u, i = FakeTensor((10,)), FakeTensor((4, 6, 4)), FakeTensor((1,))
+    expect_status(1, aero.advance_state, params(), x, u, None, x)
+    expect_status(3, aero.advance_state, params(dt=-1.0), x, u, i, x)
+    expect_status(2, aero.advance_state, params(), x, FakeTensor((0, 6, 4)), i, x)
+    expect_status(2, aero.shift_controls, FakeTensor((0, 6, 4)), i, 1, u)
+    expect_status(2, aero.shift_controls, u, i, -1, u)
+    expect_status(2, aero.step_candidates, params(), FakeTensor((6, 4)), FakeTensor((6, 4)), 0.5, 0.5,
+                  FakeTensor((0, 6, 4)))
+    expect_status(3, aero.step_candidates, params(), FakeTensor((6, 4)), FakeTensor((6, 4)), -0.5,
+                  0.5, FakeTensor((4, 6, 4)))
+
+
+def test_binding_rejects_undersized_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        aero.shift_controls(torch.zeros((2, 5, 4)), torch.zeros(1, dtype=torch.int32), 1,
+                            torch.zeros((3, 5, 3)))
+    with pytest.raises(TypeError):
+        aero.accumulate_cloud(torch.zeros((4, 3), dtype=torch.float64), torch.zeros(1, dtype=torch.int32),
+                              torch.zeros(2, dtype=torch.int32), torch.zeros((1, 7)), torch.zeros(3),
+                              torch.zeros((4, 3)))
+    with pytest.raises(ValueError):
+        aero.advance_state(params(), torch.zeros(10), torch.zeros((2, 5, 4)).transpose(0, 1),
+                           torch.zeros(1, dtype=torch.int32), torch.zeros(10))
