@@ -7,7 +7,7 @@ can consume it without sharing code.
 """
 from .scenes import (  # noqa: F401
     Cylinder, Box, lidar_sweep, forest_scene, verticals_scene, incline_scene,
-    cylinders_surface_points,
+    cylinders_surface_points, record_frame,
 )
 from .configs import (  # noqa: F401
     table1_params, make_plain_problem, make_ensemble_problem,

@@ -228,3 +228,27 @@ def cylinders_surface_points(rng, cyl, n, max_norm, center=(0.0, 0.0, 0.0)):
         out.append(p)
         have += len(p)
     return np.concatenate(out)[:n]
+
+
+def _axis_angle_matrix(q):
+    """Rotation of a unit quaternion via its axis and angle (Rodrigues' formula)."""
+    q = np.asarray(q, float)
+    q = q / np.linalg.norm(q)
+    s = np.linalg.norm(q[1:])
+    if s == 0.0:
+        return np.eye(3)
+    ang = 2.0 * np.arctan2(s, q[0])
+    k = q[1:] / s
+    K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+    return np.eye(3) + np.sin(ang) * K + (1.0 - np.cos(ang)) * (K @ K)
+
+
+def record_frame(rng, cyl, boxes, x, n_az, el_deg, max_range, noise_std):
+    """One LiDAR frame recorded by a vehicle in state x = (p, q, v): the hits of a
+    sweep from p (beams spread in world azimuth/elevation), expressed in the body
+    axes of attitude q.  Returns (points float32 (n, 3), pose float32 (7,) = (p, q))."""
+    x = np.asarray(x, float)
+    p, q = x[0:3], x[3:7]
+    hits = lidar_sweep(rng, cyl, boxes, p, n_az, el_deg, max_range, noise_std)
+    body = hits @ _axis_angle_matrix(q)       # R^T h for every row h
+    return body.astype(np.float32), np.concatenate([p, q]).astype(np.float32)

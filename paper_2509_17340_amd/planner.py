@@ -6,8 +6,9 @@ calls on the current stream; it does no arithmetic of its own.
 import numpy as np
 import torch
 
-from . import (CALL_MPPI_STEP, CALL_SELECT_BEST, Problem, build_guides, filtered_cloud,
-               mppi_step, partition_anchors, partition_tables, select_best, workspace_size)
+from . import (CALL_MPPI_STEP, CALL_SELECT_BEST, Problem, accumulate_cloud, advance_state,
+               build_guides, filtered_cloud, mppi_step, partition_anchors, partition_tables,
+               select_best, workspace_size)
 
 
 class PlanStep:
@@ -29,6 +30,7 @@ class PlanStep:
         self.M, self.K, self.N = prob["M"], prob["K"], prob["N"]
         M, K, N = self.M, self.K, self.N
         self.cloud = torch.from_numpy(np.ascontiguousarray(prob["cloud"], np.float32)).to(dev)
+        self.n_points = int(self.cloud.shape[0])
         part = prob["partition"]
         self.part = part
         self.n_az = part["n_az_c"] * part["f_a"]
@@ -84,13 +86,31 @@ class PlanStep:
     def reset(self):
         self.u_nom.copy_(self.u_init)
 
+    def set_points(self, n_points):
+        """Use the first n_points rows of the cloud buffer (raw collision mode)."""
+        if not 0 <= n_points <= self.cloud.shape[0]:
+            raise ValueError("n_points exceeds the cloud buffer")
+        self.n_points = int(n_points)
+        if self.collision == "raw":
+            self.problem.n_points = self.n_points
+
+    def set_state(self, x0, p_goal):
+        """New start state (drone-centred frame: p = 0) and goal for the next step."""
+        x0 = np.asarray(x0, np.float32)
+        p_goal = np.asarray(p_goal, np.float32)
+        self.prob = dict(self.prob, x0=x0, p_goal=p_goal,
+                         goal_dir=(p_goal - x0[:3]).astype(np.float32))
+        self.p0, self.v0 = x0[0:3].copy(), x0[7:10].copy()
+        self.problem.x0, self.problem.p_goal = x0, p_goal
+
     def front_end(self):
         if self.fixed_anchors is None:
             p = self.part
             partition_anchors(p["n_az_c"], p["n_el_c"], p["f_a"], p["f_e"], self.prob["M_h"],
                               self.prob["M_v"], p["r_max"], p["ell"], self.p0, self.tables,
                               self.cloud, self.prob["goal_dir"], self.fine_key, self.fine_idx,
-                              self.coarse_best, self.anchor_cell, self.anchor_fine, self.anchors)
+                              self.coarse_best, self.anchor_cell, self.anchor_fine, self.anchors,
+                              n_points=self.n_points)
             if self.pf is not None:
                 filtered_cloud(self.cloud, self.fine_idx, self.pf)
         build_guides(self.p0, self.v0, self.a0, self.anchors, self.T, self.M, self.coef)
@@ -218,10 +238,16 @@ class LoopRunner:
         """Next replayed pose: new cloud (same size) and goal; outside the timed step."""
         ps = self.ps
         ps.cloud.copy_(torch.from_numpy(np.ascontiguousarray(prob["cloud"], np.float32)))
-        ps.prob = prob
-        for p in (ps.problem, self.ref_problem, self.cand_problem):
-            p.p_goal = np.asarray(prob["p_goal"], np.float32)
-            p.x0 = np.asarray(prob["x0"], np.float32)
+        self.set_state(prob["x0"], prob["p_goal"])
+
+    def set_points(self, n_points):
+        self.ps.set_points(n_points)
+        self.ref_problem.n_points = self.cand_problem.n_points = self.ps.n_points
+
+    def set_state(self, x0, p_goal):
+        self.ps.set_state(x0, p_goal)
+        for p in (self.ref_problem, self.cand_problem):
+            p.x0, p.p_goal = self.ps.problem.x0, self.ps.problem.p_goal
 
     def step(self):
         ps = self.ps
@@ -231,3 +257,66 @@ class LoopRunner:
         self._cand(ps.params, self.u_sel[0], self.grad[0], self.s0, self.beta, self.cands)
         select_best(ps.params, [self.cand_problem], self.cS2, self.cbest, self.ws_c)
         self._shift(self.cands, self.cbest, 1, ps.u_nom)
+
+
+class ClosedLoop:
+    """A true closed loop on the device.
+
+    Every cycle records one LiDAR frame at the vehicle's pose (`record(x)` returns
+    sensor-frame points and the pose row (p, q)), stores it in the next slot of a
+    device ring holding the last `n_frames` frames, accumulates the ring into the
+    drone-centred cloud, runs a `LoopRunner` step (plan, refine, warm start) and
+    advances the vehicle one control period under the first control of the refined
+    plan.  `prob` gives M, K, N, partition, params and the goal in world
+    coordinates (`p_goal`), and the initial world state `x0`.
+    """
+
+    def __init__(self, prob, record, n_frames=10, frame_capacity=100000, device="cuda"):
+        dev = torch.device(device)
+        self.F, self.cap, self.record = int(n_frames), int(frame_capacity), record
+        self.goal_world = np.asarray(prob["p_goal"], np.float32)
+        self.x_world = np.asarray(prob["x0"], np.float32).copy()
+        rows = self.F * self.cap
+        tmpl = dict(prob, cloud=np.zeros((rows, 3), np.float32))
+        self.lr = LoopRunner(tmpl, device=device)
+        self.ring = torch.zeros((rows, 3), dtype=torch.float32, device=dev)
+        self.start = torch.zeros(self.F, dtype=torch.int32, device=dev)
+        self.offsets = torch.zeros(self.F + 1, dtype=torch.int32, device=dev)
+        self.poses = torch.zeros((self.F, 7), dtype=torch.float32, device=dev)
+        self.state = torch.from_numpy(self.x_world.copy()).to(dev)
+        self.held = []          # (slot, count, pose) of the frames in the ring, oldest first
+        self.cycles = 0
+
+    def _upload_frame(self, pts, pose):
+        pts = np.ascontiguousarray(pts, np.float32).reshape(-1, 3)
+        if len(pts) > self.cap:
+            raise ValueError("frame larger than the ring slot")
+        slot = self.cycles % self.F
+        if len(pts):
+            self.ring[slot * self.cap:slot * self.cap + len(pts)].copy_(torch.from_numpy(pts))
+        self.held = [h for h in self.held if h[0] != slot] + [(slot, len(pts), np.float32(pose))]
+
+    def cycle(self):
+        ps = self.lr.ps
+        pts, pose = self.record(self.x_world)
+        self._upload_frame(pts, pose)
+        F = len(self.held)
+        counts = np.array([h[1] for h in self.held], np.int32)
+        start = np.array([h[0] * self.cap for h in self.held], np.int32)
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        self.start[:F].copy_(torch.from_numpy(start))
+        self.offsets[:F + 1].copy_(torch.from_numpy(off))
+        self.poses[:F].copy_(torch.from_numpy(np.stack([h[2] for h in self.held])))
+        n = int(off[-1])
+        accumulate_cloud(self.ring, self.start[:F], self.offsets[:F + 1], self.poses[:F],
+                         self.state, ps.cloud, n_points=n)
+        self.lr.set_points(n)
+        x_local = self.x_world.copy()
+        x_local[0:3] = 0.0
+        self.lr.set_state(x_local, self.goal_world - self.x_world[0:3])
+        self.lr.step()
+        # the refined plan's first control, applied through the same model and RK4 step
+        advance_state(ps.params, self.state, self.lr.cands, self.lr.cbest, self.state)
+        self.x_world = self.state.cpu().numpy()
+        self.cycles += 1
+        return self.x_world

@@ -87,3 +87,46 @@ def test_loop_steps_run_and_warm_start():
         u = np_(lr.ps.u_nom)
         assert np.all(np.isfinite(u))
         assert np.all(u == u[:1])          # every instance warm-started from one plan
+
+
+def test_true_closed_loop_cycles():
+    """Frames recorded at the simulated pose, accumulated on the device, planned on
+    and the first control applied through the model: each cycle's cloud and state
+    against the oracle."""
+    from fixtures import forest_scene, make_plain_problem, record_frame
+    from oracle import frames as FR
+    from paper_2509_17340_amd.planner import ClosedLoop
+
+    rng = np.random.Generator(np.random.PCG64(8))
+    cyl, boxes = forest_scene(rng, half=20.0)
+    el = np.linspace(-15.0, 15.0, 16)
+
+    def record(x):
+        return record_frame(rng, cyl, boxes, x, 360, el, 25.0, 0.02)
+
+    prob = dict(make_plain_problem())
+    prob.pop("anchors")
+    prob.update(M=4, M_h=2, M_v=2, K=256, N=20,
+                x0=np.float32([0, 0, 1.5, 1, 0, 0, 0, 0, 0, 0]),
+                p_goal=np.float32([18.0, 0.0, 1.5]))
+    prob["u_nom"] = np.broadcast_to(prob["u_nom"][:1], (4, 20, 4)).copy()
+    cl = ClosedLoop(prob, record, n_frames=3, frame_capacity=6000)
+    prm = prob["params"]
+    x_start = cl.x_world.copy()
+    for c in range(5):
+        x_prev = cl.x_world.copy()
+        print(f"closed loop cycle {c}", flush=True)
+        x_new = cl.cycle()
+        torch.cuda.synchronize()
+        F = len(cl.held)
+        off = np_(cl.offsets)[:F + 1]
+        n = int(off[-1])
+        assert F == min(c + 1, 3) and n == cl.lr.ps.n_points > 1000
+        exp = FR.to_local(np_(cl.ring), np_(cl.start)[:F], off, np_(cl.poses)[:F], x_prev[:3])
+        got = np_(cl.lr.ps.cloud)[:n].astype(np.float64)
+        sp = np.spacing(np.abs(exp).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(got - exp) <= sp)
+        xs = FR.advance_state(x_prev, np_(cl.lr.cands), int(np_(cl.lr.cbest)[0]), prm["dt"],
+                              prm["mass"], prm["gravity"])
+        assert np.all(np.abs(x_new - xs) <= 2 * np.spacing(np.abs(xs).astype(np.float32)) + 1e-12)
+    assert np.all(np.isfinite(cl.x_world)) and not np.array_equal(cl.x_world, x_start)

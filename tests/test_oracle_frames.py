@@ -100,3 +100,19 @@ def test_advance_state_hover_and_selected_plan():
     a = 2 * mg / float(np.float32(prm["mass"])) - float(np.float32(prm["gravity"]))
     np.testing.assert_allclose(x1[2], 3 + 0.5 * a * dt * dt, rtol=1e-14)
     np.testing.assert_allclose(x1[9], a * dt, rtol=1e-14)
+
+
+def test_recorded_frame_maps_back_to_the_world_hits():
+    """A frame recorded in the body axes of a tilted vehicle, mapped with its pose
+    (origin at the sensor), gives back the world-axis hits of the same sweep."""
+    from fixtures import forest_scene, lidar_sweep, record_frame
+    rng = np.random.Generator(np.random.PCG64(4))
+    cyl, boxes = forest_scene(rng, half=15.0)
+    q = quat_mul(_qz(0.8), quat_mul(_qy(0.2), np.array([np.cos(0.05), np.sin(0.05), 0, 0])))
+    x = np.concatenate([[1.0, -2.0, 1.5], q, [0, 0, 0]])
+    el = np.linspace(-15, 15, 8)
+    pts, pose = record_frame(np.random.Generator(np.random.PCG64(9)), cyl, boxes, x, 180, el, 20.0, 0.0)
+    hits = lidar_sweep(np.random.Generator(np.random.PCG64(9)), cyl, boxes, x[:3], 180, el, 20.0, 0.0)
+    assert len(pts) == len(hits) > 100
+    back = FR.to_local(pts, [0], [0, len(pts)], pose, pose[:3])
+    np.testing.assert_allclose(back, hits, atol=2e-5)
