@@ -174,7 +174,7 @@ def bench_loop(n_steps, stride=40):
     probs = [make_loop_step(s) for s in poses]
     print(f"# loop fixtures: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     lr = LoopRunner(probs[0])
-    for _ in range(2):                  # warm-up: the autotuner's two timing trials
+    for _ in range(3):                  # warm-up: the autotuner's timing trials
         lr.load(probs[0])
         lr.step()
     torch.cuda.synchronize()
@@ -216,8 +216,9 @@ def bench_batched(n_steps):
     outs = {}
     for mode in ("plain", "batched"):
         run = bp.run_plain if mode == "plain" else bp.run_batched
-        bp.reset()
-        run()
+        for _ in range(4):              # past the autotuner's per-shape timing trials
+            bp.reset()
+            run()
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()

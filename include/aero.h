@@ -283,19 +283,20 @@ int aero_advance_state(const aero_params* h_prm, const float* d_x0, const float*
 
 /* ---- kernel-variant selection --------------------------------------------------- */
 
-/* The first, approximate pass of the nearest-distance computation has two
- * implementations: 0 = VALU FMAs, 1 = matrix-core MFMA.  By default (-1) the
+/* The first, approximate pass of the nearest-distance computation has three
+ * implementations: 0 = VALU FMAs, 1 = single-precision matrix cores (MFMA),
+ * 2 = half-precision matrix cores on hi/lo-split coordinates.  By default (-1) the
  * library autotunes per call shape (sum of M N K, sum of cloud sizes, problem count):
- * the first two calls of a shape each time one variant with HIP events on the
- * call's stream, the third call keeps the faster one for that shape.  Costs, controls
- * and selections are bitwise identical for both variants; only min_dist2 entries far
+ * the first three calls of a shape each time one variant with HIP events on the
+ * call's stream, the fourth call keeps the fastest for that shape.  Costs, controls
+ * and selections are bitwise identical for every variant; only min_dist2 entries
  * beyond d_max may differ.  While the stream is being captured into a graph an
  * unsettled shape uses variant 0 and records nothing.
  * aero_set_pass_a_variant forces a variant for all later calls (-1 = autotune);
  * errors: AERO_ERR_PARAM for other values. */
 int aero_set_pass_a_variant(int variant);
 
-/* The variant in use for this call shape: 0 or 1, or -1 while still being tuned. */
+/* The variant in use for this call shape: 0, 1 or 2, or -1 while still being tuned. */
 int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems);
 
 /* ---- per-kernel timing (profiling aid) ---------------------------------------- */

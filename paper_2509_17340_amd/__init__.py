@@ -352,7 +352,8 @@ def advance_state(prm, x0, u, index, x1, stream=None):
 
 
 def set_pass_a_variant(variant):
-    """Force the first distance pass: 0 = VALU, 1 = MFMA, -1 = autotune (default)."""
+    """Force the first distance pass: 0 = VALU, 1 = FP32 MFMA, 2 = split-FP16 MFMA,
+    -1 = autotune (default)."""
     _check(_lib.aero_set_pass_a_variant(int(variant)), "aero_set_pass_a_variant")
 
 

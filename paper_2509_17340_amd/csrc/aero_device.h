@@ -149,6 +149,17 @@ __device__ __forceinline__ double collision_phi(double d, const DevParams& prm) 
 // ---------------------------------------------------------------------------
 // Wave64 / block reductions with a fixed combination order (deterministic).
 // ---------------------------------------------------------------------------
+__device__ inline float wave_minf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline float wave_maxf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -22,7 +22,9 @@ constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
 // Pass-A variants (the expanded-form first pass of the distance computation).
 constexpr int kPassAValu = 0;   // VALU FMAs, kQueriesPerBlock positions per block
 constexpr int kPassAMfma = 1;   // matrix-core MFMA, 512 positions per block
-constexpr int kPassAQPB[2] = {kQueriesPerBlock, 512};
+constexpr int kPassAF16s = 2;   // half-precision matrix cores on split coordinates, 1024 per block
+constexpr int kPassAVariants = 3;
+constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 512, 1024};
 
 // Per-problem record, built on the host and copied into the workspace.
 struct DevProblem {
@@ -129,6 +131,8 @@ hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blo
                            hipStream_t s);
 hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                   int variant, hipStream_t s);
+hipError_t launch_min_dist_approx_matrix(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                                         int variant, hipStream_t s);
 hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                   hipStream_t s);

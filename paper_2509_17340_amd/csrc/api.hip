@@ -74,8 +74,8 @@ hipError_t timed(int kernel, hipStream_t s, F&& launch) {
 
 // ---------------------------------------------------------------------------
 // Online autotuner of the pass-A variant, keyed by the call's shape.  The first
-// two calls of a shape time one variant each with HIP events; the third reads
-// both and keeps the faster.  Every variant yields bitwise-identical costs and
+// kPassAVariants calls of a shape time one variant each with HIP events; the next
+// reads them all and keeps the fastest.  Every variant yields bitwise-identical costs and
 // controls, so tuning never changes results.  While a stream is being captured
 // into a graph no events are recorded and an unsettled shape uses the VALU pass.
 // ---------------------------------------------------------------------------
@@ -89,8 +89,8 @@ struct TuneKey {
 struct TuneState {
   int trials = 0;
   int choice = -1;
-  hipEvent_t ev[2][2] = {};
-  float ms[2] = {0.f, 0.f};
+  hipEvent_t ev[kPassAVariants][2] = {};
+  float ms[kPassAVariants] = {};
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneState> g_tune;
@@ -115,7 +115,7 @@ int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return kPassAValu;
-  if (st.trials < 2) {
+  if (st.trials < kPassAVariants) {
     const int v = st.trials;
     if (hipEventCreate(&st.ev[v][0]) != hipSuccess || hipEventCreate(&st.ev[v][1]) != hipSuccess)
       return kPassAValu;
@@ -123,14 +123,16 @@ int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
     *ev = st.ev[v];
     return v;
   }
-  for (int v = 0; v < 2; ++v) {
+  int best = kPassAValu;
+  for (int v = 0; v < kPassAVariants; ++v) {
     if (hipEventSynchronize(st.ev[v][1]) != hipSuccess ||
         hipEventElapsedTime(&st.ms[v], st.ev[v][0], st.ev[v][1]) != hipSuccess)
       st.ms[v] = 1e30f;
     hipEventDestroy(st.ev[v][0]);
     hipEventDestroy(st.ev[v][1]);
+    if (st.ms[v] < st.ms[best]) best = v;
   }
-  st.choice = st.ms[kPassAMfma] < st.ms[kPassAValu] ? kPassAMfma : kPassAValu;
+  st.choice = best;
   return st.choice;
 }
 
@@ -314,7 +316,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.d_max = d_max;
     const bool two_pass = q.n_points > 0;
     // sized for the smallest pass-A block of any variant: the layout does not depend on it
-    const int64_t min_qpb = std::min(kPassAQPB[0], kPassAQPB[1]);
+    const int64_t min_qpb = *std::min_element(kPassAQPB, kPassAQPB + kPassAVariants);
     qs.thresh = cur.take<float>(two_pass ? (MNK + min_qpb - 1) / min_qpb : 0);
     qs.list = cur.take<int32_t>(two_pass ? MNK : 0);
     qs.count = cur.take<int32_t>(two_pass ? 1 : 0);
@@ -733,7 +735,7 @@ int aero_advance_state(const aero_params* h_prm, const float* d_x0, const float*
 }
 
 int aero_set_pass_a_variant(int variant) {
-  if (variant < -1 || variant > 1) return AERO_ERR_PARAM;
+  if (variant < -1 || variant >= kPassAVariants) return AERO_ERR_PARAM;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_forced_variant = variant;
   return AERO_OK;

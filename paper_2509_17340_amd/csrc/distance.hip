@@ -181,16 +181,6 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
   }
 }
 
-__device__ inline float wave_minf(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ inline float wave_maxf(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 // Pass A.  Block = (query block, cloud chunk) of a two-pass set.
 __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __restrict__ sets,
@@ -305,128 +295,6 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
   }
 }
 
-// Pass A on the matrix cores.  t(point i, query j) = [-2 o'_i, |o'_i|^2] . [p'_j, 1] is a
-// K = 4 contraction: one v_mfma_f32_16x16x4f32 per 16 points x 16 queries (lane l supplies
-// A[l % 16][l / 16] = component l/16 of point l%16, B[l / 16][l % 16] = component l/16 of
-// query l%16, and receives D rows 4 (l / 16) .. +3 of column l % 16).  Each wave holds
-// kMfmaCols column blocks of 16 queries; the VALU only keeps the running minima.
-constexpr int kMfmaCols = 8;
-constexpr int kMfmaQPB = 4 * 64 / 4 * kMfmaCols;  // 4 waves x 16 queries x kMfmaCols = 512
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet* __restrict__ sets,
-                                                                 int n_sets) {
-  __shared__ float4 tile[kTilePts];
-  __shared__ float red[7][4];
-  const int64_t bid = blockIdx.x;
-  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
-  const QuerySet S = sets[s];
-  const int64_t local = bid - S.block_base;
-  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int col = lane & 15, kg = lane >> 4;
-  float px[kMfmaCols], py[kMfmaCols], pz[kMfmaCols];
-  bool ok[kMfmaCols];
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-#pragma unroll
-  for (int b = 0; b < kMfmaCols; ++b) {
-    const int64_t q = (int64_t)qb * kMfmaQPB + w * (16 * kMfmaCols) + b * 16 + col;
-    ok[b] = q < S.Q;
-    const int64_t qq = ok[b] ? q : 0;
-    px[b] = S.px[qq];
-    py[b] = S.py[qq];
-    pz[b] = S.pz[qq];
-    if (ok[b]) {
-      lo[0] = fminf(lo[0], px[b]);
-      lo[1] = fminf(lo[1], py[b]);
-      lo[2] = fminf(lo[2], pz[b]);
-      hi[0] = fmaxf(hi[0], px[b]);
-      hi[1] = fmaxf(hi[1], py[b]);
-      hi[2] = fmaxf(hi[2], pz[b]);
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_minf(lo[a]);
-    hi[a] = wave_maxf(hi[a]);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      red[a][w] = lo[a];
-      red[3 + a][w] = hi[a];
-    }
-  }
-  __syncthreads();
-  float c[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float l = fminf(fminf(red[a][0], red[a][1]), fminf(red[a][2], red[a][3]));
-    const float h = fmaxf(fmaxf(red[3 + a][0], red[3 + a][1]), fmaxf(red[3 + a][2], red[3 + a][3]));
-    c[a] = 0.5f * l + 0.5f * h;
-  }
-  float bop[kMfmaCols], pp[kMfmaCols], tmin[kMfmaCols], rr = 0.0f;
-#pragma unroll
-  for (int b = 0; b < kMfmaCols; ++b) {
-    const float x = px[b] - c[0], y = py[b] - c[1], z = pz[b] - c[2];
-    pp[b] = fmaf(z, z, fmaf(y, y, x * x));
-    if (ok[b]) rr = fmaxf(rr, pp[b]);
-    bop[b] = !ok[b] ? 0.0f : kg == 0 ? x : kg == 1 ? y : kg == 2 ? z : 1.0f;
-    tmin[b] = kFarT;
-  }
-  const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-  const float* tf = reinterpret_cast<const float*>(tile);
-  const int64_t g0 = (int64_t)ch * S.chunk_pts;
-  const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
-  for (int64_t base = g0; base < g1; base += kTilePts) {
-    const int cnt = (int)min<int64_t>(kTilePts, g1 - base);
-    const int cnt16 = (cnt + 15) & ~15;  // groups of 16 points, padded
-    for (int pt = tid; pt < cnt16; pt += kBlock) {
-      const bool in = pt < cnt;
-      const int64_t gg = in ? base + pt : base;
-      const float ox = S.cloud[3 * gg] - c[0];
-      const float oy = S.cloud[3 * gg + 1] - c[1];
-      const float oz = S.cloud[3 * gg + 2] - c[2];
-      tile[pt] = in ? make_float4(-2.0f * ox, -2.0f * oy, -2.0f * oz,
-                                  fmaf(oz, oz, fmaf(oy, oy, ox * ox)))
-                    : make_float4(0.0f, 0.0f, 0.0f, kFarT);
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int g = 0; g < cnt16; g += 16) {
-      const float a = tf[(g + col) * 4 + kg];
-#pragma unroll
-      for (int b = 0; b < kMfmaCols; ++b) {
-        const floatx4 dv = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[b], zero, 0, 0, 0);
-        tmin[b] = fminf(tmin[b], fminf(fminf(dv[0], dv[1]), fminf(dv[2], dv[3])));
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int b = 0; b < kMfmaCols; ++b) {
-    float v = tmin[b];
-    v = fminf(v, __shfl_xor(v, 16, 64));
-    v = fminf(v, __shfl_xor(v, 32, 64));
-    const int64_t q = (int64_t)qb * kMfmaQPB + w * (16 * kMfmaCols) + b * 16 + col;
-    if (ok[b] && kg == 0) atomicMin(S.out + q, __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
-  }
-  if (ch == 0) {
-    // the MFMA sums four products per entry; the bound below (the same as the VALU
-    // pass) covers that rounding with a wide margin
-    rr = wave_maxf(rr);
-    __syncthreads();
-    if (lane == 0) red[6][w] = rr;
-    __syncthreads();
-    if (tid == 0) {
-      const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
-      const float span = sqrtf(R2) * 1.001f + S.d_max;
-      S.thresh[qb] = S.d_max * S.d_max + 0x1p-17f * span * span + 1e-6f;
-      if (qb == 0) *S.count = 0;
-    }
-  }
-}
-
 // Compact the queries of two-pass sets whose pass-A value is under the bound.
 // Block = 256 consecutive queries of one set; one atomic per block.
 __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ sets, int n_sets) {
@@ -487,10 +355,9 @@ hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blo
 hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                   int variant, hipStream_t s) {
   if (total_blocks > 0) {
-    if (variant == kPassAMfma)
-      k_min_dist_approx_mfma<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
-    else
-      k_min_dist_approx<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+    if (variant == kPassAMfma || variant == kPassAF16s)
+      return launch_min_dist_approx_matrix(d_sets, n_sets, total_blocks, variant, s);
+    k_min_dist_approx<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
   }
   return hipGetLastError();
 }

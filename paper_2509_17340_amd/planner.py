@@ -179,7 +179,7 @@ class GraphStep:
     replayed: reset of u_nom followed by the four library calls.  Valid while the
     step's buffers and host inputs stay unchanged."""
 
-    def __init__(self, step, warmup=2):
+    def __init__(self, step, warmup=4):
         self.step = step
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())

@@ -187,7 +187,7 @@ def compare_stage1(prob, g, samples=None, nearest_fn=nearest):
                 u_tf_rel=float((num / den).max()), kappa=float(kappa))
 
 
-@pytest.fixture(params=[0, 1], ids=["valu", "mfma"])
+@pytest.fixture(params=[0, 1, 2], ids=["valu", "mfma", "f16s"])
 def pass_a(request):
     """Run the test with the first distance pass forced to one variant."""
     aero.set_pass_a_variant(request.param)
@@ -313,23 +313,58 @@ def test_stage1_deterministic_and_batched_equals_plain(pass_a):
         assert np.array_equal(np_(s.min_dist2), ref[2])
 
 
-def test_pass_a_variants_give_identical_costs():
-    """Both first-pass variants yield bitwise-identical S1, u_nom and exact distances
-    below d_max (they may differ only in first-pass values far beyond d_max)."""
-    prob = make_ensemble_problem()
+def variant_outputs(prob, variants=(0, 1, 2)):
     outs = []
-    for v in (0, 1):
+    for v in variants:
         aero.set_pass_a_variant(v)
-        ps, g = run_stage1(prob)
+        try:
+            ps, g = run_stage1(prob)
+        finally:
+            aero.set_pass_a_variant(-1)
         outs.append(g)
-    aero.set_pass_a_variant(-1)
-    a, b = outs
-    assert np.array_equal(a["S1"], b["S1"])
-    assert np.array_equal(a["u_new"], b["u_new"])
+    return outs
+
+
+def assert_same_costs(prob, outs, min_near=0):
+    a = outs[0]
     d_max2 = np.float32(prob["params"]["d_max"]) ** 2
-    near = (a["md2"] < d_max2) | (b["md2"] < d_max2)
-    assert np.array_equal(a["md2"][near], b["md2"][near])
-    assert near.sum() > 1000
+    for b in outs[1:]:
+        assert np.array_equal(a["S1"], b["S1"])
+        assert np.array_equal(a["u_new"], b["u_new"])
+        near = (a["md2"] < d_max2) | (b["md2"] < d_max2)
+        assert np.array_equal(a["md2"][near], b["md2"][near])
+        assert np.all(b["md2"][~near] >= d_max2)
+        assert near.sum() >= min_near
+
+
+def test_pass_a_variants_give_identical_costs():
+    """Every first-pass variant yields bitwise-identical S1, u_nom and exact distances
+    below d_max (they may differ only in first-pass values beyond d_max)."""
+    prob = make_ensemble_problem()
+    print("pass-A variants on the ensemble forest", flush=True)
+    assert_same_costs(prob, variant_outputs(prob), min_near=1000)
+
+
+def test_pass_a_far_points_and_wide_blocks():
+    """Points far outside the half-precision range of the recentred form (200 m and
+    1e18 away) and query blocks wider than its validity radius (d_max = 70 m):
+    the same costs for every variant, and the oracle's."""
+    rng = np.random.default_rng(17)
+    prob = dict(make_plain_problem())
+    prob.update(M=2, K=300, N=9, M_h=2, M_v=1)
+    near = rng.normal(size=(1500, 3)) * 3 + np.float32([4, 0, 0])
+    far = rng.normal(size=(40, 3)) * 5 + np.float32([200, -150, 30])
+    huge = np.full((3, 3), 1e18)
+    prob["cloud"] = np.concatenate([near, far, huge, near[:10] + 0.01]).astype(np.float32)
+    prob["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(2, 9, 4)) * 0.3).astype(np.float32)
+    prob["anchors"] = (rng.normal(size=(2, 3)) * 3).astype(np.float32)
+    for d_max in (1.0, 70.0):
+        prm = dict(prob["params"], d_max=d_max)
+        pr = dict(prob, params=prm)
+        print(f"far points, d_max={d_max}", flush=True)
+        outs = variant_outputs(pr)
+        assert_same_costs(pr, outs, min_near=100)
+        compare_stage1(pr, outs[2])
 
 
 def test_autotuner_settles_and_keeps_results():
@@ -338,14 +373,14 @@ def test_autotuner_settles_and_keeps_results():
     ps = PlanStep(prob)
     ps.front_end()
     res = []
-    for i in range(4):
+    for i in range(5):
         ps.reset()
         ps.stage1()
         sync()
         res.append((np_(ps.S1), np_(ps.u_nom)))
     v = aero.pass_a_variant([ps.problem])
     print(f"autotuned pass-A variant: {v}")
-    assert v in (0, 1)
+    assert v in (0, 1, 2)
     for r in res[1:]:
         assert np.array_equal(r[0], res[0][0]) and np.array_equal(r[1], res[0][1])
 
