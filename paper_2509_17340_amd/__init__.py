@@ -9,6 +9,11 @@ import ctypes
 import os
 
 import numpy as np
+# torch ships its own HIP runtime under the same soname as the system one; it must
+# be mapped before libaero.so so that the library binds to it.  Loading the library
+# first maps a second HIP/HSA runtime into the process, and the two then drive the
+# same device (kernel launches fail, later calls crash).
+import torch  # noqa: F401
 
 __all__ = [
     "AeroError", "lib", "params_struct", "Problem", "partition_tables", "partition_anchors",
