@@ -22,8 +22,27 @@ METRIC = "MPPI rollout-steps/s + plan-step ms; batched/adjoint vs plain, same GP
 FP32_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
 FLOP_PER_PAIR = 8             # 3 sub + 3 mul + 2 add per (position, point) pair
 
+# Pass-A variants: kernel, roofline bound and the published peak of the unit it runs
+# on, the FLOP it executes per pair, and the source file holding it.
+PASS_A = {
+    0: dict(kernel="k_min_dist_approx", bound="alu", peak=FP32_PEAK_TFLOPS,
+            unit_note="FP32 vector (VALU) peak", executed_flop_per_pair=6,
+            source="paper_2509_17340_amd/csrc/distance.hip"),
+    1: dict(kernel="k_min_dist_approx_mfma", bound="mfma", peak=157.3,
+            unit_note="FP32 dense MFMA peak", executed_flop_per_pair=8,
+            source="paper_2509_17340_amd/csrc/distance_mfma.hip"),
+    2: dict(kernel="k_min_dist_approx_f16s", bound="mfma", peak=2500.0,
+            unit_note="FP16 dense MFMA peak (split hi/lo operands, FP32 accumulation)",
+            executed_flop_per_pair=32,
+            source="paper_2509_17340_amd/csrc/distance_mfma.hip"),
+}
+# Pair-rate ceiling of the split-FP16 pass: the K = 16 MFMA (32 FLOP per pair at the
+# FP16 dense peak) and the running minimum (one v_min3_f32 per two pairs on 16 lanes
+# x 4 SIMDs x 256 CUs at 2.4 GHz) both allow about 7.8e13 pairs/s.
+F16S_PAIR_CEILING = min(2500e12 / 32, 16 * 4 * 256 * 2.4e9 * 2)
 
-def measured_traffic(kernel="k_min_dist_approx"):
+
+def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
     or None when the kernel's source has changed since the counters were taken."""
     import hashlib
@@ -314,8 +333,12 @@ def main():
     steps_per_plan = M * K * N + M * N
     md_ms, md_n = kt["min_dist"]
     md_avg = md_ms / max(md_n, 1)
-    flop = FLOP_PER_PAIR * (M * K * N) * P
+    pairs = (M * K * N) * P
+    flop = FLOP_PER_PAIR * pairs
     achieved = flop / (md_avg * 1e-3) / 1e12
+    variant = aero.pass_a_variant([ps.problem])
+    va = PASS_A.get(variant, PASS_A[0])
+    pairs_per_s = pairs / (md_avg * 1e-3)
     dist_ms = (kt["min_dist"][0] + kt["flag"][0] + kt["min_dist_exact"][0]) / args.steps
     best_ms = min(ms, gms)
     out = {
@@ -336,23 +359,32 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "dtype_detail": "rollout and costs in f64; distances in f32 (exact pass), pass A on "
+                        "split-f16 operands with f32 accumulation when that variant is tuned in",
         "data": "synthetic",
         "config": {"workload": f"ensemble-forest-{P // 1000}k: one planning step "
                                f"(partition 32x8 coarse x 4x4, M={M}, K={K}, N={N}, dt=0.05, "
                                f"{P}-point LiDAR cloud, Stage I + Stage II)",
                    "M": M, "K": K, "N": N, "points": P, "collision_set": "raw cloud"},
-        "roofline": {"bound": "alu",
-                     "kernel": "k_min_dist_approx (Stage I nearest distance, pass A over every "
-                               "rollout position)",
-                     "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
+        "roofline": {"bound": va["bound"],
+                     "kernel": va["kernel"] + " (Stage I nearest distance, pass A over every "
+                               "rollout position; autotuned variant %d)" % variant,
+                     "achieved": achieved, "peak": va["peak"], "unit": "TFLOP/s",
+                     "peak_is": va["unit_note"],
+                     "frac": achieved / va["peak"], "traffic": measured_traffic(va["kernel"]),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "copy-calibrated)",
-                     "flop_per_launch": flop, "avg_launch_ms": md_avg,
+                     "flop_per_launch": flop, "flop_counted": "8 per (position, point) pair",
+                     "avg_launch_ms": md_avg, "pairs_per_s": pairs_per_s,
+                     "executed_tflops": va["executed_flop_per_pair"] * pairs_per_s / 1e12,
+                     "executed_frac": va["executed_flop_per_pair"] * pairs_per_s / 1e12 / va["peak"],
                      "distance_all_passes_ms": dist_ms,
                      "distance_all_passes_tflops": flop / (dist_ms * 1e-3) / 1e12},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
     }
+    if variant == 2:
+        out["roofline"]["pair_ceiling_per_s"] = F16S_PAIR_CEILING
+        out["roofline"]["frac_of_pair_ceiling"] = pairs_per_s / F16S_PAIR_CEILING
     out["adjoint"] = bench_adjoint(prob)
     out["paper_operating_point"] = bench_paper_point()
     if args.batched:

@@ -214,7 +214,9 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h_problems,
  *   d_grad_w     [5] float32       = dL/dw = scale * sum_{m,k} J_i
  * The derivative is the exact one of the active smooth piece: clip mask, collision
  * branch and nearest point (lowest index on ties) held fixed.  Rollout states are
- * checkpointed every 8 steps and recomputed.
+ * checkpointed every 8 steps and recomputed.  The distance filter pass uses the
+ * variant already settled for this shape by aero_mppi_step (else variant 0); the
+ * gradients do not depend on it.
  * Errors: as aero_mppi_step. */
 int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h_problem,
                             float scale, float* d_grad_u_nom, float* d_grad_w, void* d_ws,

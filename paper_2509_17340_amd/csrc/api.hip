@@ -105,6 +105,14 @@ TuneKey tune_key(const aero_problem* h, int n) {
   return k;
 }
 
+// The forced or already settled variant of a shape, else the VALU pass (no trials).
+int settled_variant(const TuneKey& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_forced_variant >= 0) return g_forced_variant;
+  auto it = g_tune.find(key);
+  return (it != g_tune.end() && it->second.choice >= 0) ? it->second.choice : kPassAValu;
+}
+
 // Variant for this call; *ev receives the event pair to record around pass A (or null).
 int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
   *ev = nullptr;
@@ -350,8 +358,9 @@ struct BackwardPlan {
   size_t bytes = 0;
 };
 
-void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& bp) {
-  plan_mppi(h, 1, ws, d_max, bp.fwd);
+void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& bp,
+                   int variant = kPassAValu) {
+  plan_mppi(h, 1, ws, d_max, bp.fwd, variant);
   Cursor cur{ws};
   cur.off = bp.fwd.bytes;
   const aero_problem& q = h[0];
@@ -653,7 +662,9 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   BackwardPlan bp;
   plan_backward(h, nullptr, h_prm->d_max, bp);
   if (!d_ws || ws_bytes < bp.bytes) return AERO_ERR_WORKSPACE;
-  plan_backward(h, (char*)d_ws, h_prm->d_max, bp);
+  // pass A only filters; the shape's tuned forward variant serves here too
+  const int variant = settled_variant(tune_key(h, 1));
+  plan_backward(h, (char*)d_ws, h_prm->d_max, bp, variant);
   MppiPlan& pl = bp.fwd;
   const hipStream_t s = (hipStream_t)stream;
   const DevParams prm = promote(*h_prm);
@@ -667,7 +678,7 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
     he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, 1, pl.total_samples, prm, s); });
   if (he == hipSuccess && pl.total_blocks > 0)
     he = timed(AERO_K_MIN_DIST, s, [&] {
-      return launch_min_dist_approx(pl.d_sets, 1, pl.total_blocks, kPassAValu, s);
+      return launch_min_dist_approx(pl.d_sets, 1, pl.total_blocks, variant, s);
     });
   if (he == hipSuccess && pl.flag_blocks > 0)
     he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, 1, pl.flag_blocks, s); });

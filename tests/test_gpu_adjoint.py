@@ -106,3 +106,18 @@ def test_autograd_function_matches_direct_call():
     np.testing.assert_array_equal(u.grad.cpu().numpy(), gu.astype(np.float32))
     np.testing.assert_array_equal(w.grad.cpu().numpy(), gw.astype(np.float32))
     assert np.array_equal(u.detach().cpu().numpy(), prob["u_nom"])
+
+
+def test_backward_identical_across_pass_a_variants():
+    """The filter pass only decides which positions get the exact search: gradients
+    are bitwise the same whichever variant runs it."""
+    prob = make_ensemble_problem()
+    outs = []
+    for v in (0, 1, 2):
+        aero.set_pass_a_variant(v)
+        try:
+            outs.append(gpu_backward(prob, scale=0.5))
+        finally:
+            aero.set_pass_a_variant(-1)
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
