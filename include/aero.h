@@ -319,7 +319,8 @@ typedef enum aero_kernel {
   AERO_K_NEAREST = 11,     /* backward: nearest indices of flagged positions         */
   AERO_K_ADJOINT = 12,     /* backward: per-sample reverse sweep                     */
   AERO_K_GRAD_REDUCE = 13, /* backward: sums over samples                            */
-  AERO_K_COUNT = 14
+  AERO_K_SORT = 14,        /* Stage-I spatial sort of the positions (seven kernels)  */
+  AERO_K_COUNT = 15
 } aero_kernel;
 
 /* on != 0: from now on every launch of the kernels above is bracketed by two HIP

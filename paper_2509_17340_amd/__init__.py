@@ -100,7 +100,7 @@ _SIGS = {
 
 KERNELS = ("partition", "guides", "rollout", "min_dist", "finalize", "update", "sel_rollout",
            "sel_min_dist", "sel_final", "flag", "min_dist_exact", "nearest", "adjoint",
-           "grad_reduce")
+           "grad_reduce", "sort")
 
 
 def _load(path=LIB_PATH):

@@ -25,6 +25,9 @@ constexpr int kPassAMfma = 1;   // matrix-core MFMA, 512 positions per block
 constexpr int kPassAF16s = 2;   // half-precision matrix cores on split coordinates, 1024 per block
 constexpr int kPassAVariants = 3;
 constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 512, 1024};
+// Pass B gives each lane at most kQueriesPerLane queries of one pass-A block.
+static_assert(kQueriesPerBlock <= kQueriesPerLane * kBlock && 512 <= kQueriesPerBlock &&
+                  1024 <= kQueriesPerBlock, "pass-A blocks must fit one pass-B block");
 
 // Per-problem record, built on the host and copied into the workspace.
 struct DevProblem {
@@ -44,6 +47,27 @@ struct DevProblem {
   int64_t row_base;      // prefix of M*N over problems
   double* J;             // optional [5][M*K] unweighted terms (track, vnorm, ctrl, goal, col)
   int32_t* nidx;         // optional [M][N][K] nearest point index (-1: none within reach)
+  int32_t* work_count;   // pass-B work counter of the problem's query set (or nullptr)
+  unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
+};
+
+// Spatial sort of one problem's rollout positions (stable LSD radix sort of a 24-bit
+// Morton key over the positions' bounding box, 3 passes of 8 bits).
+constexpr int kSortDigits = 256;
+constexpr int kSortPasses = 3;
+struct SortSet {
+  const float* px;
+  const float* py;
+  const float* pz;
+  int64_t Q;
+  int64_t block_base;    // prefix of n_blocks over sets
+  int32_t n_blocks;      // ceil(Q / kBlock)
+  int32_t pad;
+  unsigned* box;         // [6] order-preserving bits: min x, y, z, max x, y, z
+  uint32_t* key[2];      // [Q] ping-pong keys
+  int32_t* val[2];       // [Q] ping-pong query indices; the result is val[1]
+  int32_t* table;        // [kSortDigits][n_blocks] per-block digit counts -> offsets
+  int32_t* rowsum;       // [kSortDigits] digit totals
 };
 
 // One set of query positions scored against one cloud by the distance kernels.
@@ -67,15 +91,19 @@ struct QuerySet {
   int64_t block_base;    // prefix of n_qblocks * n_chunks over sets
   // two-pass extension
   float* thresh;         // [n_qblocks] flag bound on the pass-A squared distance
-  int32_t* list;         // [Q] flagged query indices (nullptr: exact set)
-  int32_t* count;        // flagged count
+  int32_t* list;         // [n_qblocks * qpbA] flagged queries, segment qb at qb * qpbA
+                         //   (nullptr: exact set)
+  int32_t* seg_count;    // [n_qblocks] flagged queries of each query block
+  int2* work;            // [n_qblocks * n_tiles] (query block, tile) pairs where some
+                         //   query of the block came under the bound in pass A
+  int32_t* work_count;   // entries of `work` (zeroed by the rollout kernel)
   int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
   int32_t qpbA;          // positions per pass-A block (the variant's block size)
-  int32_t n_chunksB;     // cloud splits of pass B (chunk_ptsB points each)
-  int32_t chunk_ptsB;
+  int32_t n_tiles;       // ceil(n_points / kTilePts); pass-A chunks are whole tiles
   float d_max;
-  unsigned long long* nn;  // optional [Q]: pass B also keeps (d^2 bits << 32 | index),
-                           // indexed by list position (lowest index on ties)
+  const int32_t* perm;   // [Q] pass-A slot -> query, spatially sorted (nullptr: identity)
+  unsigned long long* nn;  // optional [n_qblocks * qpbA]: pass B also keeps
+                           // (d^2 bits << 32 | index) per list slot (lowest index on ties)
   int32_t* nidx;           // with nn: [Q] nearest index per query (-1 where not flagged)
 };
 
@@ -87,6 +115,21 @@ struct DevParams {
   double w[5];
   uint32_t seed_lo, seed_hi, iter_base, pad;
 };
+
+// Query of pass-A slot `slot` (a permutation of [0, Q); clamped, so that even a
+// corrupt permutation cannot address outside the positions).
+__device__ inline int64_t perm_query(const QuerySet& S, int64_t slot) {
+  if (!S.perm) return slot;
+  const int64_t q = S.perm[slot];
+  return q < 0 ? 0 : (q >= S.Q ? S.Q - 1 : q);
+}
+
+// Record that some query of pass-A block qb came under its bound in the cloud tile
+// starting at point `base` (pass-A chunks are whole kTilePts tiles).
+__device__ inline void append_hit(const QuerySet& S, int qb, int64_t base) {
+  const int e = atomicAdd(S.work_count, 1);
+  S.work[e] = make_int2(qb, (int)(base / kTilePts));
+}
 
 // Per-problem Stage-II record.
 struct DevSelect {
@@ -105,6 +148,8 @@ struct DevSelect {
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total_blocks,
+                               hipStream_t s);
 hipError_t launch_accumulate_cloud(const float* ring, int64_t ring_points, const int32_t* start,
                                    const int32_t* offsets, int F, int64_t n_points,
                                    const float* poses, const float* origin, float* out,

@@ -241,25 +241,29 @@ int chunks_for(int64_t total_qblocks, int n_tiles) {
   return (int)std::min<int64_t>(std::max<int64_t>(c, 1), std::max(n_tiles, 1));
 }
 
-// Split P points into about `want` chunks of a multiple of 64 points.
-void set_chunks(int64_t P, int64_t want, int32_t& n_chunks, int32_t& chunk_pts) {
+// Split P points into about `want` chunks of a multiple of `align` points.
+void set_chunks(int64_t P, int64_t want, int32_t& n_chunks, int32_t& chunk_pts,
+                int64_t align = 64) {
   if (P <= 0) {
     n_chunks = 0;
     chunk_pts = 0;
     return;
   }
-  want = std::min<int64_t>(std::max<int64_t>(want, 1), (P + 63) / 64);
+  want = std::min<int64_t>(std::max<int64_t>(want, 1), (P + align - 1) / align);
   const int64_t per = (P + want - 1) / want;
-  chunk_pts = (int32_t)((per + 63) / 64 * 64);
+  chunk_pts = (int32_t)((per + align - 1) / align * align);
   n_chunks = (int32_t)((P + chunk_pts - 1) / chunk_pts);
 }
 
 struct MppiPlan {
   std::vector<DevProblem> probs;
   std::vector<QuerySet> sets;
+  std::vector<SortSet> sorts;
   DevProblem* d_probs = nullptr;
   QuerySet* d_sets = nullptr;
+  SortSet* d_sorts = nullptr;   // adjacent to d_sets: one descriptor upload
   int64_t total_samples = 0, total_rows = 0, total_blocks = 0, flag_blocks = 0, listed_items = 0;
+  int64_t sort_blocks = 0;
   size_t bytes = 0;
 };
 
@@ -268,8 +272,11 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   Cursor cur{ws};
   pl.d_probs = cur.take<DevProblem>(n);
   pl.d_sets = cur.take<QuerySet>(n);
+  pl.d_sorts = cur.take<SortSet>(n);
   pl.probs.assign(n, DevProblem{});
   pl.sets.assign(n, QuerySet{});
+  pl.sorts.assign(n, SortSet{});
+  int64_t sort_blocks = 0;
   const int qpbA = kPassAQPB[variant];
   int64_t qblocks = 0;
   for (int b = 0; b < n; ++b) {
@@ -317,34 +324,73 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.qpbA = qpbA;
     qs.n_qblocks = (int)((MNK + qpbA - 1) / qpbA);
     const int n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
+    // pass-A chunks are whole tiles, so that its hits name pass-B tiles
     set_chunks(q.n_points, q.n_points > 0 ? chunks_for(qblocks, n_tiles) : 0, qs.n_chunks,
-               qs.chunk_pts);
+               qs.chunk_pts, kTilePts);
+    qs.n_tiles = n_tiles;
     qs.block_base = blk;
     blk += (int64_t)qs.n_qblocks * qs.n_chunks;
     qs.d_max = d_max;
     const bool two_pass = q.n_points > 0;
-    // sized for the smallest pass-A block of any variant: the layout does not depend on it
+    // sized for every variant (the smallest pass-A block gives the most blocks, the
+    // largest the most padded list slots), so the layout does not depend on it
     const int64_t min_qpb = *std::min_element(kPassAQPB, kPassAQPB + kPassAVariants);
-    qs.thresh = cur.take<float>(two_pass ? (MNK + min_qpb - 1) / min_qpb : 0);
-    qs.list = cur.take<int32_t>(two_pass ? MNK : 0);
-    qs.count = cur.take<int32_t>(two_pass ? 1 : 0);
+    const int64_t max_blocks = (MNK + min_qpb - 1) / min_qpb;
+    qs.thresh = cur.take<float>(two_pass ? max_blocks : 0);
+    qs.seg_count = cur.take<int32_t>(two_pass ? max_blocks : 0);
+    qs.list = cur.take<int32_t>(two_pass ? MNK + kQueriesPerBlock : 0);
+    qs.work = cur.take<int2>(two_pass ? max_blocks * n_tiles : 0);
+    qs.work_count = cur.take<int32_t>(two_pass ? 1 : 0);
     if (!two_pass) {
       qs.thresh = nullptr;
+      qs.seg_count = nullptr;
       qs.list = nullptr;
-      qs.count = nullptr;
+      qs.work = nullptr;
+      qs.work_count = nullptr;
+    }
+    d.work_count = qs.work_count;
+    // spatial order of the positions for pass A
+    SortSet& so = pl.sorts[b];
+    so.block_base = sort_blocks;
+    if (two_pass) {
+      so.px = qs.px;
+      so.py = qs.py;
+      so.pz = qs.pz;
+      so.Q = MNK;
+      so.n_blocks = (int32_t)((MNK + kBlock - 1) / kBlock);
+      so.box = cur.take<unsigned>(6);
+      so.key[0] = cur.take<uint32_t>(MNK);
+      so.key[1] = cur.take<uint32_t>(MNK);
+      so.val[0] = cur.take<int32_t>(MNK);
+      so.val[1] = cur.take<int32_t>(MNK);
+      so.table = cur.take<int32_t>((int64_t)kSortDigits * so.n_blocks);
+      so.rowsum = cur.take<int32_t>(kSortDigits);
+      sort_blocks += so.n_blocks;
+      qs.perm = so.val[1];
+      d.sort_box = so.box;
     }
     qs.query_base = fb;
     fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
-    qs.chunk_ptsB = two_pass ? kTilePts : 0;
-    qs.n_chunksB = two_pass ? n_tiles : 0;
-    items += two_pass ? (MNK + kQueriesPerBlock - 1) / kQueriesPerBlock * qs.n_chunksB : 0;
+    items += two_pass ? (int64_t)qs.n_qblocks * n_tiles : 0;
   }
   pl.total_samples = sb;
   pl.total_rows = rb;
   pl.total_blocks = blk;
   pl.flag_blocks = fb;
   pl.listed_items = items;
+  pl.sort_blocks = sort_blocks;
   pl.bytes = cur.off;
+}
+
+// Upload the problem, query-set and sort descriptors of a plan (adjacent in the
+// workspace) with one staged copy.
+hipError_t stage_mppi(const MppiPlan& pl, int n, hipStream_t s) {
+  const char* b0 = (const char*)pl.d_probs;
+  std::vector<char> blob((const char*)pl.d_sorts - b0 + n * sizeof(SortSet));
+  memcpy(blob.data(), pl.probs.data(), n * sizeof(DevProblem));
+  memcpy(blob.data() + ((const char*)pl.d_sets - b0), pl.sets.data(), n * sizeof(QuerySet));
+  memcpy(blob.data() + ((const char*)pl.d_sorts - b0), pl.sorts.data(), n * sizeof(SortSet));
+  return stage_copy(pl.d_probs, blob.data(), blob.size(), s);
 }
 
 struct BackwardPlan {
@@ -369,7 +415,7 @@ void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& b
   bp.J = cur.take<double>(5 * MK);
   int32_t* ni = cur.take<int32_t>(q.nearest_idx ? 0 : MNK);
   bp.nidx = q.nearest_idx ? q.nearest_idx : ni;
-  bp.nn = cur.take<unsigned long long>(q.n_points > 0 ? MNK : 0);
+  bp.nn = cur.take<unsigned long long>(q.n_points > 0 ? MNK + kQueriesPerBlock : 0);
   bp.ckpt = cur.take<double>(n_seg * 10 * MK);
   bp.seg = cur.take<double>(8 * 10 * MK);
   bp.gsamp = cur.take<double>(MNK * 4);
@@ -599,13 +645,12 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl, variant);
   const DevParams prm = promote(*h_prm);
   // One staged copy for both descriptor arrays (they are adjacent in the workspace).
-  std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_probs + n * sizeof(QuerySet));
-  memcpy(blob.data(), pl.probs.data(), n * sizeof(DevProblem));
-  memcpy(blob.data() + ((char*)pl.d_sets - (char*)pl.d_probs), pl.sets.data(),
-         n * sizeof(QuerySet));
-  hipError_t he = stage_copy(pl.d_probs, blob.data(), blob.size(), s);
+  hipError_t he = stage_mppi(pl, n, s);
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, n, pl.total_samples, prm, s); });
+  if (he == hipSuccess && pl.sort_blocks > 0)
+    he = timed(AERO_K_SORT, s,
+               [&] { return launch_spatial_sort(pl.d_sorts, n, pl.sort_blocks, s); });
   if (he == hipSuccess && tev) he = hipEventRecord(tev[0], s);
   if (he == hipSuccess && pl.total_blocks > 0)
     he = timed(AERO_K_MIN_DIST, s, [&] {
@@ -668,14 +713,14 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   MppiPlan& pl = bp.fwd;
   const hipStream_t s = (hipStream_t)stream;
   const DevParams prm = promote(*h_prm);
-  std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_probs + sizeof(QuerySet));
-  memcpy(blob.data(), pl.probs.data(), sizeof(DevProblem));
-  memcpy(blob.data() + ((char*)pl.d_sets - (char*)pl.d_probs), pl.sets.data(), sizeof(QuerySet));
   const aero_problem& q = h[0];
   const int64_t MK = (int64_t)q.M * q.K, MN = (int64_t)q.M * q.N;
-  hipError_t he = stage_copy(pl.d_probs, blob.data(), blob.size(), s);
+  hipError_t he = stage_mppi(pl, 1, s);
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, 1, pl.total_samples, prm, s); });
+  if (he == hipSuccess && pl.sort_blocks > 0)
+    he = timed(AERO_K_SORT, s,
+               [&] { return launch_spatial_sort(pl.d_sorts, 1, pl.sort_blocks, s); });
   if (he == hipSuccess && pl.total_blocks > 0)
     he = timed(AERO_K_MIN_DIST, s, [&] {
       return launch_min_dist_approx(pl.d_sets, 1, pl.total_blocks, variant, s);

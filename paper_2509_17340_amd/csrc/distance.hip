@@ -119,68 +119,84 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
   }
 }
 
-// Pass B: the flagged list of every two-pass set, persistent grid.  Work item =
-// (set, list block, tile chunk); the list lengths are read on the device.
+// One pass-B item: the flagged queries of query block qb (R per lane) against the
+// cloud tile [g0, g1).
+template <int R>
+__device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64_t g0, int64_t g1,
+                                   float4* tile) {
+  const int tid = threadIdx.x;
+  const int64_t lbase = qb * S.qpbA;
+  float px[R], py[R], pz[R], best[R];
+  int32_t qi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = r * kBlock + tid;
+    const bool ok = j < cnt;
+    const int32_t q = S.list[lbase + (ok ? j : 0)];  // cnt >= 1: slot 0 exists
+    qi[r] = ok ? q : -1;
+    px[r] = S.px[q];
+    py[r] = S.py[q];
+    pz[r] = S.pz[q];
+    best[r] = __uint_as_float(kInfBits);
+  }
+  if (S.nn) {
+    int32_t bidx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) bidx[r] = 0x7fffffff;
+    direct_range<R, true>(S, g0, g1, tile, px, py, pz, best, bidx);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (qi[r] >= 0) {
+        atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+        atomicMin(S.nn + lbase + r * kBlock + tid,
+                  ((unsigned long long)__float_as_uint(best[r]) << 32) |
+                      (unsigned long long)(unsigned)bidx[r]);
+      }
+  } else {
+    direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (qi[r] >= 0) atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+  }
+}
+
+// Pass B: exact direct form for the flagged queries, only against the tiles where
+// pass A saw some query of their block under the bound (a query's nearest point
+// within d_max always lies in such a tile).  Persistent grid over the work lists
+// of every two-pass set; the lengths are read on the device.
 __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __restrict__ sets,
                                                             int n_sets) {
   __shared__ float4 tile[kTilePts];
-  const int tid = threadIdx.x;
-  constexpr int R = kQueriesPerLane;
-  // Walk the sets; within a set, items = ceil(count / QPB) * n_chunksB.
   int64_t item_base = 0;
   for (int s = 0; s < n_sets; ++s) {
     const QuerySet& Sref = sets[s];
     if (!Sref.list || Sref.n_points <= 0) continue;
-    const int cnt = *Sref.count;
-    const int nlb = (cnt + kQueriesPerBlock - 1) / kQueriesPerBlock;
-    const int64_t items = (int64_t)nlb * Sref.n_chunksB;
-    // items of this set handled by this block: global item id = item_base + i
+    const int64_t items = *Sref.work_count;
     int64_t first = ((int64_t)blockIdx.x - item_base) % gridDim.x;
     if (first < 0) first += gridDim.x;
     if (items > 0) {
       const QuerySet S = Sref;
       for (int64_t it = first; it < items; it += gridDim.x) {
-        const int lb = (int)(it / S.n_chunksB), ch = (int)(it % S.n_chunksB);
-        float px[R], py[R], pz[R], best[R];
-        int32_t qi[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int idx = lb * kQueriesPerBlock + r * kBlock + tid;
-          const bool ok = idx < cnt;
-          const int32_t q = S.list[ok ? idx : 0];  // cnt >= 1 here: entry 0 exists
-          qi[r] = ok ? q : -1;
-          px[r] = S.px[q];
-          py[r] = S.py[q];
-          pz[r] = S.pz[q];
-          best[r] = __uint_as_float(kInfBits);
-        }
-        const int64_t g0 = (int64_t)ch * S.chunk_ptsB;
-        const int64_t g1 = min<int64_t>(g0 + S.chunk_ptsB, S.n_points);
-        if (S.nn) {
-          int32_t bidx[R];
-#pragma unroll
-          for (int r = 0; r < R; ++r) bidx[r] = 0x7fffffff;
-          direct_range<R, true>(S, g0, g1, tile, px, py, pz, best, bidx);
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-            if (qi[r] >= 0) {
-              const int idx = lb * kQueriesPerBlock + r * kBlock + tid;
-              atomicMin(S.out + qi[r], __float_as_uint(best[r]));
-              atomicMin(S.nn + idx, ((unsigned long long)__float_as_uint(best[r]) << 32) |
-                                        (unsigned long long)(unsigned)bidx[r]);
-            }
-        } else {
-          direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-            if (qi[r] >= 0) atomicMin(S.out + qi[r], __float_as_uint(best[r]));
-        }
+        const int2 wk = S.work[it];
+        const int64_t qb = wk.x;
+        const int cnt = min(S.seg_count[qb], S.qpbA);
+        if (cnt <= 0) continue;
+        const int64_t g0 = (int64_t)wk.y * kTilePts;
+        const int64_t g1 = min<int64_t>(g0 + kTilePts, S.n_points);
+        const int nr = (cnt + kBlock - 1) / kBlock;
+        if (nr == 1)
+          listed_item<1>(S, qb, cnt, g0, g1, tile);
+        else if (nr == 2)
+          listed_item<2>(S, qb, cnt, g0, g1, tile);
+        else if (nr <= 4)
+          listed_item<4>(S, qb, cnt, g0, g1, tile);
+        else
+          listed_item<kQueriesPerLane>(S, qb, cnt, g0, g1, tile);
       }
     }
     item_base += items;
   }
 }
-
 
 // Pass A.  Block = (query block, cloud chunk) of a two-pass set.
 __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __restrict__ sets,
@@ -196,12 +212,14 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
   constexpr int R = kQueriesPerLane;
   float px[R], py[R], pz[R];
   bool ok[R];
+  int32_t qid[R];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
-    ok[r] = q < S.Q;
-    const int64_t qq = ok[r] ? q : 0;
+    const int64_t slot = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    ok[r] = slot < S.Q;
+    const int64_t qq = ok[r] ? perm_query(S, slot) : 0;
+    qid[r] = (int32_t)qq;
     px[r] = S.px[qq];
     py[r] = S.py[qq];
     pz[r] = S.pz[qq];
@@ -245,6 +263,18 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
     if (ok[r]) rr = fmaxf(rr, pp[r]);
     tmin[r] = kFarT;
   }
+  // Rounding-error bound of the pass-A value of any pair within d_max:
+  // about 26 u (R + d_max)^2 with u = 2^-24; flag with a 5x margin.
+  rr = wave_maxf(rr);
+  if (lane == 0) red[6][w] = rr;
+  __syncthreads();
+  const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
+  const float span = sqrtf(R2) * 1.001f + S.d_max;
+  const float thr = S.d_max * S.d_max + 0x1p-17f * span * span + 1e-6f;
+  if (tid == 0 && ch == 0) {
+    S.thresh[qb] = thr;
+    S.seg_count[qb] = 0;
+  }
   const int64_t g0 = (int64_t)ch * S.chunk_pts;
   const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
   for (int64_t base = g0; base < g1; base += kTilePts) {
@@ -261,6 +291,9 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
                     : make_float4(0.0f, 0.0f, 0.0f, kFarT);
     }
     __syncthreads();
+    float tt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tt[r] = kFarT;
 #pragma unroll 4
     for (int j = 0; j < cnt2; j += 2) {
       const float4 a = tile[j];
@@ -269,33 +302,24 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
       for (int r = 0; r < R; ++r) {
         const float ta = fmaf(px[r], a.x, fmaf(py[r], a.y, fmaf(pz[r], a.z, a.w)));
         const float tb = fmaf(px[r], b.x, fmaf(py[r], b.y, fmaf(pz[r], b.z, b.w)));
-        tmin[r] = min3f(tmin[r], ta, tb);
+        tt[r] = min3f(tt[r], ta, tb);
       }
     }
-    __syncthreads();
+    bool hit = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      hit |= ok[r] && pp[r] + tt[r] < thr;
+      tmin[r] = fminf(tmin[r], tt[r]);
+    }
+    if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
-    if (ok[r]) atomicMin(S.out + q, __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
-  }
-  if (ch == 0) {
-    // Rounding-error bound of the pass-A value of any pair within d_max:
-    // about 26 u (R + d_max)^2 with u = 2^-24; flag with a 5x margin.
-    rr = wave_maxf(rr);
-    __syncthreads();
-    if (lane == 0) red[6][w] = rr;
-    __syncthreads();
-    if (tid == 0) {
-      const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
-      const float span = sqrtf(R2) * 1.001f + S.d_max;
-      S.thresh[qb] = S.d_max * S.d_max + 0x1p-17f * span * span + 1e-6f;
-      if (qb == 0) *S.count = 0;
-    }
-  }
+  for (int r = 0; r < R; ++r)
+    if (ok[r]) atomicMin(S.out + qid[r], __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
 }
 
-// Compact the queries of two-pass sets whose pass-A value is under the bound.
+// Compact the queries of two-pass sets whose pass-A value is under the bound into
+// the list segment of their pass-A block.
 // Block = 256 consecutive queries of one set; one atomic per block.
 __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ sets, int n_sets) {
   __shared__ int wave_cnt[4];
@@ -304,39 +328,49 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
   // query_base holds the prefix of ceil(Q / kBlock) blocks over sets
   const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.query_base; });
   const QuerySet& S = sets[s];
-  const int64_t q = (bid - S.query_base) * kBlock + threadIdx.x;
+  // pass-A slots in order; the query of a slot comes from the spatial sort
+  const int64_t slot = (bid - S.query_base) * kBlock + threadIdx.x;
+  int64_t q = 0;
   bool flag = false;
-  if (q < S.Q) {
+  if (slot < S.Q) {
+    q = perm_query(S, slot);
     const float d2 = __uint_as_float(S.out[q]);
-    flag = d2 < S.thresh[q / S.qpbA];
+    flag = d2 < S.thresh[slot / S.qpbA];
   }
   const uint64_t mask = __ballot(flag);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int before = __popcll(mask & ((1ull << lane) - 1ull));
   if (lane == 0) wave_cnt[w] = __popcll(mask);
   __syncthreads();
+  // the block's 256 queries lie in one pass-A block (qpbA is a multiple of 256)
+  const int64_t qb = ((bid - S.query_base) * kBlock) / S.qpbA;
   if (threadIdx.x == 0) {
     const int tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
-    base = tot ? atomicAdd(S.count, tot) : 0;
+    base = tot ? atomicAdd(S.seg_count + qb, tot) : 0;
   }
   __syncthreads();
   if (flag) {
     int off = base + before;
     for (int i = 0; i < w; ++i) off += wave_cnt[i];
-    S.list[off] = (int32_t)q;
+    const int64_t slot = qb * S.qpbA + off;
+    S.list[slot] = (int32_t)q;
     S.out[q] = kInfBits;
-    if (S.nn) S.nn[off] = ~0ull;
+    if (S.nn) S.nn[slot] = ~0ull;
   }
 }
 
-// Nearest indices of the flagged queries (sets with nn), persistent grid.
+// Nearest indices of the flagged queries (sets with nn), persistent grid over the
+// segment slots of every query block.
 __global__ __launch_bounds__(kBlock) void k_scatter_nearest(const QuerySet* __restrict__ sets,
                                                             int n_sets) {
   for (int s = 0; s < n_sets; ++s) {
     const QuerySet& S = sets[s];
     if (!S.nn || !S.list) continue;
-    const int cnt = *S.count;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+    const int64_t slots = (int64_t)S.n_qblocks * S.qpbA;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < slots;
+         i += (int64_t)gridDim.x * kBlock) {
+      const int64_t qb = i / S.qpbA;
+      if (i - qb * S.qpbA >= S.seg_count[qb]) continue;
       const unsigned long long v = S.nn[i];
       const unsigned idx = (unsigned)(v & 0xffffffffull);
       S.nidx[S.list[i]] = (v == ~0ull || idx >= (unsigned)S.n_points) ? -1 : (int32_t)idx;

@@ -41,12 +41,14 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
   const int col = lane & 15, kg = lane >> 4;
   float px[kMfmaCols], py[kMfmaCols], pz[kMfmaCols];
   bool ok[kMfmaCols];
+  int32_t qid[kMfmaCols];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int b = 0; b < kMfmaCols; ++b) {
-    const int64_t q = (int64_t)qb * kMfmaQPB + w * (16 * kMfmaCols) + b * 16 + col;
-    ok[b] = q < S.Q;
-    const int64_t qq = ok[b] ? q : 0;
+    const int64_t slot = (int64_t)qb * kMfmaQPB + w * (16 * kMfmaCols) + b * 16 + col;
+    ok[b] = slot < S.Q;
+    const int64_t qq = ok[b] ? perm_query(S, slot) : 0;
+    qid[b] = (int32_t)qq;
     px[b] = S.px[qq];
     py[b] = S.py[qq];
     pz[b] = S.pz[qq];
@@ -88,6 +90,18 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
     bop[b] = !ok[b] ? 0.0f : kg == 0 ? x : kg == 1 ? y : kg == 2 ? z : 1.0f;
     tmin[b] = kFarT;
   }
+  // the MFMA sums four products per entry; the bound below (the same as the VALU
+  // pass) covers that rounding with a wide margin
+  rr = wave_maxf(rr);
+  if (lane == 0) red[6][w] = rr;
+  __syncthreads();
+  const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
+  const float span = sqrtf(R2) * 1.001f + S.d_max;
+  const float thr = S.d_max * S.d_max + 0x1p-17f * span * span + 1e-6f;
+  if (tid == 0 && ch == 0) {
+    S.thresh[qb] = thr;
+    S.seg_count[qb] = 0;
+  }
   const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
   const float* tf = reinterpret_cast<const float*>(tile);
   const int64_t g0 = (int64_t)ch * S.chunk_pts;
@@ -106,38 +120,32 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
                     : make_float4(0.0f, 0.0f, 0.0f, kFarT);
     }
     __syncthreads();
+    float tt[kMfmaCols];
+#pragma unroll
+    for (int b = 0; b < kMfmaCols; ++b) tt[b] = kFarT;
 #pragma unroll 2
     for (int g = 0; g < cnt16; g += 16) {
       const float a = tf[(g + col) * 4 + kg];
 #pragma unroll
       for (int b = 0; b < kMfmaCols; ++b) {
         const floatx4 dv = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[b], zero, 0, 0, 0);
-        tmin[b] = fminf(tmin[b], fminf(fminf(dv[0], dv[1]), fminf(dv[2], dv[3])));
+        tt[b] = fminf(tt[b], fminf(fminf(dv[0], dv[1]), fminf(dv[2], dv[3])));
       }
     }
-    __syncthreads();
+    bool hit = false;
+#pragma unroll
+    for (int b = 0; b < kMfmaCols; ++b) {
+      hit |= ok[b] && pp[b] + tt[b] < thr;
+      tmin[b] = fminf(tmin[b], tt[b]);
+    }
+    if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
   }
 #pragma unroll
   for (int b = 0; b < kMfmaCols; ++b) {
     float v = tmin[b];
     v = fminf(v, __shfl_xor(v, 16, 64));
     v = fminf(v, __shfl_xor(v, 32, 64));
-    const int64_t q = (int64_t)qb * kMfmaQPB + w * (16 * kMfmaCols) + b * 16 + col;
-    if (ok[b] && kg == 0) atomicMin(S.out + q, __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
-  }
-  if (ch == 0) {
-    // the MFMA sums four products per entry; the bound below (the same as the VALU
-    // pass) covers that rounding with a wide margin
-    rr = wave_maxf(rr);
-    __syncthreads();
-    if (lane == 0) red[6][w] = rr;
-    __syncthreads();
-    if (tid == 0) {
-      const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
-      const float span = sqrtf(R2) * 1.001f + S.d_max;
-      S.thresh[qb] = S.d_max * S.d_max + 0x1p-17f * span * span + 1e-6f;
-      if (qb == 0) *S.count = 0;
-    }
+    if (ok[b] && kg == 0) atomicMin(S.out + qid[b], __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
   }
 }
 
@@ -179,12 +187,14 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet*
   const int col = lane & 31, kh = lane >> 5;
   float px[kF16Cols], py[kF16Cols], pz[kF16Cols];
   bool ok[kF16Cols];
+  int32_t qid[kF16Cols];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int b = 0; b < kF16Cols; ++b) {
-    const int64_t q = (int64_t)qb * kF16QPB + w * (32 * kF16Cols) + b * 32 + col;
-    ok[b] = q < S.Q;
-    const int64_t qq = ok[b] ? q : 0;
+    const int64_t slot = (int64_t)qb * kF16QPB + w * (32 * kF16Cols) + b * 32 + col;
+    ok[b] = slot < S.Q;
+    const int64_t qq = ok[b] ? perm_query(S, slot) : 0;
+    qid[b] = (int32_t)qq;
     px[b] = S.px[qq];
     py[b] = S.py[qq];
     pz[b] = S.pz[qq];
@@ -242,6 +252,18 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet*
     bop[b] = v;
     tmin[b] = kF16FarT;
   }
+  rr = wave_maxf(rr);
+  if (lane == 0) red[6][w] = rr;
+  __syncthreads();
+  const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
+  const float R = sqrtf(R2) * 1.001f;
+  const float span = R + S.d_max;
+  const float thr = (span <= 64.0f) ? S.d_max * S.d_max + 0x1p-15f * span * span + 1e-6f
+                                    : INFINITY;
+  if (tid == 0 && ch == 0) {
+    S.thresh[qb] = thr;
+    S.seg_count[qb] = 0;
+  }
   const floatx16 zacc = {};
   const int64_t g0 = (int64_t)ch * S.chunk_pts;
   const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
@@ -273,6 +295,9 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet*
       tile[2 * pt + 1] = u1;
     }
     __syncthreads();
+    float tt[kF16Cols];
+#pragma unroll
+    for (int b = 0; b < kF16Cols; ++b) tt[b] = kF16FarT;
     for (int g = 0; g < cnt32; g += 32) {
       const half8 a = tile[2 * (g + col) + kh];
       // two products in flight: the minima of one overlap the other's MFMA
@@ -280,37 +305,28 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet*
       for (int b = 0; b < kF16Cols; b += 2) {
         const floatx16 d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bop[b], zacc, 0, 0, 0);
         const floatx16 d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bop[b + 1], zacc, 0, 0, 0);
-        float m0 = tmin[b], m1 = tmin[b + 1];
+        float m0 = tt[b], m1 = tt[b + 1];
 #pragma unroll
         for (int r = 0; r < 16; r += 2) m0 = fminf(fminf(m0, d0[r]), d0[r + 1]);
 #pragma unroll
         for (int r = 0; r < 16; r += 2) m1 = fminf(fminf(m1, d1[r]), d1[r + 1]);
-        tmin[b] = m0;
-        tmin[b + 1] = m1;
+        tt[b] = m0;
+        tt[b + 1] = m1;
       }
     }
-    __syncthreads();
+    bool hit = false;
+#pragma unroll
+    for (int b = 0; b < kF16Cols; ++b) {
+      hit |= ok[b] && pp[b] + tt[b] < thr;
+      tmin[b] = fminf(tmin[b], tt[b]);
+    }
+    if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
   }
 #pragma unroll
   for (int b = 0; b < kF16Cols; ++b) {
     float v = tmin[b];
     v = fminf(v, __shfl_xor(v, 32, 64));   // the two lane halves hold different rows
-    const int64_t q = (int64_t)qb * kF16QPB + w * (32 * kF16Cols) + b * 32 + col;
-    if (ok[b] && kh == 0) atomicMin(S.out + q, __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
-  }
-  if (ch == 0) {
-    rr = wave_maxf(rr);
-    __syncthreads();
-    if (lane == 0) red[6][w] = rr;
-    __syncthreads();
-    if (tid == 0) {
-      const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
-      const float R = sqrtf(R2) * 1.001f;
-      const float span = R + S.d_max;
-      S.thresh[qb] = (span <= 64.0f) ? S.d_max * S.d_max + 0x1p-15f * span * span + 1e-6f
-                                     : INFINITY;
-      if (qb == 0) *S.count = 0;
-    }
+    if (ok[b] && kh == 0) atomicMin(S.out + qid[b], __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
   }
 }
 

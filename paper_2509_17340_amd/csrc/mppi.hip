@@ -37,6 +37,14 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
   const int64_t local = gid - P.sample_base;
   const int m = (int)(local / K), k = (int)(local % K);
   const int64_t MNK = (int64_t)P.M * N * K;
+  if (local == 0) {
+    if (P.work_count) *P.work_count = 0;  // pass B's work list of this call
+    if (P.sort_box)
+      for (int a = 0; a < 3; ++a) {
+        P.sort_box[a] = 0xffffffffu;      // order-preserving bits: running min, max
+        P.sort_box[3 + a] = 0u;
+      }
+  }
 
   const Dyn dyn{1.0 / prm.mass, prm.gravity};
   double x[10];

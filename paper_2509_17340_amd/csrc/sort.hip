@@ -1,0 +1,242 @@
+// Spatial sort of the rollout positions before the first distance pass.
+//
+// The first pass takes blocks of consecutive positions; its per-block bound and its
+// record of which cloud tiles a block came near are only as tight as the block is
+// compact.  Positions of one (instance, step) are spread by the sampling noise, so
+// they are reordered along a Morton (Z-order) curve over their bounding box: a
+// stable LSD radix sort of a 24-bit key (8 bits per axis) in three passes of 8 bits.
+// Every pass ranks elements without atomics (ballots inside a wave, per-wave counts
+// in LDS, per-block counts scanned in digit-major order), so the permutation is
+// deterministic and the same for a problem alone or inside a batch.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "aero_device.h"
+#include "aero_internal.h"
+
+namespace aero {
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+
+// Order-preserving map of floats to unsigned integers and back.
+__device__ inline unsigned ord_bits(float f) {
+  const unsigned b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float ord_float(unsigned o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+// The low 10 bits of v moved to every third bit.
+__device__ inline uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+struct Elem {
+  int s;          // set
+  int64_t blk;    // block within the set
+  int64_t i;      // element within the set
+  bool active;
+};
+
+__device__ inline Elem locate(const SortSet* sets, int n_sets) {
+  const int64_t bid = blockIdx.x;
+  Elem e;
+  e.s = find_owner(sets, n_sets, bid, [](const SortSet& q) { return q.block_base; });
+  e.blk = bid - sets[e.s].block_base;
+  e.i = e.blk * kBlock + threadIdx.x;
+  e.active = e.i < sets[e.s].Q;
+  return e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_box(const SortSet* __restrict__ sets,
+                                                     int n_sets) {
+  __shared__ float red[6][kWaves];
+  const Elem e = locate(sets, n_sets);
+  const SortSet& S = sets[e.s];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (e.active) {
+    const float p[3] = {S.px[e.i], S.py[e.i], S.pz[e.i]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = p[a];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_minf(lo[a]);
+    hi[a] = wave_maxf(hi[a]);
+    if (lane == 0) {
+      red[a][w] = lo[a];
+      red[3 + a][w] = hi[a];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int a = threadIdx.x;
+    float l = red[a][0], h = red[3 + a][0];
+    for (int k = 1; k < kWaves; ++k) {
+      l = fminf(l, red[a][k]);
+      h = fmaxf(h, red[3 + a][k]);
+    }
+    atomicMin(S.box + a, ord_bits(l));
+    atomicMax(S.box + 3 + a, ord_bits(h));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_keys(const SortSet* __restrict__ sets,
+                                                      int n_sets) {
+  const Elem e = locate(sets, n_sets);
+  if (!e.active) return;
+  const SortSet& S = sets[e.s];
+  float lo[3], ext = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ord_float(S.box[a]);
+    ext = fmaxf(ext, ord_float(S.box[3 + a]) - lo[a]);
+  }
+  const float scale = ext > 0.0f ? 255.99f / ext : 0.0f;
+  const float p[3] = {S.px[e.i], S.py[e.i], S.pz[e.i]};
+  uint32_t key = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float g = fminf(fmaxf((p[a] - lo[a]) * scale, 0.0f), 255.0f);
+    key |= spread3((uint32_t)g) << a;
+  }
+  S.key[0][e.i] = key;
+  S.val[0][e.i] = (int32_t)e.i;
+}
+
+// Rank of this lane's digit among the equal digits of lower lanes, and how many
+// lanes of the wave hold it (only active lanes take part).
+__device__ inline void wave_rank(bool active, uint32_t dig, int& rank, int& count) {
+  uint64_t match = __ballot(active);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (dig >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    match &= bit ? m : ~m;
+  }
+  const int lane = threadIdx.x & 63;
+  rank = __popcll(match & ((1ull << lane) - 1ull));
+  count = __popcll(match);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict__ sets, int n_sets,
+                                                      int pass, int src) {
+  __shared__ int hist[kWaves][kSortDigits];
+  const Elem e = locate(sets, n_sets);
+  const SortSet& S = sets[e.s];
+  for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
+  __syncthreads();
+  const uint32_t dig = e.active ? (S.key[src][e.i] >> (8 * pass)) & 0xffu : 0u;
+  int rank, count;
+  wave_rank(e.active, dig, rank, count);
+  if (e.active && rank == 0) hist[threadIdx.x >> 6][dig] = count;
+  __syncthreads();
+  for (int d = threadIdx.x; d < kSortDigits; d += kBlock) {
+    int tot = 0;
+    for (int w = 0; w < kWaves; ++w) tot += hist[w][d];
+    S.table[(int64_t)d * S.n_blocks + e.blk] = tot;
+  }
+}
+
+// Exclusive scan of v over the block's kBlock threads; *total receives the sum.
+__device__ inline int block_exclusive_scan(int v, int* total) {
+  __shared__ int wsum[kWaves];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int k = 0; k < kWaves; ++k) {
+    if (k < w) before += wsum[k];
+    all += wsum[k];
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+// One block per (set, digit): exclusive scan of that digit's per-block counts.
+__global__ __launch_bounds__(kBlock) void k_sort_rowscan(const SortSet* __restrict__ sets) {
+  const int s = blockIdx.x / kSortDigits, d = blockIdx.x % kSortDigits;
+  const SortSet& S = sets[s];
+  if (S.n_blocks == 0) return;  // block-uniform: a set without positions to sort
+  int32_t* row = S.table + (int64_t)d * S.n_blocks;
+  const int n = S.n_blocks;
+  const int per = (n + kBlock - 1) / kBlock;
+  const int b0 = min(n, (int)threadIdx.x * per), b1 = min(n, b0 + per);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += row[b];
+  int total;
+  int run = block_exclusive_scan(sum, &total);
+  for (int b = b0; b < b1; ++b) {
+    const int c = row[b];
+    row[b] = run;
+    run += c;
+  }
+  if (threadIdx.x == 0) S.rowsum[d] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restrict__ sets,
+                                                         int n_sets, int pass, int src) {
+  __shared__ int hist[kWaves][kSortDigits];
+  __shared__ int base[kSortDigits];
+  const Elem e = locate(sets, n_sets);
+  const SortSet& S = sets[e.s];
+  for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
+  // digit bases: exclusive scan of the digit totals (kBlock == kSortDigits)
+  int total;
+  base[threadIdx.x] = block_exclusive_scan(S.rowsum[threadIdx.x], &total);
+  __syncthreads();
+  const uint32_t k = e.active ? S.key[src][e.i] : 0u;
+  const uint32_t dig = (k >> (8 * pass)) & 0xffu;
+  int rank, count;
+  wave_rank(e.active, dig, rank, count);
+  const int w = threadIdx.x >> 6;
+  if (e.active && rank == 0) hist[w][dig] = count;
+  __syncthreads();
+  if (e.active) {
+    int before = 0;
+    for (int v = 0; v < w; ++v) before += hist[v][dig];
+    const int64_t pos = (int64_t)base[dig] + S.table[(int64_t)dig * S.n_blocks + e.blk] + before +
+                        rank;
+    if (pos >= 0 && pos < S.Q) {  // always true for consistent counts; never write outside
+      S.key[1 - src][pos] = k;
+      S.val[1 - src][pos] = S.val[src][e.i];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total_blocks,
+                               hipStream_t s) {
+  static_assert(kBlock == kSortDigits, "one thread per digit in the scans");
+  if (total_blocks <= 0 || n_sets <= 0) return hipSuccess;
+  const unsigned g = (unsigned)total_blocks;
+  k_sort_box<<<g, kBlock, 0, s>>>(d_sorts, n_sets);
+  k_sort_keys<<<g, kBlock, 0, s>>>(d_sorts, n_sets);
+  int src = 0;
+  for (int pass = 0; pass < kSortPasses; ++pass) {
+    k_sort_hist<<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src);
+    k_sort_rowscan<<<(unsigned)(n_sets * kSortDigits), kBlock, 0, s>>>(d_sorts);
+    k_sort_scatter<<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src);
+    src = 1 - src;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace aero
