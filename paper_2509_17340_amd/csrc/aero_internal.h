@@ -51,10 +51,10 @@ struct DevProblem {
   unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
 };
 
-// Spatial sort of one problem's rollout positions (stable LSD radix sort of a 24-bit
-// Morton key over the positions' bounding box, 3 passes of 8 bits).
+// Spatial sort of one problem's rollout positions (stable LSD radix sort on the top
+// 16 bits of a 24-bit Morton key over the positions' bounding box, 2 passes of 8 bits).
 constexpr int kSortDigits = 256;
-constexpr int kSortPasses = 3;
+constexpr int kSortPasses = 2;
 struct SortSet {
   const float* px;
   const float* py;

@@ -234,11 +234,23 @@ struct Cursor {
 
 int chunks_for(int64_t total_qblocks, int n_tiles) {
   // Fill the chip (about 4 workgroups per CU of 256) and keep chunks short
-  // enough (<= 16 tiles) that uneven problems load-balance.
+  // enough (<= 16 tiles) that uneven problems load-balance; among the counts up to
+  // twice that, take the one that splits the tiles most evenly (chunks are whole
+  // tiles, and the longest chunk sets the pass time).
   const int64_t target = 1024;
   int64_t c = (total_qblocks >= target) ? 1 : (target + total_qblocks - 1) / total_qblocks;
   c = std::max<int64_t>(c, (n_tiles + 15) / 16);
-  return (int)std::min<int64_t>(std::max<int64_t>(c, 1), std::max(n_tiles, 1));
+  c = std::min<int64_t>(std::max<int64_t>(c, 1), std::max(n_tiles, 1));
+  int64_t best = c, best_cost = INT64_MAX;
+  for (int64_t k = c; k <= std::min<int64_t>(2 * c, std::max(n_tiles, 1)); ++k) {
+    const int64_t per = (n_tiles + k - 1) / k;        // tiles of the longest chunk
+    const int64_t cost = per * 1024 + k;              // then prefer fewer chunks
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = k;
+    }
+  }
+  return (int)best;
 }
 
 // Split P points into about `want` chunks of a multiple of `align` points.

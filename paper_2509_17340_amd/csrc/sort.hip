@@ -4,7 +4,9 @@
 // record of which cloud tiles a block came near are only as tight as the block is
 // compact.  Positions of one (instance, step) are spread by the sampling noise, so
 // they are reordered along a Morton (Z-order) curve over their bounding box: a
-// stable LSD radix sort of a 24-bit key (8 bits per axis) in three passes of 8 bits.
+// stable LSD radix sort on the top 16 bits of a 24-bit key (8 bits per axis), in two
+// passes of 8 bits (cells of 1/32 of the box per axis; within a cell the original
+// order is kept).
 // Every pass ranks elements without atomics (ballots inside a wave, per-wave counts
 // in LDS, per-block counts scanned in digit-major order), so the permutation is
 // deterministic and the same for a problem alone or inside a batch.
@@ -19,6 +21,7 @@ namespace aero {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
+constexpr int kSortShift0 = 8;  // the key's lowest 8 bits are not sorted on
 
 // Order-preserving map of floats to unsigned integers and back.
 __device__ inline unsigned ord_bits(float f) {
@@ -90,11 +93,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_box(const SortSet* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sort_keys(const SortSet* __restrict__ sets,
-                                                      int n_sets) {
-  const Elem e = locate(sets, n_sets);
-  if (!e.active) return;
-  const SortSet& S = sets[e.s];
+// Morton key of an element from its position and the set's bounding box.
+__device__ inline uint32_t morton_key(const SortSet& S, int64_t i) {
   float lo[3], ext = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -102,15 +102,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const SortSet* __restrict_
     ext = fmaxf(ext, ord_float(S.box[3 + a]) - lo[a]);
   }
   const float scale = ext > 0.0f ? 255.99f / ext : 0.0f;
-  const float p[3] = {S.px[e.i], S.py[e.i], S.pz[e.i]};
+  const float p[3] = {S.px[i], S.py[i], S.pz[i]};
   uint32_t key = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float g = fminf(fmaxf((p[a] - lo[a]) * scale, 0.0f), 255.0f);
     key |= spread3((uint32_t)g) << a;
   }
-  S.key[0][e.i] = key;
-  S.val[0][e.i] = (int32_t)e.i;
+  return key;
 }
 
 // Rank of this lane's digit among the equal digits of lower lanes, and how many
@@ -135,7 +134,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
   const SortSet& S = sets[e.s];
   for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
   __syncthreads();
-  const uint32_t dig = e.active ? (S.key[src][e.i] >> (8 * pass)) & 0xffu : 0u;
+  uint32_t key = 0;
+  if (e.active) {
+    if (pass == 0) {  // the first pass also builds the keys
+      key = morton_key(S, e.i);
+      S.key[0][e.i] = key;
+      S.val[0][e.i] = (int32_t)e.i;
+    } else {
+      key = S.key[src][e.i];
+    }
+  }
+  const uint32_t dig = (key >> (kSortShift0 + 8 * pass)) & 0xffu;
   int rank, count;
   wave_rank(e.active, dig, rank, count);
   if (e.active && rank == 0) hist[threadIdx.x >> 6][dig] = count;
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
   base[threadIdx.x] = block_exclusive_scan(S.rowsum[threadIdx.x], &total);
   __syncthreads();
   const uint32_t k = e.active ? S.key[src][e.i] : 0u;
-  const uint32_t dig = (k >> (8 * pass)) & 0xffu;
+  const uint32_t dig = (k >> (kSortShift0 + 8 * pass)) & 0xffu;
   int rank, count;
   wave_rank(e.active, dig, rank, count);
   const int w = threadIdx.x >> 6;
@@ -228,7 +237,6 @@ hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total
   if (total_blocks <= 0 || n_sets <= 0) return hipSuccess;
   const unsigned g = (unsigned)total_blocks;
   k_sort_box<<<g, kBlock, 0, s>>>(d_sorts, n_sets);
-  k_sort_keys<<<g, kBlock, 0, s>>>(d_sorts, n_sets);
   int src = 0;
   for (int pass = 0; pass < kSortPasses; ++pass) {
     k_sort_hist<<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src);
