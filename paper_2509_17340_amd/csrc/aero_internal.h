@@ -65,7 +65,8 @@ struct SortSet {
   int32_t pad;
   unsigned* box;         // [6] order-preserving bits: min x, y, z, max x, y, z
   uint32_t* key[2];      // [Q] ping-pong keys
-  int32_t* val[2];       // [Q] ping-pong query indices; the result is val[1]
+  int32_t* val[2];       // [Q] ping-pong query indices; the result is
+                         //   val[kSortPasses % 2]
   int32_t* table;        // [kSortDigits][n_blocks] per-block digit counts -> offsets
   int32_t* rowsum;       // [kSortDigits] digit totals
 };

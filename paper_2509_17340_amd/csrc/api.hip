@@ -378,7 +378,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       so.table = cur.take<int32_t>((int64_t)kSortDigits * so.n_blocks);
       so.rowsum = cur.take<int32_t>(kSortDigits);
       sort_blocks += so.n_blocks;
-      qs.perm = so.val[1];
+      qs.perm = so.val[kSortPasses % 2];  // where the last pass leaves it
       d.sort_box = so.box;
     }
     qs.query_base = fb;
