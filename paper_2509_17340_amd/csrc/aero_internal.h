@@ -49,6 +49,8 @@ struct DevProblem {
   int32_t* nidx;         // optional [M][N][K] nearest point index (-1: none within reach)
   int32_t* work_count;   // pass-B work counter of the problem's query set (or nullptr)
   unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
+  double* noise;         // optional [M][N][4][K] standard normals drawn ahead of the rollout
+  int64_t elem_base;     // prefix of M*N*K over problems
 };
 
 // Spatial sort of one problem's rollout positions (stable LSD radix sort on the top
@@ -171,6 +173,8 @@ hipError_t launch_filter_cloud(const float* cloud, int n_points, const int32_t* 
 hipError_t launch_guides(const double p0[3], const double v0[3], const double a0[3],
                          const float* anchors, const float* end_vel, const float* end_acc,
                          double T, int M, float* coef, hipStream_t s);
+hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_samples,
+                                int64_t total_elems, const DevParams& prm, hipStream_t s);
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_samples,
                           const DevParams& prm, hipStream_t s);
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,

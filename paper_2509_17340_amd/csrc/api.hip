@@ -232,6 +232,9 @@ struct Cursor {
   }
 };
 
+// Fewest cloud tiles for which the positions are spatially sorted before pass A.
+constexpr int kSortMinTiles = 16;
+
 int chunks_for(int64_t total_qblocks, int n_tiles) {
   // Fill the chip (about 4 workgroups per CU of 256) and keep chunks short
   // enough (<= 16 tiles) that uneven problems load-balance; among the counts up to
@@ -276,6 +279,7 @@ struct MppiPlan {
   SortSet* d_sorts = nullptr;   // adjacent to d_sets: one descriptor upload
   int64_t total_samples = 0, total_rows = 0, total_blocks = 0, flag_blocks = 0, listed_items = 0;
   int64_t sort_blocks = 0;
+  int64_t total_elems = 0;      // sum of M*N*K (rollout noise draws)
   size_t bytes = 0;
 };
 
@@ -288,7 +292,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   pl.probs.assign(n, DevProblem{});
   pl.sets.assign(n, QuerySet{});
   pl.sorts.assign(n, SortSet{});
-  int64_t sort_blocks = 0;
+  int64_t sort_blocks = 0, eb = 0;
   const int qpbA = kPassAQPB[variant];
   int64_t qblocks = 0;
   for (int b = 0; b < n; ++b) {
@@ -322,8 +326,11 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     d.mind2 = q.min_dist2 ? reinterpret_cast<unsigned*>(q.min_dist2) : md;
     d.sample_base = sb;
     d.row_base = rb;
+    d.elem_base = eb;
+    d.noise = cur.take<double>(4 * MNK);
     sb += MK;
     rb += MN;
+    eb += MNK;
 
     QuerySet& qs = pl.sets[b];
     qs.px = d.pos;
@@ -364,7 +371,8 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     // spatial order of the positions for pass A
     SortSet& so = pl.sorts[b];
     so.block_base = sort_blocks;
-    if (two_pass) {
+    // the sort pays for itself only when there are enough cloud tiles to cull
+    if (two_pass && n_tiles >= kSortMinTiles) {
       so.px = qs.px;
       so.py = qs.py;
       so.pz = qs.pz;
@@ -391,6 +399,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   pl.flag_blocks = fb;
   pl.listed_items = items;
   pl.sort_blocks = sort_blocks;
+  pl.total_elems = eb;
   pl.bytes = cur.off;
 }
 
@@ -659,7 +668,9 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   // One staged copy for both descriptor arrays (they are adjacent in the workspace).
   hipError_t he = stage_mppi(pl, n, s);
   if (he == hipSuccess)
-    he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, n, pl.total_samples, prm, s); });
+    he = timed(AERO_K_ROLLOUT, s, [&] {
+      return launch_rollout_noise(pl.d_probs, n, pl.total_samples, pl.total_elems, prm, s);
+    });
   if (he == hipSuccess && pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
                [&] { return launch_spatial_sort(pl.d_sorts, n, pl.sort_blocks, s); });
@@ -729,7 +740,9 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   const int64_t MK = (int64_t)q.M * q.K, MN = (int64_t)q.M * q.N;
   hipError_t he = stage_mppi(pl, 1, s);
   if (he == hipSuccess)
-    he = timed(AERO_K_ROLLOUT, s, [&] { return launch_rollout(pl.d_probs, 1, pl.total_samples, prm, s); });
+    he = timed(AERO_K_ROLLOUT, s, [&] {
+      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, s);
+    });
   if (he == hipSuccess && pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
                [&] { return launch_spatial_sort(pl.d_sorts, 1, pl.sort_blocks, s); });

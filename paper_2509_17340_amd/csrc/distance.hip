@@ -119,6 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
   }
 }
 
+constexpr int kPassBSplit = 4;
+
 // One pass-B item: the flagged queries of query block qb (R per lane) against the
 // cloud tile [g0, g1).
 template <int R>
@@ -171,18 +173,21 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
   for (int s = 0; s < n_sets; ++s) {
     const QuerySet& Sref = sets[s];
     if (!Sref.list || Sref.n_points <= 0) continue;
-    const int64_t items = *Sref.work_count;
+    // each (query block, tile) entry is split into kPassBSplit sub-items of
+    // kTilePts / kPassBSplit points: more, shorter workgroups hide latency better
+    const int64_t items = (int64_t)*Sref.work_count * kPassBSplit;
     int64_t first = ((int64_t)blockIdx.x - item_base) % gridDim.x;
     if (first < 0) first += gridDim.x;
     if (items > 0) {
       const QuerySet S = Sref;
       for (int64_t it = first; it < items; it += gridDim.x) {
-        const int2 wk = S.work[it];
+        const int2 wk = S.work[it / kPassBSplit];
         const int64_t qb = wk.x;
         const int cnt = min(S.seg_count[qb], S.qpbA);
         if (cnt <= 0) continue;
-        const int64_t g0 = (int64_t)wk.y * kTilePts;
-        const int64_t g1 = min<int64_t>(g0 + kTilePts, S.n_points);
+        const int64_t g0 = (int64_t)wk.y * kTilePts + (it % kPassBSplit) * (kTilePts / kPassBSplit);
+        const int64_t g1 = min<int64_t>(g0 + kTilePts / kPassBSplit, S.n_points);
+        if (g0 >= g1) continue;
         const int nr = (cnt + kBlock - 1) / kBlock;
         if (nr == 1)
           listed_item<1>(S, qb, cnt, g0, g1, tile);
@@ -409,7 +414,8 @@ hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t max_items,
                                   hipStream_t s) {
   if (max_items > 0) {
-    const unsigned grid = (unsigned)(max_items < kPersistBlocks ? max_items : kPersistBlocks);
+    const int64_t sub = max_items * kPassBSplit;
+    const unsigned grid = (unsigned)(sub < kPersistBlocks ? sub : kPersistBlocks);
     k_min_dist_listed<<<grid, kBlock, 0, s>>>(d_sets, n_sets);
   }
   return hipGetLastError();

@@ -27,6 +27,25 @@ __device__ inline void load_rg(const float* qg, double Rg[9]) {
   rotmat(w, x, y, z, Rg);
 }
 
+// The rollout's standard normals for every (instance, step, sample), drawn in
+// parallel ahead of the sequential rollout (the same counter-based stream).
+__global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__ probs, int n,
+                                                  int64_t total, DevParams prm) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= total) return;
+  const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.elem_base; });
+  const DevProblem& P = probs[b];
+  if (!P.noise) return;
+  const int K = P.K, N = P.N;
+  const int64_t local = gid - P.elem_base;
+  const int64_t row = local / K;
+  const int k = (int)(local % K), m = (int)(row / N), t = (int)(row % N);
+  double nz[4];
+  normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) P.noise[(row * 4 + c) * K + k] = nz[c];
+}
+
 __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict__ probs, int n,
                                                     int64_t total, DevParams prm) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -63,9 +82,14 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
   double up[4] = {0.0, 0.0, 0.0, 0.0};
   for (int t = 0; t < N; ++t) {
     double nz[4];
-    normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
-    double u[4];
     const int64_t row = (int64_t)m * N + t;
+    if (P.noise) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) nz[c] = P.noise[(row * 4 + c) * K + k];
+    } else {
+      normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
+    }
+    double u[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double un = P.u_nom[row * 4 + c];
@@ -328,6 +352,13 @@ hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_samples,
+                                int64_t total_elems, const DevParams& prm, hipStream_t s) {
+  if (total_elems > 0) k_noise<<<grid1d(total_elems), kBlock, 0, s>>>(d_probs, n, total_elems, prm);
+  k_rollout<<<grid1d(total_samples), kBlock, 0, s>>>(d_probs, n, total_samples, prm);
+  return hipGetLastError();
 }
 
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
