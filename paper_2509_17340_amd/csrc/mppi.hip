@@ -80,19 +80,34 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
 
   double s_track = 0.0, s_vnorm = 0.0, s_u2 = 0.0, s_du2 = 0.0, s_goal = 0.0;
   double up[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int t = 0; t < N; ++t) {
-    double nz[4];
-    const int64_t row = (int64_t)m * N + t;
+  // the step's inputs (nominal control and normals) are loaded one step ahead, so
+  // that their memory latency overlaps the previous RK4 step
+  double nz_next[4], un_next[4];
+  auto fetch = [&](int t, double* nz, double* un) {
+    const int64_t r = (int64_t)m * N + t;
     if (P.noise) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) nz[c] = P.noise[(row * 4 + c) * K + k];
+      for (int c = 0; c < 4; ++c) nz[c] = P.noise[(r * 4 + c) * K + k];
     } else {
       normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) un[c] = P.u_nom[r * 4 + c];
+  };
+  fetch(0, nz_next, un_next);
+  for (int t = 0; t < N; ++t) {
+    double nz[4], unv[4];
+    const int64_t row = (int64_t)m * N + t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      nz[c] = nz_next[c];
+      unv[c] = un_next[c];
+    }
+    if (t + 1 < N) fetch(t + 1, nz_next, un_next);
     double u[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double un = P.u_nom[row * 4 + c];
+      const double un = unv[c];
       const double v = un + prm.sigma[c] * nz[c];
       u[c] = fmin(fmax(v, prm.u_min[c]), prm.u_max[c]);
       P.deff[(row * 4 + c) * K + k] = (float)(u[c] - un);
@@ -151,10 +166,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const DevProblem* __restric
   const int K = P.K, N = P.N;
   const int64_t local = gid - P.sample_base;
   const int m = (int)(local / K), k = (int)(local % K);
+  // phi vanishes from d_max on; sqrt is correctly rounded and d_max^2 is exact in
+  // binary64, so skipping d^2 >= d_max^2 changes no sum
+  const double dmax2 = prm.d_max * prm.d_max;
   double col = 0.0;
+#pragma unroll 8
   for (int t = 0; t < N; ++t) {
     const float d2 = __uint_as_float(P.mind2[((int64_t)m * N + t) * K + k]);
-    col += collision_phi(sqrt((double)d2), prm);
+    if ((double)d2 < dmax2) col += collision_phi(sqrt((double)d2), prm);
   }
   const int64_t i = (int64_t)m * K + k;
   P.S1[i] = P.S_smooth[i] + prm.w[4] * col;
@@ -232,11 +251,17 @@ __global__ __launch_bounds__(kBlock) void k_sel_rollout(const DevSelect* __restr
   double Rg[9];
   load_rg(P.qg, Rg);
   double s_goal = 0.0;
+  double u_next[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) u_next[c] = P.u_nom[(int64_t)m * N * 4 + c];
   for (int t = 0; t < N; ++t) {
     const int64_t row = (int64_t)m * N + t;
     double u[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) u[c] = P.u_nom[row * 4 + c];
+    for (int c = 0; c < 4; ++c) u[c] = u_next[c];
+    if (t + 1 < N)  // next step's control, loaded during this step
+#pragma unroll
+      for (int c = 0; c < 4; ++c) u_next[c] = P.u_nom[(row + 1) * 4 + c];
     rk4(x, u, prm.dt, dyn);
     P.pos[row] = (float)x[0];
     P.pos[MN + row] = (float)x[1];

@@ -59,16 +59,23 @@ __device__ inline Elem locate(const SortSet* sets, int n_sets) {
   return e;
 }
 
+// Bounding box: kBoxBlocks grid-strided workgroups per set, so that only a few
+// hundred atomics meet on the six words.
+constexpr int kBoxBlocks = 32;
+
 __global__ __launch_bounds__(kBlock) void k_sort_box(const SortSet* __restrict__ sets,
                                                      int n_sets) {
   __shared__ float red[6][kWaves];
-  const Elem e = locate(sets, n_sets);
-  const SortSet& S = sets[e.s];
+  const int s = blockIdx.x / kBoxBlocks, part = blockIdx.x % kBoxBlocks;
+  const SortSet& S = sets[s];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (e.active) {
-    const float p[3] = {S.px[e.i], S.py[e.i], S.pz[e.i]};
+  for (int64_t i = (int64_t)part * kBlock + threadIdx.x; i < S.Q; i += (int64_t)kBoxBlocks * kBlock) {
+    const float p[3] = {S.px[i], S.py[i], S.pz[i]};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = p[a];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], p[a]);
+      hi[a] = fmaxf(hi[a], p[a]);
+    }
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -81,15 +88,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_box(const SortSet* __restrict__
     }
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < 3 && S.Q > 0) {
     const int a = threadIdx.x;
     float l = red[a][0], h = red[3 + a][0];
     for (int k = 1; k < kWaves; ++k) {
       l = fminf(l, red[a][k]);
       h = fmaxf(h, red[3 + a][k]);
     }
-    atomicMin(S.box + a, ord_bits(l));
-    atomicMax(S.box + 3 + a, ord_bits(h));
+    if (l <= h) {  // a workgroup that saw no position leaves the box alone
+      atomicMin(S.box + a, ord_bits(l));
+      atomicMax(S.box + 3 + a, ord_bits(h));
+    }
   }
 }
 
@@ -236,7 +245,7 @@ hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total
   static_assert(kBlock == kSortDigits, "one thread per digit in the scans");
   if (total_blocks <= 0 || n_sets <= 0) return hipSuccess;
   const unsigned g = (unsigned)total_blocks;
-  k_sort_box<<<g, kBlock, 0, s>>>(d_sorts, n_sets);
+  k_sort_box<<<(unsigned)(n_sets * kBoxBlocks), kBlock, 0, s>>>(d_sorts, n_sets);
   int src = 0;
   for (int pass = 0; pass < kSortPasses; ++pass) {
     k_sort_hist<<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src);
