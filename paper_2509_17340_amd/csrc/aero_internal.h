@@ -49,7 +49,7 @@ struct DevProblem {
   int32_t* nidx;         // optional [M][N][K] nearest point index (-1: none within reach)
   int32_t* work_count;   // pass-B work counter of the problem's query set (or nullptr)
   unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
-  double* noise;         // optional [M][N][4][K] standard normals drawn ahead of the rollout
+  double* noise;         // [M][N][4][K] standard normals drawn ahead of the rollout
   int64_t elem_base;     // prefix of M*N*K over problems
 };
 

@@ -28,14 +28,14 @@ __device__ inline void load_rg(const float* qg, double Rg[9]) {
 }
 
 // The rollout's standard normals for every (instance, step, sample), drawn in
-// parallel ahead of the sequential rollout (the same counter-based stream).
+// parallel ahead of the sequential rollout (the same counter-based stream); also
+// resets the per-position distance outputs.
 __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__ probs, int n,
                                                   int64_t total, DevParams prm) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (gid >= total) return;
   const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.elem_base; });
   const DevProblem& P = probs[b];
-  if (!P.noise) return;
   const int K = P.K, N = P.N;
   const int64_t local = gid - P.elem_base;
   const int64_t row = local / K;
@@ -44,6 +44,9 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
 #pragma unroll
   for (int c = 0; c < 4; ++c) P.noise[(row * 4 + c) * K + k] = nz[c];
+  // per-position outputs of this call start empty
+  P.mind2[local] = kInfBits;
+  if (P.nidx) P.nidx[local] = -1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict__ probs, int n,
@@ -80,22 +83,41 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
 
   double s_track = 0.0, s_vnorm = 0.0, s_u2 = 0.0, s_du2 = 0.0, s_goal = 0.0;
   double up[4] = {0.0, 0.0, 0.0, 0.0};
-  // the step's inputs (nominal control and normals) are loaded one step ahead, so
-  // that their memory latency overlaps the previous RK4 step
+  // The step's inputs (nominal control and normals) are loaded one step ahead, so
+  // that their memory latency overlaps the previous RK4 step.
   double nz_next[4], un_next[4];
-  auto fetch = [&](int t, double* nz, double* un) {
+  auto fetch = [&](int t) {
     const int64_t r = (int64_t)m * N + t;
-    if (P.noise) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) nz[c] = P.noise[(r * 4 + c) * K + k];
-    } else {
-      normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
+    for (int c = 0; c < 4; ++c) {
+      nz_next[c] = P.noise[(r * 4 + c) * K + k];
+      un_next[c] = P.u_nom[r * 4 + c];
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) un[c] = P.u_nom[r * 4 + c];
   };
-  fetch(0, nz_next, un_next);
-  for (int t = 0; t < N; ++t) {
+  // Cost terms of the state reached at step t: guide error at (t+1) dt, speed and
+  // goal terms.  They are evaluated one step late, in the same straight-line code
+  // as the following RK4 step, so that the two independent dependency chains
+  // interleave; every sum still runs over t = 0 .. N-1 in order.
+  auto state_costs = [&](const double* xs, int t) {
+    const double tau = (double)(t + 1) * prm.dt;
+    double e2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double f = cf[a][5];
+#pragma unroll
+      for (int i = 4; i >= 0; --i) f = f * tau + cf[a][i];
+      const double e = xs[a] - f;
+      e2 += e * e;
+    }
+    s_track += sqrt(e2);
+    s_vnorm += xs[7] * xs[7] + xs[8] * xs[8] + xs[9] * xs[9];
+    s_goal += goal_term(xs, pg, vg, Rg, prm);
+  };
+  double xc[10];
+  // One step: perturbed, clipped control, its deviation, the RK4 update (the state
+  // before it kept in xc) and the control terms (u_t for t <= N-2, the change for
+  // 1 <= t <= N-2; predicated, so the body has no branches).
+  auto advance = [&](int t) {
     double nz[4], unv[4];
     const int64_t row = (int64_t)m * N + t;
 #pragma unroll
@@ -103,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
       nz[c] = nz_next[c];
       unv[c] = un_next[c];
     }
-    if (t + 1 < N) fetch(t + 1, nz_next, un_next);
+    fetch(t + 1 < N ? t + 1 : t);  // in bounds; unused after the last step
     double u[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -112,37 +134,28 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
       u[c] = fmin(fmax(v, prm.u_min[c]), prm.u_max[c]);
       P.deff[(row * 4 + c) * K + k] = (float)(u[c] - un);
     }
+#pragma unroll
+    for (int i = 0; i < 10; ++i) xc[i] = x[i];
     rk4(x, u, prm.dt, dyn);
     const int64_t qi = row * K + k;
     P.pos[qi] = (float)x[0];
     P.pos[MNK + qi] = (float)x[1];
     P.pos[2 * MNK + qi] = (float)x[2];
-    P.mind2[qi] = kInfBits;
-    if (P.nidx) P.nidx[qi] = -1;
-    // guide position f((t+1) dt) by Horner
-    const double tau = (double)(t + 1) * prm.dt;
-    double e2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double f = cf[a][5];
-#pragma unroll
-      for (int i = 4; i >= 0; --i) f = f * tau + cf[a][i];
-      const double e = x[a] - f;
-      e2 += e * e;
-    }
-    s_track += sqrt(e2);
-    s_vnorm += x[7] * x[7] + x[8] * x[8] + x[9] * x[9];
-    if (t <= N - 2) {
-      s_u2 += u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-      if (t >= 1) {
-        const double d0 = u[0] - up[0], d1 = u[1] - up[1], d2 = u[2] - up[2], d3 = u[3] - up[3];
-        s_du2 += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
-      }
-    }
-    s_goal += goal_term(x, pg, vg, Rg, prm);
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    const double d0 = u[0] - up[0], d1 = u[1] - up[1], d2 = u[2] - up[2], d3 = u[3] - up[3];
+    const double du2 = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+    s_u2 += t <= N - 2 ? u2 : 0.0;
+    s_du2 += (t >= 1 && t <= N - 2) ? du2 : 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) up[c] = u[c];
+  };
+  fetch(0);
+  advance(0);
+  for (int t = 1; t < N; ++t) {
+    advance(t);
+    state_costs(xc, t - 1);
   }
+  state_costs(x, N - 1);
   const double J_track = prm.Q_track * s_track;
   const double J_vnorm = prm.Q_vnorm * s_vnorm;
   const double J_ctrl = prm.Q_c * s_u2 + prm.Q_cdelta * s_du2;
@@ -254,21 +267,26 @@ __global__ __launch_bounds__(kBlock) void k_sel_rollout(const DevSelect* __restr
   double u_next[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) u_next[c] = P.u_nom[(int64_t)m * N * 4 + c];
+  double xc[10];
   for (int t = 0; t < N; ++t) {
     const int64_t row = (int64_t)m * N + t;
     double u[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) u[c] = u_next[c];
-    if (t + 1 < N)  // next step's control, loaded during this step
+    const int64_t nrow = t + 1 < N ? row + 1 : row;  // next step's control, loaded now
 #pragma unroll
-      for (int c = 0; c < 4; ++c) u_next[c] = P.u_nom[(row + 1) * 4 + c];
+    for (int c = 0; c < 4; ++c) u_next[c] = P.u_nom[nrow * 4 + c];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) xc[i] = x[i];
     rk4(x, u, prm.dt, dyn);
+    // goal term of the previous step's state, next to this RK4 step (sum order kept)
+    if (t > 0) s_goal += goal_term(xc, pg, vg, Rg, prm);
     P.pos[row] = (float)x[0];
     P.pos[MN + row] = (float)x[1];
     P.pos[2 * MN + row] = (float)x[2];
     P.mind2[row] = kInfBits;
-    s_goal += goal_term(x, pg, vg, Rg, prm);
   }
+  s_goal += goal_term(x, pg, vg, Rg, prm);
   P.goal_cost[m] = prm.w[3] * s_goal;
 }
 

@@ -61,7 +61,7 @@ __device__ inline Elem locate(const SortSet* sets, int n_sets) {
 
 // Bounding box: kBoxBlocks grid-strided workgroups per set, so that only a few
 // hundred atomics meet on the six words.
-constexpr int kBoxBlocks = 32;
+constexpr int kBoxBlocks = 128;
 
 __global__ __launch_bounds__(kBlock) void k_sort_box(const SortSet* __restrict__ sets,
                                                      int n_sets) {
