@@ -50,6 +50,7 @@ struct DevProblem {
   int32_t* work_count;   // pass-B work counter of the problem's query set (or nullptr)
   unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
   double* noise;         // [M][N][4][K] standard normals drawn ahead of the rollout
+  unsigned* out_slot;    // sorted query set's distances by slot (or nullptr)
   int64_t elem_base;     // prefix of M*N*K over problems
 };
 
@@ -104,7 +105,9 @@ struct QuerySet {
   int32_t qpbA;          // positions per pass-A block (the variant's block size)
   int32_t n_tiles;       // ceil(n_points / kTilePts); pass-A chunks are whole tiles
   float d_max;
-  const int32_t* perm;   // [Q] pass-A slot -> query, spatially sorted (nullptr: identity)
+  const int32_t* perm;   // [Q] slot -> query, spatially sorted (nullptr: identity)
+  unsigned* out_slot;    // two-pass sets: [Q] squared distances by slot (== out without
+                         //   a sort); scattered back to `out` once pass B is done
   unsigned long long* nn;  // optional [n_qblocks * qpbA]: pass B also keeps
                            // (d^2 bits << 32 | index) per list slot (lowest index on ties)
   int32_t* nidx;           // with nn: [Q] nearest index per query (-1 where not flagged)
@@ -184,6 +187,8 @@ hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t to
 hipError_t launch_min_dist_approx_matrix(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                          int variant, hipStream_t s);
 hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
+hipError_t launch_unpermute(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                            hipStream_t s);
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                   hipStream_t s);
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);

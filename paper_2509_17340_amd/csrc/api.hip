@@ -280,6 +280,7 @@ struct MppiPlan {
   int64_t total_samples = 0, total_rows = 0, total_blocks = 0, flag_blocks = 0, listed_items = 0;
   int64_t sort_blocks = 0;
   int64_t total_elems = 0;      // sum of M*N*K (rollout noise draws)
+  bool any_sorted = false;      // some set works in sorted slots (needs the unpermute)
   size_t bytes = 0;
 };
 
@@ -387,8 +388,12 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       so.rowsum = cur.take<int32_t>(kSortDigits);
       sort_blocks += so.n_blocks;
       qs.perm = so.val[kSortPasses % 2];  // where the last pass leaves it
+      qs.out_slot = cur.take<unsigned>(MNK);
       d.sort_box = so.box;
+      d.out_slot = qs.out_slot;
+      pl.any_sorted = true;
     }
+    if (!qs.out_slot) qs.out_slot = qs.out;
     qs.query_base = fb;
     fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
     items += two_pass ? (int64_t)qs.n_qblocks * n_tiles : 0;
@@ -685,6 +690,9 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   if (he == hipSuccess && pl.listed_items > 0)
     he = timed(AERO_K_MIN_DIST_EXACT, s,
                [&] { return launch_min_dist_listed(pl.d_sets, n, pl.listed_items, s); });
+  if (he == hipSuccess && pl.any_sorted)
+    he = timed(AERO_K_MIN_DIST_EXACT, s,
+               [&] { return launch_unpermute(pl.d_sets, n, pl.flag_blocks, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, n, pl.total_samples, prm, s); });
   if (he == hipSuccess)
@@ -755,6 +763,9 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   if (he == hipSuccess && pl.listed_items > 0)
     he = timed(AERO_K_MIN_DIST_EXACT, s,
                [&] { return launch_min_dist_listed(pl.d_sets, 1, pl.listed_items, s); });
+  if (he == hipSuccess && pl.any_sorted)
+    he = timed(AERO_K_MIN_DIST_EXACT, s,
+               [&] { return launch_unpermute(pl.d_sets, 1, pl.flag_blocks, s); });
   if (he == hipSuccess && q.n_points > 0)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, 1, s); });
   if (he == hipSuccess)

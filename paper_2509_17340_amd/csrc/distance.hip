@@ -134,8 +134,9 @@ __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64
   for (int r = 0; r < R; ++r) {
     const int j = r * kBlock + tid;
     const bool ok = j < cnt;
-    const int32_t q = S.list[lbase + (ok ? j : 0)];  // cnt >= 1: slot 0 exists
-    qi[r] = ok ? q : -1;
+    const int64_t slot = S.list[lbase + (ok ? j : 0)];  // cnt >= 1: entry 0 exists
+    const int64_t q = perm_query(S, slot);
+    qi[r] = ok ? (int32_t)slot : -1;
     px[r] = S.px[q];
     py[r] = S.py[q];
     pz[r] = S.pz[q];
@@ -149,7 +150,7 @@ __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (qi[r] >= 0) {
-        atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+        atomicMin(S.out_slot + qi[r], __float_as_uint(best[r]));
         atomicMin(S.nn + lbase + r * kBlock + tid,
                   ((unsigned long long)__float_as_uint(best[r]) << 32) |
                       (unsigned long long)(unsigned)bidx[r]);
@@ -158,7 +159,7 @@ __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64
     direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (qi[r] >= 0) atomicMin(S.out + qi[r], __float_as_uint(best[r]));
+      if (qi[r] >= 0) atomicMin(S.out_slot + qi[r], __float_as_uint(best[r]));
   }
 }
 
@@ -217,14 +218,12 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
   constexpr int R = kQueriesPerLane;
   float px[R], py[R], pz[R];
   bool ok[R];
-  int32_t qid[R];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t slot = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
     ok[r] = slot < S.Q;
     const int64_t qq = ok[r] ? perm_query(S, slot) : 0;
-    qid[r] = (int32_t)qq;
     px[r] = S.px[qq];
     py[r] = S.py[qq];
     pz[r] = S.pz[qq];
@@ -319,8 +318,10 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
     if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (ok[r]) atomicMin(S.out + qid[r], __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
+  for (int r = 0; r < R; ++r) {
+    const int64_t slot = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    if (ok[r]) atomicMin(S.out_slot + slot, __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
+  }
 }
 
 // Compact the queries of two-pass sets whose pass-A value is under the bound into
@@ -335,11 +336,9 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
   const QuerySet& S = sets[s];
   // pass-A slots in order; the query of a slot comes from the spatial sort
   const int64_t slot = (bid - S.query_base) * kBlock + threadIdx.x;
-  int64_t q = 0;
   bool flag = false;
   if (slot < S.Q) {
-    q = perm_query(S, slot);
-    const float d2 = __uint_as_float(S.out[q]);
+    const float d2 = __uint_as_float(S.out_slot[slot]);
     flag = d2 < S.thresh[slot / S.qpbA];
   }
   const uint64_t mask = __ballot(flag);
@@ -357,10 +356,10 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
   if (flag) {
     int off = base + before;
     for (int i = 0; i < w; ++i) off += wave_cnt[i];
-    const int64_t slot = qb * S.qpbA + off;
-    S.list[slot] = (int32_t)q;
-    S.out[q] = kInfBits;
-    if (S.nn) S.nn[slot] = ~0ull;
+    const int64_t e = qb * S.qpbA + off;
+    S.list[e] = (int32_t)slot;
+    S.out_slot[slot] = kInfBits;
+    if (S.nn) S.nn[e] = ~0ull;
   }
 }
 
@@ -378,12 +377,30 @@ __global__ __launch_bounds__(kBlock) void k_scatter_nearest(const QuerySet* __re
       if (i - qb * S.qpbA >= S.seg_count[qb]) continue;
       const unsigned long long v = S.nn[i];
       const unsigned idx = (unsigned)(v & 0xffffffffull);
-      S.nidx[S.list[i]] = (v == ~0ull || idx >= (unsigned)S.n_points) ? -1 : (int32_t)idx;
+      S.nidx[perm_query(S, S.list[i])] =
+          (v == ~0ull || idx >= (unsigned)S.n_points) ? -1 : (int32_t)idx;
     }
   }
 }
 
+// Distances by slot back to the positions' own layout (sorted sets only).
+__global__ __launch_bounds__(kBlock) void k_unpermute(const QuerySet* __restrict__ sets,
+                                                      int n_sets) {
+  const int64_t bid = blockIdx.x;
+  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.query_base; });
+  const QuerySet& S = sets[s];
+  if (!S.perm) return;
+  const int64_t slot = (bid - S.query_base) * kBlock + threadIdx.x;
+  if (slot < S.Q) S.out[perm_query(S, slot)] = S.out_slot[slot];
+}
+
 }  // namespace
+
+hipError_t launch_unpermute(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
+                            hipStream_t s) {
+  if (total_blocks > 0) k_unpermute<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+  return hipGetLastError();
+}
 
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                            hipStream_t s) {

@@ -41,14 +41,14 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
   const int col = lane & 15, kg = lane >> 4;
   float px[kMfmaCols], py[kMfmaCols], pz[kMfmaCols];
   bool ok[kMfmaCols];
-  int32_t qid[kMfmaCols];
+  int32_t sid[kMfmaCols];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int b = 0; b < kMfmaCols; ++b) {
     const int64_t slot = (int64_t)qb * kMfmaQPB + w * (16 * kMfmaCols) + b * 16 + col;
     ok[b] = slot < S.Q;
     const int64_t qq = ok[b] ? perm_query(S, slot) : 0;
-    qid[b] = (int32_t)qq;
+    sid[b] = (int32_t)slot;
     px[b] = S.px[qq];
     py[b] = S.py[qq];
     pz[b] = S.pz[qq];
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
     float v = tmin[b];
     v = fminf(v, __shfl_xor(v, 16, 64));
     v = fminf(v, __shfl_xor(v, 32, 64));
-    if (ok[b] && kg == 0) atomicMin(S.out + qid[b], __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
+    if (ok[b] && kg == 0) atomicMin(S.out_slot + sid[b], __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
   }
 }
 
@@ -187,14 +187,14 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet*
   const int col = lane & 31, kh = lane >> 5;
   float px[kF16Cols], py[kF16Cols], pz[kF16Cols];
   bool ok[kF16Cols];
-  int32_t qid[kF16Cols];
+  int32_t sid[kF16Cols];
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int b = 0; b < kF16Cols; ++b) {
     const int64_t slot = (int64_t)qb * kF16QPB + w * (32 * kF16Cols) + b * 32 + col;
     ok[b] = slot < S.Q;
     const int64_t qq = ok[b] ? perm_query(S, slot) : 0;
-    qid[b] = (int32_t)qq;
+    sid[b] = (int32_t)slot;
     px[b] = S.px[qq];
     py[b] = S.py[qq];
     pz[b] = S.pz[qq];
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet*
   for (int b = 0; b < kF16Cols; ++b) {
     float v = tmin[b];
     v = fminf(v, __shfl_xor(v, 32, 64));   // the two lane halves hold different rows
-    if (ok[b] && kh == 0) atomicMin(S.out + qid[b], __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
+    if (ok[b] && kh == 0) atomicMin(S.out_slot + sid[b], __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
   }
 }
 

@@ -46,6 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   for (int c = 0; c < 4; ++c) P.noise[(row * 4 + c) * K + k] = nz[c];
   // per-position outputs of this call start empty
   P.mind2[local] = kInfBits;
+  if (P.out_slot) P.out_slot[local] = kInfBits;
   if (P.nidx) P.nidx[local] = -1;
 }
 
