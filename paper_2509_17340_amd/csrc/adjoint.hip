@@ -28,8 +28,13 @@ constexpr int kSeg = 8;  // checkpoint interval (steps)
 __device__ inline void control_at(const DevParams& prm, const DevProblem& P, int m, int k, int t,
                                   double u[4], bool mask[4]) {
   double nz[4];
-  normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
   const int64_t row = (int64_t)m * P.N + t;
+  if (P.noise) {  // the normals the rollout drew (same counters, same values)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nz[c] = P.noise[(row * 4 + c) * P.K + k];
+  } else {
+    normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
+  }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const double v = (double)P.u_nom[row * 4 + c] + prm.sigma[c] * nz[c];
@@ -347,10 +352,16 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // Blocks 0 .. rows-1: one (instance, step) row each; block `rows`: the weights.
+// Sums over samples in a fixed order.  Blocks [0, rows) reduce one (instance, step)
+// row of the per-sample control gradients; blocks [rows, rows + 5 kWParts) each sum
+// one fixed slice of one cost term for the weight gradient, finished by
+// k_grad_w_final in slice order.
+constexpr int kWParts = 64;
+
 __global__ __launch_bounds__(kBlock) void k_grad_reduce(const DevProblem* __restrict__ prob,
                                                         int64_t rows, const double* gsamp,
                                                         double scale, float* grad_u,
-                                                        float* grad_w) {
+                                                        double* wpart) {
   __shared__ double sh[4];
   const DevProblem& P = *prob;
   const int K = P.K;
@@ -364,14 +375,24 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(const DevProblem* __rest
       if (threadIdx.x == 0) grad_u[row * 4 + c] = (float)(scale * acc);
     }
   } else {
+    const int64_t j = (int64_t)blockIdx.x - rows;
+    const int i = (int)(j / kWParts), part = (int)(j % kWParts);
     const int64_t MK = (int64_t)P.M * K;
-    for (int i = 0; i < 5; ++i) {
-      double acc = 0.0;
-      for (int64_t j = threadIdx.x; j < MK; j += kBlock) acc += P.J[i * MK + j];
-      acc = block_sum(acc, sh);
-      if (threadIdx.x == 0) grad_w[i] = (float)(scale * acc);
-    }
+    const int64_t per = (MK + kWParts - 1) / kWParts;
+    const int64_t a = part * per, b = min<int64_t>(MK, a + per);
+    double acc = 0.0;
+    for (int64_t q = a + threadIdx.x; q < b; q += kBlock) acc += P.J[i * MK + q];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) wpart[i * kWParts + part] = acc;
   }
+}
+
+__global__ void k_grad_w_final(const double* wpart, double scale, float* grad_w) {
+  const int i = threadIdx.x;
+  if (i >= 5) return;
+  double acc = 0.0;
+  for (int p = 0; p < kWParts; ++p) acc += wpart[i * kWParts + p];
+  grad_w[i] = (float)(scale * acc);
 }
 
 }  // namespace
@@ -385,11 +406,14 @@ hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_
 
 hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, int64_t rows,
                               const double* gsamp, double scale, float* grad_u, float* grad_w,
-                              hipStream_t s) {
+                              double* wpart, hipStream_t s) {
   (void)prm;
-  k_grad_reduce<<<(unsigned)(rows + 1), kBlock, 0, s>>>(d_prob, rows, gsamp, scale, grad_u,
-                                                        grad_w);
+  k_grad_reduce<<<(unsigned)(rows + 5 * kWParts), kBlock, 0, s>>>(d_prob, rows, gsamp, scale,
+                                                                  grad_u, wpart);
+  k_grad_w_final<<<1, 64, 0, s>>>(wpart, scale, grad_w);
   return hipGetLastError();
 }
+
+size_t grad_w_parts() { return 5 * kWParts; }
 
 }  // namespace aero

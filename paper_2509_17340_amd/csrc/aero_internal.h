@@ -196,7 +196,8 @@ hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_
                           double* ckpt, double* seg, double* gsamp, hipStream_t s);
 hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, int64_t rows,
                               const double* gsamp, double scale, float* grad_u, float* grad_w,
-                              hipStream_t s);
+                              double* wpart, hipStream_t s);
+size_t grad_w_parts();  // doubles of the weight-gradient partial sums
 hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_samples,
                            const DevParams& prm, hipStream_t s);
 hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,

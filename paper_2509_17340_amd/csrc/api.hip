@@ -427,6 +427,7 @@ struct BackwardPlan {
   double* ckpt = nullptr;
   double* seg = nullptr;
   double* gsamp = nullptr;
+  double* wpart = nullptr;
   size_t bytes = 0;
 };
 
@@ -445,6 +446,7 @@ void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& b
   bp.ckpt = cur.take<double>(n_seg * 10 * MK);
   bp.seg = cur.take<double>(8 * 10 * MK);
   bp.gsamp = cur.take<double>(MNK * 4);
+  bp.wpart = cur.take<double>(grad_w_parts());
   bp.bytes = cur.off;
   if (ws) {
     DevProblem& d = bp.fwd.probs[0];
@@ -777,7 +779,7 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   if (he == hipSuccess)
     he = timed(AERO_K_GRAD_REDUCE, s, [&] {
       return launch_grad_reduce(pl.d_probs, prm, MN, bp.gsamp, (double)scale, d_grad_u_nom,
-                                d_grad_w, s);
+                                d_grad_w, bp.wpart, s);
     });
   return dev_status(he);
 }
