@@ -106,7 +106,10 @@ def cpu_baseline(prob, samples_per_instance=32):
 
 
 def bench_adjoint(prob, iters=20):
-    """Forward (one Stage-I call) vs backward (aero_mppi_step_backward), same GPU."""
+    """Forward vs backward on the same GPU.  The forward is one Stage-I call that also
+    stores the nearest point of every rollout position; the backward is
+    aero_mppi_step_backward_indexed from those indices (no distance pass).  The
+    self-contained aero_mppi_step_backward (its own distance passes) is timed too."""
     import torch
 
     import paper_2509_17340_amd as aero
@@ -115,20 +118,28 @@ def bench_adjoint(prob, iters=20):
     ps = PlanStep(prob)
     ps.front_end()
     M, K, N = prob["M"], prob["K"], prob["N"]
-    pr = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], ps.u_nom, coef=ps.coef,
-                      v_goal=prob["v_goal"], q_goal=prob["q_goal"])
-    ws = torch.empty(aero.workspace_size(aero.CALL_BACKWARD, [pr]), dtype=torch.uint8,
+    nidx = torch.empty((M, N, K), dtype=torch.int32, device="cuda")
+    u_work = ps.u_nom.clone()
+    fwd = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], u_work, coef=ps.coef,
+                       v_goal=prob["v_goal"], q_goal=prob["q_goal"], S1=ps.S1, nearest_idx=nidx)
+    bwd = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], ps.u_nom, coef=ps.coef,
+                       v_goal=prob["v_goal"], q_goal=prob["q_goal"], nearest_idx=nidx)
+    plain = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], ps.u_nom, coef=ps.coef,
+                         v_goal=prob["v_goal"], q_goal=prob["q_goal"])
+    ws = torch.empty(max(aero.workspace_size(aero.CALL_BACKWARD, [bwd]),
+                         aero.workspace_size(aero.CALL_MPPI_STEP, [fwd])), dtype=torch.uint8,
                      device="cuda")
     gu = torch.empty((M, N, 4), dtype=torch.float32, device="cuda")
     gw = torch.empty(5, dtype=torch.float32, device="cuda")
     res = {}
-    for name in ("forward", "backward"):
-        def once():
-            if name == "forward":
-                ps.reset()
-                ps.stage1()
-            else:
-                aero.mppi_step_backward(prob["params"], pr, 1.0, gu, gw, ws)
+    legs = {
+        "forward": lambda: (u_work.copy_(ps.u_nom), aero.mppi_step(prob["params"], [fwd], ws)),
+        "backward": lambda: aero.mppi_step_backward_indexed(prob["params"], bwd, 1.0, gu, gw, ws),
+        "backward_self_contained": lambda: aero.mppi_step_backward(prob["params"], plain, 1.0, gu,
+                                                                   gw, ws),
+    }
+    for name in ("forward", "backward", "backward_self_contained"):
+        once = legs[name]
         for _ in range(3):
             once()
         torch.cuda.synchronize()
@@ -140,8 +151,10 @@ def bench_adjoint(prob, iters=20):
         torch.cuda.synchronize()
         res[name + "_ms"] = e0.elapsed_time(e1) / iters
     res["backward_over_forward"] = res["backward_ms"] / res["forward_ms"]
+    res["self_contained_backward_over_forward"] = res["backward_self_contained_ms"] / res["forward_ms"]
     res["workload"] = (f"gradient of sum S1 w.r.t. u_nom [{M}][{N}][4] and the 5 weights, "
-                       f"same inputs as the headline step (checkpoints every 8 steps)")
+                       f"same inputs as the headline step (checkpoints every 8 steps); the forward "
+                       f"stores nearest indices, the backward reads them")
     return res
 
 

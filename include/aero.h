@@ -90,11 +90,14 @@ typedef struct aero_problem {
   double* S1;           /* optional device [M][K]: Stage-I cost of every sample     */
   float* delta_eff;     /* optional device [M][N][4][K]: clipped perturbations      */
   float* min_dist2;     /* optional device [M][N][K]: squared nearest distance; exact  *
-                         * wherever it is below about d_max^2, elsewhere only a value *
-                         * known to be >= d_max^2                                     */
-  int32_t* nearest_idx; /* optional device [M][N][K], aero_mppi_step_backward only:   *
-                         * nearest cloud point (lowest index on ties) of positions    *
-                         * within reach of d_max, -1 elsewhere                        */
+                         * wherever it is below d_max^2, elsewhere only a value known *
+                         * to be >= d_max^2                                           */
+  int32_t* nearest_idx; /* optional device [M][N][K]: written by aero_mppi_step and    *
+                         * aero_mppi_step_backward, read by                           *
+                         * aero_mppi_step_backward_indexed: the nearest cloud point   *
+                         * (lowest index on ties) of every position closer than      *
+                         * d_max; -1 or an index of a point at least d_max away       *
+                         * elsewhere                                                  */
 } aero_problem;
 
 /* Angular grid of the multi-resolution partition (Sec. IV-A). */
@@ -221,6 +224,17 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h_problems,
 int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h_problem,
                             float scale, float* d_grad_u_nom, float* d_grad_w, void* d_ws,
                             size_t ws_bytes, void* stream);
+
+/* The same adjoint from nearest indices stored by a previous aero_mppi_step on the
+ * same problem (same u_nom, cloud, guides and parameters; the step's in-place update of
+ * u_nom must be undone or have been made on a copy): h_problem->nearest_idx is read,
+ * not written, and no distance pass runs (the collision terms use the stored point).
+ * Gradients equal those of aero_mppi_step_backward bit for bit when the indices came
+ * from that step.  Workspace: aero_workspace_size(AERO_CALL_BACKWARD, ...).
+ * Errors: as aero_mppi_step_backward; AERO_ERR_NULL if nearest_idx is null. */
+int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem* h_problem,
+                                    float scale, float* d_grad_u_nom, float* d_grad_w,
+                                    void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---- receding horizon ----------------------------------------------------------- */
 

@@ -20,7 +20,7 @@ __all__ = [
     "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
     "KERNELS", "shift_controls", "step_candidates", "set_pass_a_variant", "pass_a_variant",
-    "use_library", "accumulate_cloud", "advance_state",
+    "use_library", "accumulate_cloud", "advance_state", "mppi_step_backward_indexed",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -84,6 +84,8 @@ _SIGS = {
     "aero_select_best": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     "aero_mppi_step_backward": (ctypes.c_int, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_size_t,
                                                _P]),
+    "aero_mppi_step_backward_indexed": (ctypes.c_int, [_P, _P, ctypes.c_float, _P, _P, _P,
+                                                       ctypes.c_size_t, _P]),
     "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "aero_set_pass_a_variant": (ctypes.c_int, [ctypes.c_int]),
     "aero_shift_controls": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
@@ -391,3 +393,15 @@ def mppi_step_backward(prm, problem, scale, grad_u_nom, grad_w, ws, ws_bytes=Non
     _check(_lib.aero_mppi_step_backward(ctypes.byref(p), ctypes.byref(s), float(scale),
                                         _ptr(grad_u_nom), _ptr(grad_w), _ptr(ws), nbytes,
                                         _stream(stream)), "aero_mppi_step_backward")
+
+
+def mppi_step_backward_indexed(prm, problem, scale, grad_u_nom, grad_w, ws, ws_bytes=None,
+                               stream=None):
+    """Adjoint from the nearest indices a previous mppi_step stored in
+    problem.nearest_idx (read here); see aero_mppi_step_backward_indexed."""
+    p = params_struct(prm) if isinstance(prm, dict) else prm
+    s = problem.struct()
+    nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.aero_mppi_step_backward_indexed(ctypes.byref(p), ctypes.byref(s), float(scale),
+                                                _ptr(grad_u_nom), _ptr(grad_w), _ptr(ws), nbytes,
+                                                _stream(stream)), "aero_mppi_step_backward_indexed")

@@ -2,15 +2,18 @@
 
     L = StageOneCost.apply(u_nom, w, step)    # L = sum_{m,k} S1[m,k]
 
-forward runs aero_mppi_step on a copy of u_nom (the input is not modified) and
-returns the summed cost; backward runs aero_mppi_step_backward with the upstream
-gradient as `scale` and returns dL/du_nom and dL/dw.  Both directions are single
-library calls; this module only moves pointers and scalars.
+forward runs aero_mppi_step on a copy of u_nom (the input is not modified),
+storing the nearest cloud point of every rollout position, and returns the summed
+cost; backward runs aero_mppi_step_backward_indexed from those indices (no distance
+pass) with the upstream gradient as `scale` and returns dL/du_nom and dL/dw.  Both
+directions are single library calls; this module only moves pointers and scalars.
+One context serves one forward/backward pair at a time (the indices are its own).
 """
 import numpy as np
 import torch
 
-from . import CALL_BACKWARD, CALL_MPPI_STEP, Problem, mppi_step, mppi_step_backward, workspace_size
+from . import (CALL_BACKWARD, CALL_MPPI_STEP, Problem, mppi_step, mppi_step_backward_indexed,
+               workspace_size)
 
 
 class StageOneContext:
@@ -26,7 +29,7 @@ class StageOneContext:
         dev = cloud.device
         self.S1 = torch.empty((M, K), dtype=torch.float64, device=dev)
         self.nearest_idx = torch.empty((M, N, K), dtype=torch.int32, device=dev)
-        p = self._problem(torch.empty((M, N, 4), dtype=torch.float32, device=dev))
+        p = self._problem(torch.empty((M, N, 4), dtype=torch.float32, device=dev), with_idx=True)
         ws = max(workspace_size(CALL_MPPI_STEP, [p]), workspace_size(CALL_BACKWARD, [p]))
         self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
 
@@ -47,7 +50,7 @@ class StageOneCost(torch.autograd.Function):
     def forward(ctx, u_nom, w, sc):
         u = u_nom.detach().to(torch.float32).contiguous().clone()
         prm = sc.params_with(w)
-        mppi_step(prm, [sc._problem(u)], sc.ws)
+        mppi_step(prm, [sc._problem(u, with_idx=True)], sc.ws)
         ctx.save_for_backward(u_nom.detach().to(torch.float32).contiguous(), w.detach())
         ctx.sc = sc
         return sc.S1.sum()
@@ -58,6 +61,6 @@ class StageOneCost(torch.autograd.Function):
         sc = ctx.sc
         gu = torch.empty_like(u_nom)
         gw = torch.empty(5, dtype=torch.float32, device=u_nom.device)
-        mppi_step_backward(sc.params_with(w), sc._problem(u_nom, with_idx=True), float(gL), gu, gw,
-                           sc.ws)
+        mppi_step_backward_indexed(sc.params_with(w), sc._problem(u_nom, with_idx=True), float(gL),
+                                   gu, gw, sc.ws)
         return gu, gw.to(w.dtype), None

@@ -51,6 +51,7 @@ struct DevProblem {
   unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
   double* noise;         // [M][N][4][K] standard normals drawn ahead of the rollout
   unsigned* out_slot;    // sorted query set's distances by slot (or nullptr)
+  const int32_t* nidx_in;  // nearest indices given by the caller (indexed adjoint)
   int64_t elem_base;     // prefix of M*N*K over problems
 };
 
@@ -194,6 +195,8 @@ hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t to
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s);
+hipError_t launch_col_from_nearest(const DevProblem* d_prob, const DevParams& prm,
+                                   int64_t samples, hipStream_t s);
 hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, int64_t rows,
                               const double* gsamp, double scale, float* grad_u, float* grad_w,
                               double* wpart, hipStream_t s);

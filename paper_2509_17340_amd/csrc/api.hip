@@ -281,11 +281,12 @@ struct MppiPlan {
   int64_t sort_blocks = 0;
   int64_t total_elems = 0;      // sum of M*N*K (rollout noise draws)
   bool any_sorted = false;      // some set works in sorted slots (needs the unpermute)
+  bool any_nn = false;          // some set records nearest indices
   size_t bytes = 0;
 };
 
 void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl,
-               int variant = kPassAValu) {
+               int variant = kPassAValu, bool track_nearest = false) {
   Cursor cur{ws};
   pl.d_probs = cur.take<DevProblem>(n);
   pl.d_sets = cur.take<QuerySet>(n);
@@ -394,6 +395,15 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       pl.any_sorted = true;
     }
     if (!qs.out_slot) qs.out_slot = qs.out;
+    // nearest indices requested by the caller of a forward step
+    if (track_nearest && q.nearest_idx) {
+      d.nidx = q.nearest_idx;  // reset to -1 by the noise kernel
+      if (two_pass) {
+        qs.nn = cur.take<unsigned long long>(MNK + kQueriesPerBlock);
+        qs.nidx = q.nearest_idx;
+        pl.any_nn = true;
+      }
+    }
     qs.query_base = fb;
     fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
     items += two_pass ? (int64_t)qs.n_qblocks * n_tiles : 0;
@@ -584,7 +594,7 @@ size_t aero_workspace_size(int which, const aero_problem* h, int32_t n) {
     if (h[b].M < 1 || h[b].K < 1 || h[b].N < 2 || h[b].n_points < 0) return 0;
   if (which == AERO_CALL_MPPI_STEP) {
     MppiPlan pl;
-    plan_mppi(h, n, nullptr, 1.0f, pl);
+    plan_mppi(h, n, nullptr, 1.0f, pl, kPassAValu, true);
     return pl.bytes;
   }
   if (which == AERO_CALL_BACKWARD) {
@@ -665,12 +675,12 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   e = check_problems(h, n, true);
   if (e) return e;
   MppiPlan pl;
-  plan_mppi(h, n, nullptr, h_prm->d_max, pl);
+  plan_mppi(h, n, nullptr, h_prm->d_max, pl, kPassAValu, true);
   if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
   const hipStream_t s = (hipStream_t)stream;
   hipEvent_t* tev = nullptr;
   const int variant = pick_variant(tune_key(h, n), s, &tev);
-  plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl, variant);
+  plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl, variant, true);
   const DevParams prm = promote(*h_prm);
   // One staged copy for both descriptor arrays (they are adjacent in the workspace).
   hipError_t he = stage_mppi(pl, n, s);
@@ -695,6 +705,8 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   if (he == hipSuccess && pl.any_sorted)
     he = timed(AERO_K_MIN_DIST_EXACT, s,
                [&] { return launch_unpermute(pl.d_sets, n, pl.flag_blocks, s); });
+  if (he == hipSuccess && pl.any_nn)
+    he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, n, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, n, pl.total_samples, prm, s); });
   if (he == hipSuccess)
@@ -772,6 +784,50 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, 1, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, 1, MK, prm, s); });
+  if (he == hipSuccess)
+    he = timed(AERO_K_ADJOINT, s, [&] {
+      return launch_adjoint(pl.d_probs, prm, MK, bp.ckpt, bp.seg, bp.gsamp, s);
+    });
+  if (he == hipSuccess)
+    he = timed(AERO_K_GRAD_REDUCE, s, [&] {
+      return launch_grad_reduce(pl.d_probs, prm, MN, bp.gsamp, (double)scale, d_grad_u_nom,
+                                d_grad_w, bp.wpart, s);
+    });
+  return dev_status(he);
+}
+
+int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem* h, float scale,
+                                    float* d_grad_u_nom, float* d_grad_w, void* d_ws,
+                                    size_t ws_bytes, void* stream) {
+  int e = check_params(h_prm);
+  if (e) return e;
+  e = check_problems(h, 1, true);
+  if (e) return e;
+  if (!d_grad_u_nom || !d_grad_w || !h[0].nearest_idx) return AERO_ERR_NULL;
+  if (!finite(scale)) return AERO_ERR_PARAM;
+  BackwardPlan bp;
+  plan_backward(h, nullptr, h_prm->d_max, bp);
+  if (!d_ws || ws_bytes < bp.bytes) return AERO_ERR_WORKSPACE;
+  plan_backward(h, (char*)d_ws, h_prm->d_max, bp);
+  MppiPlan& pl = bp.fwd;
+  // the stored indices are an input: nothing resets or rewrites them
+  DevProblem& dp = pl.probs[0];
+  dp.nidx = nullptr;
+  dp.nidx_in = h[0].nearest_idx;
+  pl.sets[0].nn = nullptr;
+  pl.sets[0].nidx = nullptr;
+  const hipStream_t s = (hipStream_t)stream;
+  const DevParams prm = promote(*h_prm);
+  const aero_problem& q = h[0];
+  const int64_t MK = (int64_t)q.M * q.K, MN = (int64_t)q.M * q.N;
+  hipError_t he = stage_mppi(pl, 1, s);
+  if (he == hipSuccess)
+    he = timed(AERO_K_ROLLOUT, s, [&] {
+      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, s);
+    });
+  if (he == hipSuccess)
+    he = timed(AERO_K_FINALIZE, s,
+               [&] { return launch_col_from_nearest(pl.d_probs, prm, MK, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_ADJOINT, s, [&] {
       return launch_adjoint(pl.d_probs, prm, MK, bp.ckpt, bp.seg, bp.gsamp, s);

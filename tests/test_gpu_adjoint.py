@@ -121,3 +121,48 @@ def test_backward_identical_across_pass_a_variants():
             aero.set_pass_a_variant(-1)
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+@pytest.mark.parametrize("which", ["plain", "ensemble", "ragged"])
+def test_indexed_backward_matches_full(which):
+    """A forward step that stores nearest indices, then the adjoint from those
+    indices (no distance pass): the same indices and bit-identical gradients as the
+    self-contained adjoint."""
+    if which == "plain":
+        prob = make_plain_problem()
+    elif which == "ensemble":
+        prob = make_ensemble_problem()
+    else:
+        rng = np.random.default_rng(5)
+        prob = dict(make_plain_problem())
+        prob.update(M=2, K=37, N=9, M_h=2, M_v=1)
+        th = rng.uniform(-np.pi, np.pi, 600)
+        prob["cloud"] = np.stack([1.5 + 0.3 * np.cos(th), 0.4 + 0.3 * np.sin(th),
+                                  rng.uniform(-1, 2, 600)], 1).astype(np.float32)
+        prob["x0"] = np.float32([0, 0, 0, 1, 0, 0, 0, 2.0, 0.3, 0.0])
+        prob["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(2, 9, 4)) * 0.3).astype(np.float32)
+        prob["anchors"] = (rng.normal(size=(2, 3)) * 2 + np.float32([4, 0, 0])).astype(np.float32)
+    print(f"indexed adjoint: {which}", flush=True)
+    gu_full, gw_full, nidx_full, _ = gpu_backward(prob, scale=0.5)
+    ps = PlanStep(prob)
+    ps.front_end()
+    M, K, N = prob["M"], prob["K"], prob["N"]
+    nidx = torch.full((M, N, K), -7, dtype=torch.int32, device="cuda")
+    u_copy = ps.u_nom.clone()
+    fwd = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], u_copy, coef=ps.coef,
+                       v_goal=prob["v_goal"], q_goal=prob["q_goal"], nearest_idx=nidx,
+                       problem_id=prob.get("problem_id", 0))
+    ws = torch.empty(max(aero.workspace_size(aero.CALL_MPPI_STEP, [fwd]),
+                         aero.workspace_size(aero.CALL_BACKWARD, [fwd])), dtype=torch.uint8, device="cuda")
+    aero.mppi_step(prob["params"], [fwd], ws)
+    bwd = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], ps.u_nom, coef=ps.coef,
+                       v_goal=prob["v_goal"], q_goal=prob["q_goal"], nearest_idx=nidx,
+                       problem_id=prob.get("problem_id", 0))
+    gu = torch.empty((M, N, 4), dtype=torch.float32, device="cuda")
+    gw = torch.empty(5, dtype=torch.float32, device="cuda")
+    aero.mppi_step_backward_indexed(prob["params"], bwd, 0.5, gu, gw, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(np.transpose(nidx.cpu().numpy(), (0, 2, 1)), nidx_full)
+    assert np.array_equal(gu.cpu().numpy().astype(np.float64), gu_full)
+    assert np.array_equal(gw.cpu().numpy().astype(np.float64), gw_full)
+    assert np.array_equal(ps.u_nom.cpu().numpy(), prob["u_nom"])
