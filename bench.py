@@ -127,6 +127,7 @@ def bench_adjoint(prob, iters=20):
     plain = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], ps.u_nom, coef=ps.coef,
                          v_goal=prob["v_goal"], q_goal=prob["q_goal"])
     ws = torch.empty(max(aero.workspace_size(aero.CALL_BACKWARD, [bwd]),
+                         aero.workspace_size(aero.CALL_BACKWARD, [plain]),
                          aero.workspace_size(aero.CALL_MPPI_STEP, [fwd])), dtype=torch.uint8,
                      device="cuda")
     gu = torch.empty((M, N, 4), dtype=torch.float32, device="cuda")
