@@ -479,6 +479,14 @@ struct SelectPlan {
   size_t bytes = 0;
 };
 
+// Queries per block of an exact set: kBlock lanes times 1, 2, 4 or 8 queries each,
+// the fewest that hold the set in one block (at most kQueriesPerBlock).
+int64_t exact_block_queries(int64_t Q) {
+  int64_t r = 1;
+  while (r < kQueriesPerLane && r * kBlock < Q) r *= 2;
+  return r * kBlock;
+}
+
 void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* best,
                  SelectPlan& pl) {
   Cursor cur{ws};
@@ -488,8 +496,10 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
   pl.sets.assign(n, QuerySet{});
   int64_t qblocks = 0;
   for (int b = 0; b < n; ++b)
-    if (h[b].n_points > 0)
-      qblocks += ((int64_t)h[b].M * h[b].N + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    if (h[b].n_points > 0) {
+      const int64_t qpb = exact_block_queries((int64_t)h[b].M * h[b].N);
+      qblocks += ((int64_t)h[b].M * h[b].N + qpb - 1) / qpb;
+    }
   int64_t ib = 0, blk = 0;
   for (int b = 0; b < n; ++b) {
     const aero_problem& q = h[b];
@@ -519,10 +529,14 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     qs.cloud = q.cloud;
     qs.Q = MN;
     qs.n_points = q.n_points;
-    qs.n_qblocks = (int)((MN + kQueriesPerBlock - 1) / kQueriesPerBlock);
-    // few queries: split the cloud finely so that the chip fills (about 512 blocks)
-    set_chunks(q.n_points, (512 + qblocks - 1) / std::max<int64_t>(qblocks, 1), qs.n_chunks,
-               qs.chunk_pts);
+    qs.qpbA = (int32_t)exact_block_queries(MN);
+    qs.n_qblocks = (int)((MN + qs.qpbA - 1) / qs.qpbA);
+    // few queries: split the cloud so that about 128 workgroups share the work, with
+    // at most 2048 points each (every chunk ends in one atomic per position)
+    set_chunks(q.n_points,
+               std::max<int64_t>((128 + qblocks - 1) / std::max<int64_t>(qblocks, 1),
+                                 (q.n_points + 2047) / 2048),
+               qs.n_chunks, qs.chunk_pts);
     qs.block_base = blk;
     blk += (int64_t)qs.n_qblocks * qs.n_chunks;
   }

@@ -88,21 +88,16 @@ __device__ inline void direct_range(const QuerySet& S, int64_t g0, int64_t g1, f
   }
 }
 
-// Every query of an exact set.  Block = (query block, cloud chunk).
-__global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __restrict__ sets,
-                                                           int n_sets) {
-  __shared__ float4 tile[kTilePts];
-  const int64_t bid = blockIdx.x;
-  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
-  const QuerySet S = sets[s];
-  const int64_t local = bid - S.block_base;
-  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
+// Every query of an exact set.  Block = (query block of R * kBlock queries, cloud
+// chunk); R (queries per lane) is sized to the set, so that small sets leave few
+// lanes idle.
+template <int R>
+__device__ inline void exact_block(const QuerySet& S, int qb, int ch, float4* tile) {
   const int tid = threadIdx.x;
-  constexpr int R = kQueriesPerLane;
   float px[R], py[R], pz[R], best[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    const int64_t q = (int64_t)qb * (R * kBlock) + r * kBlock + tid;
     const int64_t qq = q < S.Q ? q : 0;  // out-of-range lanes read query 0, never stored
     px[r] = S.px[qq];
     py[r] = S.py[qq];
@@ -114,8 +109,24 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
   direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t q = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
+    const int64_t q = (int64_t)qb * (R * kBlock) + r * kBlock + tid;
     if (q < S.Q) atomicMin(S.out + q, __float_as_uint(best[r]));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __restrict__ sets,
+                                                           int n_sets) {
+  __shared__ float4 tile[kTilePts];
+  const int64_t bid = blockIdx.x;
+  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
+  const QuerySet S = sets[s];
+  const int64_t local = bid - S.block_base;
+  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
+  switch (S.qpbA / kBlock) {  // block-uniform
+    case 1: exact_block<1>(S, qb, ch, tile); break;
+    case 2: exact_block<2>(S, qb, ch, tile); break;
+    case 4: exact_block<4>(S, qb, ch, tile); break;
+    default: exact_block<kQueriesPerLane>(S, qb, ch, tile); break;
   }
 }
 
