@@ -531,10 +531,10 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     qs.n_points = q.n_points;
     qs.qpbA = (int32_t)exact_block_queries(MN);
     qs.n_qblocks = (int)((MN + qs.qpbA - 1) / qs.qpbA);
-    // few queries: split the cloud so that about 128 workgroups share the work, with
-    // at most 2048 points each (every chunk ends in one atomic per position)
+    // few queries: split the cloud so that about 512 workgroups share the work (the
+    // pass is latency-bound at this size), with at most 2048 points each
     set_chunks(q.n_points,
-               std::max<int64_t>((128 + qblocks - 1) / std::max<int64_t>(qblocks, 1),
+               std::max<int64_t>((512 + qblocks - 1) / std::max<int64_t>(qblocks, 1),
                                  (q.n_points + 2047) / 2048),
                qs.n_chunks, qs.chunk_pts);
     qs.block_base = blk;
