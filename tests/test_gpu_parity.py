@@ -458,3 +458,43 @@ def test_paper_point_filtered_collision_set():
     sync()
     sel = OM.select_best(p2, g["u_new"])
     assert np.all(np.abs(np_(ps.S2) - sel["S2"]) <= 1e-4 * np.abs(sel["S2"]))
+
+
+def test_batched_sorted_sets_with_indices_equal_plain():
+    """Clouds large enough for the spatial sort (>= 16 tiles), nearest indices
+    requested: one batched call equals the plain calls bit for bit (costs, controls,
+    distances below and beyond d_max, indices)."""
+    rng = np.random.default_rng(23)
+    probs = []
+    for b, (M, K, N, P) in enumerate([(3, 700, 12, 20000), (2, 1500, 9, 41000), (2, 300, 7, 0)]):
+        p = dict(make_plain_problem())
+        p.update(M=M, K=K, N=N, M_h=M, M_v=1, problem_id=b)
+        th = rng.uniform(-np.pi, np.pi, P)
+        r = rng.uniform(0.5, 6.0, P)
+        p["cloud"] = np.stack([2 + r * np.cos(th), r * np.sin(th), rng.uniform(-2, 3, P)], 1).astype(np.float32)
+        p["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(M, N, 4)) * 0.2).astype(np.float32)
+        p["anchors"] = (rng.normal(size=(M, 3)) * 3).astype(np.float32)
+        probs.append(p)
+    print("batched sorted sets", flush=True)
+    steps = [PlanStep(p, keep_debug=True) for p in probs]
+    idx = [torch.full((p["M"], p["N"], p["K"]), -7, dtype=torch.int32, device=DEV) for p in probs]
+    for s, i in zip(steps, idx):
+        s.front_end()
+        s.problem.nearest_idx = i
+    ws = torch.empty(aero.workspace_size(aero.CALL_MPPI_STEP, [s.problem for s in steps]),
+                     dtype=torch.uint8, device=DEV)
+    ref = []
+    for s, i in zip(steps, idx):
+        s.reset()
+        aero.mppi_step(s.params, [s.problem], ws)
+        sync()
+        ref.append((np_(s.S1), np_(s.u_nom), np_(s.min_dist2), np_(i)))
+    for s in steps:
+        s.reset()
+    aero.mppi_step(probs[0]["params"], [s.problem for s in steps], ws)
+    sync()
+    for s, i, r in zip(steps, idx, ref):
+        for got, exp in zip((np_(s.S1), np_(s.u_nom), np_(s.min_dist2), np_(i)), r):
+            assert np.array_equal(got, exp)
+    assert np.all(ref[2][3] == -1)                       # no cloud: no index
+    assert (ref[0][3] >= 0).any() and (ref[1][3] >= 0).any()
