@@ -157,7 +157,7 @@ def grad(prob, coef, act, u_nom=None, scale=1.0):
     w = torch.tensor(f64(prob["params"]["w"]), dtype=T, requires_grad=True)
     L = loss(prob, coef, u, w, act, scale)
     gu, gw = torch.autograd.grad(L, [u, w])
-    return gu.numpy(), gw.numpy(), float(L)
+    return gu.numpy(), gw.numpy(), float(L.detach())
 
 
 def fd_directional(prob, coef, act, direction, h=1e-4, u_nom=None, scale=1.0):
