@@ -395,40 +395,7 @@ __global__ void k_grad_w_final(const double* wpart, double scale, float* grad_w)
   grad_w[i] = (float)(scale * acc);
 }
 
-// J_col of every sample from stored nearest indices.  The squared distance to the
-// stored point is formed exactly as the exact distance pass forms it (single
-// precision, the same operations), so J_col equals the forward step's.
-__global__ __launch_bounds__(kBlock) void k_col_from_nearest(const DevProblem* __restrict__ prob,
-                                                             DevParams prm, int64_t total) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= total) return;
-  const DevProblem& P = *prob;
-  const int K = P.K, N = P.N;
-  const int m = (int)(gid / K), k = (int)(gid % K);
-  const int64_t MNK = (int64_t)P.M * N * K;
-  const double dmax2 = prm.d_max * prm.d_max;
-  double col = 0.0;
-  for (int t = 0; t < N; ++t) {
-    const int64_t qi = ((int64_t)m * N + t) * K + k;
-    const int idx = P.nidx_in[qi];
-    if (idx < 0 || idx >= P.n_points) continue;
-    const float ax = P.pos[qi] - P.cloud[3 * (int64_t)idx];
-    const float ay = P.pos[MNK + qi] - P.cloud[3 * (int64_t)idx + 1];
-    const float az = P.pos[2 * MNK + qi] - P.cloud[3 * (int64_t)idx + 2];
-    const float d2 = fmaf(az, az, fmaf(ay, ay, ax * ax));
-    if ((double)d2 < dmax2) col += collision_phi(sqrt((double)d2), prm);
-  }
-  P.J[4 * (int64_t)P.M * K + gid] = col;
-}
-
 }  // namespace
-
-hipError_t launch_col_from_nearest(const DevProblem* d_prob, const DevParams& prm,
-                                   int64_t samples, hipStream_t s) {
-  k_col_from_nearest<<<(unsigned)((samples + kBlock - 1) / kBlock), kBlock, 0, s>>>(d_prob, prm,
-                                                                                   samples);
-  return hipGetLastError();
-}
 
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s) {

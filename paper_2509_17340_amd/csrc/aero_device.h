@@ -7,6 +7,17 @@
 
 namespace aero {
 
+// Pointers known to address device (global) memory.  A pointer read out of a
+// descriptor is generic to the compiler, and generic (flat) accesses count on both
+// the vector-memory and the LDS/scalar counters, so a wait for one such load also
+// waits for every flat store in flight; global accesses keep loads and stores on
+// the vector-memory counter only, in order.
+#define AERO_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ AERO_GLOBAL T* global_ptr(T* p) {
+  return (AERO_GLOBAL T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // Counter-based noise: Philox4x32 with 10 rounds (Salmon et al., SC'11).  Each
 // round multiplies counter words 0 and 2 by the two round constants, folds the
@@ -144,6 +155,13 @@ __device__ __forceinline__ double collision_phi(double d, const DevParams& prm) 
   if (d < prm.d_min) return prm.C;
   if (d < prm.d_max) return prm.C * exp(-prm.a * (d - prm.d_min));
   return 0.0;
+}
+
+// Order-preserving map of floats to unsigned integers (a < b as floats, NaN aside,
+// iff ord_bits(a) < ord_bits(b)), for bounds merged with integer atomics.
+__device__ __forceinline__ unsigned ord_bits(float f) {
+  const unsigned b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,7 +39,9 @@ struct DevProblem {
   const float* coef;     // [M][3][6]
   float* u_nom;          // [M][N][4]
   double* S1;            // [M][K]
-  double* S_smooth;      // [M][K]  weighted J_track + J_vnorm + J_ctrl + J_goal
+  double* J_ctrl;        // [M][K]  control term, written by the rollout
+  double* state;         // [M][N][10][K] state after every step (p, q, v), written by the
+                         //   rollout and scored by the finalize kernel
   float* deff;           // [M][N][4][K]
   float* pos;            // [3][M][N][K] planes x, y, z
   unsigned* mind2;       // [M][N][K] float bits of the squared nearest distance
@@ -145,7 +147,7 @@ struct DevSelect {
   float x0[10];
   float pg[3], vg[3], qg[4];
   const float* u_nom;    // [M][N][4]
-  double* goal_cost;     // [M] weighted J_goal
+  double* state;         // [M][N][10] states of the noise-free rollouts
   float* pos;            // [3][M][N]
   unsigned* mind2;       // [M][N]
   double* S2;            // [M] (caller's array + offset)
@@ -195,14 +197,12 @@ hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t to
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s);
-hipError_t launch_col_from_nearest(const DevProblem* d_prob, const DevParams& prm,
-                                   int64_t samples, hipStream_t s);
 hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, int64_t rows,
                               const double* gsamp, double scale, float* grad_u, float* grad_w,
                               double* wpart, hipStream_t s);
 size_t grad_w_parts();  // doubles of the weight-gradient partial sums
 hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_samples,
-                           const DevParams& prm, hipStream_t s);
+                           const DevParams& prm, bool write_s1, hipStream_t s);
 hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
                          const DevParams& prm, hipStream_t s);
 hipError_t launch_select_rollout(const DevSelect* d_sel, int n, int64_t total_inst,

@@ -318,7 +318,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     memcpy(d.qg, q.q_goal, sizeof d.qg);
     d.coef = q.coef;
     d.u_nom = q.u_nom;
-    d.S_smooth = cur.take<double>(MK);
+    d.J_ctrl = cur.take<double>(MK);
     double* s1 = cur.take<double>(q.S1 ? 0 : MK);
     d.S1 = q.S1 ? q.S1 : s1;
     float* de = cur.take<float>(q.delta_eff ? 0 : MNK * 4);
@@ -330,6 +330,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     d.row_base = rb;
     d.elem_base = eb;
     d.noise = cur.take<double>(4 * MNK);
+    d.state = cur.take<double>(10 * MNK);
     sb += MK;
     rb += MN;
     eb += MNK;
@@ -514,7 +515,7 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     memcpy(d.vg, q.v_goal, sizeof d.vg);
     memcpy(d.qg, q.q_goal, sizeof d.qg);
     d.u_nom = q.u_nom;
-    d.goal_cost = cur.take<double>(q.M);
+    d.state = cur.take<double>(10 * MN);
     d.pos = cur.take<float>(3 * MN);
     d.mind2 = cur.take<unsigned>(MN);
     d.S2 = S2 ? S2 + ib : nullptr;
@@ -722,7 +723,7 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   if (he == hipSuccess && pl.any_nn)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, n, s); });
   if (he == hipSuccess)
-    he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, n, pl.total_samples, prm, s); });
+    he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, n, pl.total_samples, prm, true, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_UPDATE, s, [&] { return launch_update(pl.d_probs, n, pl.total_rows, prm, s); });
   return dev_status(he);
@@ -797,7 +798,7 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   if (he == hipSuccess && q.n_points > 0)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, 1, s); });
   if (he == hipSuccess)
-    he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, 1, MK, prm, s); });
+    he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, 1, MK, prm, true, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_ADJOINT, s, [&] {
       return launch_adjoint(pl.d_probs, prm, MK, bp.ckpt, bp.seg, bp.gsamp, s);
@@ -841,7 +842,7 @@ int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem
     });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s,
-               [&] { return launch_col_from_nearest(pl.d_probs, prm, MK, s); });
+               [&] { return launch_finalize(pl.d_probs, 1, MK, prm, false, s); });
   if (he == hipSuccess)
     he = timed(AERO_K_ADJOINT, s, [&] {
       return launch_adjoint(pl.d_probs, prm, MK, bp.ckpt, bp.seg, bp.gsamp, s);

@@ -155,9 +155,10 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
 // points x 32 queries,
 //   t = n_hi + n_lo - 2 (o_hi.p_hi + o_lo.p_hi + o_hi.p_lo + o_lo.p_lo)
 // with the K = 16 slots laid out as
-//   A (point)  [-2o_hi, n_hi, -2o_lo, n_lo | -2o_hi, 0, -2o_lo, 0]
-//   B (query)  [  p_hi,    1,   p_hi,    1 |   p_lo, 0,   p_lo, 0].
-// Half products are exact in the single-precision accumulator, so t carries the
+//   A (point)  [-2o_hi, n_hi, -2o_lo, n_lo | -2o_hi, n_hi, -2o_lo, n_lo]
+//   B (query)  [  p_hi,    1,   p_hi,    1 |   p_lo,    0,   p_lo,    0]
+// (the zero query slots cancel the repeated norms, so both lane halves read the
+// same 16-byte point record from LDS).  Half products are exact in the single-precision accumulator, so t carries the
 // split error (2^-22 relative per coordinate) plus the accumulation rounding; the
 // bound below is four times the single-precision passes' one.  Halves cover
 // |v| < 65504: points with |o'| >= 128 become the constant t = 32768 (never
@@ -174,9 +175,11 @@ __device__ __forceinline__ void split_half(float v, _Float16& hi, _Float16& lo) 
   lo = (_Float16)(v - (float)hi);
 }
 
-__global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet* __restrict__ sets,
-                                                                 int n_sets) {
-  __shared__ half8 tile[2 * kTilePts];   // point g: [2g] first K half, [2g + 1] second
+// (at most 128 registers: four waves per SIMD, where the scheduler would otherwise
+// keep four products in flight at three waves)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void
+k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
+  __shared__ half8 tile[kTilePts];
   __shared__ float red[7][4];
   const int64_t bid = blockIdx.x;
   const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
@@ -277,29 +280,26 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_f16s(const QuerySet*
       const float oy = S.cloud[3 * gg + 1] - c[1];
       const float oz = S.cloud[3 * gg + 2] - c[2];
       const float n = fmaf(oz, oz, fmaf(oy, oy, ox * ox));
-      half8 u0 = {}, u1 = {};
+      half8 rec = {};
       if (in && n < 16384.0f) {
         _Float16 xh, xl, yh, yl, zh, zl, nh, nl;
         split_half(-2.0f * ox, xh, xl);
         split_half(-2.0f * oy, yh, yl);
         split_half(-2.0f * oz, zh, zl);
         split_half(n, nh, nl);
-        u0[0] = xh; u0[1] = yh; u0[2] = zh; u0[3] = nh;
-        u0[4] = xl; u0[5] = yl; u0[6] = zl; u0[7] = nl;
-        u1[0] = xh; u1[1] = yh; u1[2] = zh;
-        u1[4] = xl; u1[5] = yl; u1[6] = zl;
+        rec[0] = xh; rec[1] = yh; rec[2] = zh; rec[3] = nh;
+        rec[4] = xl; rec[5] = yl; rec[6] = zl; rec[7] = nl;
       } else {
-        u0[3] = (_Float16)kF16FarT;
+        rec[3] = (_Float16)kF16FarT;
       }
-      tile[2 * pt] = u0;
-      tile[2 * pt + 1] = u1;
+      tile[pt] = rec;
     }
     __syncthreads();
     float tt[kF16Cols];
 #pragma unroll
     for (int b = 0; b < kF16Cols; ++b) tt[b] = kF16FarT;
     for (int g = 0; g < cnt32; g += 32) {
-      const half8 a = tile[2 * (g + col) + kh];
+      const half8 a = tile[g + col];
       // two products in flight: the minima of one overlap the other's MFMA
 #pragma unroll
       for (int b = 0; b < kF16Cols; b += 2) {

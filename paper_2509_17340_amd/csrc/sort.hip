@@ -1,4 +1,5 @@
-// Spatial sort of the rollout positions before the first distance pass.
+// Spatial sort of the rollout positions before the first distance pass (the
+// positions' bounding box is merged by the rollout kernel as it writes them).
 //
 // The first pass takes blocks of consecutive positions; its per-block bound and its
 // record of which cloud tiles a block came near are only as tight as the block is
@@ -23,11 +24,7 @@ namespace {
 constexpr int kWaves = kBlock / 64;
 constexpr int kSortShift0 = 8;  // the key's lowest 8 bits are not sorted on
 
-// Order-preserving map of floats to unsigned integers and back.
-__device__ inline unsigned ord_bits(float f) {
-  const unsigned b = __float_as_uint(f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
+// Inverse of ord_bits: the float whose order-preserving bits are o.
 __device__ inline float ord_float(unsigned o) {
   return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
 }
@@ -57,49 +54,6 @@ __device__ inline Elem locate(const SortSet* sets, int n_sets) {
   e.i = e.blk * kBlock + threadIdx.x;
   e.active = e.i < sets[e.s].Q;
   return e;
-}
-
-// Bounding box: kBoxBlocks grid-strided workgroups per set, so that only a few
-// hundred atomics meet on the six words.
-constexpr int kBoxBlocks = 128;
-
-__global__ __launch_bounds__(kBlock) void k_sort_box(const SortSet* __restrict__ sets,
-                                                     int n_sets) {
-  __shared__ float red[6][kWaves];
-  const int s = blockIdx.x / kBoxBlocks, part = blockIdx.x % kBoxBlocks;
-  const SortSet& S = sets[s];
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t i = (int64_t)part * kBlock + threadIdx.x; i < S.Q; i += (int64_t)kBoxBlocks * kBlock) {
-    const float p[3] = {S.px[i], S.py[i], S.pz[i]};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], p[a]);
-      hi[a] = fmaxf(hi[a], p[a]);
-    }
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_minf(lo[a]);
-    hi[a] = wave_maxf(hi[a]);
-    if (lane == 0) {
-      red[a][w] = lo[a];
-      red[3 + a][w] = hi[a];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < 3 && S.Q > 0) {
-    const int a = threadIdx.x;
-    float l = red[a][0], h = red[3 + a][0];
-    for (int k = 1; k < kWaves; ++k) {
-      l = fminf(l, red[a][k]);
-      h = fmaxf(h, red[3 + a][k]);
-    }
-    if (l <= h) {  // a workgroup that saw no position leaves the box alone
-      atomicMin(S.box + a, ord_bits(l));
-      atomicMax(S.box + 3 + a, ord_bits(h));
-    }
-  }
 }
 
 // Morton key of an element from its position and the set's bounding box.
@@ -245,7 +199,6 @@ hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total
   static_assert(kBlock == kSortDigits, "one thread per digit in the scans");
   if (total_blocks <= 0 || n_sets <= 0) return hipSuccess;
   const unsigned g = (unsigned)total_blocks;
-  k_sort_box<<<(unsigned)(n_sets * kBoxBlocks), kBlock, 0, s>>>(d_sorts, n_sets);
   int src = 0;
   for (int pass = 0; pass < kSortPasses; ++pass) {
     k_sort_hist<<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src);
