@@ -71,41 +71,75 @@ struct Dyn {
   double inv_m, g;
 };
 
-__device__ __forceinline__ void xdot(const double* x, const double* u, const Dyn& d, double* dx) {
+// Per-step factors of the held control: half the body rates and twice the mass-
+// specific thrust (scalings by powers of two, so every product below rounds exactly
+// as the unscaled formula would).
+struct HeldControl {
+  double hwx, hwy, hwz;  // omega / 2
+  double am, am2;        // F / m and 2 F / m
+};
+
+__device__ __forceinline__ HeldControl held_control(const double* u, const Dyn& d) {
+  HeldControl c;
+  c.hwx = 0.5 * u[1];
+  c.hwy = 0.5 * u[2];
+  c.hwz = 0.5 * u[3];
+  c.am = u[0] * d.inv_m;
+  c.am2 = 2.0 * c.am;
+  return c;
+}
+
+__device__ __forceinline__ void xdot_held(const double* x, const HeldControl& c, const Dyn& d,
+                                          double* dx) {
   const double qw = x[3], qx = x[4], qy = x[5], qz = x[6];
-  const double wx = u[1], wy = u[2], wz = u[3];
   dx[0] = x[7];
   dx[1] = x[8];
   dx[2] = x[9];
   // q' = 1/2 q (x) (0, omega)
-  dx[3] = 0.5 * (-qx * wx - qy * wy - qz * wz);
-  dx[4] = 0.5 * (qw * wx + qy * wz - qz * wy);
-  dx[5] = 0.5 * (qw * wy - qx * wz + qz * wx);
-  dx[6] = 0.5 * (qw * wz + qx * wy - qy * wx);
+  dx[3] = -qx * c.hwx - qy * c.hwy - qz * c.hwz;
+  dx[4] = qw * c.hwx + qy * c.hwz - qz * c.hwy;
+  dx[5] = qw * c.hwy - qx * c.hwz + qz * c.hwx;
+  dx[6] = qw * c.hwz + qx * c.hwy - qy * c.hwx;
   // v' = (F/m) R(q) e3 + g, R(q) e3 = (2(xz+wy), 2(yz-wx), 1-2(x^2+y^2))
-  const double am = u[0] * d.inv_m;
-  dx[7] = am * (2.0 * (qx * qz + qw * qy));
-  dx[8] = am * (2.0 * (qy * qz - qw * qx));
-  dx[9] = am * (1.0 - 2.0 * (qx * qx + qy * qy)) - d.g;
+  dx[7] = c.am2 * (qx * qz + qw * qy);
+  dx[8] = c.am2 * (qy * qz - qw * qx);
+  dx[9] = c.am * (1.0 - 2.0 * (qx * qx + qy * qy)) - d.g;
+}
+
+__device__ __forceinline__ void xdot(const double* x, const double* u, const Dyn& d, double* dx) {
+  xdot_held(x, held_control(u, d), d, dx);
+}
+
+// 1/sqrt(s) for the quaternion renormalisation: the hardware estimate refined by
+// two Newton steps, r <- r (3/2 - s r^2 / 2), each of which doubles the number of
+// correct bits (within a couple of ulp of the correctly rounded value; s = |q|^2 is
+// close to 1 after every step).
+__device__ __forceinline__ double rsqrt_refined(double s) {
+  double r = __builtin_amdgcn_rsq(s);
+  const double hs = 0.5 * s;
+  r = r * fma(-hs * r, r, 1.5);
+  r = r * fma(-hs * r, r, 1.5);
+  return r;
 }
 
 // One RK4 step with the control held, then quaternion renormalisation.
 __device__ __forceinline__ void rk4(double* x, const double* u, double dt, const Dyn& d) {
   double k1[10], k2[10], k3[10], k4[10], y[10];
-  xdot(x, u, d, k1);
+  const HeldControl c = held_control(u, d);
+  xdot_held(x, c, d, k1);
 #pragma unroll
   for (int i = 0; i < 10; ++i) y[i] = x[i] + 0.5 * dt * k1[i];
-  xdot(y, u, d, k2);
+  xdot_held(y, c, d, k2);
 #pragma unroll
   for (int i = 0; i < 10; ++i) y[i] = x[i] + 0.5 * dt * k2[i];
-  xdot(y, u, d, k3);
+  xdot_held(y, c, d, k3);
 #pragma unroll
   for (int i = 0; i < 10; ++i) y[i] = x[i] + dt * k3[i];
-  xdot(y, u, d, k4);
+  xdot_held(y, c, d, k4);
   const double h6 = dt / 6.0;
 #pragma unroll
   for (int i = 0; i < 10; ++i) x[i] = x[i] + h6 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
-  const double inv = 1.0 / sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
+  const double inv = rsqrt_refined(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
   x[3] *= inv;
   x[4] *= inv;
   x[5] *= inv;

@@ -13,6 +13,9 @@ namespace aero {
 #ifndef AERO_QUERIES_PER_LANE
 #define AERO_QUERIES_PER_LANE 8
 #endif
+#ifndef AERO_F16_COLS
+#define AERO_F16_COLS 8
+#endif
 
 constexpr int kBlock = 256;                              // threads per workgroup (4 wave64)
 constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points staged in LDS per tile
@@ -24,10 +27,11 @@ constexpr int kPassAValu = 0;   // VALU FMAs, kQueriesPerBlock positions per blo
 constexpr int kPassAMfma = 1;   // matrix-core MFMA, 512 positions per block
 constexpr int kPassAF16s = 2;   // half-precision matrix cores on split coordinates, 1024 per block
 constexpr int kPassAVariants = 3;
-constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 512, 1024};
+constexpr int kF16Cols = AERO_F16_COLS;   // split-f16 pass A: column blocks of 32 queries per wave
+constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 512, 4 * 32 * kF16Cols};
 // Pass B gives each lane at most kQueriesPerLane queries of one pass-A block.
 static_assert(kQueriesPerBlock <= kQueriesPerLane * kBlock && 512 <= kQueriesPerBlock &&
-                  1024 <= kQueriesPerBlock, "pass-A blocks must fit one pass-B block");
+                  4 * 32 * kF16Cols <= kQueriesPerBlock, "pass-A blocks must fit one pass-B block");
 
 // Per-problem record, built on the host and copied into the workspace.
 struct DevProblem {
@@ -40,7 +44,7 @@ struct DevProblem {
   float* u_nom;          // [M][N][4]
   double* S1;            // [M][K]
   double* J_ctrl;        // [M][K]  control term, written by the rollout
-  double* state;         // [M][N][10][K] state after every step (p, q, v), written by the
+  double* state;         // [M][N][K][10] state after every step (p, q, v), written by the
                          //   rollout and scored by the finalize kernel
   float* deff;           // [M][N][4][K]
   float* pos;            // [3][M][N][K] planes x, y, z

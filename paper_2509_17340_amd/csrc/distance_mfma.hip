@@ -158,15 +158,23 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
 //   A (point)  [-2o_hi, n_hi, -2o_lo, n_lo | -2o_hi, n_hi, -2o_lo, n_lo]
 //   B (query)  [  p_hi,    1,   p_hi,    1 |   p_lo,    0,   p_lo,    0]
 // (the zero query slots cancel the repeated norms, so both lane halves read the
-// same 16-byte point record from LDS).  Half products are exact in the single-precision accumulator, so t carries the
-// split error (2^-22 relative per coordinate) plus the accumulation rounding; the
-// bound below is four times the single-precision passes' one.  Halves cover
+// same 16-byte point record from LDS).  Half products are exact in the
+// single-precision accumulator, so t carries the split error (2^-22 relative per
+// coordinate) plus the accumulation rounding; the bound below is four times the
+// single-precision passes' one.  Halves cover
 // |v| < 65504: points with |o'| >= 128 become the constant t = 32768 (never
 // flagged; they are provably farther than d_max whenever R + d_max <= 64), and a
 // block whose radius breaks that condition flags every query (pass B is exact).
-constexpr int kF16Cols = 8;                              // column blocks of 32 queries per wave (even)
-constexpr int kF16QPB = 4 * 32 * kF16Cols;               // 1024 queries per block
+#ifndef AERO_F16_PIPE
+#define AERO_F16_PIPE 2
+#endif
+#ifndef AERO_F16_WPE
+#define AERO_F16_WPE 4
+#endif
+constexpr int kF16QPB = kPassAQPB[kPassAF16s];  // 4 waves x 32 queries x kF16Cols
+constexpr int kF16Pipe = AERO_F16_PIPE;          // products reduced together
 constexpr float kF16FarT = 32768.0f;
+static_assert(kF16Cols % kF16Pipe == 0, "column blocks come in groups of kF16Pipe");
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -175,9 +183,9 @@ __device__ __forceinline__ void split_half(float v, _Float16& hi, _Float16& lo) 
   lo = (_Float16)(v - (float)hi);
 }
 
-// (at most 128 registers: four waves per SIMD, where the scheduler would otherwise
-// keep four products in flight at three waves)
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void
+// (at most 512 / AERO_F16_WPE registers: four waves per SIMD by default, where the
+// scheduler would otherwise keep four products in flight at three waves)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AERO_F16_WPE))) void
 k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
   __shared__ half8 tile[kTilePts];
   __shared__ float red[7][4];
@@ -188,26 +196,23 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
   const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int col = lane & 31, kh = lane >> 5;
-  float px[kF16Cols], py[kF16Cols], pz[kF16Cols];
-  bool ok[kF16Cols];
-  int32_t sid[kF16Cols];
+  const int64_t slot0 = (int64_t)qb * kF16QPB + w * (32 * kF16Cols) + col;  // + 32 b
+  // The block's positions are read twice (bounds, then the split operands), so
+  // that only the operands stay in registers.
+  unsigned okm = 0;  // bit b: column block b's query of this lane exists
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int b = 0; b < kF16Cols; ++b) {
-    const int64_t slot = (int64_t)qb * kF16QPB + w * (32 * kF16Cols) + b * 32 + col;
-    ok[b] = slot < S.Q;
-    const int64_t qq = ok[b] ? perm_query(S, slot) : 0;
-    sid[b] = (int32_t)slot;
-    px[b] = S.px[qq];
-    py[b] = S.py[qq];
-    pz[b] = S.pz[qq];
-    if (ok[b]) {
-      lo[0] = fminf(lo[0], px[b]);
-      lo[1] = fminf(lo[1], py[b]);
-      lo[2] = fminf(lo[2], pz[b]);
-      hi[0] = fmaxf(hi[0], px[b]);
-      hi[1] = fmaxf(hi[1], py[b]);
-      hi[2] = fmaxf(hi[2], pz[b]);
+    const int64_t slot = slot0 + b * 32;
+    if (slot < S.Q) {
+      okm |= 1u << b;
+      const int64_t qq = perm_query(S, slot);
+      const float p[3] = {S.px[qq], S.py[qq], S.pz[qq]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], p[a]);
+        hi[a] = fmaxf(hi[a], p[a]);
+      }
     }
   }
 #pragma unroll
@@ -234,14 +239,16 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
   float pp[kF16Cols], tmin[kF16Cols], rr = 0.0f;
 #pragma unroll
   for (int b = 0; b < kF16Cols; ++b) {
-    const float x = px[b] - c[0], y = py[b] - c[1], z = pz[b] - c[2];
+    const bool ok = (okm >> b) & 1u;
+    const int64_t qq = ok ? perm_query(S, slot0 + b * 32) : 0;
+    const float x = S.px[qq] - c[0], y = S.py[qq] - c[1], z = S.pz[qq] - c[2];
     pp[b] = fmaf(z, z, fmaf(y, y, x * x));
-    if (ok[b]) rr = fmaxf(rr, pp[b]);
+    if (ok) rr = fmaxf(rr, pp[b]);
     _Float16 xh, xl, yh, yl, zh, zl;
     split_half(x, xh, xl);
     split_half(y, yh, yl);
     split_half(z, zh, zl);
-    const _Float16 one = ok[b] ? (_Float16)1.0f : (_Float16)0.0f;
+    const _Float16 one = ok ? (_Float16)1.0f : (_Float16)0.0f;
     const _Float16 zero = (_Float16)0.0f;
     half8 v;
     if (kh == 0) {
@@ -251,7 +258,7 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
       v[0] = xl; v[1] = yl; v[2] = zl; v[3] = zero;
       v[4] = xl; v[5] = yl; v[6] = zl; v[7] = zero;
     }
-    if (!ok[b]) v = (half8){};
+    if (!ok) v = (half8){};
     bop[b] = v;
     tmin[b] = kF16FarT;
   }
@@ -300,24 +307,26 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
     for (int b = 0; b < kF16Cols; ++b) tt[b] = kF16FarT;
     for (int g = 0; g < cnt32; g += 32) {
       const half8 a = tile[g + col];
-      // two products in flight: the minima of one overlap the other's MFMA
+      // kF16Pipe products in flight: the minima of one overlap the next MFMA
 #pragma unroll
-      for (int b = 0; b < kF16Cols; b += 2) {
-        const floatx16 d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bop[b], zacc, 0, 0, 0);
-        const floatx16 d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bop[b + 1], zacc, 0, 0, 0);
-        float m0 = tt[b], m1 = tt[b + 1];
+      for (int b = 0; b < kF16Cols; b += kF16Pipe) {
+        floatx16 dv[kF16Pipe];
 #pragma unroll
-        for (int r = 0; r < 16; r += 2) m0 = fminf(fminf(m0, d0[r]), d0[r + 1]);
+        for (int j = 0; j < kF16Pipe; ++j)
+          dv[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bop[b + j], zacc, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 16; r += 2) m1 = fminf(fminf(m1, d1[r]), d1[r + 1]);
-        tt[b] = m0;
-        tt[b + 1] = m1;
+        for (int j = 0; j < kF16Pipe; ++j) {
+          float m = tt[b + j];
+#pragma unroll
+          for (int r = 0; r < 16; r += 2) m = fminf(fminf(m, dv[j][r]), dv[j][r + 1]);
+          tt[b + j] = m;
+        }
       }
     }
     bool hit = false;
 #pragma unroll
     for (int b = 0; b < kF16Cols; ++b) {
-      hit |= ok[b] && pp[b] + tt[b] < thr;
+      hit |= ((okm >> b) & 1u) && pp[b] + tt[b] < thr;
       tmin[b] = fminf(tmin[b], tt[b]);
     }
     if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
@@ -326,7 +335,8 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
   for (int b = 0; b < kF16Cols; ++b) {
     float v = tmin[b];
     v = fminf(v, __shfl_xor(v, 32, 64));   // the two lane halves hold different rows
-    if (ok[b] && kh == 0) atomicMin(S.out_slot + sid[b], __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
+    if (((okm >> b) & 1u) && kh == 0)
+      atomicMin(S.out_slot + slot0 + b * 32, __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
   }
 }
 

@@ -25,6 +25,7 @@ namespace aero {
 namespace {
 
 constexpr unsigned kInfBits = 0x7f800000u;
+typedef double dvec2 __attribute__((ext_vector_type(2)));  // 16-byte state accesses
 
 __device__ inline void load_rg(const float* qg, double Rg[9]) {
   const double w = qg[0], x = qg[1], y = qg[2], z = qg[3];
@@ -96,11 +97,15 @@ __device__ inline void merge_box(const DevProblem* __restrict__ probs, bool acti
 // The sequential part of Stage I: only the dynamics and the control term, so that
 // the chain of dependent binary64 operations per step is as short as the model
 // allows; the state terms are scored in parallel by k_finalize.
+// One wave per workgroup: the sequential rollouts are few (one lane per sample), and
+// spreading their waves over as many CUs as possible gives each wave a CU's whole
+// store path (every step writes 108 bytes per sample).
+constexpr int kRollBlock = 64;
 constexpr int kAhead = 2;  // steps of inputs loaded ahead (the stores of two steps stay
                            // below the 63 outstanding vector-memory operations)
-__global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict__ probs, int n,
-                                                    int64_t total, DevParams prm) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __restrict__ probs,
+                                                        int n, int64_t total, DevParams prm) {
+  const int64_t gid = (int64_t)blockIdx.x * kRollBlock + threadIdx.x;
   const bool active = gid < total;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   int b = 0;
@@ -169,9 +174,10 @@ __global__ __launch_bounds__(kBlock) void k_rollout(const DevProblem* __restrict
           lo[a] = fminf(lo[a], p3[a]);
           hi[a] = fmaxf(hi[a], p3[a]);
         }
-        AERO_GLOBAL double* st = state + row * 10 * K + k;
+        // one 80-byte record per position (five 16-byte stores from one address)
+        AERO_GLOBAL dvec2* st = reinterpret_cast<AERO_GLOBAL dvec2*>(state + qi * 10);
 #pragma unroll
-        for (int i = 0; i < 10; ++i) st[(int64_t)i * K] = x[i];
+        for (int i = 0; i < 5; ++i) st[i] = dvec2{x[2 * i], x[2 * i + 1]};
         const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
         const double d0 = u[0] - up[0], d1 = u[1] - up[1], d2 = u[2] - up[2], d3 = u[3] - up[3];
         const double du2 = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
@@ -234,9 +240,14 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(const DevProblem* _
     AERO_GLOBAL const double* __restrict__ state = global_ptr(P.state);
     double xn[10];
     auto load_state = [&](int t) {
-      AERO_GLOBAL const double* st = state + ((int64_t)m * N + (t < t1 ? t : t1 - 1)) * 10 * K + k;
+      const int64_t qi = ((int64_t)m * N + (t < t1 ? t : t1 - 1)) * K + k;
+      AERO_GLOBAL const dvec2* st = reinterpret_cast<AERO_GLOBAL const dvec2*>(state + qi * 10);
 #pragma unroll
-      for (int i = 0; i < 10; ++i) xn[i] = st[(int64_t)i * K];
+      for (int i = 0; i < 5; ++i) {
+        const dvec2 v = st[i];
+        xn[2 * i] = v[0];
+        xn[2 * i + 1] = v[1];
+      }
     };
     if (t0 < t1) load_state(t0);
     for (int t = t0; t < t1; ++t) {
@@ -544,13 +555,15 @@ hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_
 hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_samples,
                                 int64_t total_elems, const DevParams& prm, hipStream_t s) {
   if (total_elems > 0) k_noise<<<grid1d(total_elems), kBlock, 0, s>>>(d_probs, n, total_elems, prm);
-  k_rollout<<<grid1d(total_samples), kBlock, 0, s>>>(d_probs, n, total_samples, prm);
+  k_rollout<<<(unsigned)((total_samples + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(
+      d_probs, n, total_samples, prm);
   return hipGetLastError();
 }
 
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
                           hipStream_t s) {
-  k_rollout<<<grid1d(total), kBlock, 0, s>>>(d_probs, n, total, prm);
+  k_rollout<<<(unsigned)((total + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(d_probs, n,
+                                                                                     total, prm);
   return hipGetLastError();
 }
 
