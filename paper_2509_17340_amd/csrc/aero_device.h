@@ -234,4 +234,38 @@ __device__ __forceinline__ int find_owner(const T* recs, int n, int64_t i, F bas
   return lo;
 }
 
+// Bounding box of sub-tile `bid` (counted over the two-pass sets in box_base order)
+// of a cloud: kSubPts consecutive points, one per thread of a kBlock block.  Read
+// by pass A's hit records.
+__device__ inline void cloud_box_block(const QuerySet* __restrict__ sets, int n_sets, int64_t bid) {
+  static_assert(kSubPts == kBlock, "one point per thread");
+  __shared__ float red[6][kBlock / 64];
+  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.box_base; });
+  const QuerySet& S = sets[s];
+  const int64_t sub = bid - S.box_base;
+  const int64_t g = sub * kSubPts + threadIdx.x;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (g < S.n_points) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = S.cloud[3 * g + a];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_minf(lo[a]);
+    hi[a] = wave_maxf(hi[a]);
+    if (lane == 0) {
+      red[a][w] = lo[a];
+      red[3 + a][w] = hi[a];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    float v = red[a][0];
+    for (int k = 1; k < kBlock / 64; ++k) v = a < 3 ? fminf(v, red[a][k]) : fmaxf(v, red[a][k]);
+    S.qbox[6 * sub + a] = v;
+  }
+}
+
 }  // namespace aero

@@ -19,6 +19,8 @@ namespace aero {
 
 constexpr int kBlock = 256;                              // threads per workgroup (4 wave64)
 constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points staged in LDS per tile
+constexpr int kTileSplit = 4;                            // sub-tiles per tile (pass-B work units)
+constexpr int kSubPts = kTilePts / kTileSplit;           // cloud points per sub-tile
 constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
 constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
 
@@ -105,8 +107,12 @@ struct QuerySet {
   int32_t* list;         // [n_qblocks * qpbA] flagged queries, segment qb at qb * qpbA
                          //   (nullptr: exact set)
   int32_t* seg_count;    // [n_qblocks] flagged queries of each query block
-  int2* work;            // [n_qblocks * n_tiles] (query block, tile) pairs where some
-                         //   query of the block came under the bound in pass A
+  int2* work;            // [n_qblocks * n_tiles * kTileSplit] (query block, sub-tile)
+                         //   pairs: some query of the block came under the bound in the
+                         //   sub-tile's tile in pass A, and the sub-tile's bounding box
+                         //   lies within reach of the block's bounding box
+  float* qbox;           // [ceil(n_points / kSubPts)][6] sub-tile bounding boxes (lo, hi)
+  int64_t box_base;      // prefix of ceil(n_points / kSubPts) over two-pass sets
   int32_t* work_count;   // entries of `work` (zeroed by the rollout kernel)
   int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
   int32_t qpbA;          // positions per pass-A block (the variant's block size)
@@ -137,11 +143,46 @@ __device__ inline int64_t perm_query(const QuerySet& S, int64_t slot) {
   return q < 0 ? 0 : (q >= S.Q ? S.Q - 1 : q);
 }
 
-// Record that some query of pass-A block qb came under its bound in the cloud tile
-// starting at point `base` (pass-A chunks are whole kTilePts tiles).
-__device__ inline void append_hit(const QuerySet& S, int qb, int64_t base) {
-  const int e = atomicAdd(S.work_count, 1);
-  S.work[e] = make_int2(qb, (int)(base / kTilePts));
+// Pass-A hit of query block qb (bounding box [blo, bhi]) in cloud tile `tile`:
+// record the tile's sub-tiles whose bounding box lies within squared distance r2 of
+// the block's box.  With r2 = 2 thresh - d_max^2 (pass A errs by at most
+// thresh - d_max^2, and a flagged query's pass-A value is below thresh) every point
+// within d_max of a flagged query, and the point that flagged it, is in a recorded
+// sub-tile; the relative margin covers the rounding of the box distance.
+__device__ inline void append_hits(const QuerySet& S, int qb, int64_t tile, const float blo[3],
+                                   const float bhi[3], float r2) {
+  const float lim = r2 * (1.0f + 1e-5f) + 1e-6f;
+  for (int j = 0; j < kTileSplit; ++j) {
+    const int64_t sub = tile * kTileSplit + j;
+    if (sub * kSubPts >= S.n_points) break;
+    const float* b = S.qbox + 6 * sub;
+    float d2 = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+      const float dd = fmaxf(0.0f, fmaxf(b[a] - bhi[a], blo[a] - b[3 + a]));
+      d2 = fmaf(dd, dd, d2);
+    }
+    if (d2 <= lim) {
+      const int e = atomicAdd(S.work_count, 1);
+      S.work[e] = make_int2(qb, (int)sub);
+    }
+  }
+}
+
+// Pass-A hit from a block whose per-wave query bounds are red[0..2][w] (min) and
+// red[3..5][w] (max) in LDS.
+__device__ inline void append_block_hits(const QuerySet& S, int qb, int64_t tile,
+                                         const float (*red)[4], float r2) {
+  float blo[3], bhi[3];
+  for (int a = 0; a < 3; ++a) {
+    blo[a] = fminf(fminf(red[a][0], red[a][1]), fminf(red[a][2], red[a][3]));
+    bhi[a] = fmaxf(fmaxf(red[3 + a][0], red[3 + a][1]), fmaxf(red[3 + a][2], red[3 + a][3]));
+  }
+  append_hits(S, qb, tile, blo, bhi, r2);
+}
+
+// Squared reach of pass B around a block with pass-A bound thr (see append_hits).
+__device__ inline float pass_b_reach2(float thr, float d_max) {
+  return thr < INFINITY ? thr + (thr - d_max * d_max) : INFINITY;
 }
 
 // Per-problem Stage-II record.
@@ -184,7 +225,8 @@ hipError_t launch_guides(const double p0[3], const double v0[3], const double a0
                          const float* anchors, const float* end_vel, const float* end_acc,
                          double T, int M, float* coef, hipStream_t s);
 hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_samples,
-                                int64_t total_elems, const DevParams& prm, hipStream_t s);
+                                int64_t total_elems, const DevParams& prm, const QuerySet* d_sets,
+                                int64_t box_blocks, hipStream_t s);
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_samples,
                           const DevParams& prm, hipStream_t s);
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,

@@ -279,6 +279,7 @@ struct MppiPlan {
   SortSet* d_sorts = nullptr;   // adjacent to d_sets: one descriptor upload
   int64_t total_samples = 0, total_rows = 0, total_blocks = 0, flag_blocks = 0, listed_items = 0;
   int64_t sort_blocks = 0;
+  int64_t box_blocks = 0;       // sub-tile bounding boxes of the two-pass sets' clouds
   int64_t total_elems = 0;      // sum of M*N*K (rollout noise draws)
   bool any_sorted = false;      // some set works in sorted slots (needs the unpermute)
   bool any_nn = false;          // some set records nearest indices
@@ -301,7 +302,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     const int64_t Q = (int64_t)h[b].M * h[b].N * h[b].K;
     if (h[b].n_points > 0) qblocks += (Q + qpbA - 1) / qpbA;
   }
-  int64_t sb = 0, rb = 0, blk = 0, fb = 0, items = 0;
+  int64_t sb = 0, rb = 0, blk = 0, fb = 0, items = 0, bb = 0;
   for (int b = 0; b < n; ++b) {
     const aero_problem& q = h[b];
     DevProblem& d = pl.probs[b];
@@ -361,7 +362,11 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.thresh = cur.take<float>(two_pass ? max_blocks : 0);
     qs.seg_count = cur.take<int32_t>(two_pass ? max_blocks : 0);
     qs.list = cur.take<int32_t>(two_pass ? MNK + kQueriesPerBlock : 0);
-    qs.work = cur.take<int2>(two_pass ? max_blocks * n_tiles : 0);
+    qs.work = cur.take<int2>(two_pass ? max_blocks * n_tiles * kTileSplit : 0);
+    const int64_t n_sub = ((int64_t)q.n_points + kSubPts - 1) / kSubPts;
+    qs.qbox = cur.take<float>(two_pass ? 6 * n_sub : 0);
+    qs.box_base = bb;
+    bb += two_pass ? n_sub : 0;
     qs.work_count = cur.take<int32_t>(two_pass ? 1 : 0);
     if (!two_pass) {
       qs.thresh = nullptr;
@@ -369,6 +374,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.list = nullptr;
       qs.work = nullptr;
       qs.work_count = nullptr;
+      qs.qbox = nullptr;
     }
     d.work_count = qs.work_count;
     // spatial order of the positions for pass A
@@ -407,13 +413,14 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     }
     qs.query_base = fb;
     fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
-    items += two_pass ? (int64_t)qs.n_qblocks * n_tiles : 0;
+    items += two_pass ? (int64_t)qs.n_qblocks * n_tiles * kTileSplit : 0;
   }
   pl.total_samples = sb;
   pl.total_rows = rb;
   pl.total_blocks = blk;
   pl.flag_blocks = fb;
   pl.listed_items = items;
+  pl.box_blocks = bb;
   pl.sort_blocks = sort_blocks;
   pl.total_elems = eb;
   pl.bytes = cur.off;
@@ -701,7 +708,8 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   hipError_t he = stage_mppi(pl, n, s);
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] {
-      return launch_rollout_noise(pl.d_probs, n, pl.total_samples, pl.total_elems, prm, s);
+      return launch_rollout_noise(pl.d_probs, n, pl.total_samples, pl.total_elems, prm,
+                                  pl.d_sets, pl.box_blocks, s);
     });
   if (he == hipSuccess && pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
@@ -778,7 +786,8 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   hipError_t he = stage_mppi(pl, 1, s);
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] {
-      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, s);
+      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm,
+                                  pl.d_sets, pl.box_blocks, s);
     });
   if (he == hipSuccess && pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
@@ -838,7 +847,8 @@ int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem
   hipError_t he = stage_mppi(pl, 1, s);
   if (he == hipSuccess)
     he = timed(AERO_K_ROLLOUT, s, [&] {
-      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, s);
+      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm,
+                                  pl.d_sets, pl.box_blocks, s);
     });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s,

@@ -130,7 +130,6 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
   }
 }
 
-constexpr int kPassBSplit = 4;
 
 // One pass-B item: the flagged queries of query block qb (R per lane) against the
 // cloud tile [g0, g1).
@@ -185,20 +184,20 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
   for (int s = 0; s < n_sets; ++s) {
     const QuerySet& Sref = sets[s];
     if (!Sref.list || Sref.n_points <= 0) continue;
-    // each (query block, tile) entry is split into kPassBSplit sub-items of
-    // kTilePts / kPassBSplit points: more, shorter workgroups hide latency better
-    const int64_t items = (int64_t)*Sref.work_count * kPassBSplit;
+    // one item per (query block, sub-tile) entry: kSubPts points, short enough
+    // workgroups to hide latency
+    const int64_t items = (int64_t)*Sref.work_count;
     int64_t first = ((int64_t)blockIdx.x - item_base) % gridDim.x;
     if (first < 0) first += gridDim.x;
     if (items > 0) {
       const QuerySet S = Sref;
       for (int64_t it = first; it < items; it += gridDim.x) {
-        const int2 wk = S.work[it / kPassBSplit];
+        const int2 wk = S.work[it];
         const int64_t qb = wk.x;
         const int cnt = min(S.seg_count[qb], S.qpbA);
         if (cnt <= 0) continue;
-        const int64_t g0 = (int64_t)wk.y * kTilePts + (it % kPassBSplit) * (kTilePts / kPassBSplit);
-        const int64_t g1 = min<int64_t>(g0 + kTilePts / kPassBSplit, S.n_points);
+        const int64_t g0 = (int64_t)wk.y * kSubPts;
+        const int64_t g1 = min<int64_t>(g0 + kSubPts, S.n_points);
         if (g0 >= g1) continue;
         const int nr = (cnt + kBlock - 1) / kBlock;
         if (nr == 1)
@@ -326,7 +325,8 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
       hit |= ok[r] && pp[r] + tt[r] < thr;
       tmin[r] = fminf(tmin[r], tt[r]);
     }
-    if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
+    if (__syncthreads_or(hit) && tid == 0)
+      append_block_hits(S, qb, base / kTilePts, red, pass_b_reach2(thr, S.d_max));
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -442,7 +442,7 @@ hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t max_items,
                                   hipStream_t s) {
   if (max_items > 0) {
-    const int64_t sub = max_items * kPassBSplit;
+    const int64_t sub = max_items;  // entries are sub-tiles already
     const unsigned grid = (unsigned)(sub < kPersistBlocks ? sub : kPersistBlocks);
     k_min_dist_listed<<<grid, kBlock, 0, s>>>(d_sets, n_sets);
   }

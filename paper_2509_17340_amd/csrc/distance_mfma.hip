@@ -138,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
       hit |= ok[b] && pp[b] + tt[b] < thr;
       tmin[b] = fminf(tmin[b], tt[b]);
     }
-    if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
+    if (__syncthreads_or(hit) && tid == 0)
+      append_block_hits(S, qb, base / kTilePts, red, pass_b_reach2(thr, S.d_max));
   }
 #pragma unroll
   for (int b = 0; b < kMfmaCols; ++b) {
@@ -329,7 +330,8 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
       hit |= ((okm >> b) & 1u) && pp[b] + tt[b] < thr;
       tmin[b] = fminf(tmin[b], tt[b]);
     }
-    if (__syncthreads_or(hit) && tid == 0) append_hit(S, qb, base);
+    if (__syncthreads_or(hit) && tid == 0)
+      append_block_hits(S, qb, base / kTilePts, red, pass_b_reach2(thr, S.d_max));
   }
 #pragma unroll
   for (int b = 0; b < kF16Cols; ++b) {

@@ -36,8 +36,16 @@ __device__ inline void load_rg(const float* qg, double Rg[9]) {
 // parallel ahead of the sequential rollout (the same counter-based stream); also
 // resets the per-position distance outputs, the pass-B work counter and the
 // spatial sort's bounding box.
+// Blocks from noise_blocks on compute the sub-tile bounding boxes of the two-pass
+// sets' clouds instead (independent work, one launch fewer).
 __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__ probs, int n,
-                                                  int64_t total, DevParams prm) {
+                                                  int64_t total, DevParams prm,
+                                                  const QuerySet* __restrict__ sets, int n_sets,
+                                                  int64_t noise_blocks) {
+  if ((int64_t)blockIdx.x >= noise_blocks) {
+    cloud_box_block(sets, n_sets, (int64_t)blockIdx.x - noise_blocks);
+    return;
+  }
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (gid >= total) return;
   const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.elem_base; });
@@ -553,8 +561,12 @@ hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_
 }
 
 hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_samples,
-                                int64_t total_elems, const DevParams& prm, hipStream_t s) {
-  if (total_elems > 0) k_noise<<<grid1d(total_elems), kBlock, 0, s>>>(d_probs, n, total_elems, prm);
+                                int64_t total_elems, const DevParams& prm, const QuerySet* d_sets,
+                                int64_t box_blocks, hipStream_t s) {
+  const int64_t nb = (total_elems + kBlock - 1) / kBlock;
+  if (nb + box_blocks > 0)
+    k_noise<<<(unsigned)(nb + box_blocks), kBlock, 0, s>>>(d_probs, n, total_elems, prm, d_sets, n,
+                                                          nb);
   k_rollout<<<(unsigned)((total_samples + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(
       d_probs, n, total_samples, prm);
   return hipGetLastError();
