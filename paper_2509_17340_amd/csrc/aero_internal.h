@@ -32,6 +32,7 @@ constexpr int kPassAVariants = 3;
 constexpr int kF16Cols = AERO_F16_COLS;   // split-f16 pass A: column blocks of 32 queries per wave
 constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 512, 4 * 32 * kF16Cols};
 // Pass B gives each lane at most kQueriesPerLane queries of one pass-A block.
+static_assert(kTileSplit <= 4, "sub-tile masks take the low 4 bits of a work entry");
 static_assert(kQueriesPerBlock <= kQueriesPerLane * kBlock && 512 <= kQueriesPerBlock &&
                   4 * 32 * kF16Cols <= kQueriesPerBlock, "pass-A blocks must fit one pass-B block");
 
@@ -107,10 +108,12 @@ struct QuerySet {
   int32_t* list;         // [n_qblocks * qpbA] flagged queries, segment qb at qb * qpbA
                          //   (nullptr: exact set)
   int32_t* seg_count;    // [n_qblocks] flagged queries of each query block
-  int2* work;            // [n_qblocks * n_tiles * kTileSplit] (query block, sub-tile)
-                         //   pairs: some query of the block came under the bound in the
-                         //   sub-tile's tile in pass A, and the sub-tile's bounding box
-                         //   lies within reach of the block's bounding box
+  int2* work;            // [n_qblocks * n_tiles] (query block, tile << 4 | sub-tile mask):
+                         //   some query of the block came under the bound in the tile
+                         //   in pass A; bit j: sub-tile j's bounding box lies within
+                         //   reach of the block's bounding box
+  float4* fpos;          // [n_qblocks * qpbA] positions of the flagged queries, in the
+                         //   order of `list` (written by the flag kernel)
   float* qbox;           // [ceil(n_points / kSubPts)][6] sub-tile bounding boxes (lo, hi)
   int64_t box_base;      // prefix of ceil(n_points / kSubPts) over two-pass sets
   int32_t* work_count;   // entries of `work` (zeroed by the rollout kernel)
@@ -144,14 +147,15 @@ __device__ inline int64_t perm_query(const QuerySet& S, int64_t slot) {
 }
 
 // Pass-A hit of query block qb (bounding box [blo, bhi]) in cloud tile `tile`:
-// record the tile's sub-tiles whose bounding box lies within squared distance r2 of
-// the block's box.  With r2 = 2 thresh - d_max^2 (pass A errs by at most
+// record the tile with the mask of its sub-tiles whose bounding box lies within
+// squared distance r2 of the block's box.  With r2 = 2 thresh - d_max^2 (pass A errs by at most
 // thresh - d_max^2, and a flagged query's pass-A value is below thresh) every point
 // within d_max of a flagged query, and the point that flagged it, is in a recorded
 // sub-tile; the relative margin covers the rounding of the box distance.
 __device__ inline void append_hits(const QuerySet& S, int qb, int64_t tile, const float blo[3],
                                    const float bhi[3], float r2) {
   const float lim = r2 * (1.0f + 1e-5f) + 1e-6f;
+  int mask = 0;
   for (int j = 0; j < kTileSplit; ++j) {
     const int64_t sub = tile * kTileSplit + j;
     if (sub * kSubPts >= S.n_points) break;
@@ -161,10 +165,11 @@ __device__ inline void append_hits(const QuerySet& S, int qb, int64_t tile, cons
       const float dd = fmaxf(0.0f, fmaxf(b[a] - bhi[a], blo[a] - b[3 + a]));
       d2 = fmaf(dd, dd, d2);
     }
-    if (d2 <= lim) {
-      const int e = atomicAdd(S.work_count, 1);
-      S.work[e] = make_int2(qb, (int)sub);
-    }
+    if (d2 <= lim) mask |= 1 << j;
+  }
+  if (mask) {
+    const int e = atomicAdd(S.work_count, 1);
+    S.work[e] = make_int2(qb, (int)(tile << 4) | mask);
   }
 }
 

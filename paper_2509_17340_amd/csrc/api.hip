@@ -362,7 +362,8 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.thresh = cur.take<float>(two_pass ? max_blocks : 0);
     qs.seg_count = cur.take<int32_t>(two_pass ? max_blocks : 0);
     qs.list = cur.take<int32_t>(two_pass ? MNK + kQueriesPerBlock : 0);
-    qs.work = cur.take<int2>(two_pass ? max_blocks * n_tiles * kTileSplit : 0);
+    qs.work = cur.take<int2>(two_pass ? max_blocks * n_tiles : 0);
+    qs.fpos = cur.take<float4>(two_pass ? MNK + kQueriesPerBlock : 0);
     const int64_t n_sub = ((int64_t)q.n_points + kSubPts - 1) / kSubPts;
     qs.qbox = cur.take<float>(two_pass ? 6 * n_sub : 0);
     qs.box_base = bb;
@@ -375,6 +376,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.work = nullptr;
       qs.work_count = nullptr;
       qs.qbox = nullptr;
+      qs.fpos = nullptr;
     }
     d.work_count = qs.work_count;
     // spatial order of the positions for pass A
@@ -413,7 +415,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     }
     qs.query_base = fb;
     fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
-    items += two_pass ? (int64_t)qs.n_qblocks * n_tiles * kTileSplit : 0;
+    items += two_pass ? (int64_t)qs.n_qblocks * n_tiles : 0;
   }
   pl.total_samples = sb;
   pl.total_rows = rb;

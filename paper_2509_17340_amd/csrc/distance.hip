@@ -131,83 +131,119 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
 }
 
 
-// One pass-B item: the flagged queries of query block qb (R per lane) against the
-// cloud tile [g0, g1).
-template <int R>
+// One pass-B item: the flagged queries of query block qb (R per lane; their
+// positions as the flag kernel wrote them) against the cloud sub-tile [g0, g1).
+// With kIdx also the lowest point index attaining the minimum (points are visited
+// in increasing index order and ties never replace).
+template <int R, bool kIdx>
 __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64_t g0, int64_t g1,
                                    float4* tile) {
   const int tid = threadIdx.x;
   const int64_t lbase = qb * S.qpbA;
   float px[R], py[R], pz[R], best[R];
-  int32_t qi[R];
+  int32_t qi[R], bidx[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = r * kBlock + tid;
     const bool ok = j < cnt;
-    const int64_t slot = S.list[lbase + (ok ? j : 0)];  // cnt >= 1: entry 0 exists
-    const int64_t q = perm_query(S, slot);
-    qi[r] = ok ? (int32_t)slot : -1;
-    px[r] = S.px[q];
-    py[r] = S.py[q];
-    pz[r] = S.pz[q];
+    const int64_t e = lbase + (ok ? j : 0);  // cnt >= 1: entry 0 exists
+    qi[r] = ok ? S.list[e] : -1;
+    const float4 p = S.fpos[e];
+    px[r] = p.x;
+    py[r] = p.y;
+    pz[r] = p.z;
     best[r] = __uint_as_float(kInfBits);
+    bidx[r] = 0x7fffffff;
   }
-  if (S.nn) {
-    int32_t bidx[R];
+  const int n = (int)(g1 - g0);  // <= kSubPts
+  const int n2 = (n + 1) & ~1;    // even: the loop takes points in pairs
+  for (int pt = tid; pt < n2; pt += kBlock) {
+    const int64_t g = g0 + (pt < n ? pt : 0);  // always a valid address
+    tile[pt] = pt < n ? make_float4(S.cloud[3 * g], S.cloud[3 * g + 1], S.cloud[3 * g + 2], 0.0f)
+                      : make_float4(kFar, kFar, kFar, 0.0f);
+  }
+  __syncthreads();
+#pragma unroll 2
+  for (int j = 0; j < n2; j += 2) {
+    const float4 a = tile[j];
+    const float4 c = tile[j + 1];
 #pragma unroll
-    for (int r = 0; r < R; ++r) bidx[r] = 0x7fffffff;
-    direct_range<R, true>(S, g0, g1, tile, px, py, pz, best, bidx);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (qi[r] >= 0) {
-        atomicMin(S.out_slot + qi[r], __float_as_uint(best[r]));
-        atomicMin(S.nn + lbase + r * kBlock + tid,
-                  ((unsigned long long)__float_as_uint(best[r]) << 32) |
-                      (unsigned long long)(unsigned)bidx[r]);
+    for (int r = 0; r < R; ++r) {
+      const float ax = px[r] - a.x, ay = py[r] - a.y, az = pz[r] - a.z;
+      const float cx = px[r] - c.x, cy = py[r] - c.y, cz = pz[r] - c.z;
+      const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
+      const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+      if constexpr (kIdx) {
+        const int ia = (int)(g0 + j);
+        if (da < best[r]) {
+          best[r] = da;
+          bidx[r] = ia;
+        }
+        if (dc < best[r]) {
+          best[r] = dc;
+          bidx[r] = ia + 1;
+        }
+      } else {
+        best[r] = min3f(best[r], da, dc);
       }
-  } else {
-    direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
+    }
+  }
+  __syncthreads();  // the next item stages over the tile
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (qi[r] >= 0) atomicMin(S.out_slot + qi[r], __float_as_uint(best[r]));
+  for (int r = 0; r < R; ++r) {
+    if (qi[r] < 0) continue;
+    atomicMin(S.out_slot + qi[r], __float_as_uint(best[r]));
+    if constexpr (kIdx)
+      atomicMin(S.nn + lbase + r * kBlock + tid,
+                ((unsigned long long)__float_as_uint(best[r]) << 32) |
+                    (unsigned long long)(unsigned)bidx[r]);
   }
 }
 
-// Pass B: exact direct form for the flagged queries, only against the tiles where
-// pass A saw some query of their block under the bound (a query's nearest point
-// within d_max always lies in such a tile).  Persistent grid over the work lists
-// of every two-pass set; the lengths are read on the device.
+template <int R>
+__device__ inline void listed_item_r(const QuerySet& S, int64_t qb, int cnt, int64_t g0,
+                                     int64_t g1, float4* tile) {
+  if (S.nn)
+    listed_item<R, true>(S, qb, cnt, g0, g1, tile);
+  else
+    listed_item<R, false>(S, qb, cnt, g0, g1, tile);
+}
+
+// Pass B: exact direct form for the flagged queries, only against the sub-tiles that
+// pass A listed for their block (a query's nearest point within d_max always lies
+// in one).  Persistent grid over the work lists of every two-pass set (each entry
+// expanded into its kTileSplit sub-tiles, unlisted ones skipped); the lengths are
+// read on the device.
 __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __restrict__ sets,
                                                             int n_sets) {
-  __shared__ float4 tile[kTilePts];
+  __shared__ float4 tile[kSubPts];
   int64_t item_base = 0;
   for (int s = 0; s < n_sets; ++s) {
     const QuerySet& Sref = sets[s];
     if (!Sref.list || Sref.n_points <= 0) continue;
-    // one item per (query block, sub-tile) entry: kSubPts points, short enough
-    // workgroups to hide latency
-    const int64_t items = (int64_t)*Sref.work_count;
+    const int64_t items = (int64_t)*Sref.work_count * kTileSplit;
     int64_t first = ((int64_t)blockIdx.x - item_base) % gridDim.x;
     if (first < 0) first += gridDim.x;
     if (items > 0) {
       const QuerySet S = Sref;
       for (int64_t it = first; it < items; it += gridDim.x) {
-        const int2 wk = S.work[it];
+        const int2 wk = S.work[it / kTileSplit];
+        const int j = (int)(it % kTileSplit);
+        if (!((wk.y >> j) & 1)) continue;  // sub-tile not listed
         const int64_t qb = wk.x;
         const int cnt = min(S.seg_count[qb], S.qpbA);
-        if (cnt <= 0) continue;
-        const int64_t g0 = (int64_t)wk.y * kSubPts;
+        const int64_t g0 = ((int64_t)((unsigned)wk.y >> 4) * kTileSplit + j) * kSubPts;
         const int64_t g1 = min<int64_t>(g0 + kSubPts, S.n_points);
-        if (g0 >= g1) continue;
+        if (cnt <= 0 || g0 >= g1) continue;
         const int nr = (cnt + kBlock - 1) / kBlock;
         if (nr == 1)
-          listed_item<1>(S, qb, cnt, g0, g1, tile);
+          listed_item_r<1>(S, qb, cnt, g0, g1, tile);
         else if (nr == 2)
-          listed_item<2>(S, qb, cnt, g0, g1, tile);
+          listed_item_r<2>(S, qb, cnt, g0, g1, tile);
         else if (nr <= 4)
-          listed_item<4>(S, qb, cnt, g0, g1, tile);
+          listed_item_r<4>(S, qb, cnt, g0, g1, tile);
         else
-          listed_item<kQueriesPerLane>(S, qb, cnt, g0, g1, tile);
+          listed_item_r<kQueriesPerLane>(S, qb, cnt, g0, g1, tile);
       }
     }
     item_base += items;
@@ -369,6 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
     for (int i = 0; i < w; ++i) off += wave_cnt[i];
     const int64_t e = qb * S.qpbA + off;
     S.list[e] = (int32_t)slot;
+    const int64_t q = perm_query(S, slot);
+    S.fpos[e] = make_float4(S.px[q], S.py[q], S.pz[q], 0.0f);  // read back by pass B
     S.out_slot[slot] = kInfBits;
     if (S.nn) S.nn[e] = ~0ull;
   }
@@ -442,7 +480,7 @@ hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t max_items,
                                   hipStream_t s) {
   if (max_items > 0) {
-    const int64_t sub = max_items;  // entries are sub-tiles already
+    const int64_t sub = max_items * kTileSplit;  // entries expand into their sub-tiles
     const unsigned grid = (unsigned)(sub < kPersistBlocks ? sub : kPersistBlocks);
     k_min_dist_listed<<<grid, kBlock, 0, s>>>(d_sets, n_sets);
   }
