@@ -236,14 +236,17 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
         const int64_t g1 = min<int64_t>(g0 + kSubPts, S.n_points);
         if (cnt <= 0 || g0 >= g1) continue;
         const int nr = (cnt + kBlock - 1) / kBlock;
-        if (nr == 1)
-          listed_item_r<1>(S, qb, cnt, g0, g1, tile);
-        else if (nr == 2)
-          listed_item_r<2>(S, qb, cnt, g0, g1, tile);
-        else if (nr <= 4)
-          listed_item_r<4>(S, qb, cnt, g0, g1, tile);
-        else
-          listed_item_r<kQueriesPerLane>(S, qb, cnt, g0, g1, tile);
+        // exactly as many flagged queries per lane as the block has (no idle groups)
+        switch (nr) {
+          case 1: listed_item_r<1>(S, qb, cnt, g0, g1, tile); break;
+          case 2: listed_item_r<2>(S, qb, cnt, g0, g1, tile); break;
+          case 3: listed_item_r<3>(S, qb, cnt, g0, g1, tile); break;
+          case 4: listed_item_r<4>(S, qb, cnt, g0, g1, tile); break;
+          case 5: listed_item_r<5>(S, qb, cnt, g0, g1, tile); break;
+          case 6: listed_item_r<6>(S, qb, cnt, g0, g1, tile); break;
+          case 7: listed_item_r<7>(S, qb, cnt, g0, g1, tile); break;
+          default: listed_item_r<kQueriesPerLane>(S, qb, cnt, g0, g1, tile); break;
+        }
       }
     }
     item_base += items;
