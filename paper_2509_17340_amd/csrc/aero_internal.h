@@ -60,6 +60,7 @@ struct DevProblem {
   unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
   double* noise;         // [M][N][4][K] standard normals drawn ahead of the rollout
   unsigned* out_slot;    // sorted query set's distances by slot (or nullptr)
+  const int32_t* inv;    // sorted query set: query -> slot (or nullptr: distances in mind2)
   const int32_t* nidx_in;  // nearest indices given by the caller (indexed adjoint)
   int64_t elem_base;     // prefix of M*N*K over problems
 };
@@ -80,6 +81,7 @@ struct SortSet {
   uint32_t* key[2];      // [Q] ping-pong keys
   int32_t* val[2];       // [Q] ping-pong query indices; the result is
                          //   val[kSortPasses % 2]
+  int32_t* inv;          // [Q] query -> slot (written by the last pass)
   int32_t* table;        // [kSortDigits][n_blocks] per-block digit counts -> offsets
   int32_t* rowsum;       // [kSortDigits] digit totals
 };
@@ -241,8 +243,6 @@ hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t to
 hipError_t launch_min_dist_approx_matrix(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                          int variant, hipStream_t s);
 hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
-hipError_t launch_unpermute(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                            hipStream_t s);
 hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                                   hipStream_t s);
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);

@@ -281,7 +281,7 @@ struct MppiPlan {
   int64_t sort_blocks = 0;
   int64_t box_blocks = 0;       // sub-tile bounding boxes of the two-pass sets' clouds
   int64_t total_elems = 0;      // sum of M*N*K (rollout noise draws)
-  bool any_sorted = false;      // some set works in sorted slots (needs the unpermute)
+  bool any_sorted = false;      // some set works in sorted slots
   bool any_nn = false;          // some set records nearest indices
   size_t bytes = 0;
 };
@@ -394,6 +394,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       so.key[1] = cur.take<uint32_t>(MNK);
       so.val[0] = cur.take<int32_t>(MNK);
       so.val[1] = cur.take<int32_t>(MNK);
+      so.inv = cur.take<int32_t>(MNK);
       so.table = cur.take<int32_t>((int64_t)kSortDigits * so.n_blocks);
       so.rowsum = cur.take<int32_t>(kSortDigits);
       sort_blocks += so.n_blocks;
@@ -401,6 +402,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.out_slot = cur.take<unsigned>(MNK);
       d.sort_box = so.box;
       d.out_slot = qs.out_slot;
+      d.inv = so.inv;
       pl.any_sorted = true;
     }
     if (!qs.out_slot) qs.out_slot = qs.out;
@@ -727,9 +729,6 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   if (he == hipSuccess && pl.listed_items > 0)
     he = timed(AERO_K_MIN_DIST_EXACT, s,
                [&] { return launch_min_dist_listed(pl.d_sets, n, pl.listed_items, s); });
-  if (he == hipSuccess && pl.any_sorted)
-    he = timed(AERO_K_MIN_DIST_EXACT, s,
-               [&] { return launch_unpermute(pl.d_sets, n, pl.flag_blocks, s); });
   if (he == hipSuccess && pl.any_nn)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, n, s); });
   if (he == hipSuccess)
@@ -803,9 +802,6 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   if (he == hipSuccess && pl.listed_items > 0)
     he = timed(AERO_K_MIN_DIST_EXACT, s,
                [&] { return launch_min_dist_listed(pl.d_sets, 1, pl.listed_items, s); });
-  if (he == hipSuccess && pl.any_sorted)
-    he = timed(AERO_K_MIN_DIST_EXACT, s,
-               [&] { return launch_unpermute(pl.d_sets, 1, pl.flag_blocks, s); });
   if (he == hipSuccess && q.n_points > 0)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, 1, s); });
   if (he == hipSuccess)

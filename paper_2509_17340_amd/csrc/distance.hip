@@ -435,24 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_nearest(const QuerySet* __re
   }
 }
 
-// Distances by slot back to the positions' own layout (sorted sets only).
-__global__ __launch_bounds__(kBlock) void k_unpermute(const QuerySet* __restrict__ sets,
-                                                      int n_sets) {
-  const int64_t bid = blockIdx.x;
-  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.query_base; });
-  const QuerySet& S = sets[s];
-  if (!S.perm) return;
-  const int64_t slot = (bid - S.query_base) * kBlock + threadIdx.x;
-  if (slot < S.Q) S.out[perm_query(S, slot)] = S.out_slot[slot];
-}
-
 }  // namespace
-
-hipError_t launch_unpermute(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                            hipStream_t s) {
-  if (total_blocks > 0) k_unpermute<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
-  return hipGetLastError();
-}
 
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                            hipStream_t s) {

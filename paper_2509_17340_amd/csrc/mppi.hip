@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __rest
 // Per sample: the state terms over the horizon (tracking error to the guide at
 // (t+1) dt, speed, goal) and J_col, from the stored states and distances (or, with
 // stored nearest indices, from the distance to the stored point, formed exactly as
-// the exact distance pass forms it).  A block holds kFinSamples consecutive samples,
+// the exact distance pass forms it).  A spatially sorted set's distances are read
+// by slot through the inverse permutation and written back to min_dist2 here.  A block holds kFinSamples consecutive samples,
 // one per lane; its kFinWaves waves take consecutive parts of the horizon, and the
 // parts' sums are added in order.  write_s1 = false leaves S1 alone (the adjoint
 // needs the terms only).
@@ -286,6 +287,13 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(const DevProblem* _
         const float ay = P.pos[MNK + qi] - P.cloud[3 * (int64_t)idx + 1];
         const float az = P.pos[2 * MNK + qi] - P.cloud[3 * (int64_t)idx + 2];
         d2 = fmaf(az, az, fmaf(ay, ay, ax * ax));
+      } else if (P.inv) {
+        // sorted set: the distance by slot, written back to the positions' layout
+        // (the min_dist2 output) as it is read
+        const int32_t sl = P.inv[qi];
+        const unsigned bits = (sl >= 0 && sl < MNK) ? P.out_slot[sl] : kInfBits;
+        P.mind2[qi] = bits;
+        d2 = __uint_as_float(bits);
       } else {
         d2 = __uint_as_float(P.mind2[qi]);
       }

@@ -186,8 +186,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
     const int64_t pos = (int64_t)base[dig] + S.table[(int64_t)dig * S.n_blocks + e.blk] + before +
                         rank;
     if (pos >= 0 && pos < S.Q) {  // always true for consistent counts; never write outside
+      const int32_t v = S.val[src][e.i];
       S.key[1 - src][pos] = k;
-      S.val[1 - src][pos] = S.val[src][e.i];
+      S.val[1 - src][pos] = v;
+      if (pass == kSortPasses - 1 && v >= 0 && v < S.Q) S.inv[v] = (int32_t)pos;
     }
   }
 }
