@@ -103,16 +103,44 @@ __global__ void k_part_init(unsigned long long* key, unsigned* idx, int n, unsig
 }
 
 // Pass 1: per cone, the minimum r^2 (positive binary64 bit patterns order as integers).
+// Consecutive points of a scan fall into few cones, so the lanes of a wave first
+// combine their keys cone by cone (up to kConeRounds cones, one atomic each); lanes
+// still left after that issue their own atomic.  The minimum is the same either way.
+constexpr int kConeRounds = 8;
+
 __global__ void k_part_key(const float* __restrict__ cloud, int n_points, const float* tab,
                            int n_az, int n_el, double rmax2, unsigned long long* key) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_points) return;
-  const float x = cloud[3 * p], y = cloud[3 * p + 1], z = cloud[3 * p + 2];
-  const double r2 = range_key(x, y, z);
-  if (!(r2 > 0.0) || r2 > rmax2) return;
-  const Grid g = make_grid(tab, n_az, n_el);
-  const int c = el_bin(g, x, y, z) * n_az + az_bin(g, x, y);
-  atomicMin(key + c, (unsigned long long)__double_as_longlong(r2));
+  bool pending = false;
+  int c = 0;
+  unsigned long long k = ~0ull;
+  if (p < n_points) {
+    const float x = cloud[3 * p], y = cloud[3 * p + 1], z = cloud[3 * p + 2];
+    const double r2 = range_key(x, y, z);
+    if (r2 > 0.0 && r2 <= rmax2) {
+      const Grid g = make_grid(tab, n_az, n_el);
+      c = el_bin(g, x, y, z) * n_az + az_bin(g, x, y);
+      k = (unsigned long long)__double_as_longlong(r2);
+      pending = true;
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  for (int round = 0; round < kConeRounds; ++round) {  // every lane of the wave takes part
+    const unsigned long long pm = __ballot(pending);
+    if (pm == 0) break;
+    const int leader = __ffsll((long long)pm) - 1;
+    const int c0 = __shfl(c, leader, 64);
+    const bool mine = pending && c == c0;
+    unsigned long long m = mine ? k : ~0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long t = __shfl_xor(m, o, 64);
+      m = t < m ? t : m;
+    }
+    if (lane == leader) atomicMin(key + c0, m);
+    pending = pending && !mine;
+  }
+  if (pending) atomicMin(key + c, k);
 }
 
 // Pass 2: the lowest point index attaining the cone minimum.
