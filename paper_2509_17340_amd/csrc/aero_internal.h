@@ -19,6 +19,7 @@ namespace aero {
 
 constexpr int kBlock = 256;                              // threads per workgroup (4 wave64)
 constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points staged in LDS per tile
+constexpr int kSelCopies = 8;                            // Stage-II distance copies (atomics spread)
 constexpr int kTileSplit = 4;                            // sub-tiles per tile (pass-B work units)
 constexpr int kSubPts = kTilePts / kTileSplit;           // cloud points per sub-tile
 constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
@@ -51,7 +52,7 @@ struct DevProblem {
                          //   rollout and scored by the finalize kernel
   float* deff;           // [M][N][4][K]
   float* pos;            // [3][M][N][K] planes x, y, z
-  unsigned* mind2;       // [M][N][K] float bits of the squared nearest distance
+  unsigned* mind2;       // [kSelCopies][M][N] partial minima, merged by k_sel_final[K] float bits of the squared nearest distance
   int64_t sample_base;   // prefix of M*K over problems
   int64_t row_base;      // prefix of M*N over problems
   double* J;             // optional [5][M*K] unweighted terms (track, vnorm, ctrl, goal, col)
@@ -97,9 +98,12 @@ struct QuerySet {
   const float* px;
   const float* py;
   const float* pz;
-  unsigned* out;         // min squared distance as float bits, pre-filled with +inf
+  unsigned* out;         // min squared distance as float bits, pre-filled with +inf;
+                         //   exact sets: n_copies arrays of Q, merged by their reader
   const float* cloud;    // [n_points][3]
   int64_t Q;             // queries
+  int32_t n_copies;      // exact sets: copies of `out` that workgroups spread their
+                         //   atomics over (workgroup b uses copy b % n_copies)
   int32_t n_points;
   int32_t n_qblocks;     // ceil(Q / kQueriesPerBlock)
   int32_t n_chunks;      // cloud splits of the full pass: chunk c covers points
@@ -201,7 +205,7 @@ struct DevSelect {
   const float* u_nom;    // [M][N][4]
   double* state;         // [M][N][10] states of the noise-free rollouts
   float* pos;            // [3][M][N]
-  unsigned* mind2;       // [M][N]
+  unsigned* mind2;       // [kSelCopies][M][N] partial minima, merged by k_sel_final
   double* S2;            // [M] (caller's array + offset)
   int32_t* best;         // caller's array + problem index
   int64_t inst_base;     // prefix of M

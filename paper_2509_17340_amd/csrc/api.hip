@@ -528,7 +528,7 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     d.u_nom = q.u_nom;
     d.state = cur.take<double>(10 * MN);
     d.pos = cur.take<float>(3 * MN);
-    d.mind2 = cur.take<unsigned>(MN);
+    d.mind2 = cur.take<unsigned>(kSelCopies * MN);
     d.S2 = S2 ? S2 + ib : nullptr;
     d.best = best ? best + b : nullptr;
     d.inst_base = ib;
@@ -538,6 +538,7 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     qs.py = d.pos ? d.pos + MN : nullptr;
     qs.pz = d.pos ? d.pos + 2 * MN : nullptr;
     qs.out = d.mind2;
+    qs.n_copies = kSelCopies;  // hundreds of workgroups meet on each query's minimum
     qs.cloud = q.cloud;
     qs.Q = MN;
     qs.n_points = q.n_points;

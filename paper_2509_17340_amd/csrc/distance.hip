@@ -107,10 +107,11 @@ __device__ inline void exact_block(const QuerySet& S, int qb, int ch, float4* ti
   const int64_t g0 = (int64_t)ch * S.chunk_pts;
   const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
   direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
+  unsigned* out = S.out + (int64_t)(blockIdx.x % max(S.n_copies, 1)) * S.Q;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t q = (int64_t)qb * (R * kBlock) + r * kBlock + tid;
-    if (q < S.Q) atomicMin(S.out + q, __float_as_uint(best[r]));
+    if (q < S.Q) atomicMin(out + q, __float_as_uint(best[r]));
   }
 }
 

@@ -428,7 +428,8 @@ __global__ __launch_bounds__(kBlock) void k_sel_rollout(const DevSelect* __restr
       pos[row] = (float)x[0];
       pos[MN + row] = (float)x[1];
       pos[2 * MN + row] = (float)x[2];
-      mind2[row] = kInfBits;
+#pragma unroll
+      for (int c = 0; c < kSelCopies; ++c) mind2[c * MN + row] = kInfBits;
     }
   }
 }
@@ -445,6 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_final(const DevSelect* __restric
   __shared__ double term[2][kSelTerms];
   const DevSelect& P = sel[blockIdx.x];
   const int M = P.M, N = P.N;
+  const int64_t MN = (int64_t)M * N;
   const double pg[3] = {P.pg[0], P.pg[1], P.pg[2]}, vg[3] = {P.vg[0], P.vg[1], P.vg[2]};
   double Rg[9];
   load_rg(P.qg, Rg);
@@ -459,7 +461,10 @@ __global__ __launch_bounds__(kBlock) void k_sel_final(const DevSelect* __restric
 #pragma unroll
       for (int i = 0; i < 10; ++i) x[i] = P.state[row * 10 + i];
       term[0][r] = goal_term(x, pg, vg, Rg, prm);
-      term[1][r] = collision_phi(sqrt((double)__uint_as_float(P.mind2[row])), prm);
+      unsigned bits = P.mind2[row];  // merge the distance copies
+#pragma unroll
+      for (int c = 1; c < kSelCopies; ++c) bits = min(bits, P.mind2[c * MN + row]);
+      term[1][r] = collision_phi(sqrt((double)__uint_as_float(bits)), prm);
     }
     __syncthreads();
     if ((int)threadIdx.x < M)
