@@ -396,6 +396,9 @@ def main():
                      "distance_all_passes_tflops": flop / (dist_ms * 1e-3) / 1e12},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
     }
+    # the cost kernel's algorithmic FLOP rate against the FP32 vector peak (the scale
+    # on which the plain VALU form of the pass is judged), whichever variant runs
+    out["roofline"]["algorithmic_frac_of_fp32_valu_peak"] = achieved / FP32_PEAK_TFLOPS
     if variant == 2:
         out["roofline"]["pair_ceiling_per_s"] = F16S_PAIR_CEILING
         out["roofline"]["frac_of_pair_ceiling"] = pairs_per_s / F16S_PAIR_CEILING
