@@ -146,6 +146,128 @@ __device__ __forceinline__ void rk4(double* x, const double* u, double dt, const
   x[6] *= inv;
 }
 
+// ---------------------------------------------------------------------------
+// The same RK4 step spread over the four lanes of a quad (one rollout per quad).
+// Lane c (0..3) holds the quaternion component q_c (w, x, y, z) and, for c < 3, the
+// position and velocity components p_c and v_c; a lane computes the derivatives of
+// its own components only.  The quaternion is the one state the others depend on
+// (q' = Omega(omega) q / 2, v' from R(q) e3, p' = v), so after each stage the four
+// lanes exchange their components with DPP moves inside the quad.  The per-component
+// arithmetic is that of xdot_held and rk4 above.
+// ---------------------------------------------------------------------------
+constexpr int quad_perm(int a, int b, int c, int d) { return a | b << 2 | c << 4 | d << 6; }
+
+// Lane src_c of the quad's value, for lane c of every quad (Ctrl a quad permutation).
+template <int Ctrl>
+__device__ __forceinline__ double quad_move(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  // every lane of a quad permutation has a source, so no old value is needed
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, Ctrl, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), Ctrl, 0xf, 0xf,
+                                                         true);
+  return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+__device__ __forceinline__ void quad_gather(double own, double all[4]) {
+  all[0] = quad_move<quad_perm(0, 0, 0, 0)>(own);
+  all[1] = quad_move<quad_perm(1, 1, 1, 1)>(own);
+  all[2] = quad_move<quad_perm(2, 2, 2, 2)>(own);
+  all[3] = quad_move<quad_perm(3, 3, 3, 3)>(own);
+}
+
+__device__ __forceinline__ double flip_sign(double x, uint32_t sign_hi) {
+  uint64_t b = __builtin_bit_cast(uint64_t, x);
+  b ^= (uint64_t)sign_hi << 32;
+  return __builtin_bit_cast(double, b);
+}
+
+// Lane constants of the quad layout.
+struct QuadLane {
+  int c;                   // component / control channel of this lane
+  uint32_t sgn1, sgn2, sgn3;  // sign bits of this lane's row of Omega (columns x, y, z)
+};
+
+__device__ __forceinline__ QuadLane quad_lane(int lane) {
+  QuadLane L;
+  L.c = lane & 3;
+  // Row c of Omega(omega/2) over (w, x, y, z):
+  //   c=0 ( 0, -hx, -hy, -hz)   c=1 (hx,  0,  hz, -hy)
+  //   c=2 (hy, -hz,  0,  hx)    c=3 (hz,  hy, -hx,  0)
+  // column 0 is this lane's own held half rate (0 on lane 0), and columns 1..3 are
+  // the held half rates of lanes (1,0,3,2), (2,3,0,1), (3,2,1,0) with these signs.
+  const uint32_t m = 0x80000000u;
+  L.sgn1 = (L.c == 0 || L.c == 2) ? m : 0u;
+  L.sgn2 = (L.c == 0 || L.c == 3) ? m : 0u;
+  L.sgn3 = (L.c == 0 || L.c == 1) ? m : 0u;
+  return L;
+}
+
+// The held control of one step in quad form: this lane's row of Omega(omega)/2 and the
+// mass-specific thrust (from lane 0's channel).
+struct QuadControl {
+  double row[4];
+  double am, am2;
+};
+
+__device__ __forceinline__ QuadControl quad_control(double u_c, const QuadLane& L, const Dyn& d) {
+  QuadControl q;
+  const double h = L.c == 0 ? 0.0 : 0.5 * u_c;  // omega_c / 2 on lanes 1..3
+  q.am = quad_move<quad_perm(0, 0, 0, 0)>(u_c * d.inv_m);
+  q.am2 = 2.0 * q.am;
+  q.row[0] = h;
+  q.row[1] = flip_sign(quad_move<quad_perm(1, 0, 3, 2)>(h), L.sgn1);
+  q.row[2] = flip_sign(quad_move<quad_perm(2, 3, 0, 1)>(h), L.sgn2);
+  q.row[3] = flip_sign(quad_move<quad_perm(3, 2, 1, 0)>(h), L.sgn3);
+  return q;
+}
+
+// Derivatives of this lane's quaternion and velocity components at the stage whose
+// quaternion (all four components) is qa.
+__device__ __forceinline__ void quad_xdot(const double qa[4], const QuadControl& u,
+                                          const QuadLane& L, const Dyn& d, double& dq,
+                                          double& dv) {
+  const double qw = qa[0], qx = qa[1], qy = qa[2], qz = qa[3];
+  double r = u.row[0] * qw;
+  r = fma(u.row[1], qx, r);
+  r = fma(u.row[2], qy, r);
+  dq = fma(u.row[3], qz, r);
+  const double e0 = qx * qz + qw * qy;
+  const double e1 = qy * qz - qw * qx;
+  const double e2 = qx * qx + qy * qy;
+  const double vxy = u.am2 * (L.c == 0 ? e0 : e1);
+  const double vz = u.am * (1.0 - 2.0 * e2) - d.g;
+  dv = L.c == 2 ? vz : vxy;
+}
+
+// One RK4 step of the quad's rollout with the control held, then the quaternion
+// renormalisation.  p, v, q are this lane's components (p, v unused on lane 3); qa
+// holds all four quaternion components on entry and on return.
+__device__ __forceinline__ void quad_rk4(double& p, double& v, double& q, double qa[4],
+                                         const QuadControl& u, const QuadLane& L, double dt,
+                                         const Dyn& d) {
+  double kq1, kv1, kq2, kv2, kq3, kv3, kq4, kv4, ya[4];
+  quad_xdot(qa, u, L, d, kq1, kv1);
+  const double kp1 = v;
+  const double kp2 = v + 0.5 * dt * kv1;
+  quad_gather(q + 0.5 * dt * kq1, ya);
+  quad_xdot(ya, u, L, d, kq2, kv2);
+  const double kp3 = v + 0.5 * dt * kv2;
+  quad_gather(q + 0.5 * dt * kq2, ya);
+  quad_xdot(ya, u, L, d, kq3, kv3);
+  const double kp4 = v + dt * kv3;
+  quad_gather(q + dt * kq3, ya);
+  quad_xdot(ya, u, L, d, kq4, kv4);
+  const double h6 = dt / 6.0;
+  p = p + h6 * (kp1 + 2.0 * kp2 + 2.0 * kp3 + kp4);
+  v = v + h6 * (kv1 + 2.0 * kv2 + 2.0 * kv3 + kv4);
+  q = q + h6 * (kq1 + 2.0 * kq2 + 2.0 * kq3 + kq4);
+  quad_gather(q, qa);
+  const double inv = rsqrt_refined(qa[0] * qa[0] + qa[1] * qa[1] + qa[2] * qa[2] + qa[3] * qa[3]);
+  q *= inv;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) qa[i] *= inv;
+}
+
 // R(q) of a unit quaternion, row-major.
 __device__ __forceinline__ void rotmat(double w, double x, double y, double z, double R[9]) {
   R[0] = 1.0 - 2.0 * (y * y + z * z);

@@ -20,6 +20,12 @@ namespace aero {
 constexpr int kBlock = 256;                              // threads per workgroup (4 wave64)
 constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points staged in LDS per tile
 constexpr int kSelCopies = 8;                            // Stage-II distance copies (atomics spread)
+// The rollout's waves merge their position bounds into kBoxCopies copies of the sort
+// box (a wave's copy is its workgroup index modulo kBoxCopies), each in a 256-byte
+// line of its own, so that hundreds of waves do not meet on one word; the sort
+// merges the copies.
+constexpr int kBoxCopies = 16;
+constexpr int kBoxStride = 64;  // words per copy
 constexpr int kTileSplit = 4;                            // sub-tiles per tile (pass-B work units)
 constexpr int kSubPts = kTilePts / kTileSplit;           // cloud points per sub-tile
 constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
@@ -52,13 +58,14 @@ struct DevProblem {
                          //   rollout and scored by the finalize kernel
   float* deff;           // [M][N][4][K]
   float* pos;            // [3][M][N][K] planes x, y, z
-  unsigned* mind2;       // [kSelCopies][M][N] partial minima, merged by k_sel_final[K] float bits of the squared nearest distance
+  unsigned* mind2;       // [M][N][K] float bits of the squared nearest distance
   int64_t sample_base;   // prefix of M*K over problems
   int64_t row_base;      // prefix of M*N over problems
   double* J;             // optional [5][M*K] unweighted terms (track, vnorm, ctrl, goal, col)
   int32_t* nidx;         // optional [M][N][K] nearest point index (-1: none within reach)
   int32_t* work_count;   // pass-B work counter of the problem's query set (or nullptr)
-  unsigned* sort_box;    // [6] position bounding box of the spatial sort (or nullptr)
+  unsigned* sort_box;    // [kBoxCopies][kBoxStride] copies of the position bounding box
+                         //   of the spatial sort (or nullptr)
   double* noise;         // [M][N][4][K] standard normals drawn ahead of the rollout
   unsigned* out_slot;    // sorted query set's distances by slot (or nullptr)
   const int32_t* inv;    // sorted query set: query -> slot (or nullptr: distances in mind2)
@@ -78,7 +85,8 @@ struct SortSet {
   int64_t block_base;    // prefix of n_blocks over sets
   int32_t n_blocks;      // ceil(Q / kBlock)
   int32_t pad;
-  unsigned* box;         // [6] order-preserving bits: min x, y, z, max x, y, z
+  unsigned* box;         // [kBoxCopies][kBoxStride] copies; words 0..5 of each hold the
+                         //   order-preserving bits of min x, y, z, max x, y, z
   uint32_t* key[2];      // [Q] ping-pong keys
   int32_t* val[2];       // [Q] ping-pong query indices; the result is
                          //   val[kSortPasses % 2]

@@ -389,7 +389,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       so.pz = qs.pz;
       so.Q = MNK;
       so.n_blocks = (int32_t)((MNK + kBlock - 1) / kBlock);
-      so.box = cur.take<unsigned>(6);
+      so.box = cur.take<unsigned>(kBoxCopies * kBoxStride);
       so.key[0] = cur.take<uint32_t>(MNK);
       so.key[1] = cur.take<uint32_t>(MNK);
       so.val[0] = cur.take<int32_t>(MNK);

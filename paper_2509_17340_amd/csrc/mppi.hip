@@ -2,13 +2,13 @@
 //
 //   k_noise        the rollout's standard normals (Philox, Box-Muller), drawn in
 //                  parallel; resets the per-call outputs
-//   k_rollout      one lane per (problem, instance, sample): clip, RK4 in binary64,
+//   k_rollout      one quad of lanes per (problem, instance, sample): clip, RK4 in binary64,
 //                  the control term; writes the clipped perturbations, float32
 //                  positions and binary64 states as sample-fastest planes, and the
 //                  positions' bounding box for the spatial sort
 //   (the nearest-distance kernels live in distance.hip)
 //   k_finalize     per sample, the state terms (tracking, speed, goal) and J_col,
-//                  with the horizon split over the block's four waves; S1
+//                  with the horizon split over the block's eight waves; S1
 //   k_update       per (instance, step): rho, eta, and sum_k eps_k delta_eff_k
 //                  with fixed-order wave/block reductions in binary64
 //   k_sel_rollout  Stage II noise-free rollouts (states and positions)
@@ -57,10 +57,11 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   if (local == 0) {
     if (P.work_count) *P.work_count = 0;  // pass B's work list of this call
     if (P.sort_box)
-      for (int a = 0; a < 3; ++a) {
-        P.sort_box[a] = 0xffffffffu;      // order-preserving bits: running min, max
-        P.sort_box[3 + a] = 0u;
-      }
+      for (int cp = 0; cp < kBoxCopies; ++cp)
+        for (int a = 0; a < 3; ++a) {
+          P.sort_box[cp * kBoxStride + a] = 0xffffffffu;  // order-preserving bits: running
+          P.sort_box[cp * kBoxStride + 3 + a] = 0u;       // min, max
+        }
   }
   double nz[4];
   normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
@@ -72,50 +73,65 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   if (P.nidx) P.nidx[local] = -1;
 }
 
-// Merge this lane's position bounds into its problem's sort box: one atomic per
-// wave and bound where the wave's active lanes share a problem, else per lane.
-__device__ inline void merge_box(const DevProblem* __restrict__ probs, bool active, int b,
-                                 float lo[3], float hi[3]) {
+// Merge the position bounds of a wave's rollouts into their problems' sort boxes
+// (the workgroup's copy).  Lane c < 3 of each quad holds the bounds of component c:
+// one atomic per wave and component where the wave's active quads share a problem,
+// else per lane.
+__device__ inline void merge_box_quad(const DevProblem* __restrict__ probs, bool active, int b,
+                                      int c, float lo, float hi) {
   const int b0 = __shfl(b, 0, 64);
   const bool one = __all(!active || b == b0);
   if (one) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = wave_minf(lo[a]);
-      hi[a] = wave_maxf(hi[a]);
+    for (int o = 4; o < 64; o <<= 1) {
+      lo = fminf(lo, __shfl_xor(lo, o, 64));
+      hi = fmaxf(hi, __shfl_xor(hi, o, 64));
     }
     unsigned* box = probs[b0].sort_box;
-    if ((threadIdx.x & 63) == 0 && box && lo[0] <= hi[0])
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        atomicMin(box + a, ord_bits(lo[a]));
-        atomicMax(box + 3 + a, ord_bits(hi[a]));
-      }
-  } else if (active && lo[0] <= hi[0]) {
+    if ((threadIdx.x & 63) < 3 && box && lo <= hi) {
+      box += (blockIdx.x % kBoxCopies) * kBoxStride;
+      atomicMin(box + c, ord_bits(lo));
+      atomicMax(box + 3 + c, ord_bits(hi));
+    }
+  } else if (active && c < 3 && lo <= hi) {
     unsigned* box = probs[b].sort_box;
-    if (box)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        atomicMin(box + a, ord_bits(lo[a]));
-        atomicMax(box + 3 + a, ord_bits(hi[a]));
-      }
+    if (box) {
+      box += (blockIdx.x % kBoxCopies) * kBoxStride;
+      atomicMin(box + c, ord_bits(lo));
+      atomicMax(box + 3 + c, ord_bits(hi));
+    }
   }
 }
 
 // The sequential part of Stage I: only the dynamics and the control term, so that
 // the chain of dependent binary64 operations per step is as short as the model
 // allows; the state terms are scored in parallel by k_finalize.
-// One wave per workgroup: the sequential rollouts are few (one lane per sample), and
-// spreading their waves over as many CUs as possible gives each wave a CU's whole
-// store path (every step writes 108 bytes per sample).
+// One rollout per quad of lanes (quad_rk4): lane c perturbs and clips control channel
+// c, writes its clipped perturbation, and integrates state components c (quaternion)
+// and, for c < 3, position and velocity c.  Four lanes per sample give the
+// sequential part four times the waves, and each lane a quarter of the arithmetic.
+// One wave per workgroup spreads the waves over as many CUs as possible.
 constexpr int kRollBlock = 64;
-constexpr int kAhead = 2;  // steps of inputs loaded ahead (the stores of two steps stay
-                           // below the 63 outstanding vector-memory operations)
+// Steps of inputs loaded ahead.  Loads and stores share the in-order vector-memory
+// counter, so the wait for a step's inputs also waits for the stores issued before
+// them: with inputs loaded A steps ahead a step waits only for the stores of step
+// t - A - 1, and the latency of a store's acknowledgement is spread over A + 1 steps.
+// Each lane has 7 vector-memory operations per step in flight (2 loads, 5 stores),
+// within the 63 the counter holds for A <= 8.
+#ifndef AERO_ROLL_AHEAD
+#define AERO_ROLL_AHEAD 2
+#endif
+constexpr int kAhead = AERO_ROLL_AHEAD;
+static_assert(kAhead >= 1 && 7 * kAhead <= 63, "inputs ahead within the vector-memory counter");
+static_assert(kSelCopies == 8, "Stage II: each lane of a quad resets two distance copies");
+
 __global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __restrict__ probs,
                                                         int n, int64_t total, DevParams prm) {
-  const int64_t gid = (int64_t)blockIdx.x * kRollBlock + threadIdx.x;
-  const bool active = gid < total;
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  const int64_t gid = ((int64_t)blockIdx.x * kRollBlock + threadIdx.x) >> 2;  // sample
+  const QuadLane L = quad_lane(threadIdx.x);
+  const int c = L.c;
+  const bool active = gid < total;  // uniform over the quad
+  float lo = INFINITY, hi = -INFINITY;
   int b = 0;
   if (active) {
     b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.sample_base; });
@@ -133,23 +149,29 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __rest
     AERO_GLOBAL float* __restrict__ pos = global_ptr(P.pos);
     AERO_GLOBAL double* __restrict__ state = global_ptr(P.state);
     const Dyn dyn{1.0 / prm.mass, prm.gravity};
-    double x[10];
-#pragma unroll
-    for (int i = 0; i < 10; ++i) x[i] = P.x0[i];
-    double s_u2 = 0.0, s_du2 = 0.0;
-    double up[4] = {0.0, 0.0, 0.0, 0.0};
+    // this lane's channel constants (selected, not indexed: the arrays are kernel
+    // arguments)
+    const double sig = c == 0 ? prm.sigma[0] : c == 1 ? prm.sigma[1] : c == 2 ? prm.sigma[2]
+                                                                              : prm.sigma[3];
+    const double umin = c == 0 ? prm.u_min[0] : c == 1 ? prm.u_min[1] : c == 2 ? prm.u_min[2]
+                                                                               : prm.u_min[3];
+    const double umax = c == 0 ? prm.u_max[0] : c == 1 ? prm.u_max[1] : c == 2 ? prm.u_max[2]
+                                                                               : prm.u_max[3];
+    const bool pv = c < 3;  // lane 3 carries no position or velocity
+    double p = P.x0[pv ? c : 0], v = P.x0[pv ? 7 + c : 7], q = P.x0[3 + c];
+    double qa[4] = {P.x0[3], P.x0[4], P.x0[5], P.x0[6]};
+    double s_u2 = 0.0, s_du2 = 0.0, up = 0.0;
     // The steps' inputs (normals and nominal controls) are loaded kAhead steps ahead
     // into a ring: a wait for a load also waits for every store issued before it,
     // so a load issued only one step ahead would put that step's stores on the
     // chain of dependent steps.
-    double nzr[kAhead][4], unr[kAhead][4];
-    auto fetch = [&](int t, double* nz, double* un) {
+    // (kept as loaded: converting a value when it is loaded would wait for it there)
+    double nzr[kAhead];
+    float unr[kAhead];
+    auto fetch = [&](int t, double& nz, float& un) {
       const int64_t r = (int64_t)m * N + (t < N ? t : N - 1);  // in bounds; unused past N-1
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        nz[c] = noise[(r * 4 + c) * K + k];
-        un[c] = u_nom[r * 4 + c];
-      }
+      nz = noise[(r * 4 + c) * K + k];
+      un = u_nom[r * 4 + c];
     };
 #pragma unroll
     for (int j = 0; j < kAhead; ++j) fetch(j, nzr[j], unr[j]);
@@ -158,49 +180,49 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __rest
       for (int j = 0; j < kAhead; ++j) {
         const int t = t0 + j;
         if (t >= N) break;
-        // perturbed, clipped control and its deviation, the RK4 update, and the
-        // control terms (u_t for t <= N-2, the change for 1 <= t <= N-2; predicated)
+        // perturbed, clipped control channel c and its deviation, the RK4 update, and
+        // the control terms (u_t for t <= N-2, the change for 1 <= t <= N-2)
         const int64_t row = (int64_t)m * N + t;
-        double u[4], unv[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          unv[c] = unr[j][c];
-          const double v = unv[c] + prm.sigma[c] * nzr[j][c];
-          u[c] = fmin(fmax(v, prm.u_min[c]), prm.u_max[c]);
-        }
+        const double un = unr[j];
+        const double u = fmin(fmax(un + sig * nzr[j], umin), umax);
         fetch(t + kAhead, nzr[j], unr[j]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) deff[(row * 4 + c) * K + k] = (float)(u[c] - unv[c]);
-        rk4(x, u, prm.dt, dyn);
+        const float de = (float)(u - un);
+        AERO_GLOBAL float* de_at = deff + (row * 4 + c) * K + k;
+        *de_at = de;
+        const QuadControl qc = quad_control(u, L, dyn);
+        quad_rk4(p, v, q, qa, qc, L, prm.dt, dyn);
         const int64_t qi = row * K + k;
-        const float p3[3] = {(float)x[0], (float)x[1], (float)x[2]};
-        pos[qi] = p3[0];
-        pos[MNK + qi] = p3[1];
-        pos[2 * MNK + qi] = p3[2];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          lo[a] = fminf(lo[a], p3[a]);
-          hi[a] = fmaxf(hi[a], p3[a]);
-        }
-        // one 80-byte record per position (five 16-byte stores from one address)
-        AERO_GLOBAL dvec2* st = reinterpret_cast<AERO_GLOBAL dvec2*>(state + qi * 10);
-#pragma unroll
-        for (int i = 0; i < 5; ++i) st[i] = dvec2{x[2 * i], x[2 * i + 1]};
-        const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-        const double d0 = u[0] - up[0], d1 = u[1] - up[1], d2 = u[2] - up[2], d3 = u[3] - up[3];
-        const double du2 = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
-        s_u2 += t <= N - 2 ? u2 : 0.0;
-        s_du2 += (t >= 1 && t <= N - 2) ? du2 : 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) up[c] = u[c];
+        // one 80-byte record [p, q, v] per position, written by the quad.  The loop
+        // body has no branch (so that the compiler's waits for the loads ahead stay
+        // exact): lane 3, which has no position or velocity, stores its own values
+        // again to its own addresses instead.
+        AERO_GLOBAL double* rec = state + qi * 10;
+        const float pf = (float)p;
+        rec[3 + c] = q;
+        *(pv ? pos + c * MNK + qi : de_at) = pv ? pf : de;
+        rec[pv ? c : 6] = pv ? p : q;
+        rec[pv ? 7 + c : 6] = pv ? v : q;
+        lo = fminf(lo, pv ? pf : INFINITY);
+        hi = fmaxf(hi, pv ? pf : -INFINITY);
+        const double du = u - up;
+        s_u2 += t <= N - 2 ? u * u : 0.0;
+        s_du2 += (t >= 1 && t <= N - 2) ? du * du : 0.0;
+        up = u;
       }
     }
-    const double J_ctrl = prm.Q_c * s_u2 + prm.Q_cdelta * s_du2;
-    const int64_t i = (int64_t)m * K + k;
-    P.J_ctrl[i] = J_ctrl;
-    if (P.J) P.J[2 * (int64_t)P.M * K + i] = J_ctrl;
+    // the quad's channel sums, added in a fixed order
+    s_u2 += __shfl_xor(s_u2, 1, 64);
+    s_du2 += __shfl_xor(s_du2, 1, 64);
+    s_u2 += __shfl_xor(s_u2, 2, 64);
+    s_du2 += __shfl_xor(s_du2, 2, 64);
+    if (c == 0) {
+      const double J_ctrl = prm.Q_c * s_u2 + prm.Q_cdelta * s_du2;
+      const int64_t i = (int64_t)m * K + k;
+      P.J_ctrl[i] = J_ctrl;
+      if (P.J) P.J[2 * (int64_t)P.M * K + i] = J_ctrl;
+    }
   }
-  merge_box(probs, active, b, lo, hi);
+  merge_box_quad(probs, active, b, c, lo, hi);
 }
 
 // Per sample: the state terms over the horizon (tracking error to the guide at
@@ -386,50 +408,51 @@ __global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict_
   }
 }
 
+// Stage II noise-free rollouts, one per quad of lanes as in k_rollout.
 __global__ __launch_bounds__(kBlock) void k_sel_rollout(const DevSelect* __restrict__ sel, int n,
                                                         int64_t total, DevParams prm) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= total) return;
+  const int64_t gid = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 2;  // instance
+  if (gid >= total) return;  // whole quads
+  const QuadLane L = quad_lane(threadIdx.x);
+  const int c = L.c;
   const int b = find_owner(sel, n, gid, [](const DevSelect& p) { return p.inst_base; });
   const DevSelect& P = sel[b];
   const int m = (int)(gid - P.inst_base), N = P.N;
   const int64_t MN = (int64_t)P.M * N;
   const Dyn dyn{1.0 / prm.mass, prm.gravity};
-  double x[10];
-#pragma unroll
-  for (int i = 0; i < 10; ++i) x[i] = P.x0[i];
+  const bool pv = c < 3;  // lane 3 carries no position or velocity
+  double p = P.x0[pv ? c : 0], v = P.x0[pv ? 7 + c : 7], q = P.x0[3 + c];
+  double qa[4] = {P.x0[3], P.x0[4], P.x0[5], P.x0[6]};
   // global pointers in registers (see k_rollout)
   AERO_GLOBAL const float* __restrict__ u_nom = global_ptr(P.u_nom);
   AERO_GLOBAL double* __restrict__ state = global_ptr(P.state);
   AERO_GLOBAL float* __restrict__ pos = global_ptr(P.pos);
   AERO_GLOBAL unsigned* __restrict__ mind2 = global_ptr(P.mind2);
-  // controls loaded kAhead steps ahead (see k_rollout)
-  double ur[kAhead][4];
-  auto fetch = [&](int t, double* u) {
-    const int64_t r = (int64_t)m * N + (t < N ? t : N - 1);
+  // control channel c loaded kAhead steps ahead (see k_rollout)
+  float ur[kAhead];  // as loaded (see k_rollout)
+  auto fetch = [&](int t) { return u_nom[((int64_t)m * N + (t < N ? t : N - 1)) * 4 + c]; };
 #pragma unroll
-    for (int c = 0; c < 4; ++c) u[c] = u_nom[r * 4 + c];
-  };
-#pragma unroll
-  for (int j = 0; j < kAhead; ++j) fetch(j, ur[j]);
+  for (int j = 0; j < kAhead; ++j) ur[j] = fetch(j);
   for (int t0 = 0; t0 < N; t0 += kAhead) {
 #pragma unroll
     for (int j = 0; j < kAhead; ++j) {
       const int t = t0 + j;
       if (t >= N) break;
       const int64_t row = (int64_t)m * N + t;
-      double u[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) u[c] = ur[j][c];
-      fetch(t + kAhead, ur[j]);
-      rk4(x, u, prm.dt, dyn);
-#pragma unroll
-      for (int i = 0; i < 10; ++i) state[row * 10 + i] = x[i];
-      pos[row] = (float)x[0];
-      pos[MN + row] = (float)x[1];
-      pos[2 * MN + row] = (float)x[2];
-#pragma unroll
-      for (int c = 0; c < kSelCopies; ++c) mind2[c * MN + row] = kInfBits;
+      const double u = ur[j];
+      ur[j] = fetch(t + kAhead);
+      const QuadControl qc = quad_control(u, L, dyn);
+      quad_rk4(p, v, q, qa, qc, L, prm.dt, dyn);
+      // branch-free stores as in k_rollout (lane 3 repeats its own)
+      AERO_GLOBAL double* rec = state + row * 10;
+      AERO_GLOBAL unsigned* md = mind2 + (2 * c) * MN + row;
+      md[0] = kInfBits;
+      md[MN] = kInfBits;
+      rec[3 + c] = q;
+      rec[pv ? c : 6] = pv ? p : q;
+      rec[pv ? 7 + c : 6] = pv ? v : q;
+      *(pv ? reinterpret_cast<AERO_GLOBAL unsigned*>(pos + c * MN + row) : md) =
+          pv ? __float_as_uint((float)p) : kInfBits;
     }
   }
 }
@@ -580,15 +603,15 @@ hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_
   if (nb + box_blocks > 0)
     k_noise<<<(unsigned)(nb + box_blocks), kBlock, 0, s>>>(d_probs, n, total_elems, prm, d_sets, n,
                                                           nb);
-  k_rollout<<<(unsigned)((total_samples + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(
+  k_rollout<<<(unsigned)((4 * total_samples + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(
       d_probs, n, total_samples, prm);
   return hipGetLastError();
 }
 
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
                           hipStream_t s) {
-  k_rollout<<<(unsigned)((total + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(d_probs, n,
-                                                                                     total, prm);
+  k_rollout<<<(unsigned)((4 * total + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(
+      d_probs, n, total, prm);
   return hipGetLastError();
 }
 
@@ -608,7 +631,7 @@ hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
 
 hipError_t launch_select_rollout(const DevSelect* d_sel, int n, int64_t total_inst,
                                  const DevParams& prm, hipStream_t s) {
-  k_sel_rollout<<<grid1d(total_inst), kBlock, 0, s>>>(d_sel, n, total_inst, prm);
+  k_sel_rollout<<<grid1d(4 * total_inst), kBlock, 0, s>>>(d_sel, n, total_inst, prm);
   return hipGetLastError();
 }
 

@@ -57,12 +57,14 @@ __device__ inline Elem locate(const SortSet* sets, int n_sets) {
 }
 
 // Morton key of an element from its position and the set's bounding box.
-__device__ inline uint32_t morton_key(const SortSet& S, int64_t i) {
+// box: the set's bounding box (order-preserving bits), merged from the rollout's
+// copies by merge_box_copies.
+__device__ inline uint32_t morton_key(const SortSet& S, const unsigned box[6], int64_t i) {
   float lo[3], ext = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = ord_float(S.box[a]);
-    ext = fmaxf(ext, ord_float(S.box[3 + a]) - lo[a]);
+    lo[a] = ord_float(box[a]);
+    ext = fmaxf(ext, ord_float(box[3 + a]) - lo[a]);
   }
   const float scale = ext > 0.0f ? 255.99f / ext : 0.0f;
   const float p[3] = {S.px[i], S.py[i], S.pz[i]};
@@ -93,14 +95,24 @@ __device__ inline void wave_rank(bool active, uint32_t dig, int& rank, int& coun
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict__ sets, int n_sets,
                                                       int pass, int src) {
   __shared__ int hist[kWaves][kSortDigits];
+  __shared__ unsigned box[6];
   const Elem e = locate(sets, n_sets);
   const SortSet& S = sets[e.s];
   for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
+  if (pass == 0 && threadIdx.x < 6) {  // merge the box copies (minima, then maxima)
+    const int a = threadIdx.x;
+    unsigned v = S.box[a];
+    for (int cp = 1; cp < kBoxCopies; ++cp) {
+      const unsigned w = S.box[cp * kBoxStride + a];
+      v = a < 3 ? min(v, w) : max(v, w);
+    }
+    box[a] = v;
+  }
   __syncthreads();
   uint32_t key = 0;
   if (e.active) {
     if (pass == 0) {  // the first pass also builds the keys
-      key = morton_key(S, e.i);
+      key = morton_key(S, box, e.i);
       S.key[0][e.i] = key;
       S.val[0][e.i] = (int32_t)e.i;
     } else {
