@@ -144,9 +144,9 @@ __global__ void k_part_key(const float* __restrict__ cloud, int n_points, const 
 }
 
 // Pass 2: the lowest point index attaining the cone minimum.
-__global__ void k_part_idx(const float* __restrict__ cloud, int n_points, const float* tab,
-                           int n_az, int n_el, double rmax2, const unsigned long long* key,
-                           unsigned* idx) {
+__device__ inline void part_idx_block(const float* __restrict__ cloud, int n_points,
+                                      const float* tab, int n_az, int n_el, double rmax2,
+                                      const unsigned long long* key, unsigned* idx) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_points) return;
   const float x = cloud[3 * p], y = cloud[3 * p + 1], z = cloud[3 * p + 2];
@@ -158,11 +158,12 @@ __global__ void k_part_idx(const float* __restrict__ cloud, int n_points, const 
 }
 
 // Coarse argmax (ties: lowest fine index) and the anchor block around the goal.
-__global__ void k_part_coarse_anchor(const float* tab, int n_az_c, int n_el_c, int f_a, int f_e,
-                                     const unsigned long long* key, int32_t* coarse_best,
-                                     float gx, float gy, float gz, int M_h, int M_v, float ell,
-                                     float p0x, float p0y, float p0z, int32_t* anchor_cell,
-                                     int32_t* anchor_fine, float* anchors) {
+__device__ inline void coarse_anchor_block(const float* tab, int n_az_c, int n_el_c, int f_a,
+                                           int f_e, const unsigned long long* key,
+                                           int32_t* coarse_best, float gx, float gy, float gz,
+                                           int M_h, int M_v, float ell, float p0x, float p0y,
+                                           float p0z, int32_t* anchor_cell, int32_t* anchor_fine,
+                                           float* anchors) {
   const int n_az = n_az_c * f_a, n_el = n_el_c * f_e;
   const int n_coarse = n_az_c * n_el_c;
   for (int C = threadIdx.x; C < n_coarse; C += blockDim.x) {
@@ -212,6 +213,23 @@ __global__ void k_part_coarse_anchor(const float* tab, int n_az_c, int n_el_c, i
     anchors[3 * m + 1] = (float)(p0y + (double)ell * dy);
     anchors[3 * m + 2] = (float)(p0z + (double)ell * dz);
   }
+}
+
+// Pass 2 and the coarse step in one launch, since both read only the cone minima
+// of pass 1: blocks below n_idx_blocks run pass 2, the last block the coarse argmax
+// and the anchors.
+__global__ __launch_bounds__(kBlock) void k_part_idx_anchor(
+    const float* __restrict__ cloud, int n_points, const float* tab, int n_az_c, int n_el_c,
+    int f_a, int f_e, double rmax2, const unsigned long long* key, unsigned* idx,
+    int32_t* coarse_best, float gx, float gy, float gz, int M_h, int M_v, float ell, float p0x,
+    float p0y, float p0z, int32_t* anchor_cell, int32_t* anchor_fine, float* anchors,
+    int n_idx_blocks) {
+  if ((int)blockIdx.x < n_idx_blocks) {  // block-uniform
+    part_idx_block(cloud, n_points, tab, n_az_c * f_a, n_el_c * f_e, rmax2, key, idx);
+    return;
+  }
+  coarse_anchor_block(tab, n_az_c, n_el_c, f_a, f_e, key, coarse_best, gx, gy, gz, M_h, M_v, ell,
+                      p0x, p0y, p0z, anchor_cell, anchor_fine, anchors);
 }
 
 // Closed-form quintic per (anchor, axis): a0 = p0, a1 = v0, a2 = a0/2 and
@@ -287,15 +305,13 @@ hipError_t launch_partition(const aero_partition_spec& spec, const float* cloud,
   auto* idx = reinterpret_cast<unsigned*>(fine_idx);
   k_part_init<<<(n_fine + kBlock - 1) / kBlock, kBlock, 0, s>>>(
       key, idx, n_fine, (unsigned long long)__builtin_bit_cast(long long, rmax2));
-  if (n_points > 0) {
-    const int nb = (n_points + kBlock - 1) / kBlock;
+  const int nb = n_points > 0 ? (n_points + kBlock - 1) / kBlock : 0;
+  if (nb > 0)
     k_part_key<<<nb, kBlock, 0, s>>>(cloud, n_points, spec.d_tables, n_az, n_el, rmax2, key);
-    k_part_idx<<<nb, kBlock, 0, s>>>(cloud, n_points, spec.d_tables, n_az, n_el, rmax2, key, idx);
-  }
-  k_part_coarse_anchor<<<1, kBlock, 0, s>>>(spec.d_tables, spec.n_az_c, spec.n_el_c, spec.f_a,
-                                            spec.f_e, key, coarse_best, goal[0], goal[1], goal[2],
-                                            spec.M_h, spec.M_v, spec.ell, spec.p0[0], spec.p0[1],
-                                            spec.p0[2], anchor_cell, anchor_fine, anchors);
+  k_part_idx_anchor<<<nb + 1, kBlock, 0, s>>>(
+      cloud, n_points, spec.d_tables, spec.n_az_c, spec.n_el_c, spec.f_a, spec.f_e, rmax2, key,
+      idx, coarse_best, goal[0], goal[1], goal[2], spec.M_h, spec.M_v, spec.ell, spec.p0[0],
+      spec.p0[1], spec.p0[2], anchor_cell, anchor_fine, anchors, nb);
   return hipGetLastError();
 }
 
