@@ -81,6 +81,7 @@ struct SortSet {
   const float* px;
   const float* py;
   const float* pz;
+  float* sp;             // [3][Q] positions in slot order (written by the last pass)
   int64_t Q;
   int64_t block_base;    // prefix of n_blocks over sets
   int32_t n_blocks;      // ceil(Q / kBlock)
@@ -106,6 +107,8 @@ struct QuerySet {
   const float* px;
   const float* py;
   const float* pz;
+  const float* sp;       // [3][Q] positions in slot order (planes x, y, z): the spatial
+                         //   sort's output for sorted sets, else px itself
   unsigned* out;         // min squared distance as float bits, pre-filled with +inf;
                          //   exact sets: n_copies arrays of Q, merged by their reader
   const float* cloud;    // [n_points][3]

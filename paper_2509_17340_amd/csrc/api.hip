@@ -340,6 +340,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.px = d.pos;
     qs.py = d.pos ? d.pos + MNK : nullptr;
     qs.pz = d.pos ? d.pos + 2 * MNK : nullptr;
+    qs.sp = d.pos;  // planes at stride Q; the spatial sort replaces it below
     qs.out = d.mind2;
     qs.cloud = q.cloud;
     qs.Q = MNK;
@@ -395,10 +396,12 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       so.val[0] = cur.take<int32_t>(MNK);
       so.val[1] = cur.take<int32_t>(MNK);
       so.inv = cur.take<int32_t>(MNK);
+      so.sp = cur.take<float>(3 * MNK);
       so.table = cur.take<int32_t>((int64_t)kSortDigits * so.n_blocks);
       so.rowsum = cur.take<int32_t>(kSortDigits);
       sort_blocks += so.n_blocks;
       qs.perm = so.val[kSortPasses % 2];  // where the last pass leaves it
+      qs.sp = so.sp;
       qs.out_slot = cur.take<unsigned>(MNK);
       d.sort_box = so.box;
       d.out_slot = qs.out_slot;
@@ -537,6 +540,7 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     qs.px = d.pos;
     qs.py = d.pos ? d.pos + MN : nullptr;
     qs.pz = d.pos ? d.pos + 2 * MN : nullptr;
+    qs.sp = d.pos;
     qs.out = d.mind2;
     qs.n_copies = kSelCopies;  // hundreds of workgroups meet on each query's minimum
     qs.cloud = q.cloud;

@@ -273,10 +273,10 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
   for (int r = 0; r < R; ++r) {
     const int64_t slot = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
     ok[r] = slot < S.Q;
-    const int64_t qq = ok[r] ? perm_query(S, slot) : 0;
-    px[r] = S.px[qq];
-    py[r] = S.py[qq];
-    pz[r] = S.pz[qq];
+    const int64_t qs = ok[r] ? slot : 0;  // positions in slot order
+    px[r] = S.sp[qs];
+    py[r] = S.sp[S.Q + qs];
+    pz[r] = S.sp[2 * S.Q + qs];
     if (ok[r]) {
       lo[0] = fminf(lo[0], px[r]);
       lo[1] = fminf(lo[1], py[r]);
@@ -409,8 +409,8 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
     for (int i = 0; i < w; ++i) off += wave_cnt[i];
     const int64_t e = qb * S.qpbA + off;
     S.list[e] = (int32_t)slot;
-    const int64_t q = perm_query(S, slot);
-    S.fpos[e] = make_float4(S.px[q], S.py[q], S.pz[q], 0.0f);  // read back by pass B
+    S.fpos[e] = make_float4(S.sp[slot], S.sp[S.Q + slot], S.sp[2 * S.Q + slot],
+                            0.0f);  // read back by pass B
     S.out_slot[slot] = kInfBits;
     if (S.nn) S.nn[e] = ~0ull;
   }

@@ -47,11 +47,11 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx_mfma(const QuerySet*
   for (int b = 0; b < kMfmaCols; ++b) {
     const int64_t slot = (int64_t)qb * kMfmaQPB + w * (16 * kMfmaCols) + b * 16 + col;
     ok[b] = slot < S.Q;
-    const int64_t qq = ok[b] ? perm_query(S, slot) : 0;
+    const int64_t qs = ok[b] ? slot : 0;  // positions in slot order
     sid[b] = (int32_t)slot;
-    px[b] = S.px[qq];
-    py[b] = S.py[qq];
-    pz[b] = S.pz[qq];
+    px[b] = S.sp[qs];
+    py[b] = S.sp[S.Q + qs];
+    pz[b] = S.sp[2 * S.Q + qs];
     if (ok[b]) {
       lo[0] = fminf(lo[0], px[b]);
       lo[1] = fminf(lo[1], py[b]);
@@ -207,8 +207,7 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
     const int64_t slot = slot0 + b * 32;
     if (slot < S.Q) {
       okm |= 1u << b;
-      const int64_t qq = perm_query(S, slot);
-      const float p[3] = {S.px[qq], S.py[qq], S.pz[qq]};
+      const float p[3] = {S.sp[slot], S.sp[S.Q + slot], S.sp[2 * S.Q + slot]};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         lo[a] = fminf(lo[a], p[a]);
@@ -241,8 +240,8 @@ k_min_dist_approx_f16s(const QuerySet* __restrict__ sets, int n_sets) {
 #pragma unroll
   for (int b = 0; b < kF16Cols; ++b) {
     const bool ok = (okm >> b) & 1u;
-    const int64_t qq = ok ? perm_query(S, slot0 + b * 32) : 0;
-    const float x = S.px[qq] - c[0], y = S.py[qq] - c[1], z = S.pz[qq] - c[2];
+    const int64_t qs = ok ? slot0 + b * 32 : 0;  // positions in slot order
+    const float x = S.sp[qs] - c[0], y = S.sp[S.Q + qs] - c[1], z = S.sp[2 * S.Q + qs] - c[2];
     pp[b] = fmaf(z, z, fmaf(y, y, x * x));
     if (ok) rr = fmaxf(rr, pp[b]);
     _Float16 xh, xl, yh, yl, zh, zl;

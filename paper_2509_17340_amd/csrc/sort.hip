@@ -201,7 +201,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
       const int32_t v = S.val[src][e.i];
       S.key[1 - src][pos] = k;
       S.val[1 - src][pos] = v;
-      if (pass == kSortPasses - 1 && v >= 0 && v < S.Q) S.inv[v] = (int32_t)pos;
+      if (pass == kSortPasses - 1 && v >= 0 && v < S.Q) {
+        // the inverse permutation, and the positions in slot order for the
+        // distance passes (read there without a gather through the permutation)
+        S.inv[v] = (int32_t)pos;
+        S.sp[pos] = S.px[v];
+        S.sp[S.Q + pos] = S.py[v];
+        S.sp[2 * S.Q + pos] = S.pz[v];
+      }
     }
   }
 }
