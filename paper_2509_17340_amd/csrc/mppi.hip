@@ -2,9 +2,10 @@
 //
 //   k_noise        the rollout's standard normals (Philox, Box-Muller), drawn in
 //                  parallel; resets the per-call outputs
-//   k_rollout      one quad of lanes per (problem, instance, sample): clip, RK4 in binary64,
-//                  the control term; writes the clipped perturbations, float32
-//                  positions and binary64 states as sample-fastest planes, and the
+//   k_rollout      one quad of lanes per (problem, instance, sample): clip, RK4 in
+//                  binary64, the control term; writes the clipped perturbations and
+//                  float32 positions as sample-fastest planes, the binary64 state
+//                  after every step as one 80-byte record per position, and the
 //                  positions' bounding box for the spatial sort
 //   (the nearest-distance kernels live in distance.hip)
 //   k_finalize     per sample, the state terms (tracking, speed, goal) and J_col,
