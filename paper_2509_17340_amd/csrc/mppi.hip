@@ -281,6 +281,16 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(const DevProblem* _
         xn[2 * i + 1] = v[1];
       }
     };
+    // the descriptor's pointers in registers, as global pointers (see k_rollout): the
+    // distance write-back could otherwise alias the descriptor, which would then be
+    // reloaded at every step
+    AERO_GLOBAL const int32_t* __restrict__ nidx_in = global_ptr(P.nidx_in);
+    AERO_GLOBAL const int32_t* __restrict__ inv = global_ptr(P.inv);
+    AERO_GLOBAL const unsigned* __restrict__ out_slot = global_ptr(P.out_slot);
+    AERO_GLOBAL unsigned* __restrict__ mind2 = global_ptr(P.mind2);
+    AERO_GLOBAL const float* __restrict__ pos = global_ptr(P.pos);
+    AERO_GLOBAL const float* __restrict__ cloud = global_ptr(P.cloud);
+    const int n_points = P.n_points;
     if (t0 < t1) load_state(t0);
     for (int t = t0; t < t1; ++t) {
       const int64_t row = (int64_t)m * N + t;
@@ -303,22 +313,22 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(const DevProblem* _
       s[2] += goal_term(x, pg, vg, Rg, prm);
       const int64_t qi = row * K + k;
       float d2;
-      if (P.nidx_in) {
-        const int idx = P.nidx_in[qi];
-        if (idx < 0 || idx >= P.n_points) continue;
-        const float ax = P.pos[qi] - P.cloud[3 * (int64_t)idx];
-        const float ay = P.pos[MNK + qi] - P.cloud[3 * (int64_t)idx + 1];
-        const float az = P.pos[2 * MNK + qi] - P.cloud[3 * (int64_t)idx + 2];
+      if (nidx_in) {
+        const int idx = nidx_in[qi];
+        if (idx < 0 || idx >= n_points) continue;
+        const float ax = pos[qi] - cloud[3 * (int64_t)idx];
+        const float ay = pos[MNK + qi] - cloud[3 * (int64_t)idx + 1];
+        const float az = pos[2 * MNK + qi] - cloud[3 * (int64_t)idx + 2];
         d2 = fmaf(az, az, fmaf(ay, ay, ax * ax));
-      } else if (P.inv) {
+      } else if (inv) {
         // sorted set: the distance by slot, written back to the positions' layout
         // (the min_dist2 output) as it is read
-        const int32_t sl = P.inv[qi];
-        const unsigned bits = (sl >= 0 && sl < MNK) ? P.out_slot[sl] : kInfBits;
-        P.mind2[qi] = bits;
+        const int32_t sl = inv[qi];
+        const unsigned bits = (sl >= 0 && sl < MNK) ? out_slot[sl] : kInfBits;
+        mind2[qi] = bits;
         d2 = __uint_as_float(bits);
       } else {
-        d2 = __uint_as_float(P.mind2[qi]);
+        d2 = __uint_as_float(mind2[qi]);
       }
       if ((double)d2 < dmax2) s[3] += collision_phi(sqrt((double)d2), prm);
     }
