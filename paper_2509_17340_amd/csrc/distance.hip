@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
   const int64_t bid = blockIdx.x;
   // query_base holds the prefix of ceil(Q / kBlock) blocks over sets
   const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.query_base; });
-  const QuerySet& S = sets[s];
+  const QuerySet S = sets[s];  // a copy: the stores below cannot alias it
   // pass-A slots in order; the query of a slot comes from the spatial sort
   const int64_t slot = (bid - S.query_base) * kBlock + threadIdx.x;
   bool flag = false;
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ se
 __global__ __launch_bounds__(kBlock) void k_scatter_nearest(const QuerySet* __restrict__ sets,
                                                             int n_sets) {
   for (int s = 0; s < n_sets; ++s) {
-    const QuerySet& S = sets[s];
+    const QuerySet S = sets[s];  // a copy: the stores below cannot alias it
     if (!S.nn || !S.list) continue;
     const int64_t slots = (int64_t)S.n_qblocks * S.qpbA;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < slots;

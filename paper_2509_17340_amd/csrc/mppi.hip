@@ -55,23 +55,32 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   const int64_t local = gid - P.elem_base;
   const int64_t row = local / K;
   const int k = (int)(local % K), m = (int)(row / N), t = (int)(row % N);
+  // the descriptor's fields in registers before the first store (a store could alias
+  // the descriptor and force it to be read again behind the stores)
+  const uint32_t problem_id = P.problem_id;
+  AERO_GLOBAL double* __restrict__ noise = global_ptr(P.noise);
+  AERO_GLOBAL unsigned* __restrict__ mind2 = global_ptr(P.mind2);
+  AERO_GLOBAL unsigned* __restrict__ out_slot = global_ptr(P.out_slot);
+  AERO_GLOBAL int32_t* __restrict__ nidx = global_ptr(P.nidx);
   if (local == 0) {
-    if (P.work_count) *P.work_count = 0;  // pass B's work list of this call
-    if (P.sort_box)
+    AERO_GLOBAL int32_t* __restrict__ work_count = global_ptr(P.work_count);
+    AERO_GLOBAL unsigned* __restrict__ sort_box = global_ptr(P.sort_box);
+    if (work_count) *work_count = 0;  // pass B's work list of this call
+    if (sort_box)
       for (int cp = 0; cp < kBoxCopies; ++cp)
         for (int a = 0; a < 3; ++a) {
-          P.sort_box[cp * kBoxStride + a] = 0xffffffffu;  // order-preserving bits: running
-          P.sort_box[cp * kBoxStride + 3 + a] = 0u;       // min, max
+          sort_box[cp * kBoxStride + a] = 0xffffffffu;  // order-preserving bits: running
+          sort_box[cp * kBoxStride + 3 + a] = 0u;       // min, max
         }
   }
   double nz[4];
-  normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
+  normals4(prm, problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) P.noise[(row * 4 + c) * K + k] = nz[c];
+  for (int c = 0; c < 4; ++c) noise[(row * 4 + c) * K + k] = nz[c];
   // per-position outputs of this call start empty
-  P.mind2[local] = kInfBits;
-  if (P.out_slot) P.out_slot[local] = kInfBits;
-  if (P.nidx) P.nidx[local] = -1;
+  mind2[local] = kInfBits;
+  if (out_slot) out_slot[local] = kInfBits;
+  if (nidx) nidx[local] = -1;
 }
 
 // Merge the position bounds of a wave's rollouts into their problems' sort boxes

@@ -110,11 +110,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
   }
   __syncthreads();
   uint32_t key = 0;
+  AERO_GLOBAL int32_t* __restrict__ table = global_ptr(S.table);
+  const int64_t n_blocks = S.n_blocks;
   if (e.active) {
     if (pass == 0) {  // the first pass also builds the keys
       key = morton_key(S, box, e.i);
-      S.key[0][e.i] = key;
-      S.val[0][e.i] = (int32_t)e.i;
+      AERO_GLOBAL uint32_t* __restrict__ key0 = global_ptr(S.key[0]);
+      AERO_GLOBAL int32_t* __restrict__ val0 = global_ptr(S.val[0]);
+      key0[e.i] = key;
+      val0[e.i] = (int32_t)e.i;
     } else {
       key = S.key[src][e.i];
     }
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
   for (int d = threadIdx.x; d < kSortDigits; d += kBlock) {
     int tot = 0;
     for (int w = 0; w < kWaves; ++w) tot += hist[w][d];
-    S.table[(int64_t)d * S.n_blocks + e.blk] = tot;
+    table[(int64_t)d * n_blocks + e.blk] = tot;
   }
 }
 
@@ -197,17 +201,31 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
     for (int v = 0; v < w; ++v) before += hist[v][dig];
     const int64_t pos = (int64_t)base[dig] + S.table[(int64_t)dig * S.n_blocks + e.blk] + before +
                         rank;
-    if (pos >= 0 && pos < S.Q) {  // always true for consistent counts; never write outside
+    const int64_t Q = S.Q;
+    if (pos >= 0 && pos < Q) {  // always true for consistent counts; never write outside
+      // every field used below is read before the first store (a store could alias
+      // the descriptor and force it to be read again behind the stores)
       const int32_t v = S.val[src][e.i];
-      S.key[1 - src][pos] = k;
-      S.val[1 - src][pos] = v;
-      if (pass == kSortPasses - 1 && v >= 0 && v < S.Q) {
+      AERO_GLOBAL uint32_t* __restrict__ key_out = global_ptr(S.key[1 - src]);
+      AERO_GLOBAL int32_t* __restrict__ val_out = global_ptr(S.val[1 - src]);
+      const bool last = pass == kSortPasses - 1 && v >= 0 && v < Q;
+      AERO_GLOBAL int32_t* __restrict__ inv = global_ptr(S.inv);
+      AERO_GLOBAL float* __restrict__ sp = global_ptr(S.sp);
+      float p[3] = {0.0f, 0.0f, 0.0f};
+      if (last) {
+        p[0] = S.px[v];
+        p[1] = S.py[v];
+        p[2] = S.pz[v];
+      }
+      key_out[pos] = k;
+      val_out[pos] = v;
+      if (last) {
         // the inverse permutation, and the positions in slot order for the
         // distance passes (read there without a gather through the permutation)
-        S.inv[v] = (int32_t)pos;
-        S.sp[pos] = S.px[v];
-        S.sp[S.Q + pos] = S.py[v];
-        S.sp[2 * S.Q + pos] = S.pz[v];
+        inv[v] = (int32_t)pos;
+        sp[pos] = p[0];
+        sp[Q + pos] = p[1];
+        sp[2 * Q + pos] = p[2];
       }
     }
   }
