@@ -250,10 +250,15 @@ __device__ inline void cost_grad(const double* x, int t, const DevParams& prm, c
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_adjoint(const DevProblem* __restrict__ prob,
+// One wave per workgroup (as the forward rollout): the sequential sweeps are few, one
+// lane per sample, and each step stores a state record and four gradients per
+// sample, so the waves are spread over as many CUs as there are.
+constexpr int kAdjBlock = 64;
+
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint(const DevProblem* __restrict__ prob,
                                                     DevParams prm, int64_t total, double* ckpt,
                                                     double* seg, double* gsamp) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * kAdjBlock + threadIdx.x;
   if (gid >= total) return;
   const DevProblem& P = *prob;
   const int K = P.K, N = P.N;
@@ -399,8 +404,8 @@ __global__ void k_grad_w_final(const double* wpart, double scale, float* grad_w)
 
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s) {
-  k_adjoint<<<(unsigned)((samples + kBlock - 1) / kBlock), kBlock, 0, s>>>(d_prob, prm, samples,
-                                                                          ckpt, seg, gsamp);
+  k_adjoint<<<(unsigned)((samples + kAdjBlock - 1) / kAdjBlock), kAdjBlock, 0, s>>>(
+      d_prob, prm, samples, ckpt, seg, gsamp);
   return hipGetLastError();
 }
 
