@@ -248,7 +248,8 @@ hipError_t launch_guides(const double p0[3], const double v0[3], const double a0
                          double T, int M, float* coef, hipStream_t s);
 hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_samples,
                                 int64_t total_elems, const DevParams& prm, const QuerySet* d_sets,
-                                int64_t box_blocks, hipStream_t s);
+                                int64_t box_blocks, const void* h_blob, size_t blob_bytes,
+                                hipStream_t s);
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_samples,
                           const DevParams& prm, hipStream_t s);
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
@@ -272,7 +273,8 @@ hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_sampl
 hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
                          const DevParams& prm, hipStream_t s);
 hipError_t launch_select_rollout(const DevSelect* d_sel, int n, int64_t total_inst,
-                                 const DevParams& prm, hipStream_t s);
+                                 const DevParams& prm, const void* h_blob, size_t blob_bytes,
+                                 hipStream_t s);
 hipError_t launch_select_final(const DevSelect* d_sel, int n, const DevParams& prm,
                                hipStream_t s);
 

@@ -21,13 +21,12 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 inline bool finite(float v) { return std::isfinite(v); }
 
 // ---------------------------------------------------------------------------
-// Descriptors reach the workspace through kernel arguments (launch_put_bytes),
-// so every call enqueues kernels only: no host staging memory, no host-side
-// synchronisation, and the calls can be captured into a graph by the caller.
+// Descriptors reach the workspace through kernel arguments: the first kernel of a
+// call carries them and writes them for the kernels that follow (or, when they do
+// not fit in an argument, launch_put_bytes does), so every call enqueues kernels
+// only: no host staging memory, no host-side synchronisation, and the calls can be
+// captured into a graph by the caller.
 // ---------------------------------------------------------------------------
-hipError_t stage_copy(void* d_dst, const void* src, size_t bytes, hipStream_t s) {
-  return launch_put_bytes(d_dst, src, bytes, s);
-}
 
 // ---------------------------------------------------------------------------
 // Optional per-kernel event timing.
@@ -433,15 +432,15 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   pl.bytes = cur.off;
 }
 
-// Upload the problem, query-set and sort descriptors of a plan (adjacent in the
-// workspace) with one staged copy.
-hipError_t stage_mppi(const MppiPlan& pl, int n, hipStream_t s) {
+// The image of a plan's problem, query-set and sort descriptors (adjacent in the
+// workspace from d_probs on), written to the workspace by the noise launch.
+std::vector<char> mppi_blob(const MppiPlan& pl, int n) {
   const char* b0 = (const char*)pl.d_probs;
   std::vector<char> blob((const char*)pl.d_sorts - b0 + n * sizeof(SortSet));
   memcpy(blob.data(), pl.probs.data(), n * sizeof(DevProblem));
   memcpy(blob.data() + ((const char*)pl.d_sets - b0), pl.sets.data(), n * sizeof(QuerySet));
   memcpy(blob.data() + ((const char*)pl.d_sorts - b0), pl.sorts.data(), n * sizeof(SortSet));
-  return stage_copy(pl.d_probs, blob.data(), blob.size(), s);
+  return blob;
 }
 
 struct BackwardPlan {
@@ -714,12 +713,11 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl, variant, true);
   const DevParams prm = promote(*h_prm);
   // One staged copy for both descriptor arrays (they are adjacent in the workspace).
-  hipError_t he = stage_mppi(pl, n, s);
-  if (he == hipSuccess)
-    he = timed(AERO_K_ROLLOUT, s, [&] {
-      return launch_rollout_noise(pl.d_probs, n, pl.total_samples, pl.total_elems, prm,
-                                  pl.d_sets, pl.box_blocks, s);
-    });
+  const std::vector<char> blob = mppi_blob(pl, n);
+  hipError_t he = timed(AERO_K_ROLLOUT, s, [&] {
+    return launch_rollout_noise(pl.d_probs, n, pl.total_samples, pl.total_elems, prm, pl.d_sets,
+                                pl.box_blocks, blob.data(), blob.size(), s);
+  });
   if (he == hipSuccess && pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
                [&] { return launch_spatial_sort(pl.d_sorts, n, pl.sort_blocks, s); });
@@ -759,9 +757,9 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h, int32_t n,
   std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_sel + n * sizeof(QuerySet));
   memcpy(blob.data(), pl.sel.data(), n * sizeof(DevSelect));
   memcpy(blob.data() + ((char*)pl.d_sets - (char*)pl.d_sel), pl.sets.data(), n * sizeof(QuerySet));
-  hipError_t he = stage_copy(pl.d_sel, blob.data(), blob.size(), s);
-  if (he == hipSuccess)
-    he = timed(AERO_K_SEL_ROLLOUT, s, [&] { return launch_select_rollout(pl.d_sel, n, pl.total_inst, prm, s); });
+  hipError_t he = timed(AERO_K_SEL_ROLLOUT, s, [&] {
+    return launch_select_rollout(pl.d_sel, n, pl.total_inst, prm, blob.data(), blob.size(), s);
+  });
   if (he == hipSuccess && pl.total_blocks > 0)
     he = timed(AERO_K_SEL_MIN_DIST, s, [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, s); });
   if (he == hipSuccess)
@@ -789,12 +787,11 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
   const DevParams prm = promote(*h_prm);
   const aero_problem& q = h[0];
   const int64_t MK = (int64_t)q.M * q.K, MN = (int64_t)q.M * q.N;
-  hipError_t he = stage_mppi(pl, 1, s);
-  if (he == hipSuccess)
-    he = timed(AERO_K_ROLLOUT, s, [&] {
-      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm,
-                                  pl.d_sets, pl.box_blocks, s);
-    });
+  const std::vector<char> blob = mppi_blob(pl, 1);
+  hipError_t he = timed(AERO_K_ROLLOUT, s, [&] {
+    return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, pl.d_sets,
+                                pl.box_blocks, blob.data(), blob.size(), s);
+  });
   if (he == hipSuccess && pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
                [&] { return launch_spatial_sort(pl.d_sorts, 1, pl.sort_blocks, s); });
@@ -847,12 +844,11 @@ int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem
   const DevParams prm = promote(*h_prm);
   const aero_problem& q = h[0];
   const int64_t MK = (int64_t)q.M * q.K, MN = (int64_t)q.M * q.N;
-  hipError_t he = stage_mppi(pl, 1, s);
-  if (he == hipSuccess)
-    he = timed(AERO_K_ROLLOUT, s, [&] {
-      return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm,
-                                  pl.d_sets, pl.box_blocks, s);
-    });
+  const std::vector<char> blob = mppi_blob(pl, 1);
+  hipError_t he = timed(AERO_K_ROLLOUT, s, [&] {
+    return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, pl.d_sets,
+                                pl.box_blocks, blob.data(), blob.size(), s);
+  });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s,
                [&] { return launch_finalize(pl.d_probs, 1, MK, prm, false, s); });

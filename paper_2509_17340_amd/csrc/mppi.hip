@@ -33,6 +33,25 @@ __device__ inline void load_rg(const float* qg, double Rg[9]) {
   rotmat(w, x, y, z, Rg);
 }
 
+// Bytes carried in a kernel argument (descriptors written without a host staging
+// buffer).  16-byte aligned, so that records read in place from the argument are
+// aligned.
+constexpr int kPutBytes = 2048;
+struct alignas(16) PutBlob {
+  uint32_t n;
+  uint32_t pad;
+  unsigned char b[kPutBytes];
+};
+
+// A launch that carries the call's descriptors in `blob` (blob.n > 0) reads them
+// from the argument and has its block 0 write them to the workspace at `dst` for the
+// kernels that follow (no separate upload launch).
+__device__ inline void put_blob(const PutBlob& blob, unsigned char* dst) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(blob.b);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (uint32_t i = threadIdx.x; i < blob.n / 4; i += blockDim.x) d[i] = src[i];
+}
+
 // The rollout's standard normals for every (instance, step, sample), drawn in
 // parallel ahead of the sequential rollout (the same counter-based stream); also
 // resets the per-position distance outputs, the pass-B work counter and the
@@ -42,7 +61,13 @@ __device__ inline void load_rg(const float* qg, double Rg[9]) {
 __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__ probs, int n,
                                                   int64_t total, DevParams prm,
                                                   const QuerySet* __restrict__ sets, int n_sets,
-                                                  int64_t noise_blocks) {
+                                                  int64_t noise_blocks, PutBlob blob,
+                                                  int64_t sets_off) {
+  if (blob.n > 0) {  // descriptors in the argument (see put_blob)
+    if (blockIdx.x == 0) put_blob(blob, (unsigned char*)probs);
+    sets = reinterpret_cast<const QuerySet*>(blob.b + sets_off);
+    probs = reinterpret_cast<const DevProblem*>(blob.b);
+  }
   if ((int64_t)blockIdx.x >= noise_blocks) {
     cloud_box_block(sets, n_sets, (int64_t)blockIdx.x - noise_blocks);
     return;
@@ -430,7 +455,12 @@ __global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict_
 
 // Stage II noise-free rollouts, one per quad of lanes as in k_rollout.
 __global__ __launch_bounds__(kBlock) void k_sel_rollout(const DevSelect* __restrict__ sel, int n,
-                                                        int64_t total, DevParams prm) {
+                                                        int64_t total, DevParams prm,
+                                                        PutBlob blob) {
+  if (blob.n > 0) {  // descriptors in the argument (see put_blob)
+    if (blockIdx.x == 0) put_blob(blob, (unsigned char*)sel);
+    sel = reinterpret_cast<const DevSelect*>(blob.b);
+  }
   const int64_t gid = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 2;  // instance
   if (gid >= total) return;  // whole quads
   const QuadLane L = quad_lane(threadIdx.x);
@@ -575,12 +605,6 @@ __global__ void k_step_candidates(const float* __restrict__ u, const float* __re
 }
 
 // Host bytes carried in the kernel arguments and written to device memory.
-constexpr int kPutBytes = 2048;
-struct PutBlob {
-  uint32_t n;
-  uint32_t pad;
-  unsigned char b[kPutBytes];
-};
 
 __global__ void k_put_bytes(unsigned char* dst, PutBlob blob) {
   for (uint32_t i = threadIdx.x; i < blob.n; i += blockDim.x) dst[i] = blob.b[i];
@@ -616,13 +640,27 @@ hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_
   return hipSuccess;
 }
 
+// The descriptors (h_blob, blob_bytes: the image of the workspace from d_probs on)
+// travel in the noise launch when they fit in its argument, else by upload launches.
 hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_samples,
                                 int64_t total_elems, const DevParams& prm, const QuerySet* d_sets,
-                                int64_t box_blocks, hipStream_t s) {
+                                int64_t box_blocks, const void* h_blob, size_t blob_bytes,
+                                hipStream_t s) {
   const int64_t nb = (total_elems + kBlock - 1) / kBlock;
+  PutBlob blob;
+  blob.n = 0;
+  blob.pad = 0;
+  if (blob_bytes <= (size_t)kPutBytes && blob_bytes % 4 == 0 && nb + box_blocks > 0) {
+    blob.n = (uint32_t)blob_bytes;
+    memcpy(blob.b, h_blob, blob_bytes);
+  } else {
+    const hipError_t e = launch_put_bytes((void*)d_probs, h_blob, blob_bytes, s);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t sets_off = (const char*)d_sets - (const char*)d_probs;
   if (nb + box_blocks > 0)
     k_noise<<<(unsigned)(nb + box_blocks), kBlock, 0, s>>>(d_probs, n, total_elems, prm, d_sets, n,
-                                                          nb);
+                                                          nb, blob, sets_off);
   k_rollout<<<(unsigned)((4 * total_samples + kRollBlock - 1) / kRollBlock), kRollBlock, 0, s>>>(
       d_probs, n, total_samples, prm);
   return hipGetLastError();
@@ -649,9 +687,22 @@ hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
   return hipGetLastError();
 }
 
+// The descriptors (h_blob, blob_bytes: the image of the workspace from d_sel on)
+// travel in the rollout launch when they fit in its argument, else by upload launches.
 hipError_t launch_select_rollout(const DevSelect* d_sel, int n, int64_t total_inst,
-                                 const DevParams& prm, hipStream_t s) {
-  k_sel_rollout<<<grid1d(4 * total_inst), kBlock, 0, s>>>(d_sel, n, total_inst, prm);
+                                 const DevParams& prm, const void* h_blob, size_t blob_bytes,
+                                 hipStream_t s) {
+  PutBlob blob;
+  blob.n = 0;
+  blob.pad = 0;
+  if (blob_bytes <= (size_t)kPutBytes && blob_bytes % 4 == 0 && total_inst > 0) {
+    blob.n = (uint32_t)blob_bytes;
+    memcpy(blob.b, h_blob, blob_bytes);
+  } else {
+    const hipError_t e = launch_put_bytes((void*)d_sel, h_blob, blob_bytes, s);
+    if (e != hipSuccess) return e;
+  }
+  k_sel_rollout<<<grid1d(4 * total_inst), kBlock, 0, s>>>(d_sel, n, total_inst, prm, blob);
   return hipGetLastError();
 }
 
