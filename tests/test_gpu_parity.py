@@ -431,6 +431,40 @@ def test_stage2_select_matches_oracle():
     print(f"S2 {S2} best {int(np_(ps.best)[0])} oracle {o['best']}")
 
 
+def test_stage2_batched_equals_plain():
+    """Seven problems in one Stage-I and one Stage-II call (descriptors too large for
+    a kernel argument, so they are uploaded by their own launches) give bitwise the
+    S2 and selected instances of the plain per-problem calls (whose descriptors
+    travel in the rollout launch's argument)."""
+    from paper_2509_17340_amd.planner import BatchPlan
+    rng = np.random.default_rng(29)
+    probs = []
+    for b in range(7):
+        M, K, N, P = 1 + b % 3, 96 + 32 * b, 6 + b, 800 + 300 * b
+        p = dict(make_plain_problem())
+        p.update(M=M, K=K, N=N, M_h=M, M_v=1, problem_id=b)
+        p["cloud"] = (rng.normal(size=(P, 3)) * 3 + np.float32([3, 0, 0])).astype(np.float32)
+        p["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(M, N, 4)) * 0.2).astype(np.float32)
+        p["anchors"] = (rng.normal(size=(M, 3)) * 3).astype(np.float32)
+        probs.append(p)
+    print("stage2 batched: 7 problems", flush=True)
+    bp = BatchPlan(probs)
+    bp.reset()
+    bp.run_plain()
+    sync()
+    plain_S2 = np.concatenate([np_(s.S2) for s in bp.steps])
+    plain_best = np.array([int(np_(s.best)[0]) for s in bp.steps])
+    bp.reset()
+    bp.run_batched()
+    sync()
+    assert np.array_equal(np_(bp.S2), plain_S2)
+    assert np.array_equal(np_(bp.best), plain_best)
+    # and the first problem against the oracle
+    o = OM.select_best(probs[0], np_(bp.steps[0].u_nom))
+    S2 = plain_S2[:probs[0]["M"]]
+    assert np.all(np.abs(S2 - o["S2"]) <= 1e-4 * np.abs(o["S2"]))
+
+
 def test_stage2_rejects_instance_through_obstacle():
     rng = np.random.default_rng(0)
     th = rng.uniform(-np.pi, np.pi, 4000)
