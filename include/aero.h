@@ -319,18 +319,19 @@ int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems);
 
 /* Kernel identifiers for aero_timing_read. */
 typedef enum aero_kernel {
-  AERO_K_PARTITION = 0,    /* the four partition/anchor kernels of one call         */
+  AERO_K_PARTITION = 0,    /* the three partition/anchor kernels of one call        */
   AERO_K_GUIDES = 1,
-  AERO_K_ROLLOUT = 2,      /* Stage-I noise (+ cloud sub-tile boxes) and RK4 rollout */
+  AERO_K_ROLLOUT = 2,      /* Stage-I noise (+ cloud sub-tile boxes and the call's
+                              descriptors) and RK4 rollout                         */
   AERO_K_MIN_DIST = 3,     /* Stage-I nearest distance, pass A (every position)      */
-  AERO_K_FINALIZE = 4,     /* Stage-I state terms, J_col and S1                     */
+  AERO_K_FINALIZE = 4,     /* Stage-I state terms, J_col and S1 (and the write-back
+                              of a sorted set's distances to the positions' order) */
   AERO_K_UPDATE = 5,       /* softmax weights and control update                    */
-  AERO_K_SEL_ROLLOUT = 6,  /* Stage-II rollout                                      */
+  AERO_K_SEL_ROLLOUT = 6,  /* Stage-II rollout (+ the call's descriptors)           */
   AERO_K_SEL_MIN_DIST = 7, /* Stage-II nearest distance                             */
   AERO_K_SEL_FINAL = 8,    /* Stage-II S2 and argmin                                */
   AERO_K_FLAG = 9,         /* Stage-I compaction of positions near the cloud        */
-  AERO_K_MIN_DIST_EXACT = 10, /* Stage-I nearest distance, pass B (flagged only) and
-                              the write-back of the sorted distances               */
+  AERO_K_MIN_DIST_EXACT = 10, /* Stage-I nearest distance, pass B (flagged only)   */
   AERO_K_NEAREST = 11,     /* backward: nearest indices of flagged positions         */
   AERO_K_ADJOINT = 12,     /* backward: per-sample reverse sweep                     */
   AERO_K_GRAD_REDUCE = 13, /* backward: sums over samples                            */
