@@ -9,7 +9,7 @@
 //                  positions' bounding box for the spatial sort
 //   (the nearest-distance kernels live in distance.hip)
 //   k_finalize     per sample, the state terms (tracking, speed, goal) and J_col,
-//                  with the horizon split over the block's eight waves; S1
+//                  with the horizon split into eight parts per sample; S1
 //   k_update       per (instance, step): rho, eta, and sum_k eps_k delta_eff_k
 //                  with fixed-order wave/block reductions in binary64
 //   k_sel_rollout  Stage II noise-free rollouts (states and positions)
@@ -264,20 +264,23 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __rest
 // (t+1) dt, speed, goal) and J_col, from the stored states and distances (or, with
 // stored nearest indices, from the distance to the stored point, formed exactly as
 // the exact distance pass forms it).  A spatially sorted set's distances are read
-// by slot through the inverse permutation and written back to min_dist2 here.  A block holds kFinSamples consecutive samples,
-// one per lane; its kFinWaves waves take consecutive parts of the horizon, and the
-// parts' sums are added in order.  write_s1 = false leaves S1 alone (the adjoint
+// by slot through the inverse permutation and written back to min_dist2 here.  A
+// block holds kFinSamples consecutive samples; its threads take kFinWaves consecutive
+// parts of the horizon (two per wave, so that the blocks spread over all CUs), and
+// the parts' sums are added in order.  write_s1 = false leaves S1 alone (the adjoint
 // needs the terms only).
-constexpr int kFinSamples = 64;
-constexpr int kFinWaves = 8;  // parts of the horizon per sample (512 threads per block)
+constexpr int kFinSamples = 32;
+constexpr int kFinWaves = 8;  // parts of the horizon per sample
+constexpr int kFinThreads = kFinSamples * kFinWaves;  // two parts per wave
 
-__global__ __launch_bounds__(64 * kFinWaves) void k_finalize(const DevProblem* __restrict__ probs,
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const DevProblem* __restrict__ probs,
                                                              int n, int64_t total, DevParams prm,
                                                              int write_s1) {
   constexpr int kWaves = kFinWaves;
   constexpr int kTerms = 4;  // track, speed, goal, collision
   __shared__ double part[kWaves][kTerms][kFinSamples];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // lane: the sample within the block; w: the part of the horizon
+  const int lane = threadIdx.x % kFinSamples, w = threadIdx.x / kFinSamples;
   const int64_t gid = (int64_t)blockIdx.x * kFinSamples + lane;
   const bool active = gid < total;
   double s[kTerms] = {0.0, 0.0, 0.0, 0.0};
@@ -676,7 +679,7 @@ hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total, const
 hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total, const DevParams& prm,
                            bool write_s1, hipStream_t s) {
   if (total > 0)
-    k_finalize<<<(unsigned)((total + kFinSamples - 1) / kFinSamples), 64 * kFinWaves, 0, s>>>(
+    k_finalize<<<(unsigned)((total + kFinSamples - 1) / kFinSamples), kFinThreads, 0, s>>>(
         d_probs, n, total, prm, write_s1 ? 1 : 0);
   return hipGetLastError();
 }
