@@ -434,13 +434,39 @@ __global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict_
   const int64_t row = gid - P.row_base;  // m * N + t
   const int m = (int)(row / N);
   const double* S = P.S1 + (int64_t)m * K;
+  const float* D = P.deff + row * 4 * K;
+  // The first kUpdCache samples of each thread are loaded (costs and perturbations)
+  // before the minimum is reduced, so that the perturbations' loads overlap the
+  // reduction; the sums run over the samples in the same order as without the cache.
+  constexpr int kUpdCache = 4;
+  double sv[kUpdCache];
+  float dv[kUpdCache][4];
   double mn = INFINITY;
-  for (int k = threadIdx.x; k < K; k += kBlock) mn = fmin(mn, S[k]);
+#pragma unroll
+  for (int j = 0; j < kUpdCache; ++j) {
+    const int k = threadIdx.x + j * kBlock;
+    sv[j] = 0.0;
+    if (k < K) {
+      sv[j] = S[k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dv[j][c] = D[c * K + k];
+      mn = fmin(mn, sv[j]);
+    }
+  }
+  for (int k = threadIdx.x + kUpdCache * kBlock; k < K; k += kBlock) mn = fmin(mn, S[k]);
   const double rho = block_min(mn, sh);
   const double inv_lam = 1.0 / prm.lambda;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const float* D = P.deff + row * 4 * K;
-  for (int k = threadIdx.x; k < K; k += kBlock) {
+#pragma unroll
+  for (int j = 0; j < kUpdCache; ++j) {
+    if (threadIdx.x + j * kBlock < K) {
+      const double e = exp(-(sv[j] - rho) * inv_lam);
+      acc[0] += e;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[1 + c] += e * (double)dv[j][c];
+    }
+  }
+  for (int k = threadIdx.x + kUpdCache * kBlock; k < K; k += kBlock) {
     const double e = exp(-(S[k] - rho) * inv_lam);
     acc[0] += e;
     acc[1] += e * (double)D[k];
