@@ -59,7 +59,7 @@ __device__ inline Elem locate(const SortSet* sets, int n_sets) {
 // Morton key of an element from its position and the set's bounding box.
 // box: the set's bounding box (order-preserving bits), merged from the rollout's
 // copies by merge_box_copies.
-__device__ inline uint32_t morton_key(const SortSet& S, const unsigned box[6], int64_t i) {
+__device__ inline uint32_t morton_key(const unsigned box[6], const float p[3]) {
   float lo[3], ext = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -67,7 +67,6 @@ __device__ inline uint32_t morton_key(const SortSet& S, const unsigned box[6], i
     ext = fmaxf(ext, ord_float(box[3 + a]) - lo[a]);
   }
   const float scale = ext > 0.0f ? 255.99f / ext : 0.0f;
-  const float p[3] = {S.px[i], S.py[i], S.pz[i]};
   uint32_t key = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -99,6 +98,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
   const Elem e = locate(sets, n_sets);
   const SortSet& S = sets[e.s];
   for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
+  // this element's input, loaded before the barrier so that its latency overlaps the
+  // merge of the box copies
+  float p[3] = {0.0f, 0.0f, 0.0f};
+  uint32_t key = 0;
+  if (e.active) {
+    if (pass == 0) {
+      p[0] = S.px[e.i];
+      p[1] = S.py[e.i];
+      p[2] = S.pz[e.i];
+    } else {
+      key = S.key[src][e.i];
+    }
+  }
   if (pass == 0 && threadIdx.x < 6) {  // merge the box copies (minima, then maxima)
     const int a = threadIdx.x;
     unsigned v = S.box[a];
@@ -109,19 +121,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
     box[a] = v;
   }
   __syncthreads();
-  uint32_t key = 0;
   AERO_GLOBAL int32_t* __restrict__ table = global_ptr(S.table);
   const int64_t n_blocks = S.n_blocks;
-  if (e.active) {
-    if (pass == 0) {  // the first pass also builds the keys
-      key = morton_key(S, box, e.i);
-      AERO_GLOBAL uint32_t* __restrict__ key0 = global_ptr(S.key[0]);
-      AERO_GLOBAL int32_t* __restrict__ val0 = global_ptr(S.val[0]);
-      key0[e.i] = key;
-      val0[e.i] = (int32_t)e.i;
-    } else {
-      key = S.key[src][e.i];
-    }
+  if (e.active && pass == 0) {  // the first pass also builds the keys
+    key = morton_key(box, p);
+    AERO_GLOBAL uint32_t* __restrict__ key0 = global_ptr(S.key[0]);
+    AERO_GLOBAL int32_t* __restrict__ val0 = global_ptr(S.val[0]);
+    key0[e.i] = key;
+    val0[e.i] = (int32_t)e.i;
   }
   const uint32_t dig = (key >> (kSortShift0 + 8 * pass)) & 0xffu;
   int rank, count;
@@ -185,11 +192,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
   const Elem e = locate(sets, n_sets);
   const SortSet& S = sets[e.s];
   for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
+  // this element's key and value, loaded before the scan so that their latency
+  // overlaps it
+  const uint32_t k = e.active ? S.key[src][e.i] : 0u;
+  const int32_t v = e.active ? S.val[src][e.i] : 0;
   // digit bases: exclusive scan of the digit totals (kBlock == kSortDigits)
   int total;
   base[threadIdx.x] = block_exclusive_scan(S.rowsum[threadIdx.x], &total);
   __syncthreads();
-  const uint32_t k = e.active ? S.key[src][e.i] : 0u;
   const uint32_t dig = (k >> (kSortShift0 + 8 * pass)) & 0xffu;
   int rank, count;
   wave_rank(e.active, dig, rank, count);
@@ -198,14 +208,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
   __syncthreads();
   if (e.active) {
     int before = 0;
-    for (int v = 0; v < w; ++v) before += hist[v][dig];
+    for (int u = 0; u < w; ++u) before += hist[u][dig];
     const int64_t pos = (int64_t)base[dig] + S.table[(int64_t)dig * S.n_blocks + e.blk] + before +
                         rank;
     const int64_t Q = S.Q;
     if (pos >= 0 && pos < Q) {  // always true for consistent counts; never write outside
       // every field used below is read before the first store (a store could alias
       // the descriptor and force it to be read again behind the stores)
-      const int32_t v = S.val[src][e.i];
       AERO_GLOBAL uint32_t* __restrict__ key_out = global_ptr(S.key[1 - src]);
       AERO_GLOBAL int32_t* __restrict__ val_out = global_ptr(S.val[1 - src]);
       const bool last = pass == kSortPasses - 1 && v >= 0 && v < Q;
