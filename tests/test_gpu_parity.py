@@ -465,6 +465,36 @@ def test_stage2_batched_equals_plain():
     assert np.all(np.abs(S2 - o["S2"]) <= 1e-4 * np.abs(o["S2"]))
 
 
+def test_two_problems_batched_equal_plain():
+    """Two problems in one Stage-I and one Stage-II call: their descriptors still fit
+    in the first kernel's argument (each kernel reads both problems' records from it)
+    and the results equal the plain calls bit for bit."""
+    from paper_2509_17340_amd.planner import BatchPlan
+    rng = np.random.default_rng(31)
+    probs = []
+    for b, (M, K, N, P) in enumerate([(3, 200, 11, 2500), (2, 352, 7, 20000)]):
+        p = dict(make_plain_problem())
+        p.update(M=M, K=K, N=N, M_h=M, M_v=1, problem_id=b)
+        p["cloud"] = (rng.normal(size=(P, 3)) * 3 + np.float32([3, 0, 0])).astype(np.float32)
+        p["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(M, N, 4)) * 0.2).astype(np.float32)
+        p["anchors"] = (rng.normal(size=(M, 3)) * 3).astype(np.float32)
+        probs.append(p)
+    print("two problems batched", flush=True)
+    bp = BatchPlan(probs)
+    bp.reset()
+    bp.run_plain()
+    sync()
+    plain = [(np_(s.S1), np_(s.u_nom), np_(s.S2), int(np_(s.best)[0])) for s in bp.steps]
+    bp.reset()
+    bp.run_batched()
+    sync()
+    for s, ref in zip(bp.steps, plain):
+        assert np.array_equal(np_(s.S1), ref[0])
+        assert np.array_equal(np_(s.u_nom), ref[1])
+    assert np.array_equal(np_(bp.S2), np.concatenate([r[2] for r in plain]))
+    assert np.array_equal(np_(bp.best), np.array([r[3] for r in plain]))
+
+
 def test_stage2_rejects_instance_through_obstacle():
     rng = np.random.default_rng(0)
     th = rng.uniform(-np.pi, np.pi, 4000)
