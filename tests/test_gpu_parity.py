@@ -276,6 +276,28 @@ def test_stage1_zero_noise_returns_nominal():
     assert np.all(g["deff"] == 0.0)
 
 
+@pytest.mark.parametrize("M,K,N,P", [(2, 64, 512, 3000), (256, 16, 8, 2000)],
+                         ids=["longest_horizon", "most_instances"])
+def test_largest_horizon_and_instance_count(M, K, N, P):
+    """The longest horizon (512) and the most instances (256) the ABI accepts: Stage I (costs,
+    distances and update against the oracle on a subset of samples) and Stage II (S2
+    against the oracle)."""
+    rng = np.random.default_rng(M + N)
+    prob = dict(make_plain_problem())
+    prob.update(M=M, K=K, N=N, M_h=M, M_v=1, problem_id=5)
+    prob["cloud"] = (rng.normal(size=(P, 3)) * 3 + np.float32([4, 0, 0])).astype(np.float32)
+    prob["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(M, N, 4)) * 0.2).astype(np.float32)
+    prob["anchors"] = (rng.normal(size=(M, 3)) * 3).astype(np.float32)
+    print(f"largest shapes M={M} K={K} N={N} P={P}", flush=True)
+    ps, g = run_stage1(prob)
+    compare_stage1(prob, g, samples=[0, K // 2, K - 1])
+    ps.stage2()
+    sync()
+    o = OM.select_best(prob, g["u_new"])
+    S2 = np_(ps.S2)
+    assert np.all(np.abs(S2 - o["S2"]) <= 1e-4 * np.abs(o["S2"]))
+
+
 def test_stage1_deterministic_and_batched_equals_plain(pass_a):
     rng = np.random.default_rng(11)
     probs = []
