@@ -276,11 +276,13 @@ def test_stage1_zero_noise_returns_nominal():
     assert np.all(g["deff"] == 0.0)
 
 
-@pytest.mark.parametrize("M,K,N,P", [(2, 64, 512, 3000), (256, 16, 8, 2000), (2, 5000, 4, 600)],
-                         ids=["longest_horizon", "most_instances", "many_samples"])
+@pytest.mark.parametrize("M,K,N,P", [(2, 64, 512, 3000), (256, 16, 8, 2000), (2, 5000, 4, 600),
+                                     (1, 1 << 20, 2, 200)],
+                         ids=["longest_horizon", "most_instances", "many_samples", "most_samples"])
 def test_largest_horizon_and_instance_count(M, K, N, P):
-    """The longest horizon (512) and the most instances (256) the ABI accepts, and
-    more samples than the update kernel's threads hold in registers (5000): Stage I
+    """The longest horizon (512), the most instances (256) and the most samples (2^20)
+    the ABI accepts, and more samples than the update kernel's threads hold in
+    registers (5000): Stage I
     (costs and distances against the oracle on a subset of samples, the update over
     all of them) and Stage II (S2 against the oracle)."""
     rng = np.random.default_rng(M + N)
