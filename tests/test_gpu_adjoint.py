@@ -77,7 +77,8 @@ def test_adjoint_ensemble_forest():
     check(make_ensemble_problem(), n_dirs=6)
 
 
-@pytest.mark.parametrize("M,K,N,P", [(2, 37, 9, 600), (1, 300, 17, 0), (3, 64, 2, 1)])
+@pytest.mark.parametrize("M,K,N,P", [(2, 37, 9, 600), (1, 300, 17, 0), (3, 64, 2, 1),
+                                     (1, 16, 100, 400)])
 def test_adjoint_ragged(M, K, N, P):
     rng = np.random.default_rng(K)
     prob = dict(make_plain_problem())
