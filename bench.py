@@ -135,8 +135,8 @@ def bench_adjoint(prob, iters=20):
     res = {}
     legs = {
         "forward": lambda: (u_work.copy_(ps.u_nom), aero.mppi_step(prob["params"], [fwd], ws)),
-        "backward": lambda: aero.mppi_step_backward_indexed(prob["params"], bwd, 1.0, gu, gw, ws),
-        "backward_self_contained": lambda: aero.mppi_step_backward(prob["params"], plain, 1.0, gu,
+        "backward": lambda: aero.mppi_step_backward_indexed(prob["params"], bwd, None, gu, gw, ws),
+        "backward_self_contained": lambda: aero.mppi_step_backward(prob["params"], plain, None, gu,
                                                                    gw, ws),
     }
     for name in ("forward", "backward", "backward_self_contained"):

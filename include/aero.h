@@ -55,6 +55,8 @@ typedef enum aero_status {
 #define AERO_BATCH_MAX 2048   /* most problems per call                           */
 #define AERO_GRID_MAX 8192    /* most fine cells along one angular axis           */
 #define AERO_FRAMES_MAX 256   /* most LiDAR frames per accumulated cloud          */
+#define AERO_POSITIONS_MAX 2147483647LL /* rollout positions M*N*K of one problem and  *
+                                         * their sum over one call stay below this     */
 
 /* Table I parameters shared by all problems of a call (float32 values). */
 typedef struct aero_params {
@@ -98,6 +100,9 @@ typedef struct aero_problem {
                          * (lowest index on ties) of every position closer than      *
                          * d_max; -1 or an index of a point at least d_max away       *
                          * elsewhere                                                  */
+  const float* w;       /* optional device [5]: the term multipliers of this problem   *
+                         * (track, vnorm, ctrl, goal, col), read on the device in     *
+                         * place of h_prm->w (NULL: use h_prm->w)                     */
 } aero_problem;
 
 /* Angular grid of the multi-resolution partition (Sec. IV-A). */
@@ -195,7 +200,9 @@ int aero_build_guides(const float* h_p0, const float* h_v0, const float* h_a0,
  * them in one batched launch sequence.
  *   h_problems  host array [n_problems]
  *   d_ws        device workspace of aero_workspace_size(AERO_CALL_MPPI_STEP, ...)
- * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE, AERO_ERR_PARAM (lambda <= 0, dt <= 0,
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (a size outside its range, or M*N*K of a
+ * problem or its sum over the call at AERO_POSITIONS_MAX or above: positions are
+ * addressed with 32-bit slots), AERO_ERR_PARAM (lambda <= 0, dt <= 0,
  * mass <= 0, sigma < 0, u_min > u_max, d_min >= d_max, non-finite values),
  * AERO_ERR_WORKSPACE, AERO_ERR_DEVICE. */
 int aero_mppi_step(const aero_params* h_prm, const aero_problem* h_problems,
@@ -211,10 +218,14 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h_problems,
                      int32_t n_problems, double* d_S2, int32_t* d_best, void* d_ws,
                      size_t ws_bytes, void* stream);
 
-/* Adjoint of L = scale * sum_{m,k} S1[m,k] for one problem, evaluated at the
+/* Adjoint of L = g * sum_{m,k} S1[m,k] for one problem, evaluated at the
  * problem's u_nom (read only) with the same noise as aero_mppi_step:
+ *   d_grad_L     device float32 scalar g, the upstream gradient (read on the
+ *                device, so that an autograd caller needs no host copy; NULL
+ *                means g = 1)
  *   d_grad_u_nom [M][N][4] float32 = dL/du_nom (zero where the sample was clipped)
- *   d_grad_w     [5] float32       = dL/dw = scale * sum_{m,k} J_i
+ *   d_grad_w     [5] float32       = dL/dw = g * sum_{m,k} J_i
+ * The weights are h_problem->w when given (device memory), else h_prm->w.
  * The derivative is the exact one of the active smooth piece: clip mask, collision
  * branch and nearest point (lowest index on ties) held fixed.  Rollout states are
  * checkpointed every 8 steps and recomputed.  The distance filter pass uses the
@@ -222,8 +233,8 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h_problems,
  * gradients do not depend on it.
  * Errors: as aero_mppi_step. */
 int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h_problem,
-                            float scale, float* d_grad_u_nom, float* d_grad_w, void* d_ws,
-                            size_t ws_bytes, void* stream);
+                            const float* d_grad_L, float* d_grad_u_nom, float* d_grad_w,
+                            void* d_ws, size_t ws_bytes, void* stream);
 
 /* The same adjoint from nearest indices stored by a previous aero_mppi_step on the
  * same problem (same u_nom, cloud, guides and parameters; the step's in-place update of
@@ -233,8 +244,9 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h_prob
  * from that step.  Workspace: aero_workspace_size(AERO_CALL_BACKWARD, ...).
  * Errors: as aero_mppi_step_backward; AERO_ERR_NULL if nearest_idx is null. */
 int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem* h_problem,
-                                    float scale, float* d_grad_u_nom, float* d_grad_w,
-                                    void* d_ws, size_t ws_bytes, void* stream);
+                                    const float* d_grad_L, float* d_grad_u_nom,
+                                    float* d_grad_w, void* d_ws, size_t ws_bytes,
+                                    void* stream);
 
 /* ---- receding horizon ----------------------------------------------------------- */
 

@@ -57,7 +57,7 @@ class ProblemStruct(ctypes.Structure):
         ("v_goal", ctypes.c_float * 3), ("q_goal", ctypes.c_float * 4),
         ("coef", ctypes.c_void_p), ("u_nom", ctypes.c_void_p), ("S1", ctypes.c_void_p),
         ("delta_eff", ctypes.c_void_p), ("min_dist2", ctypes.c_void_p),
-        ("nearest_idx", ctypes.c_void_p),
+        ("nearest_idx", ctypes.c_void_p), ("w", ctypes.c_void_p),
     ]
 
 
@@ -82,10 +82,9 @@ _SIGS = {
                                          _P, _P]),
     "aero_mppi_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "aero_select_best": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
-    "aero_mppi_step_backward": (ctypes.c_int, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_size_t,
-                                               _P]),
-    "aero_mppi_step_backward_indexed": (ctypes.c_int, [_P, _P, ctypes.c_float, _P, _P, _P,
-                                                       ctypes.c_size_t, _P]),
+    "aero_mppi_step_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "aero_mppi_step_backward_indexed": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                                       _P]),
     "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "aero_set_pass_a_variant": (ctypes.c_int, [ctypes.c_int]),
     "aero_shift_controls": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
@@ -195,7 +194,7 @@ class Problem:
 
     def __init__(self, cloud, M, K, N, x0, p_goal, u_nom, coef=None, v_goal=(0, 0, 0),
                  q_goal=(1, 0, 0, 0), S1=None, delta_eff=None, min_dist2=None, problem_id=0,
-                 n_points=None, nearest_idx=None):
+                 n_points=None, nearest_idx=None, w=None):
         self.cloud, self.M, self.K, self.N = cloud, int(M), int(K), int(N)
         self.n_points = int(cloud.shape[0]) if n_points is None else int(n_points)
         self.x0 = np.asarray(x0, np.float32)
@@ -205,6 +204,7 @@ class Problem:
         self.u_nom, self.coef = u_nom, coef
         self.S1, self.delta_eff, self.min_dist2 = S1, delta_eff, min_dist2
         self.nearest_idx = nearest_idx
+        self.w = w  # optional device [5] term weights (replace the call's params["w"])
         self.problem_id = int(problem_id)
 
     def check(self):
@@ -216,6 +216,7 @@ class Problem:
         _need(self.delta_eff, M * N * 4 * K, "f32", "delta_eff")
         _need(self.min_dist2, M * N * K, "f32", "min_dist2")
         _need(self.nearest_idx, M * N * K, "i32", "nearest_idx")
+        _need(self.w, 5, "f32", "w")
 
     def struct(self):
         self.check()
@@ -230,6 +231,7 @@ class Problem:
         s.coef, s.u_nom = _ptr(self.coef), _ptr(self.u_nom)
         s.S1, s.delta_eff, s.min_dist2 = _ptr(self.S1), _ptr(self.delta_eff), _ptr(self.min_dist2)
         s.nearest_idx = _ptr(self.nearest_idx)
+        s.w = _ptr(self.w)
         return s
 
 
@@ -386,22 +388,28 @@ def timing_read(reset=False):
     return out
 
 
-def mppi_step_backward(prm, problem, scale, grad_u_nom, grad_w, ws, ws_bytes=None, stream=None):
+def mppi_step_backward(prm, problem, grad_L, grad_u_nom, grad_w, ws, ws_bytes=None,
+                       stream=None):
+    """Adjoint of L = g * sum S1 (see aero_mppi_step_backward); grad_L is the device
+    float32 scalar g, or None for g = 1."""
     p = params_struct(prm) if isinstance(prm, dict) else prm
     s = problem.struct()
+    _need(grad_L, 1, "f32", "grad_L")
     nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
-    _check(_lib.aero_mppi_step_backward(ctypes.byref(p), ctypes.byref(s), float(scale),
+    _check(_lib.aero_mppi_step_backward(ctypes.byref(p), ctypes.byref(s), _ptr(grad_L),
                                         _ptr(grad_u_nom), _ptr(grad_w), _ptr(ws), nbytes,
                                         _stream(stream)), "aero_mppi_step_backward")
 
 
-def mppi_step_backward_indexed(prm, problem, scale, grad_u_nom, grad_w, ws, ws_bytes=None,
+def mppi_step_backward_indexed(prm, problem, grad_L, grad_u_nom, grad_w, ws, ws_bytes=None,
                                stream=None):
     """Adjoint from the nearest indices a previous mppi_step stored in
-    problem.nearest_idx (read here); see aero_mppi_step_backward_indexed."""
+    problem.nearest_idx (read here); see aero_mppi_step_backward_indexed.  grad_L is
+    the device float32 scalar upstream gradient, or None for 1."""
     p = params_struct(prm) if isinstance(prm, dict) else prm
     s = problem.struct()
+    _need(grad_L, 1, "f32", "grad_L")
     nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
-    _check(_lib.aero_mppi_step_backward_indexed(ctypes.byref(p), ctypes.byref(s), float(scale),
+    _check(_lib.aero_mppi_step_backward_indexed(ctypes.byref(p), ctypes.byref(s), _ptr(grad_L),
                                                 _ptr(grad_u_nom), _ptr(grad_w), _ptr(ws), nbytes,
                                                 _stream(stream)), "aero_mppi_step_backward_indexed")

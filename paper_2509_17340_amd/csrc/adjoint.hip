@@ -1,4 +1,4 @@
-// Adjoint of L = scale * sum_{m,k} S1[m,k] with respect to u_nom and the five
+// Adjoint of L = g * sum_{m,k} S1[m,k] with respect to u_nom and the five
 // term weights (built on Sec. III-A eq. (dynamics), the RK4 step of
 // eq. (mppi_rollout) and the Stage-I terms of Sec. IV-C).
 //
@@ -235,7 +235,7 @@ __device__ inline void cost_grad(const double* x, int t, const DevParams& prm, c
   if (P.n_points > 0) {
     const int64_t qi = ((int64_t)m * P.N + t) * P.K + k;
     const int idx = P.nidx_in ? P.nidx_in[qi] : P.nidx[qi];
-    if (idx >= 0) {
+    if (idx >= 0 && idx < P.n_points) {  // caller-given indices may be stale
       const double dx = x[0] - (double)P.cloud[3 * (int64_t)idx];
       const double dy = x[1] - (double)P.cloud[3 * (int64_t)idx + 1];
       const double dz = x[2] - (double)P.cloud[3 * (int64_t)idx + 2];
@@ -261,6 +261,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const DevProblem* __restr
   const int64_t gid = (int64_t)blockIdx.x * kAdjBlock + threadIdx.x;
   if (gid >= total) return;
   const DevProblem& P = *prob;
+  load_weights(P.w_dev, prm);
   const int K = P.K, N = P.N;
   const int m = (int)(gid / K), k = (int)(gid % K);
   const int64_t MK = total;
@@ -363,13 +364,19 @@ __device__ inline double block_sum(double v, double* sh) {
 // k_grad_w_final in slice order.
 constexpr int kWParts = 64;
 
+// The upstream gradient: a device scalar, or 1 when none is given.
+__device__ inline double upstream(const float* grad_L) {
+  return grad_L ? (double)*grad_L : 1.0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_grad_reduce(const DevProblem* __restrict__ prob,
                                                         int64_t rows, const double* gsamp,
-                                                        double scale, float* grad_u,
+                                                        const float* grad_L, float* grad_u,
                                                         double* wpart) {
   __shared__ double sh[4];
   const DevProblem& P = *prob;
   const int K = P.K;
+  const double scale = upstream(grad_L);
   if ((int64_t)blockIdx.x < rows) {
     const int64_t row = blockIdx.x;
     for (int c = 0; c < 4; ++c) {
@@ -392,9 +399,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(const DevProblem* __rest
   }
 }
 
-__global__ void k_grad_w_final(const double* wpart, double scale, float* grad_w) {
+__global__ void k_grad_w_final(const double* wpart, const float* grad_L, float* grad_w) {
   const int i = threadIdx.x;
   if (i >= 5) return;
+  const double scale = upstream(grad_L);
   double acc = 0.0;
   for (int p = 0; p < kWParts; ++p) acc += wpart[i * kWParts + p];
   grad_w[i] = (float)(scale * acc);
@@ -410,12 +418,12 @@ hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_
 }
 
 hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, int64_t rows,
-                              const double* gsamp, double scale, float* grad_u, float* grad_w,
-                              double* wpart, hipStream_t s) {
+                              const double* gsamp, const float* grad_L, float* grad_u,
+                              float* grad_w, double* wpart, hipStream_t s) {
   (void)prm;
-  k_grad_reduce<<<(unsigned)(rows + 5 * kWParts), kBlock, 0, s>>>(d_prob, rows, gsamp, scale,
+  k_grad_reduce<<<(unsigned)(rows + 5 * kWParts), kBlock, 0, s>>>(d_prob, rows, gsamp, grad_L,
                                                                   grad_u, wpart);
-  k_grad_w_final<<<1, 64, 0, s>>>(wpart, scale, grad_w);
+  k_grad_w_final<<<1, 64, 0, s>>>(wpart, grad_L, grad_w);
   return hipGetLastError();
 }
 

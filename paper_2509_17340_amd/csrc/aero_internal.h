@@ -71,6 +71,7 @@ struct DevProblem {
   const int32_t* inv;    // sorted query set: query -> slot (or nullptr: distances in mind2)
   const int32_t* nidx_in;  // nearest indices given by the caller (indexed adjoint)
   int64_t elem_base;     // prefix of M*N*K over problems
+  const float* w_dev;    // optional [5] device term weights replacing DevParams::w
 };
 
 // Spatial sort of one problem's rollout positions (stable LSD radix sort on the top
@@ -220,7 +221,14 @@ struct DevSelect {
   double* S2;            // [M] (caller's array + offset)
   int32_t* best;         // caller's array + problem index
   int64_t inst_base;     // prefix of M
+  const float* w_dev;    // optional [5] device term weights replacing DevParams::w
 };
+
+// The term weights of a problem: its device weights when given, else the call's.
+__device__ inline void load_weights(const float* w_dev, DevParams& prm) {
+  if (w_dev)
+    for (int i = 0; i < 5; ++i) prm.w[i] = (double)w_dev[i];
+}
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
@@ -265,8 +273,8 @@ hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s);
 hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, int64_t rows,
-                              const double* gsamp, double scale, float* grad_u, float* grad_w,
-                              double* wpart, hipStream_t s);
+                              const double* gsamp, const float* grad_L, float* grad_u,
+                              float* grad_w, double* wpart, hipStream_t s);
 size_t grad_w_parts();  // doubles of the weight-gradient partial sums
 hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_samples,
                            const DevParams& prm, bool write_s1, hipStream_t s);

@@ -130,10 +130,13 @@ int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
     *ev = st.ev[v];
     return v;
   }
+  // the trials are read without waiting: while the last one is still in flight this
+  // call runs the VALU pass and a later call settles the shape
+  for (int v = 0; v < kPassAVariants; ++v)
+    if (hipEventQuery(st.ev[v][1]) == hipErrorNotReady) return kPassAValu;
   int best = kPassAValu;
   for (int v = 0; v < kPassAVariants; ++v) {
-    if (hipEventSynchronize(st.ev[v][1]) != hipSuccess ||
-        hipEventElapsedTime(&st.ms[v], st.ev[v][0], st.ev[v][1]) != hipSuccess)
+    if (hipEventElapsedTime(&st.ms[v], st.ev[v][0], st.ev[v][1]) != hipSuccess)
       st.ms[v] = 1e30f;
     hipEventDestroy(st.ev[v][0]);
     hipEventDestroy(st.ev[v][1]);
@@ -180,9 +183,15 @@ int check_problem(const aero_problem& q, bool need_coef) {
 int check_problems(const aero_problem* h, int32_t n, bool need_coef) {
   if (!h) return AERO_ERR_NULL;
   if (n < 1 || n > AERO_BATCH_MAX) return AERO_ERR_SHAPE;
+  int64_t total = 0;
   for (int b = 0; b < n; ++b) {
     const int e = check_problem(h[b], need_coef);
     if (e) return e;
+    // positions are addressed by 32-bit slots (sort permutation, flag lists, nearest
+    // indices): a problem, and the call, must stay below 2^31 of them
+    const int64_t q = (int64_t)h[b].M * h[b].N * h[b].K;
+    total += q;
+    if (q >= AERO_POSITIONS_MAX || total >= AERO_POSITIONS_MAX) return AERO_ERR_SHAPE;
   }
   return AERO_OK;
 }
@@ -318,6 +327,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     memcpy(d.qg, q.q_goal, sizeof d.qg);
     d.coef = q.coef;
     d.u_nom = q.u_nom;
+    d.w_dev = q.w;
     d.J_ctrl = cur.take<double>(MK);
     double* s1 = cur.take<double>(q.S1 ? 0 : MK);
     d.S1 = q.S1 ? q.S1 : s1;
@@ -528,6 +538,7 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     memcpy(d.vg, q.v_goal, sizeof d.vg);
     memcpy(d.qg, q.q_goal, sizeof d.qg);
     d.u_nom = q.u_nom;
+    d.w_dev = q.w;
     d.state = cur.take<double>(10 * MN);
     d.pos = cur.take<float>(3 * MN);
     d.mind2 = cur.take<unsigned>(kSelCopies * MN);
@@ -767,15 +778,14 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h, int32_t n,
   return dev_status(he);
 }
 
-int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, float scale,
-                            float* d_grad_u_nom, float* d_grad_w, void* d_ws, size_t ws_bytes,
-                            void* stream) {
+int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h,
+                            const float* d_grad_L, float* d_grad_u_nom, float* d_grad_w,
+                            void* d_ws, size_t ws_bytes, void* stream) {
   int e = check_params(h_prm);
   if (e) return e;
   e = check_problems(h, 1, true);
   if (e) return e;
   if (!d_grad_u_nom || !d_grad_w) return AERO_ERR_NULL;
-  if (!finite(scale)) return AERO_ERR_PARAM;
   BackwardPlan bp;
   plan_backward(h, nullptr, h_prm->d_max, bp);
   if (!d_ws || ws_bytes < bp.bytes) return AERO_ERR_WORKSPACE;
@@ -814,21 +824,21 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h, flo
     });
   if (he == hipSuccess)
     he = timed(AERO_K_GRAD_REDUCE, s, [&] {
-      return launch_grad_reduce(pl.d_probs, prm, MN, bp.gsamp, (double)scale, d_grad_u_nom,
+      return launch_grad_reduce(pl.d_probs, prm, MN, bp.gsamp, d_grad_L, d_grad_u_nom,
                                 d_grad_w, bp.wpart, s);
     });
   return dev_status(he);
 }
 
-int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem* h, float scale,
-                                    float* d_grad_u_nom, float* d_grad_w, void* d_ws,
-                                    size_t ws_bytes, void* stream) {
+int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem* h,
+                                    const float* d_grad_L, float* d_grad_u_nom,
+                                    float* d_grad_w, void* d_ws, size_t ws_bytes,
+                                    void* stream) {
   int e = check_params(h_prm);
   if (e) return e;
   e = check_problems(h, 1, true);
   if (e) return e;
   if (!d_grad_u_nom || !d_grad_w || !h[0].nearest_idx) return AERO_ERR_NULL;
-  if (!finite(scale)) return AERO_ERR_PARAM;
   BackwardPlan bp;
   plan_backward(h, nullptr, h_prm->d_max, bp);
   if (!d_ws || ws_bytes < bp.bytes) return AERO_ERR_WORKSPACE;
@@ -858,7 +868,7 @@ int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem
     });
   if (he == hipSuccess)
     he = timed(AERO_K_GRAD_REDUCE, s, [&] {
-      return launch_grad_reduce(pl.d_probs, prm, MN, bp.gsamp, (double)scale, d_grad_u_nom,
+      return launch_grad_reduce(pl.d_probs, prm, MN, bp.gsamp, d_grad_L, d_grad_u_nom,
                                 d_grad_w, bp.wpart, s);
     });
   return dev_status(he);

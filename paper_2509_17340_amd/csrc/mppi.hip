@@ -284,9 +284,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const DevProblem* __re
   const int64_t gid = (int64_t)blockIdx.x * kFinSamples + lane;
   const bool active = gid < total;
   double s[kTerms] = {0.0, 0.0, 0.0, 0.0};
-  int b = 0;
+  const int b =
+      active ? find_owner(probs, n, gid, [](const DevProblem& p) { return p.sample_base; }) : 0;
+  load_weights(probs[b].w_dev, prm);
   if (active) {
-    b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.sample_base; });
     const DevProblem& P = probs[b];
     const int K = P.K, N = P.N;
     const int64_t local = gid - P.sample_base;
@@ -547,6 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_final(const DevSelect* __restric
   __shared__ double s2[AERO_M_MAX];
   __shared__ double term[2][kSelTerms];
   const DevSelect& P = sel[blockIdx.x];
+  load_weights(P.w_dev, prm);
   const int M = P.M, N = P.N;
   const int64_t MN = (int64_t)M * N;
   const double pg[3] = {P.pg[0], P.pg[1], P.pg[2]}, vg[3] = {P.vg[0], P.vg[1], P.vg[2]};

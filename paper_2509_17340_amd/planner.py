@@ -253,7 +253,7 @@ class LoopRunner:
         ps = self.ps
         ps.run()
         self._shift(ps.u_nom, ps.best, 0, self.u_sel)
-        self._bwd(self.refine_params, self.ref_problem, 1.0, self.grad, self.grad_w, self.ws_b)
+        self._bwd(self.refine_params, self.ref_problem, None, self.grad, self.grad_w, self.ws_b)
         self._cand(ps.params, self.u_sel[0], self.grad[0], self.s0, self.beta, self.cands)
         select_best(ps.params, [self.cand_problem], self.cS2, self.cbest, self.ws_c)
         self._shift(self.cands, self.cbest, 1, ps.u_nom)

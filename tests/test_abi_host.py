@@ -148,8 +148,27 @@ def test_select_and_backward_validation_without_device():
     expect_status(4, aero.select_best, params(), [ok], S2, best, FakeTensor((8,)))
     expect_status(3, aero.select_best, params(mass=0.0), [ok], S2, best, ws)
     g = FakeTensor((2, 10, 4))
-    expect_status(1, aero.mppi_step_backward, params(), ok, 1.0, None, FakeTensor((5,)), ws)
-    expect_status(3, aero.mppi_step_backward, params(), ok, float("inf"), g, FakeTensor((5,)), ws)
+    expect_status(1, aero.mppi_step_backward, params(), ok, None, None, FakeTensor((5,)), ws)
+    expect_status(1, aero.mppi_step_backward, params(), ok, FakeTensor((1,)), g, None, ws)
+    expect_status(4, aero.mppi_step_backward, params(), ok, None, g, FakeTensor((5,)),
+                  FakeTensor((8,)))
+    expect_status(1, aero.mppi_step_backward_indexed, params(), ok, None, g, FakeTensor((5,)), ws)
+
+
+def test_position_count_limit():
+    """Positions are addressed by 32-bit slots: M*N*K of a problem, and the sum over a
+    call, must stay below 2^31 (AERO_ERR_SHAPE otherwise, before any workspace check)."""
+    ws = FakeTensor((1 << 20,))
+    at = make_problem(M=256, N=512, K=1 << 14)          # exactly 2^31 positions
+    expect_status(2, aero.mppi_step, params(), [at], ws)
+    expect_status(2, aero.select_best, params(), [at], FakeTensor((256,)), FakeTensor((1,)), ws)
+    g = FakeTensor((256, 512, 4))
+    expect_status(2, aero.mppi_step_backward, params(), at, None, g, FakeTensor((5,)), ws)
+    below = make_problem(M=256, N=512, K=(1 << 14) - 1)  # allowed: fails only on the workspace
+    expect_status(4, aero.mppi_step, params(), [below], ws)
+    half = make_problem(M=128, N=512, K=1 << 14)         # 2^30 each, 2^31 together
+    expect_status(4, aero.mppi_step, params(), [half], ws)
+    expect_status(2, aero.mppi_step, params(), [half, half], ws)
 
 
 def test_partition_and_guides_validation_without_device():

@@ -32,7 +32,8 @@ def gpu_backward(prob, scale=1.0):
     ws = torch.empty(aero.workspace_size(aero.CALL_BACKWARD, [pr]), dtype=torch.uint8, device="cuda")
     gu = torch.empty((M, N, 4), dtype=torch.float32, device="cuda")
     gw = torch.empty(5, dtype=torch.float32, device="cuda")
-    aero.mppi_step_backward(prob["params"], pr, scale, gu, gw, ws)
+    g = torch.full((1,), scale, dtype=torch.float32, device="cuda")  # upstream gradient
+    aero.mppi_step_backward(prob["params"], pr, g, gu, gw, ws)
     torch.cuda.synchronize()
     u_after = ps.u_nom.cpu().numpy()
     assert np.array_equal(u_after, prob["u_nom"]), "backward must not modify u_nom"
@@ -109,6 +110,73 @@ def test_autograd_function_matches_direct_call():
     assert np.array_equal(u.detach().cpu().numpy(), prob["u_nom"])
 
 
+def test_autograd_device_weights_without_host_sync():
+    """Weights and the upstream gradient stay on the device: forward and backward make
+    no synchronising torch call, and the result equals the direct calls with the same
+    weights given on the host."""
+    prob = make_plain_problem()
+    ps = PlanStep(prob)
+    ps.front_end()
+    wv = np.float32([1.5, 0.5, 2.0, 0.7, 1.25])
+    sc = StageOneContext(ps.cloud, ps.coef, prob["M"], prob["K"], prob["N"], prob["x0"],
+                         prob["p_goal"], prob["params"])
+    u = torch.tensor(prob["u_nom"], device="cuda", requires_grad=True)
+    w = torch.tensor(wv, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    torch.cuda.set_sync_debug_mode("error")
+    try:
+        L = StageOneCost.apply(u, w, sc)
+        (3.0 * L).backward()
+    finally:
+        torch.cuda.set_sync_debug_mode("default")
+    torch.cuda.synchronize()
+    host = dict(prob, params=dict(prob["params"], w=wv))
+    gu, gw, _, _ = gpu_backward(host, scale=3.0)
+    np.testing.assert_array_equal(u.grad.cpu().numpy(), gu.astype(np.float32))
+    np.testing.assert_array_equal(w.grad.cpu().numpy(), gw.astype(np.float32))
+    ps2 = PlanStep(host)
+    ps2.front_end()
+    ps2.stage1()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sc.S1.cpu().numpy(), ps2.S1.cpu().numpy())
+
+
+def test_indexed_backward_ignores_out_of_range_indices():
+    """Caller-given nearest indices at or beyond the cloud's end (stale ones from a
+    larger cloud) are treated as 'no point within reach', as -1 is."""
+    prob = make_plain_problem()
+    ps = PlanStep(prob)
+    ps.front_end()
+    M, K, N, P = prob["M"], prob["K"], prob["N"], len(prob["cloud"])
+    nidx = torch.full((M, N, K), -7, dtype=torch.int32, device="cuda")
+    u_copy = ps.u_nom.clone()
+    fwd = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], u_copy, coef=ps.coef,
+                       v_goal=prob["v_goal"], q_goal=prob["q_goal"], nearest_idx=nidx)
+    ws = torch.empty(max(aero.workspace_size(aero.CALL_MPPI_STEP, [fwd]),
+                         aero.workspace_size(aero.CALL_BACKWARD, [fwd])), dtype=torch.uint8,
+                     device="cuda")
+    aero.mppi_step(prob["params"], [fwd], ws)
+    torch.cuda.synchronize()
+    base = nidx.clone()
+    live = base >= 0
+    assert int(live.sum()) > 10
+    # drop every other live index: once to -1, once to an index just past the cloud
+    sel = live & (torch.arange(K, device="cuda") % 2 == 0)
+    minus, stale = base.clone(), base.clone()
+    minus[sel] = -1
+    stale[sel] = P + ((torch.arange(K, device="cuda") // 2) % 2).to(torch.int32).expand_as(base)[sel]
+    outs = []
+    for idx in (minus, stale):
+        bwd = aero.Problem(ps.cloud, M, K, N, prob["x0"], prob["p_goal"], ps.u_nom, coef=ps.coef,
+                           v_goal=prob["v_goal"], q_goal=prob["q_goal"], nearest_idx=idx)
+        gu = torch.empty((M, N, 4), dtype=torch.float32, device="cuda")
+        gw = torch.empty(5, dtype=torch.float32, device="cuda")
+        aero.mppi_step_backward_indexed(prob["params"], bwd, None, gu, gw, ws)
+        torch.cuda.synchronize()
+        outs.append((gu.cpu().numpy(), gw.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_backward_identical_across_pass_a_variants():
     """The filter pass only decides which positions get the exact search: gradients
     are bitwise the same whichever variant runs it."""
@@ -161,7 +229,8 @@ def test_indexed_backward_matches_full(which):
                        problem_id=prob.get("problem_id", 0))
     gu = torch.empty((M, N, 4), dtype=torch.float32, device="cuda")
     gw = torch.empty(5, dtype=torch.float32, device="cuda")
-    aero.mppi_step_backward_indexed(prob["params"], bwd, 0.5, gu, gw, ws)
+    half = torch.full((1,), 0.5, dtype=torch.float32, device="cuda")
+    aero.mppi_step_backward_indexed(prob["params"], bwd, half, gu, gw, ws)
     torch.cuda.synchronize()
     assert np.array_equal(np.transpose(nidx.cpu().numpy(), (0, 2, 1)), nidx_full)
     assert np.array_equal(gu.cpu().numpy().astype(np.float64), gu_full)
