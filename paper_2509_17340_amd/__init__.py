@@ -135,14 +135,18 @@ def _check(status, where):
 
 
 def _ptr(t):
-    """Device (or host) address of a tensor / array, or None."""
+    """Device (or host) address of a tensor / array, an explicit integer address, or
+    None.  Anything else (a Python float such as an upstream gradient given by value)
+    is refused: it would otherwise become a bogus address that a kernel dereferences."""
     if t is None:
         return None
     if hasattr(t, "data_ptr"):
         return t.data_ptr()
     if isinstance(t, np.ndarray):
         return t.ctypes.data
-    return int(t)
+    if isinstance(t, (int, np.integer)) and not isinstance(t, (bool, np.bool_)):
+        return int(t)
+    raise TypeError(f"expected a tensor, an array, an address or None, got {type(t).__name__}")
 
 
 _DT = {"f32": "torch.float32", "f64": "torch.float64", "i32": "torch.int32", "u8": "torch.uint8"}
@@ -161,6 +165,18 @@ def _need(t, numel, kind, name):
         raise ValueError(f"{name}: tensor must be contiguous")
     if t.numel() < numel:
         raise ValueError(f"{name}: {t.numel()} elements, the call needs {numel}")
+    if getattr(t, "is_cuda", True) is False:
+        raise ValueError(f"{name}: must be a device tensor (the kernels read it on the GPU)")
+
+
+def _need_device_scalar(g):
+    """The upstream gradient of a backward call: None (= 1) or a device float32 tensor
+    holding at least one element (the kernels read it on the device)."""
+    if g is None:
+        return
+    if not hasattr(g, "data_ptr"):
+        raise TypeError(f"grad_L must be None or a device float32 tensor, got {type(g).__name__}")
+    _need(g, 1, "f32", "grad_L")
 
 
 def _stream(stream=None):
@@ -394,7 +410,9 @@ def mppi_step_backward(prm, problem, grad_L, grad_u_nom, grad_w, ws, ws_bytes=No
     float32 scalar g, or None for g = 1."""
     p = params_struct(prm) if isinstance(prm, dict) else prm
     s = problem.struct()
-    _need(grad_L, 1, "f32", "grad_L")
+    _need_device_scalar(grad_L)
+    _need(grad_u_nom, problem.M * problem.N * 4, "f32", "grad_u_nom")
+    _need(grad_w, 5, "f32", "grad_w")
     nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
     _check(_lib.aero_mppi_step_backward(ctypes.byref(p), ctypes.byref(s), _ptr(grad_L),
                                         _ptr(grad_u_nom), _ptr(grad_w), _ptr(ws), nbytes,
@@ -408,7 +426,9 @@ def mppi_step_backward_indexed(prm, problem, grad_L, grad_u_nom, grad_w, ws, ws_
     the device float32 scalar upstream gradient, or None for 1."""
     p = params_struct(prm) if isinstance(prm, dict) else prm
     s = problem.struct()
-    _need(grad_L, 1, "f32", "grad_L")
+    _need_device_scalar(grad_L)
+    _need(grad_u_nom, problem.M * problem.N * 4, "f32", "grad_u_nom")
+    _need(grad_w, 5, "f32", "grad_w")
     nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
     _check(_lib.aero_mppi_step_backward_indexed(ctypes.byref(p), ctypes.byref(s), _ptr(grad_L),
                                                 _ptr(grad_u_nom), _ptr(grad_w), _ptr(ws), nbytes,

@@ -233,3 +233,25 @@ def test_binding_rejects_undersized_tensors():
     with pytest.raises(ValueError):
         aero.advance_state(params(), torch.zeros(10), torch.zeros((2, 5, 4)).transpose(0, 1),
                            torch.zeros(1, dtype=torch.int32), torch.zeros(10))
+
+
+def test_binding_refuses_values_where_device_pointers_go():
+    """A backward call reads the upstream gradient on the device: a Python number given
+    in its place is refused on the host (it must never become an address), and so are
+    host tensors for device arguments."""
+    import torch
+    ws = FakeTensor((1 << 30,))
+    ok = make_problem()
+    g, gw = FakeTensor((2, 10, 4)), FakeTensor((5,))
+    for fn in (aero.mppi_step_backward, aero.mppi_step_backward_indexed):
+        with pytest.raises(TypeError):
+            fn(params(), ok, 1.0, g, gw, ws)
+        with pytest.raises(ValueError):
+            fn(params(), ok, torch.ones(1), g, gw, ws)     # host tensor
+        with pytest.raises(TypeError):
+            fn(params(), ok, torch.ones(1, dtype=torch.float64), g, gw, ws)
+    with pytest.raises(TypeError):
+        aero.shift_controls(FakeTensor((2, 5, 4)), 0.5, 1, FakeTensor((2, 5, 4)))
+    with pytest.raises(ValueError):
+        aero.advance_state(params(), torch.zeros(10), FakeTensor((2, 5, 4)),
+                           FakeTensor((1,)), FakeTensor((10,)))

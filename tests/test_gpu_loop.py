@@ -42,7 +42,7 @@ def test_loop_refinement_and_warm_start():
     torch.cuda.synchronize()
     assert np.array_equal(np_(lr.u_sel)[0], u_nom[best])
     # refinement gradient of S2 (one noise-free rollout, weights (0,0,0,1,1))
-    lr._bwd(lr.refine_params, lr.ref_problem, 1.0, lr.grad, lr.grad_w, lr.ws_b)
+    lr._bwd(lr.refine_params, lr.ref_problem, None, lr.grad, lr.grad_w, lr.ws_b)
     torch.cuda.synchronize()
     ref = dict(prob)
     ref.update(M=1, K=1, params=lr.refine_params, u_nom=np_(lr.u_sel))
