@@ -311,15 +311,22 @@ int aero_advance_state(const aero_params* h_prm, const float* d_x0, const float*
 
 /* ---- kernel-variant selection --------------------------------------------------- */
 
-/* The first, approximate pass of the nearest-distance computation has three
- * implementations: 0 = VALU FMAs, 1 = single-precision matrix cores (MFMA),
- * 2 = half-precision matrix cores on hi/lo-split coordinates.  By default (-1) the
- * library autotunes per call shape (sum of M N K, sum of cloud sizes, problem count):
- * the first three calls of a shape each time one variant with HIP events on the
- * call's stream, the fourth call keeps the fastest for that shape.  Costs, controls
- * and selections are bitwise identical for every variant; only min_dist2 entries
- * beyond d_max may differ.  While the stream is being captured into a graph an
- * unsettled shape uses variant 0 and records nothing.
+/* The nearest distance d_t of the collision cost (Sec. IV-C) only matters below d_max
+ * (the penalty is zero from there on).  Each call therefore cuts the rollout
+ * positions into spatially sorted blocks, lists for every block the cloud sub-tiles
+ * (256 consecutive points, in the given order or in a Morton order of the cloud)
+ * whose bounding box lies within reach of the block's box (the cull step), runs a
+ * cheap approximate first pass over those pairs only, and an exact second pass over
+ * the positions the first pass finds near the cloud.  The first pass has three
+ * implementations: 0 = VALU FMAs on blocks of 2048 positions, 1 = half-precision
+ * matrix cores on hi/lo-split coordinates with blocks of 512 positions, 2 = the same
+ * with blocks of 1024.  By default (-1) the library autotunes per call shape (sum of
+ * M N K, sum of cloud sizes, problem count): the first three calls of a shape each
+ * time one variant with HIP events on the call's stream, a later call keeps the
+ * fastest for that shape.  Costs, controls and selections are bitwise identical for
+ * every variant, with or without the cull step; only min_dist2 and nearest_idx
+ * entries beyond d_max may differ.  While the stream is being captured into a graph
+ * an unsettled shape uses variant 0 and records nothing.
  * aero_set_pass_a_variant forces a variant for all later calls (-1 = autotune);
  * errors: AERO_ERR_PARAM for other values. */
 int aero_set_pass_a_variant(int variant);
@@ -327,15 +334,30 @@ int aero_set_pass_a_variant(int variant);
 /* The variant in use for this call shape: 0, 1 or 2, or -1 while still being tuned. */
 int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems);
 
+/* on = 1 (default): the cull step lists only the sub-tiles within reach of each block;
+ * on = 0: every sub-tile of every block (the two passes become brute force over the
+ * whole cloud; for tests and measurements).  Applies to later calls.  Errors:
+ * AERO_ERR_PARAM for other values. */
+int aero_set_pass_a_cull(int on);
+
+/* Profiling aid: the number of (query block, cloud sub-tile) items that the cull step
+ * of the last aero_mppi_step on this workspace listed (the first pass evaluates
+ * items x 256 x block-size position-point pairs).  Reads device memory synchronously
+ * (hipMemcpy): call it once the stream has finished the step.  Errors: AERO_ERR_NULL,
+ * AERO_ERR_SHAPE / AERO_ERR_PARAM as aero_mppi_step's size checks, AERO_ERR_WORKSPACE,
+ * AERO_ERR_DEVICE. */
+int aero_cull_items(const aero_problem* h_problems, int32_t n_problems, const void* d_ws,
+                    size_t ws_bytes, int64_t* h_items);
+
 /* ---- per-kernel timing (profiling aid) ---------------------------------------- */
 
 /* Kernel identifiers for aero_timing_read. */
 typedef enum aero_kernel {
   AERO_K_PARTITION = 0,    /* the three partition/anchor kernels of one call        */
   AERO_K_GUIDES = 1,
-  AERO_K_ROLLOUT = 2,      /* Stage-I noise (+ cloud sub-tile boxes and the call's
+  AERO_K_ROLLOUT = 2,      /* Stage-I noise (+ cloud tile boxes and the call's
                               descriptors) and RK4 rollout                         */
-  AERO_K_MIN_DIST = 3,     /* Stage-I nearest distance, pass A (every position)      */
+  AERO_K_MIN_DIST = 3,     /* Stage-I nearest distance, pass A (the listed pairs)    */
   AERO_K_FINALIZE = 4,     /* Stage-I state terms, J_col and S1 (and the write-back
                               of a sorted set's distances to the positions' order) */
   AERO_K_UPDATE = 5,       /* softmax weights and control update                    */
@@ -347,8 +369,10 @@ typedef enum aero_kernel {
   AERO_K_NEAREST = 11,     /* backward: nearest indices of flagged positions         */
   AERO_K_ADJOINT = 12,     /* backward: per-sample reverse sweep                     */
   AERO_K_GRAD_REDUCE = 13, /* backward: sums over samples                            */
-  AERO_K_SORT = 14,        /* Stage-I spatial sort of the positions (six kernels)    */
-  AERO_K_COUNT = 15
+  AERO_K_SORT = 14,        /* Stage-I spatial sort of the positions and the cloud
+                              (six kernels)                                          */
+  AERO_K_CULL = 15,        /* Stage-I cull step (sorted-cloud boxes, block lists)    */
+  AERO_K_COUNT = 16
 } aero_kernel;
 
 /* on != 0: from now on every launch of the kernels above is bracketed by two HIP

@@ -20,6 +20,7 @@ __all__ = [
     "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
     "KERNELS", "shift_controls", "step_candidates", "set_pass_a_variant", "pass_a_variant",
+    "set_pass_a_cull", "cull_items",
     "use_library", "accumulate_cloud", "advance_state", "mppi_step_backward_indexed",
 ]
 
@@ -87,6 +88,8 @@ _SIGS = {
                                                        _P]),
     "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "aero_set_pass_a_variant": (ctypes.c_int, [ctypes.c_int]),
+    "aero_set_pass_a_cull": (ctypes.c_int, [ctypes.c_int]),
+    "aero_cull_items": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "aero_shift_controls": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                            _P, ctypes.c_int32, _P]),
     "aero_step_candidates": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float,
@@ -101,7 +104,7 @@ _SIGS = {
 
 KERNELS = ("partition", "guides", "rollout", "min_dist", "finalize", "update", "sel_rollout",
            "sel_min_dist", "sel_final", "flag", "min_dist_exact", "nearest", "adjoint",
-           "grad_reduce", "sort")
+           "grad_reduce", "sort", "cull")
 
 
 def _load(path=LIB_PATH):
@@ -377,9 +380,25 @@ def advance_state(prm, x0, u, index, x1, stream=None):
 
 
 def set_pass_a_variant(variant):
-    """Force the first distance pass: 0 = VALU, 1 = FP32 MFMA, 2 = split-FP16 MFMA,
-    -1 = autotune (default)."""
+    """Force the first distance pass: 0 = VALU (2048-position blocks), 1 = split-FP16
+    matrix cores (512-position blocks), 2 = split-FP16 matrix cores (1024-position
+    blocks), -1 = autotune (default)."""
     _check(_lib.aero_set_pass_a_variant(int(variant)), "aero_set_pass_a_variant")
+
+
+def set_pass_a_cull(on=True):
+    """Cull step on (default) or off (every block against the whole cloud)."""
+    _check(_lib.aero_set_pass_a_cull(1 if on else 0), "aero_set_pass_a_cull")
+
+
+def cull_items(problems, ws, ws_bytes=None):
+    """Items (query block, cloud sub-tile) the last mppi_step on `ws` listed (synchronous)."""
+    arr = _problem_array(problems)
+    out = ctypes.c_int64()
+    nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.aero_cull_items(ctypes.cast(arr, ctypes.c_void_p), len(problems), _ptr(ws), nbytes,
+                                ctypes.byref(out)), "aero_cull_items")
+    return out.value
 
 
 def pass_a_variant(problems):

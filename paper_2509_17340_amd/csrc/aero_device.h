@@ -356,37 +356,122 @@ __device__ __forceinline__ int find_owner(const T* recs, int n, int64_t i, F bas
   return lo;
 }
 
-// Bounding box of sub-tile `bid` (counted over the two-pass sets in box_base order)
-// of a cloud: kSubPts consecutive points, one per thread of a kBlock block.  Read
-// by pass A's hit records.
-__device__ inline void cloud_box_block(const QuerySet* __restrict__ sets, int n_sets, int64_t bid) {
-  static_assert(kSubPts == kBlock, "one point per thread");
-  __shared__ float red[6][kBlock / 64];
-  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.box_base; });
-  const QuerySet& S = sets[s];
-  const int64_t sub = bid - S.box_base;
-  const int64_t g = sub * kSubPts + threadIdx.x;
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (g < S.n_points) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = S.cloud[3 * g + a];
+// ---------------------------------------------------------------------------
+// Items of the first distance pass: (global query block, sub-tile | order << 31).
+// ---------------------------------------------------------------------------
+
+// The two-pass set owning global query block gqb; `c` caches the last lookup
+// (items of one block, and mostly of one set, come in runs).
+struct SetCache {
+  int s;
+  int64_t lo, hi;
+};
+__device__ inline int set_of(const QuerySet* __restrict__ sets, int n_sets, int64_t gqb,
+                             SetCache& c) {
+  if (gqb >= c.lo && gqb < c.hi) return c.s;
+  c.s = find_owner(sets, n_sets, gqb, [](const QuerySet& q) { return q.qb_base; });
+  c.lo = sets[c.s].qb_base;
+  c.hi = c.lo + sets[c.s].n_qblocks;
+  return c.s;
+}
+
+// This thread's point of an item's sub-tile (thread i takes point i), from the raw
+// cloud or the sorted records; *cnt receives the sub-tile's point count (0 for an
+// item that names no sub-tile of the set, which is then skipped).  Addresses are
+// always inside the cloud.
+__device__ inline void item_point(const QuerySet& S, unsigned ys, float& x, float& y, float& z,
+                                  int32_t& idx, bool& in, int& cnt) {
+  const int64_t n = S.n_points;
+  if (n <= 0) {  // not a set with a cloud: nothing to read
+    x = y = z = 0.0f;
+    idx = -1;
+    in = false;
+    cnt = 0;
+    return;
   }
+  const int64_t g0 = (int64_t)(ys & 0x7fffffffu) * kSubPts;
+  const bool srt = (ys >> 31) != 0;
+  cnt = (g0 < n && (!srt || S.scloud)) ? (int)min<int64_t>(kSubPts, n - g0) : 0;
+  in = (int)threadIdx.x < cnt;
+  const int64_t g = in ? g0 + threadIdx.x : 0;
+  if (srt && S.scloud) {
+    const float4 r = S.scloud[g];
+    x = r.x;
+    y = r.y;
+    z = r.z;
+    idx = __float_as_int(r.w);
+  } else {
+    x = S.cloud[3 * g];
+    y = S.cloud[3 * g + 1];
+    z = S.cloud[3 * g + 2];
+    idx = (int32_t)g;
+  }
+}
+
+// Whether global block gqb is a block of set S.
+__device__ inline bool block_of(const QuerySet& S, int64_t gqb) {
+  return gqb >= S.qb_base && gqb < S.qb_base + S.n_qblocks;
+}
+
+// Mark item i as hit when some lane of the wave saw a query under its block's bound.
+__device__ inline void mark_hit(bool hit, unsigned char* hitf, int64_t i) {
+  const unsigned long long hb = __ballot(hit);
+  if (hb && (int)(threadIdx.x & 63) == __ffsll((long long)hb) - 1) hitf[i] = 1;
+}
+
+// Bounding boxes of cloud tile `t` (kTilePts consecutive points) and of its kTileSplit
+// sub-tiles, from the raw points ([n][3], c4 == nullptr) or the sorted records (c4).
+// One workgroup of kBlock threads; sub-tile j's points are taken one per thread.
+// Sub-tiles past the end of the cloud are not written.
+__device__ inline void tile_boxes(const float* __restrict__ c3, const float4* __restrict__ c4,
+                                  int64_t n_points, int64_t t, float* __restrict__ tbox,
+                                  float* __restrict__ sbox) {
+  static_assert(kSubPts == kBlock, "one point per thread");
+  constexpr int kW = kBlock / 64;
+  __shared__ float red[kTileSplit][6][kW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_minf(lo[a]);
-    hi[a] = wave_maxf(hi[a]);
-    if (lane == 0) {
-      red[a][w] = lo[a];
-      red[3 + a][w] = hi[a];
+  for (int j = 0; j < kTileSplit; ++j) {
+    const int64_t g = t * kTilePts + j * kSubPts + threadIdx.x;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (g < n_points) {
+      float p[3];
+      if (c4) {
+        const float4 r = c4[g];
+        p[0] = r.x;
+        p[1] = r.y;
+        p[2] = r.z;
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p[a] = c3[3 * g + a];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) lo[a] = hi[a] = p[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = wave_minf(lo[a]);
+      hi[a] = wave_maxf(hi[a]);
+      if (lane == 0) {
+        red[j][a][w] = lo[a];
+        red[j][3 + a][w] = hi[a];
+      }
     }
   }
   __syncthreads();
-  if (threadIdx.x < 6) {
-    const int a = threadIdx.x;
-    float v = red[a][0];
-    for (int k = 1; k < kBlock / 64; ++k) v = a < 3 ? fminf(v, red[a][k]) : fmaxf(v, red[a][k]);
-    S.qbox[6 * sub + a] = v;
+  const int tid = threadIdx.x;
+  if (tid < kTileSplit * 6) {  // sub-tile boxes
+    const int j = tid / 6, a = tid % 6;
+    float v = red[j][a][0];
+    for (int k = 1; k < kW; ++k) v = a < 3 ? fminf(v, red[j][a][k]) : fmaxf(v, red[j][a][k]);
+    const int64_t sub = t * kTileSplit + j;
+    if (sub * kSubPts < n_points) sbox[6 * sub + a] = v;
+  } else if (tid < kTileSplit * 6 + 6) {  // the tile's box
+    const int a = tid - kTileSplit * 6;
+    float v = red[0][a][0];
+    for (int j = 0; j < kTileSplit; ++j)
+      for (int k = 0; k < kW; ++k) v = a < 3 ? fminf(v, red[j][a][k]) : fmaxf(v, red[j][a][k]);
+    tbox[6 * t + a] = v;
   }
 }
 

@@ -13,12 +13,9 @@ namespace aero {
 #ifndef AERO_QUERIES_PER_LANE
 #define AERO_QUERIES_PER_LANE 8
 #endif
-#ifndef AERO_F16_COLS
-#define AERO_F16_COLS 8
-#endif
 
 constexpr int kBlock = 256;                              // threads per workgroup (4 wave64)
-constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points staged in LDS per tile
+constexpr int kTilePts = AERO_TILE_PTS;                  // cloud points per tile (box hierarchy)
 constexpr int kSelCopies = 8;                            // Stage-II distance copies (atomics spread)
 // The rollout's waves merge their position bounds into kBoxCopies copies of the sort
 // box (a wave's copy is its workgroup index modulo kBoxCopies), each in a 256-byte
@@ -26,22 +23,24 @@ constexpr int kSelCopies = 8;                            // Stage-II distance co
 // merges the copies.
 constexpr int kBoxCopies = 16;
 constexpr int kBoxStride = 64;  // words per copy
-constexpr int kTileSplit = 4;                            // sub-tiles per tile (pass-B work units)
-constexpr int kSubPts = kTilePts / kTileSplit;           // cloud points per sub-tile
+constexpr int kTileSplit = 4;                            // sub-tiles per tile
+constexpr int kSubPts = kTilePts / kTileSplit;           // cloud points per sub-tile (work unit)
 constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
 constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
+static_assert(kSubPts == kBlock, "a sub-tile is staged one point per thread");
 
-// Pass-A variants (the expanded-form first pass of the distance computation).
-constexpr int kPassAValu = 0;   // VALU FMAs, kQueriesPerBlock positions per block
-constexpr int kPassAMfma = 1;   // matrix-core MFMA, 512 positions per block
-constexpr int kPassAF16s = 2;   // half-precision matrix cores on split coordinates, 1024 per block
+// Pass-A variants (the expanded-form first pass of the distance computation).  Each
+// runs over the (query block, cloud sub-tile) pairs that the cull step lists.
+constexpr int kPassAValu = 0;    // VALU FMAs, kQueriesPerBlock positions per block
+constexpr int kPassAF16s4 = 1;   // half-precision matrix cores on split coordinates,
+                                 //   4 column blocks of 32 per wave: 512 per block
+constexpr int kPassAF16s8 = 2;   //   the same with 8 column blocks: 1024 per block
 constexpr int kPassAVariants = 3;
-constexpr int kF16Cols = AERO_F16_COLS;   // split-f16 pass A: column blocks of 32 queries per wave
-constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 512, 4 * 32 * kF16Cols};
+constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 4 * 32 * 4, 4 * 32 * 8};
+constexpr int kPassAMinQPB = 4 * 32 * 4;
 // Pass B gives each lane at most kQueriesPerLane queries of one pass-A block.
-static_assert(kTileSplit <= 4, "sub-tile masks take the low 4 bits of a work entry");
-static_assert(kQueriesPerBlock <= kQueriesPerLane * kBlock && 512 <= kQueriesPerBlock &&
-                  4 * 32 * kF16Cols <= kQueriesPerBlock, "pass-A blocks must fit one pass-B block");
+static_assert(kQueriesPerBlock <= kQueriesPerLane * kBlock && kPassAMinQPB <= kQueriesPerBlock &&
+                  4 * 32 * 8 <= kQueriesPerBlock, "pass-A blocks must fit one pass-B block");
 
 // Per-problem record, built on the host and copied into the workspace.
 struct DevProblem {
@@ -63,7 +62,7 @@ struct DevProblem {
   int64_t row_base;      // prefix of M*N over problems
   double* J;             // optional [5][M*K] unweighted terms (track, vnorm, ctrl, goal, col)
   int32_t* nidx;         // optional [M][N][K] nearest point index (-1: none within reach)
-  int32_t* work_count;   // pass-B work counter of the problem's query set (or nullptr)
+  int32_t* item_count;   // the call's (query block, sub-tile) item counter (or nullptr)
   unsigned* sort_box;    // [kBoxCopies][kBoxStride] copies of the position bounding box
                          //   of the spatial sort (or nullptr)
   double* noise;         // [M][N][4][K] standard normals drawn ahead of the rollout
@@ -74,36 +73,45 @@ struct DevProblem {
   const float* w_dev;    // optional [5] device term weights replacing DevParams::w
 };
 
-// Spatial sort of one problem's rollout positions (stable LSD radix sort on the top
-// 16 bits of a 24-bit Morton key over the positions' bounding box, 2 passes of 8 bits).
+// Spatial sort of one problem's rollout positions, or of its cloud (stable LSD radix
+// sort on the top 16 bits of a 24-bit Morton key, 2 passes of 8 bits).  Both key on the
+// positions' bounding box (the cloud's box widened by `margin`, so that cloud points
+// near the positions get fine cells and the far ones collect in boundary cells).
 constexpr int kSortDigits = 256;
 constexpr int kSortPasses = 2;
 struct SortSet {
-  const float* px;
+  const float* px;       // element i at px[i * stride] (planes: stride 1; cloud: stride 3)
   const float* py;
   const float* pz;
-  float* sp;             // [3][Q] positions in slot order (written by the last pass)
+  float* sp;             // positions: [3][Q] in slot order (written by the last pass)
   int64_t Q;
   int64_t block_base;    // prefix of n_blocks over sets
   int32_t n_blocks;      // ceil(Q / kBlock)
-  int32_t pad;
+  int32_t stride;
   unsigned* box;         // [kBoxCopies][kBoxStride] copies; words 0..5 of each hold the
                          //   order-preserving bits of min x, y, z, max x, y, z
   uint32_t* key[2];      // [Q] ping-pong keys
-  int32_t* val[2];       // [Q] ping-pong query indices; the result is
+  int32_t* val[2];       // [Q] ping-pong element indices; the result is
                          //   val[kSortPasses % 2]
-  int32_t* inv;          // [Q] query -> slot (written by the last pass)
+  int32_t* inv;          // positions: [Q] query -> slot (written by the last pass)
   int32_t* table;        // [kSortDigits][n_blocks] per-block digit counts -> offsets
   int32_t* rowsum;       // [kSortDigits] digit totals
+  float4* sc;            // cloud: [Q] sorted points (x, y, z, original index as int bits)
+  float margin;          // key box = box widened by margin on every side
+  int32_t pad;
 };
 
 // One set of query positions scored against one cloud by the distance kernels.
 //
-// Exact sets (list == nullptr) run the direct-form kernel over every query.
-// Two-pass sets run the recentred expanded form over every query (pass A), flag
-// the queries whose approximate squared distance is below a per-block bound
-// (`thresh`, derived from the rounding error of pass A), and rerun the direct
-// form on the flagged list only (pass B).
+// Exact sets (list == nullptr) run the direct-form kernel over every query against
+// every cloud point.  Two-pass sets are cut into query blocks of qpbA consecutive
+// (spatially sorted) positions.  The cull step gives each block a centre, a bound
+// `thresh` on its pass-A rounding error, and the list of cloud sub-tiles whose
+// bounding box lies within reach of the block's box, in the raw or the sorted cloud
+// order (whichever lists fewer); pass A runs the recentred expanded form over those
+// (block, sub-tile) items only and marks the items in which some query came under
+// the bound; the flag step lists the queries under the bound, and pass B reruns the
+// direct form for them against the marked items.
 struct QuerySet {
   const float* px;
   const float* py;
@@ -117,28 +125,36 @@ struct QuerySet {
   int32_t n_copies;      // exact sets: copies of `out` that workgroups spread their
                          //   atomics over (workgroup b uses copy b % n_copies)
   int32_t n_points;
-  int32_t n_qblocks;     // ceil(Q / kQueriesPerBlock)
-  int32_t n_chunks;      // cloud splits of the full pass: chunk c covers points
+  int32_t n_qblocks;     // ceil(Q / qpbA)
+  int32_t n_chunks;      // exact sets: cloud splits, chunk c covers points
   int32_t chunk_pts;     //   [c chunk_pts, min((c+1) chunk_pts, n_points))
-  int64_t block_base;    // prefix of n_qblocks * n_chunks over sets
+  int32_t qpbA;          // positions per query block
+  int64_t block_base;    // exact sets: prefix of n_qblocks * n_chunks over sets
   // two-pass extension
   float* thresh;         // [n_qblocks] flag bound on the pass-A squared distance
   int32_t* list;         // [n_qblocks * qpbA] flagged queries, segment qb at qb * qpbA
                          //   (nullptr: exact set)
   int32_t* seg_count;    // [n_qblocks] flagged queries of each query block
-  int2* work;            // [n_qblocks * n_tiles] (query block, tile << 4 | sub-tile mask):
-                         //   some query of the block came under the bound in the tile
-                         //   in pass A; bit j: sub-tile j's bounding box lies within
-                         //   reach of the block's bounding box
   float4* fpos;          // [n_qblocks * qpbA] positions of the flagged queries, in the
                          //   order of `list` (written by the flag kernel)
-  float* qbox;           // [ceil(n_points / kSubPts)][6] sub-tile bounding boxes (lo, hi)
-  int64_t box_base;      // prefix of ceil(n_points / kSubPts) over two-pass sets
-  int32_t* work_count;   // entries of `work` (zeroed by the rollout kernel)
+  float4* binfo;         // [n_qblocks] block centre (x, y, z) and thresh (w)
+  float* tbox;           // [n_tiles][6] tile bounding boxes (lo, hi) of the raw cloud
+  float* sbox;           // [n_sub][6] sub-tile bounding boxes of the raw cloud
+  const float4* scloud;  // [n_points] the cloud in Morton order (x, y, z, original
+                         //   index bits), or nullptr: raw order only
+  float* stbox;          // [n_tiles][6], [n_sub][6]: boxes of the sorted cloud
+  float* ssbox;
+  int2* items;           // the call's item list: (global query block, sub-tile | order
+                         //   << 31); a block's items are consecutive
+  int32_t* item_count;   // entries of `items` (zeroed by the noise kernel)
+  unsigned char* hitf;   // [items]: 1 where some query of the block came under the bound
+  int64_t qb_base;       // prefix of n_qblocks over two-pass sets (global block index)
+  int64_t tile_base;     // prefix of n_tiles over two-pass sets
   int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
-  int32_t qpbA;          // positions per pass-A block (the variant's block size)
-  int32_t n_tiles;       // ceil(n_points / kTilePts); pass-A chunks are whole tiles
+  int32_t n_tiles;       // ceil(n_points / kTilePts)
+  int32_t cull;          // 0: every sub-tile of the raw cloud is listed (brute force)
   float d_max;
+  int32_t pad1;
   const int32_t* perm;   // [Q] slot -> query, spatially sorted (nullptr: identity)
   unsigned* out_slot;    // two-pass sets: [Q] squared distances by slot (== out without
                          //   a sort); scattered back to `out` once pass B is done
@@ -164,48 +180,26 @@ __device__ inline int64_t perm_query(const QuerySet& S, int64_t slot) {
   return q < 0 ? 0 : (q >= S.Q ? S.Q - 1 : q);
 }
 
-// Pass-A hit of query block qb (bounding box [blo, bhi]) in cloud tile `tile`:
-// record the tile with the mask of its sub-tiles whose bounding box lies within
-// squared distance r2 of the block's box.  With r2 = 2 thresh - d_max^2 (pass A errs by at most
-// thresh - d_max^2, and a flagged query's pass-A value is below thresh) every point
-// within d_max of a flagged query, and the point that flagged it, is in a recorded
-// sub-tile; the relative margin covers the rounding of the box distance.
-__device__ inline void append_hits(const QuerySet& S, int qb, int64_t tile, const float blo[3],
-                                   const float bhi[3], float r2) {
-  const float lim = r2 * (1.0f + 1e-5f) + 1e-6f;
-  int mask = 0;
-  for (int j = 0; j < kTileSplit; ++j) {
-    const int64_t sub = tile * kTileSplit + j;
-    if (sub * kSubPts >= S.n_points) break;
-    const float* b = S.qbox + 6 * sub;
-    float d2 = 0.0f;
-    for (int a = 0; a < 3; ++a) {
-      const float dd = fmaxf(0.0f, fmaxf(b[a] - bhi[a], blo[a] - b[3 + a]));
-      d2 = fmaf(dd, dd, d2);
-    }
-    if (d2 <= lim) mask |= 1 << j;
-  }
-  if (mask) {
-    const int e = atomicAdd(S.work_count, 1);
-    S.work[e] = make_int2(qb, (int)(tile << 4) | mask);
-  }
-}
-
-// Pass-A hit from a block whose per-wave query bounds are red[0..2][w] (min) and
-// red[3..5][w] (max) in LDS.
-__device__ inline void append_block_hits(const QuerySet& S, int qb, int64_t tile,
-                                         const float (*red)[4], float r2) {
-  float blo[3], bhi[3];
+// Squared distance between two axis-aligned boxes (0 when they overlap).  Monotone:
+// a box containing another is never farther.
+__device__ __forceinline__ float box_dist2(const float* b, const float lo[3], const float hi[3]) {
+  float d2 = 0.0f;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    blo[a] = fminf(fminf(red[a][0], red[a][1]), fminf(red[a][2], red[a][3]));
-    bhi[a] = fmaxf(fmaxf(red[3 + a][0], red[3 + a][1]), fmaxf(red[3 + a][2], red[3 + a][3]));
+    const float dd = fmaxf(0.0f, fmaxf(b[a] - hi[a], lo[a] - b[3 + a]));
+    d2 = fmaf(dd, dd, d2);
   }
-  append_hits(S, qb, tile, blo, bhi, r2);
+  return d2;
 }
 
-// Squared reach of pass B around a block with pass-A bound thr (see append_hits).
-__device__ inline float pass_b_reach2(float thr, float d_max) {
-  return thr < INFINITY ? thr + (thr - d_max * d_max) : INFINITY;
+// Squared reach of a query block with pass-A bound thr: pass A errs by at most
+// thr - d_max^2 on every pair within d_max, so every point within d_max of a query, and
+// every point whose pass-A value falls below thr, lies within r2 = 2 thr - d_max^2 of
+// it, hence its sub-tile's box within r2 of the block's box.  The relative margin
+// covers the rounding of the box distance.
+__device__ inline float reach_limit(float thr, float d_max) {
+  const float r2 = thr < INFINITY ? thr + (thr - d_max * d_max) : INFINITY;
+  return r2 * (1.0f + 1e-5f) + 1e-6f;
 }
 
 // Per-problem Stage-II record.
@@ -258,17 +252,26 @@ hipError_t launch_rollout_noise(const DevProblem* d_probs, int n, int64_t total_
                                 int64_t total_elems, const DevParams& prm, const QuerySet* d_sets,
                                 int64_t box_blocks, const void* h_blob, size_t blob_bytes,
                                 hipStream_t s);
+hipError_t launch_sorted_boxes(const QuerySet* d_sets, int n_sets, int64_t total_tiles,
+                               hipStream_t s);
+hipError_t launch_cull(const QuerySet* d_sets, int n_sets, int64_t total_qblocks, int variant,
+                       hipStream_t s);
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_samples,
                           const DevParams& prm, hipStream_t s);
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
                            hipStream_t s);
-hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                                  int variant, hipStream_t s);
-hipError_t launch_min_dist_approx_matrix(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                                         int variant, hipStream_t s);
+// The first pass over the call's item list (items, item_count and hitf are shared by
+// every two-pass set of the call); max_items bounds the list (the grid is sized by it).
+hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
+                         const int32_t* item_count, unsigned char* hitf, int64_t max_items,
+                         int variant, hipStream_t s);
+hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* items,
+                                const int32_t* item_count, unsigned char* hitf, int64_t max_items,
+                                int variant, hipStream_t s);
 hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
-hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                                  hipStream_t s);
+hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, const int2* items,
+                                  const int32_t* item_count, const unsigned char* hitf,
+                                  int64_t max_items, hipStream_t s);
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s);

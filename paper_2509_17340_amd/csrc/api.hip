@@ -240,31 +240,11 @@ struct Cursor {
   }
 };
 
-// Fewest cloud tiles for which the positions are spatially sorted before pass A.
+// Fewest cloud tiles for which the positions (and the cloud) are spatially sorted
+// before the cull step.
 constexpr int kSortMinTiles = 16;
 
-int chunks_for(int64_t total_qblocks, int n_tiles) {
-  // Fill the chip (about 4 workgroups per CU of 256) and keep chunks short
-  // enough (<= 16 tiles) that uneven problems load-balance; among the counts up to
-  // twice that, take the one that splits the tiles most evenly (chunks are whole
-  // tiles, and the longest chunk sets the pass time).
-  const int64_t target = 1024;
-  int64_t c = (total_qblocks >= target) ? 1 : (target + total_qblocks - 1) / total_qblocks;
-  c = std::max<int64_t>(c, (n_tiles + 15) / 16);
-  c = std::min<int64_t>(std::max<int64_t>(c, 1), std::max(n_tiles, 1));
-  int64_t best = c, best_cost = INT64_MAX;
-  for (int64_t k = c; k <= std::min<int64_t>(2 * c, std::max(n_tiles, 1)); ++k) {
-    const int64_t per = (n_tiles + k - 1) / k;        // tiles of the longest chunk
-    const int64_t cost = per * 1024 + k;              // then prefer fewer chunks
-    if (cost < best_cost) {
-      best_cost = cost;
-      best = k;
-    }
-  }
-  return (int)best;
-}
-
-// Split P points into about `want` chunks of a multiple of `align` points.
+// Split P points into about `want` chunks of a multiple of `align` points (exact sets).
 void set_chunks(int64_t P, int64_t want, int32_t& n_chunks, int32_t& chunk_pts,
                 int64_t align = 64) {
   if (P <= 0) {
@@ -278,18 +258,28 @@ void set_chunks(int64_t P, int64_t want, int32_t& n_chunks, int32_t& chunk_pts,
   n_chunks = (int32_t)((P + chunk_pts - 1) / chunk_pts);
 }
 
+// Whether the cull step limits each query block to the sub-tiles within its reach
+// (0: every sub-tile is listed, which turns the two passes back into brute force).
+int g_cull = 1;
+
 struct MppiPlan {
   std::vector<DevProblem> probs;
   std::vector<QuerySet> sets;
-  std::vector<SortSet> sorts;
+  std::vector<SortSet> sorts;   // two per problem: positions, then the cloud
   DevProblem* d_probs = nullptr;
   QuerySet* d_sets = nullptr;
   SortSet* d_sorts = nullptr;   // adjacent to d_sets: one descriptor upload
-  int64_t total_samples = 0, total_rows = 0, total_blocks = 0, flag_blocks = 0, listed_items = 0;
+  int64_t total_samples = 0, total_rows = 0, flag_blocks = 0;
   int64_t sort_blocks = 0;
-  int64_t box_blocks = 0;       // sub-tile bounding boxes of the two-pass sets' clouds
+  int64_t total_tiles = 0;      // cloud tiles of the two-pass sets (box launches)
+  int64_t total_qblocks = 0;    // query blocks of the two-pass sets (cull launch)
+  int64_t item_cap = 0;         // capacity of the call's item list
   int64_t total_elems = 0;      // sum of M*N*K (rollout noise draws)
+  int2* items = nullptr;
+  int32_t* item_count = nullptr;
+  unsigned char* hitf = nullptr;
   bool any_sorted = false;      // some set works in sorted slots
+  bool any_scloud = false;      // some set has a sorted cloud
   bool any_nn = false;          // some set records nearest indices
   size_t bytes = 0;
 };
@@ -299,18 +289,25 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   Cursor cur{ws};
   pl.d_probs = cur.take<DevProblem>(n);
   pl.d_sets = cur.take<QuerySet>(n);
-  pl.d_sorts = cur.take<SortSet>(n);
+  pl.d_sorts = cur.take<SortSet>(2 * n);
   pl.probs.assign(n, DevProblem{});
   pl.sets.assign(n, QuerySet{});
-  pl.sorts.assign(n, SortSet{});
-  int64_t sort_blocks = 0, eb = 0;
+  pl.sorts.assign(2 * n, SortSet{});
   const int qpbA = kPassAQPB[variant];
-  int64_t qblocks = 0;
-  for (int b = 0; b < n; ++b) {
-    const int64_t Q = (int64_t)h[b].M * h[b].N * h[b].K;
-    if (h[b].n_points > 0) qblocks += (Q + qpbA - 1) / qpbA;
-  }
-  int64_t sb = 0, rb = 0, blk = 0, fb = 0, items = 0, bb = 0;
+  // the call's item list: a block lists each sub-tile at most once, so the blocks of
+  // the smallest block size times the sub-tiles bound it (the layout does not depend
+  // on the variant)
+  int64_t cap = 0;
+  for (int b = 0; b < n; ++b)
+    if (h[b].n_points > 0) {
+      const int64_t Q = (int64_t)h[b].M * h[b].N * h[b].K;
+      cap += (Q + kPassAMinQPB - 1) / kPassAMinQPB * (((int64_t)h[b].n_points + kSubPts - 1) / kSubPts);
+    }
+  pl.item_cap = cap;
+  pl.items = cur.take<int2>(cap);
+  pl.hitf = cur.take<unsigned char>(cap);
+  pl.item_count = cur.take<int32_t>(1);
+  int64_t sort_blocks = 0, eb = 0, sb = 0, rb = 0, fb = 0, qbb = 0, tb = 0;
   for (int b = 0; b < n; ++b) {
     const aero_problem& q = h[b];
     DevProblem& d = pl.probs[b];
@@ -341,6 +338,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     d.elem_base = eb;
     d.noise = cur.take<double>(4 * MNK);
     d.state = cur.take<double>(10 * MNK);
+    d.item_count = pl.item_count;
     sb += MK;
     rb += MN;
     eb += MNK;
@@ -355,48 +353,43 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.Q = MNK;
     qs.n_points = q.n_points;
     qs.qpbA = qpbA;
-    qs.n_qblocks = (int)((MNK + qpbA - 1) / qpbA);
-    const int n_tiles = (q.n_points + kTilePts - 1) / kTilePts;
-    // pass-A chunks are whole tiles, so that its hits name pass-B tiles
-    set_chunks(q.n_points, q.n_points > 0 ? chunks_for(qblocks, n_tiles) : 0, qs.n_chunks,
-               qs.chunk_pts, kTilePts);
-    qs.n_tiles = n_tiles;
-    qs.block_base = blk;
-    blk += (int64_t)qs.n_qblocks * qs.n_chunks;
     qs.d_max = d_max;
+    qs.cull = g_cull;
     const bool two_pass = q.n_points > 0;
-    // sized for every variant (the smallest pass-A block gives the most blocks, the
-    // largest the most padded list slots), so the layout does not depend on it
-    const int64_t min_qpb = *std::min_element(kPassAQPB, kPassAQPB + kPassAVariants);
-    const int64_t max_blocks = (MNK + min_qpb - 1) / min_qpb;
-    qs.thresh = cur.take<float>(two_pass ? max_blocks : 0);
-    qs.seg_count = cur.take<int32_t>(two_pass ? max_blocks : 0);
-    qs.list = cur.take<int32_t>(two_pass ? MNK + kQueriesPerBlock : 0);
-    qs.work = cur.take<int2>(two_pass ? max_blocks * n_tiles : 0);
-    qs.fpos = cur.take<float4>(two_pass ? MNK + kQueriesPerBlock : 0);
+    const int64_t n_tiles = ((int64_t)q.n_points + kTilePts - 1) / kTilePts;
     const int64_t n_sub = ((int64_t)q.n_points + kSubPts - 1) / kSubPts;
-    qs.qbox = cur.take<float>(two_pass ? 6 * n_sub : 0);
-    qs.box_base = bb;
-    bb += two_pass ? n_sub : 0;
-    qs.work_count = cur.take<int32_t>(two_pass ? 1 : 0);
-    if (!two_pass) {
-      qs.thresh = nullptr;
-      qs.seg_count = nullptr;
-      qs.list = nullptr;
-      qs.work = nullptr;
-      qs.work_count = nullptr;
-      qs.qbox = nullptr;
-      qs.fpos = nullptr;
+    qs.n_qblocks = two_pass ? (int)((MNK + qpbA - 1) / qpbA) : 0;
+    qs.n_tiles = (int32_t)n_tiles;
+    qs.qb_base = qbb;
+    qs.tile_base = tb;
+    qs.query_base = fb;
+    if (two_pass) {
+      qbb += qs.n_qblocks;
+      tb += n_tiles;
+      fb += (MNK + kBlock - 1) / kBlock;
+      // sized for the smallest block size (the most blocks), so the layout does not
+      // depend on the variant
+      const int64_t max_blocks = (MNK + kPassAMinQPB - 1) / kPassAMinQPB;
+      qs.thresh = cur.take<float>(max_blocks);
+      qs.seg_count = cur.take<int32_t>(max_blocks);
+      qs.binfo = cur.take<float4>(max_blocks);
+      qs.list = cur.take<int32_t>(MNK + kQueriesPerBlock);
+      qs.fpos = cur.take<float4>(MNK + kQueriesPerBlock);
+      qs.tbox = cur.take<float>(6 * n_tiles);
+      qs.sbox = cur.take<float>(6 * n_sub);
+      qs.items = pl.items;
+      qs.item_count = pl.item_count;
+      qs.hitf = pl.hitf;
     }
-    d.work_count = qs.work_count;
-    // spatial order of the positions for pass A
-    SortSet& so = pl.sorts[b];
+    // spatial order of the positions, and of the cloud, for the cull step
+    SortSet& so = pl.sorts[2 * b];
+    SortSet& sc = pl.sorts[2 * b + 1];
     so.block_base = sort_blocks;
-    // the sort pays for itself only when there are enough cloud tiles to cull
     if (two_pass && n_tiles >= kSortMinTiles) {
       so.px = qs.px;
       so.py = qs.py;
       so.pz = qs.pz;
+      so.stride = 1;
       so.Q = MNK;
       so.n_blocks = (int32_t)((MNK + kBlock - 1) / kBlock);
       so.box = cur.take<unsigned>(kBoxCopies * kBoxStride);
@@ -416,6 +409,31 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       d.out_slot = qs.out_slot;
       d.inv = so.inv;
       pl.any_sorted = true;
+      // the cloud, keyed on the positions' box widened by d_max and a metre
+      const int64_t P = q.n_points;
+      sc.block_base = sort_blocks;
+      sc.px = q.cloud;
+      sc.py = q.cloud ? q.cloud + 1 : nullptr;
+      sc.pz = q.cloud ? q.cloud + 2 : nullptr;
+      sc.stride = 3;
+      sc.Q = P;
+      sc.n_blocks = (int32_t)((P + kBlock - 1) / kBlock);
+      sc.box = so.box;
+      sc.margin = d_max + 1.0f;
+      sc.key[0] = cur.take<uint32_t>(P);
+      sc.key[1] = cur.take<uint32_t>(P);
+      sc.val[0] = cur.take<int32_t>(P);
+      sc.val[1] = cur.take<int32_t>(P);
+      sc.table = cur.take<int32_t>((int64_t)kSortDigits * sc.n_blocks);
+      sc.rowsum = cur.take<int32_t>(kSortDigits);
+      sc.sc = cur.take<float4>(P);
+      sort_blocks += sc.n_blocks;
+      qs.scloud = sc.sc;
+      qs.stbox = cur.take<float>(6 * n_tiles);
+      qs.ssbox = cur.take<float>(6 * n_sub);
+      pl.any_scloud = true;
+    } else {
+      sc.block_base = sort_blocks;
     }
     if (!qs.out_slot) qs.out_slot = qs.out;
     // nearest indices requested by the caller of a forward step
@@ -427,16 +445,12 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
         pl.any_nn = true;
       }
     }
-    qs.query_base = fb;
-    fb += two_pass ? (MNK + kBlock - 1) / kBlock : 0;
-    items += two_pass ? (int64_t)qs.n_qblocks * n_tiles : 0;
   }
   pl.total_samples = sb;
   pl.total_rows = rb;
-  pl.total_blocks = blk;
   pl.flag_blocks = fb;
-  pl.listed_items = items;
-  pl.box_blocks = bb;
+  pl.total_tiles = tb;
+  pl.total_qblocks = qbb;
   pl.sort_blocks = sort_blocks;
   pl.total_elems = eb;
   pl.bytes = cur.off;
@@ -446,11 +460,41 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
 // workspace from d_probs on), written to the workspace by the noise launch.
 std::vector<char> mppi_blob(const MppiPlan& pl, int n) {
   const char* b0 = (const char*)pl.d_probs;
-  std::vector<char> blob((const char*)pl.d_sorts - b0 + n * sizeof(SortSet));
+  std::vector<char> blob((const char*)pl.d_sorts - b0 + 2 * n * sizeof(SortSet));
   memcpy(blob.data(), pl.probs.data(), n * sizeof(DevProblem));
   memcpy(blob.data() + ((const char*)pl.d_sets - b0), pl.sets.data(), n * sizeof(QuerySet));
-  memcpy(blob.data() + ((const char*)pl.d_sorts - b0), pl.sorts.data(), n * sizeof(SortSet));
+  memcpy(blob.data() + ((const char*)pl.d_sorts - b0), pl.sorts.data(), 2 * n * sizeof(SortSet));
   return blob;
+}
+
+// The distance passes of a planned Stage-I call: the spatial sorts, the cull step,
+// pass A (timed by `tev` when given), the flag step and pass B.
+hipError_t run_distance(const MppiPlan& pl, int n, int variant, hipEvent_t* tev, hipStream_t s) {
+  hipError_t he = hipSuccess;
+  if (pl.sort_blocks > 0)
+    he = timed(AERO_K_SORT, s,
+               [&] { return launch_spatial_sort(pl.d_sorts, 2 * n, pl.sort_blocks, s); });
+  if (he == hipSuccess && pl.total_qblocks > 0)
+    he = timed(AERO_K_CULL, s, [&] {
+      hipError_t e = pl.any_scloud ? launch_sorted_boxes(pl.d_sets, n, pl.total_tiles, s)
+                                   : hipSuccess;
+      return e == hipSuccess ? launch_cull(pl.d_sets, n, pl.total_qblocks, variant, s) : e;
+    });
+  if (he == hipSuccess && tev) he = hipEventRecord(tev[0], s);
+  if (he == hipSuccess && pl.item_cap > 0)
+    he = timed(AERO_K_MIN_DIST, s, [&] {
+      return launch_pass_a(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap, variant,
+                           s);
+    });
+  if (he == hipSuccess && tev) he = hipEventRecord(tev[1], s);
+  if (he == hipSuccess && pl.flag_blocks > 0)
+    he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, n, pl.flag_blocks, s); });
+  if (he == hipSuccess && pl.item_cap > 0)
+    he = timed(AERO_K_MIN_DIST_EXACT, s, [&] {
+      return launch_min_dist_listed(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap,
+                                    s);
+    });
+  return he;
 }
 
 struct BackwardPlan {
@@ -727,22 +771,9 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   const std::vector<char> blob = mppi_blob(pl, n);
   hipError_t he = timed(AERO_K_ROLLOUT, s, [&] {
     return launch_rollout_noise(pl.d_probs, n, pl.total_samples, pl.total_elems, prm, pl.d_sets,
-                                pl.box_blocks, blob.data(), blob.size(), s);
+                                pl.total_tiles, blob.data(), blob.size(), s);
   });
-  if (he == hipSuccess && pl.sort_blocks > 0)
-    he = timed(AERO_K_SORT, s,
-               [&] { return launch_spatial_sort(pl.d_sorts, n, pl.sort_blocks, s); });
-  if (he == hipSuccess && tev) he = hipEventRecord(tev[0], s);
-  if (he == hipSuccess && pl.total_blocks > 0)
-    he = timed(AERO_K_MIN_DIST, s, [&] {
-      return launch_min_dist_approx(pl.d_sets, n, pl.total_blocks, variant, s);
-    });
-  if (he == hipSuccess && tev) he = hipEventRecord(tev[1], s);
-  if (he == hipSuccess && pl.flag_blocks > 0)
-    he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, n, pl.flag_blocks, s); });
-  if (he == hipSuccess && pl.listed_items > 0)
-    he = timed(AERO_K_MIN_DIST_EXACT, s,
-               [&] { return launch_min_dist_listed(pl.d_sets, n, pl.listed_items, s); });
+  if (he == hipSuccess) he = run_distance(pl, n, variant, tev, s);
   if (he == hipSuccess && pl.any_nn)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, n, s); });
   if (he == hipSuccess)
@@ -800,20 +831,9 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h,
   const std::vector<char> blob = mppi_blob(pl, 1);
   hipError_t he = timed(AERO_K_ROLLOUT, s, [&] {
     return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, pl.d_sets,
-                                pl.box_blocks, blob.data(), blob.size(), s);
+                                pl.total_tiles, blob.data(), blob.size(), s);
   });
-  if (he == hipSuccess && pl.sort_blocks > 0)
-    he = timed(AERO_K_SORT, s,
-               [&] { return launch_spatial_sort(pl.d_sorts, 1, pl.sort_blocks, s); });
-  if (he == hipSuccess && pl.total_blocks > 0)
-    he = timed(AERO_K_MIN_DIST, s, [&] {
-      return launch_min_dist_approx(pl.d_sets, 1, pl.total_blocks, variant, s);
-    });
-  if (he == hipSuccess && pl.flag_blocks > 0)
-    he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, 1, pl.flag_blocks, s); });
-  if (he == hipSuccess && pl.listed_items > 0)
-    he = timed(AERO_K_MIN_DIST_EXACT, s,
-               [&] { return launch_min_dist_listed(pl.d_sets, 1, pl.listed_items, s); });
+  if (he == hipSuccess) he = run_distance(pl, 1, variant, nullptr, s);
   if (he == hipSuccess && q.n_points > 0)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, 1, s); });
   if (he == hipSuccess)
@@ -857,7 +877,7 @@ int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem
   const std::vector<char> blob = mppi_blob(pl, 1);
   hipError_t he = timed(AERO_K_ROLLOUT, s, [&] {
     return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, pl.d_sets,
-                                pl.box_blocks, blob.data(), blob.size(), s);
+                                0, blob.data(), blob.size(), s);  // no distance pass: no cloud boxes
   });
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s,
@@ -922,6 +942,29 @@ int aero_set_pass_a_variant(int variant) {
   if (variant < -1 || variant >= kPassAVariants) return AERO_ERR_PARAM;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_forced_variant = variant;
+  return AERO_OK;
+}
+
+int aero_cull_items(const aero_problem* h, int32_t n, const void* d_ws, size_t ws_bytes,
+                    int64_t* h_items) {
+  if (!h_items || !d_ws) return AERO_ERR_NULL;
+  const int e = check_problems(h, n, false);
+  if (e) return e;
+  MppiPlan pl;
+  plan_mppi(h, n, nullptr, 1.0f, pl, kPassAValu, true);
+  if (ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
+  plan_mppi(h, n, (char*)const_cast<void*>(d_ws), 1.0f, pl, kPassAValu, true);
+  int32_t v = 0;
+  if (hipMemcpy(&v, pl.item_count, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+    return AERO_ERR_DEVICE;
+  *h_items = v;
+  return AERO_OK;
+}
+
+int aero_set_pass_a_cull(int on) {
+  if (on != 0 && on != 1) return AERO_ERR_PARAM;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_cull = on;
   return AERO_OK;
 }
 

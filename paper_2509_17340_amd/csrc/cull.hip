@@ -1,0 +1,183 @@
+// Cull step of the nearest-distance computation (the d_t of the collision cost,
+// Sec. IV-C): which cloud sub-tiles each query block of the first pass must visit.
+//
+// The collision penalty vanishes from d_max on, so a query block only needs the
+// cloud points within d_max of its queries (plus those whose first-pass value could
+// fall under the block's flag bound, all within the reach sqrt(2 thresh - d_max^2)).
+// The cloud is cut into tiles of kTilePts and sub-tiles of kSubPts consecutive
+// points with bounding boxes; a block lists every sub-tile whose box lies within
+// reach of the block's box, testing tiles first (a tile's box contains its
+// sub-tiles').  Two orders of the cloud are considered when the cloud has been
+// spatially sorted: the order it was given in (a LiDAR sweep in beam order is already
+// made of compact runs) and the Morton order; each block takes the one that lists
+// fewer sub-tiles.  A block's items are written consecutively, so that the first pass
+// sets a block up once per run of its items.
+//
+//   k_sorted_boxes  tile and sub-tile boxes of the sorted clouds
+//   k_cull          per query block: bounding box, centre, radius, flag bound,
+//                   and its items
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "aero_device.h"
+#include "aero_internal.h"
+
+namespace aero {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_sorted_boxes(const QuerySet* __restrict__ sets,
+                                                         int n_sets) {
+  const int64_t t = blockIdx.x;
+  const int s = find_owner(sets, n_sets, t, [](const QuerySet& q) { return q.tile_base; });
+  const QuerySet& S = sets[s];
+  if (!S.scloud) return;  // block-uniform
+  tile_boxes(nullptr, S.scloud, S.n_points, t - S.tile_base, S.stbox, S.ssbox);
+}
+
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sub-tiles of one cloud order within reach of the block box [lo, hi]: bit j of the
+// result is sub-tile 4 t + j of tile t.
+__device__ inline unsigned reach_mask(const float* __restrict__ tbox,
+                                      const float* __restrict__ sbox, int64_t t, int64_t n_sub,
+                                      const float lo[3], const float hi[3], float lim) {
+  unsigned mask = 0;
+  if (box_dist2(tbox + 6 * t, lo, hi) <= lim) {
+#pragma unroll
+    for (int j = 0; j < kTileSplit; ++j) {
+      const int64_t sub = t * kTileSplit + j;
+      if (sub < n_sub && box_dist2(sbox + 6 * sub, lo, hi) <= lim) mask |= 1u << j;
+    }
+  }
+  return mask;
+}
+
+// One wave per query block (four per workgroup, no workgroup barriers).
+__global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ sets, int n_sets,
+                                                 int64_t total_qblocks, int variant) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gqb = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (gqb >= total_qblocks) return;  // wave-uniform
+  const int s = find_owner(sets, n_sets, gqb, [](const QuerySet& q) { return q.qb_base; });
+  const QuerySet& S = sets[s];
+  const int64_t qb = gqb - S.qb_base;
+  const int64_t Q = S.Q;
+  const float* __restrict__ sp = S.sp;
+  const int64_t s0 = qb * S.qpbA, s1 = min<int64_t>(Q, s0 + S.qpbA);
+  // bounding box of the block's positions (exact min/max: order independent)
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = s0 + lane; i < s1; i += 64) {
+    const float p[3] = {sp[i], sp[Q + i], sp[2 * Q + i]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], p[a]);
+      hi[a] = fmaxf(hi[a], p[a]);
+    }
+  }
+  float c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_minf(lo[a]);
+    hi[a] = wave_maxf(hi[a]);
+    c[a] = 0.5f * lo[a] + 0.5f * hi[a];
+  }
+  // radius about the centre, formed as the first pass forms |p'|^2
+  float rr = 0.0f;
+  for (int64_t i = s0 + lane; i < s1; i += 64) {
+    const float x = sp[i] - c[0], y = sp[Q + i] - c[1], z = sp[2 * Q + i] - c[2];
+    rr = fmaxf(rr, fmaf(z, z, fmaf(y, y, x * x)));
+  }
+  rr = wave_maxf(rr);
+  // Flag bound: the pass-A value of a pair within d_max errs by at most
+  //   VALU  about 26 u (R + d_max)^2 with u = 2^-24 (three FMAs on recentred
+  //         coordinates): 2^-17 (R + d_max)^2 leaves a 5x margin;
+  //   split FP16 matrix cores  2^-15 (R + d_max)^2, valid while the recentred
+  //         coordinates fit the halves (R + d_max <= 64); a wider block flags all.
+  const float d_max = S.d_max;
+  float thr;
+  if (variant == kPassAValu) {
+    const float span = sqrtf(rr) * 1.001f + d_max;
+    thr = d_max * d_max + 0x1p-17f * span * span + 1e-6f;
+  } else {
+    const float span = sqrtf(rr) * 1.001f + d_max;
+    thr = span <= 64.0f ? d_max * d_max + 0x1p-15f * span * span + 1e-6f : INFINITY;
+  }
+  if (lane == 0) {
+    S.thresh[qb] = thr;
+    S.seg_count[qb] = 0;
+    S.binfo[qb] = make_float4(c[0], c[1], c[2], thr);
+  }
+  const int64_t n_tiles = S.n_tiles;
+  const int64_t n_sub = ((int64_t)S.n_points + kSubPts - 1) / kSubPts;
+  const float lim = S.cull ? reach_limit(thr, d_max) : INFINITY;
+  // items of each order
+  int cnt_raw = 0, cnt_srt = 0;
+  for (int64_t t = lane; t < n_tiles; t += 64)
+    cnt_raw += __popc(reach_mask(S.tbox, S.sbox, t, n_sub, lo, hi, lim));
+  cnt_raw = wave_sum_i(cnt_raw);
+  const bool sorted_ok = S.scloud != nullptr && S.cull;
+  if (sorted_ok) {
+    for (int64_t t = lane; t < n_tiles; t += 64)
+      cnt_srt += __popc(reach_mask(S.stbox, S.ssbox, t, n_sub, lo, hi, lim));
+    cnt_srt = wave_sum_i(cnt_srt);
+  }
+  const int order = (sorted_ok && cnt_srt < cnt_raw) ? 1 : 0;
+  const int cnt = order ? cnt_srt : cnt_raw;
+  if (cnt == 0) return;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(S.item_count, cnt);
+  base = __shfl(base, 0, 64);
+  const float* __restrict__ tb = order ? S.stbox : S.tbox;
+  const float* __restrict__ sb = order ? S.ssbox : S.sbox;
+  int2* __restrict__ items = S.items;
+  AERO_GLOBAL unsigned char* __restrict__ hitf = global_ptr(S.hitf);
+  const unsigned flag = (unsigned)order << 31;
+  // the same tests again, now writing the listed sub-tiles in increasing order
+  int run = 0;
+  for (int64_t t0 = 0; t0 < n_tiles; t0 += 64) {
+    const int64_t t = t0 + lane;
+    const unsigned mask = t < n_tiles ? reach_mask(tb, sb, t, n_sub, lo, hi, lim) : 0u;
+    const int m = __popc(mask);
+    int x = m;  // inclusive scan over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    int at = base + run + x - m;
+#pragma unroll
+    for (int j = 0; j < kTileSplit; ++j)
+      if ((mask >> j) & 1u) {
+        if (at < base + cnt) {  // always, for the same tests; never write past the run
+          items[at] = make_int2((int)gqb, (int)((unsigned)(t * kTileSplit + j) | flag));
+          hitf[at] = 0;
+        }
+        ++at;
+      }
+    run += __shfl(x, 63, 64);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sorted_boxes(const QuerySet* d_sets, int n_sets, int64_t total_tiles,
+                               hipStream_t s) {
+  if (total_tiles > 0) k_sorted_boxes<<<(unsigned)total_tiles, kBlock, 0, s>>>(d_sets, n_sets);
+  return hipGetLastError();
+}
+
+hipError_t launch_cull(const QuerySet* d_sets, int n_sets, int64_t total_qblocks, int variant,
+                       hipStream_t s) {
+  constexpr int per = kBlock / 64;
+  if (total_qblocks > 0)
+    k_cull<<<(unsigned)((total_qblocks + per - 1) / per), kBlock, 0, s>>>(d_sets, n_sets,
+                                                                          total_qblocks, variant);
+  return hipGetLastError();
+}
+
+}  // namespace aero

@@ -133,11 +133,11 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
 
 
 // One pass-B item: the flagged queries of query block qb (R per lane; their
-// positions as the flag kernel wrote them) against the cloud sub-tile [g0, g1).
-// With kIdx also the lowest point index attaining the minimum (points are visited
-// in increasing index order and ties never replace).
+// positions as the flag kernel wrote them) against the points of one cloud sub-tile
+// (raw or sorted order).  With kIdx also the lowest point index attaining the
+// minimum (the sorted order visits indices in any order, so ties compare indices).
 template <int R, bool kIdx>
-__device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64_t g0, int64_t g1,
+__device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, unsigned ys,
                                    float4* tile) {
   const int tid = threadIdx.x;
   const int64_t lbase = qb * S.qpbA;
@@ -156,13 +156,16 @@ __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64
     best[r] = __uint_as_float(kInfBits);
     bidx[r] = 0x7fffffff;
   }
-  const int n = (int)(g1 - g0);  // <= kSubPts
-  const int n2 = (n + 1) & ~1;    // even: the loop takes points in pairs
-  for (int pt = tid; pt < n2; pt += kBlock) {
-    const int64_t g = g0 + (pt < n ? pt : 0);  // always a valid address
-    tile[pt] = pt < n ? make_float4(S.cloud[3 * g], S.cloud[3 * g + 1], S.cloud[3 * g + 2], 0.0f)
-                      : make_float4(kFar, kFar, kFar, 0.0f);
-  }
+  float x, y, z;
+  int32_t idx;
+  bool in;
+  int n;
+  item_point(S, ys, x, y, z, idx, in, n);
+  // every thread writes its own slot (a far record past the sub-tile's points), so an
+  // odd count still leaves a valid record after the last point
+  tile[tid] = in ? make_float4(x, y, z, __int_as_float(idx))
+                 : make_float4(kFar, kFar, kFar, __int_as_float(0x7fffffff));
+  const int n2 = (n + 1) & ~1;  // even: the loop takes points in pairs
   __syncthreads();
 #pragma unroll 2
   for (int j = 0; j < n2; j += 2) {
@@ -175,14 +178,14 @@ __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64
       const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
       const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
       if constexpr (kIdx) {
-        const int ia = (int)(g0 + j);
-        if (da < best[r]) {
+        const int32_t ia = __float_as_int(a.w), ic = __float_as_int(c.w);
+        if (da < best[r] || (da == best[r] && ia < bidx[r])) {
           best[r] = da;
           bidx[r] = ia;
         }
-        if (dc < best[r]) {
+        if (dc < best[r] || (dc == best[r] && ic < bidx[r])) {
           best[r] = dc;
-          bidx[r] = ia + 1;
+          bidx[r] = ic;
         }
       } else {
         best[r] = min3f(best[r], da, dc);
@@ -202,156 +205,146 @@ __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, int64
 }
 
 template <int R>
-__device__ inline void listed_item_r(const QuerySet& S, int64_t qb, int cnt, int64_t g0,
-                                     int64_t g1, float4* tile) {
+__device__ inline void listed_item_r(const QuerySet& S, int64_t qb, int cnt, unsigned ys,
+                                     float4* tile) {
   if (S.nn)
-    listed_item<R, true>(S, qb, cnt, g0, g1, tile);
+    listed_item<R, true>(S, qb, cnt, ys, tile);
   else
-    listed_item<R, false>(S, qb, cnt, g0, g1, tile);
+    listed_item<R, false>(S, qb, cnt, ys, tile);
 }
 
-// Pass B: exact direct form for the flagged queries, only against the sub-tiles that
-// pass A listed for their block (a query's nearest point within d_max always lies
-// in one).  Persistent grid over the work lists of every two-pass set (each entry
-// expanded into its kTileSplit sub-tiles, unlisted ones skipped); the lengths are
+// Pass B: exact direct form for the flagged queries, only against the items (block,
+// sub-tile) that pass A marked for their block (a query's nearest point within d_max
+// always lies in one).  Persistent grid over the call's item list, whose length is
 // read on the device.
 __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __restrict__ sets,
-                                                            int n_sets) {
+                                                            int n_sets,
+                                                            const int2* __restrict__ items,
+                                                            const int32_t* __restrict__ item_count,
+                                                            const unsigned char* __restrict__ hitf) {
   __shared__ float4 tile[kSubPts];
-  int64_t item_base = 0;
-  for (int s = 0; s < n_sets; ++s) {
-    const QuerySet& Sref = sets[s];
-    if (!Sref.list || Sref.n_points <= 0) continue;
-    const int64_t items = (int64_t)*Sref.work_count * kTileSplit;
-    int64_t first = ((int64_t)blockIdx.x - item_base) % gridDim.x;
-    if (first < 0) first += gridDim.x;
-    if (items > 0) {
-      const QuerySet S = Sref;
-      for (int64_t it = first; it < items; it += gridDim.x) {
-        const int2 wk = S.work[it / kTileSplit];
-        const int j = (int)(it % kTileSplit);
-        if (!((wk.y >> j) & 1)) continue;  // sub-tile not listed
-        const int64_t qb = wk.x;
-        const int cnt = min(S.seg_count[qb], S.qpbA);
-        const int64_t g0 = ((int64_t)((unsigned)wk.y >> 4) * kTileSplit + j) * kSubPts;
-        const int64_t g1 = min<int64_t>(g0 + kSubPts, S.n_points);
-        if (cnt <= 0 || g0 >= g1) continue;
-        const int nr = (cnt + kBlock - 1) / kBlock;
-        // exactly as many flagged queries per lane as the block has (no idle groups)
-        switch (nr) {
-          case 1: listed_item_r<1>(S, qb, cnt, g0, g1, tile); break;
-          case 2: listed_item_r<2>(S, qb, cnt, g0, g1, tile); break;
-          case 3: listed_item_r<3>(S, qb, cnt, g0, g1, tile); break;
-          case 4: listed_item_r<4>(S, qb, cnt, g0, g1, tile); break;
-          case 5: listed_item_r<5>(S, qb, cnt, g0, g1, tile); break;
-          case 6: listed_item_r<6>(S, qb, cnt, g0, g1, tile); break;
-          case 7: listed_item_r<7>(S, qb, cnt, g0, g1, tile); break;
-          default: listed_item_r<kQueriesPerLane>(S, qb, cnt, g0, g1, tile); break;
-        }
-      }
+  const int64_t total = *item_count;
+  SetCache cache{0, 0, 0};
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    if (!hitf[it]) continue;  // block-uniform
+    const int2 e = items[it];
+    const int s = set_of(sets, n_sets, e.x, cache);
+    const QuerySet S = sets[s];
+    if (!block_of(S, e.x) || !S.list) continue;
+    const int64_t qb = e.x - S.qb_base;
+    const int cnt = min(S.seg_count[qb], S.qpbA);
+    if (cnt <= 0) continue;
+    const int nr = (cnt + kBlock - 1) / kBlock;
+    // exactly as many flagged queries per lane as the block has (no idle groups)
+    switch (nr) {
+      case 1: listed_item_r<1>(S, qb, cnt, (unsigned)e.y, tile); break;
+      case 2: listed_item_r<2>(S, qb, cnt, (unsigned)e.y, tile); break;
+      case 3: listed_item_r<3>(S, qb, cnt, (unsigned)e.y, tile); break;
+      case 4: listed_item_r<4>(S, qb, cnt, (unsigned)e.y, tile); break;
+      case 5: listed_item_r<5>(S, qb, cnt, (unsigned)e.y, tile); break;
+      case 6: listed_item_r<6>(S, qb, cnt, (unsigned)e.y, tile); break;
+      case 7: listed_item_r<7>(S, qb, cnt, (unsigned)e.y, tile); break;
+      default: listed_item_r<kQueriesPerLane>(S, qb, cnt, (unsigned)e.y, tile); break;
     }
-    item_base += items;
   }
 }
 
-// Pass A.  Block = (query block, cloud chunk) of a two-pass set.
-__global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __restrict__ sets,
-                                                            int n_sets) {
-  __shared__ float4 tile[kTilePts];
-  __shared__ float red[7][4];
-  const int64_t bid = blockIdx.x;
-  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
-  const QuerySet S = sets[s];
-  const int64_t local = bid - S.block_base;
-  const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+// Pass A on the VALU.  Persistent grid over the cull step's item list (see the
+// matrix-core pass): a block's kQueriesPerBlock positions are recentred on its
+// centre and held in registers (kQueriesPerLane per lane) while the run of its items
+// goes by; each item's sub-tile is staged in LDS as (-2 o', |o'|^2) records (double
+// buffered), and t = |o'|^2 - 2 p'.o' takes three FMAs and half a min3 per pair.
+constexpr int kPassAGridValu = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restrict__ sets,
+                                                        int n_sets, const int2* __restrict__ items,
+                                                        const int32_t* __restrict__ item_count,
+                                                        unsigned char* __restrict__ hitf) {
   constexpr int R = kQueriesPerLane;
-  float px[R], py[R], pz[R];
-  bool ok[R];
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  __shared__ float4 tile[2][kSubPts];
+  const int tid = threadIdx.x;
+  const int64_t total = *item_count;
+  const int64_t G = gridDim.x;
+  const int64_t per = (total + G - 1) / G;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min<int64_t>(total, i0 + per);
+  if (i0 >= i1) return;  // block-uniform
+  SetCache cache{0, 0, 0};
+  int64_t cur = -1, slot0 = 0;
+  unsigned* out_slot = nullptr;
+  unsigned okm = 0;  // bit r: this lane's query r exists
+  float c[3] = {0.0f, 0.0f, 0.0f}, thr = 0.0f;
+  float px[R], py[R], pz[R], pp[R], tmin[R];
+  auto flush = [&]() {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t slot = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
-    ok[r] = slot < S.Q;
-    const int64_t qs = ok[r] ? slot : 0;  // positions in slot order
-    px[r] = S.sp[qs];
-    py[r] = S.sp[S.Q + qs];
-    pz[r] = S.sp[2 * S.Q + qs];
-    if (ok[r]) {
-      lo[0] = fminf(lo[0], px[r]);
-      lo[1] = fminf(lo[1], py[r]);
-      lo[2] = fminf(lo[2], pz[r]);
-      hi[0] = fmaxf(hi[0], px[r]);
-      hi[1] = fmaxf(hi[1], py[r]);
-      hi[2] = fmaxf(hi[2], pz[r]);
+    for (int r = 0; r < R; ++r)
+      if ((okm >> r) & 1u)
+        atomicMin(out_slot + slot0 + r * kBlock, __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
+  };
+  int2 it = items[i0];
+  int ns = set_of(sets, n_sets, it.x, cache);
+  float ox, oy, oz;
+  int32_t oidx;
+  bool oin;
+  int cnt;
+  item_point(sets[ns], (unsigned)it.y, ox, oy, oz, oidx, oin, cnt);
+  bool valid = block_of(sets[ns], it.x) && cnt > 0;
+  int buf = 0;
+  for (int64_t i = i0; i < i1; ++i) {
+    const int64_t gqb = it.x;
+    const int icnt = cnt;
+    const bool ivalid = valid;
+    if (ivalid && gqb != cur) {  // block-uniform
+      if (cur >= 0) flush();
+      const QuerySet& S = sets[ns];
+      const int64_t qb = gqb - S.qb_base;
+      const int64_t Q = S.Q;
+      const float* __restrict__ sp = S.sp;
+      out_slot = S.out_slot;
+      const float4 bi = S.binfo[qb];
+      c[0] = bi.x;
+      c[1] = bi.y;
+      c[2] = bi.z;
+      thr = bi.w;
+      slot0 = qb * kQueriesPerBlock + tid;
+      okm = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t slot = slot0 + r * kBlock;
+        const bool ok = slot < Q;
+        okm |= ok ? 1u << r : 0u;
+        const int64_t qs = ok ? slot : 0;  // positions in slot order
+        px[r] = sp[qs] - c[0];
+        py[r] = sp[Q + qs] - c[1];
+        pz[r] = sp[2 * Q + qs] - c[2];
+        pp[r] = fmaf(pz[r], pz[r], fmaf(py[r], py[r], px[r] * px[r]));
+        tmin[r] = kFarT;
+      }
+      cur = gqb;
     }
-  }
-  // Bounding-box centre of the block's queries (exact min/max, order independent).
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = wave_minf(lo[a]);
-    hi[a] = wave_maxf(hi[a]);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      red[a][w] = lo[a];
-      red[3 + a][w] = hi[a];
+    if (ivalid) {
+      const float x = ox - c[0], y = oy - c[1], z = oz - c[2];
+      tile[buf][tid] = oin ? make_float4(-2.0f * x, -2.0f * y, -2.0f * z,
+                                         fmaf(z, z, fmaf(y, y, x * x)))
+                           : make_float4(0.0f, 0.0f, 0.0f, kFarT);
     }
-  }
-  __syncthreads();
-  float c[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float l = fminf(fminf(red[a][0], red[a][1]), fminf(red[a][2], red[a][3]));
-    const float h = fmaxf(fmaxf(red[3 + a][0], red[3 + a][1]), fmaxf(red[3 + a][2], red[3 + a][3]));
-    c[a] = 0.5f * l + 0.5f * h;
-  }
-  float pp[R], tmin[R], rr = 0.0f;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    px[r] -= c[0];
-    py[r] -= c[1];
-    pz[r] -= c[2];
-    pp[r] = fmaf(pz[r], pz[r], fmaf(py[r], py[r], px[r] * px[r]));
-    if (ok[r]) rr = fmaxf(rr, pp[r]);
-    tmin[r] = kFarT;
-  }
-  // Rounding-error bound of the pass-A value of any pair within d_max:
-  // about 26 u (R + d_max)^2 with u = 2^-24; flag with a 5x margin.
-  rr = wave_maxf(rr);
-  if (lane == 0) red[6][w] = rr;
-  __syncthreads();
-  const float R2 = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
-  const float span = sqrtf(R2) * 1.001f + S.d_max;
-  const float thr = S.d_max * S.d_max + 0x1p-17f * span * span + 1e-6f;
-  if (tid == 0 && ch == 0) {
-    S.thresh[qb] = thr;
-    S.seg_count[qb] = 0;
-  }
-  const int64_t g0 = (int64_t)ch * S.chunk_pts;
-  const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
-  for (int64_t base = g0; base < g1; base += kTilePts) {
-    const int cnt = (int)min<int64_t>(kTilePts, g1 - base);
-    const int cnt2 = (cnt + 1) & ~1;
-    for (int pt = tid; pt < cnt2; pt += kBlock) {
-      const bool in = pt < cnt;
-      const int64_t gg = in ? base + pt : base;
-      const float ox = S.cloud[3 * gg] - c[0];
-      const float oy = S.cloud[3 * gg + 1] - c[1];
-      const float oz = S.cloud[3 * gg + 2] - c[2];
-      tile[pt] = in ? make_float4(-2.0f * ox, -2.0f * oy, -2.0f * oz,
-                                  fmaf(oz, oz, fmaf(oy, oy, ox * ox)))
-                    : make_float4(0.0f, 0.0f, 0.0f, kFarT);
+    if (i + 1 < i1) {
+      it = items[i + 1];
+      ns = set_of(sets, n_sets, it.x, cache);
+      item_point(sets[ns], (unsigned)it.y, ox, oy, oz, oidx, oin, cnt);
+      valid = block_of(sets[ns], it.x) && cnt > 0;
     }
+    if (!ivalid) continue;  // block-uniform; the buffers alternate over processed items only
     __syncthreads();
+    const float4* tl = tile[buf];
+    buf ^= 1;
     float tt[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) tt[r] = kFarT;
+    const int cnt2 = (icnt + 1) & ~1;  // pairs; an odd tail reads a far record
 #pragma unroll 4
     for (int j = 0; j < cnt2; j += 2) {
-      const float4 a = tile[j];
-      const float4 b = tile[j + 1];
+      const float4 a = tl[j];
+      const float4 b = tl[j + 1];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const float ta = fmaf(px[r], a.x, fmaf(py[r], a.y, fmaf(pz[r], a.z, a.w)));
@@ -362,17 +355,12 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_approx(const QuerySet* __re
     bool hit = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      hit |= ok[r] && pp[r] + tt[r] < thr;
+      hit |= ((okm >> r) & 1u) && pp[r] + tt[r] < thr;
       tmin[r] = fminf(tmin[r], tt[r]);
     }
-    if (__syncthreads_or(hit) && tid == 0)
-      append_block_hits(S, qb, base / kTilePts, red, pass_b_reach2(thr, S.d_max));
+    mark_hit(hit, hitf, i);
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t slot = (int64_t)qb * kQueriesPerBlock + r * kBlock + tid;
-    if (ok[r]) atomicMin(S.out_slot + slot, __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
-  }
+  if (cur >= 0) flush();
 }
 
 // Compact the queries of two-pass sets whose pass-A value is under the bound into
@@ -444,13 +432,14 @@ hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blo
   return hipGetLastError();
 }
 
-hipError_t launch_min_dist_approx(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                                  int variant, hipStream_t s) {
-  if (total_blocks > 0) {
-    if (variant == kPassAMfma || variant == kPassAF16s)
-      return launch_min_dist_approx_matrix(d_sets, n_sets, total_blocks, variant, s);
-    k_min_dist_approx<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
-  }
+hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
+                         const int32_t* item_count, unsigned char* hitf, int64_t max_items,
+                         int variant, hipStream_t s) {
+  if (max_items <= 0) return hipSuccess;
+  if (variant == kPassAF16s4 || variant == kPassAF16s8)
+    return launch_pass_a_matrix(d_sets, n_sets, items, item_count, hitf, max_items, variant, s);
+  const unsigned grid = (unsigned)(max_items < kPassAGridValu ? max_items : kPassAGridValu);
+  k_pass_a_valu<<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
   return hipGetLastError();
 }
 
@@ -464,12 +453,12 @@ hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, int64_t max_items,
-                                  hipStream_t s) {
+hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, const int2* items,
+                                  const int32_t* item_count, const unsigned char* hitf,
+                                  int64_t max_items, hipStream_t s) {
   if (max_items > 0) {
-    const int64_t sub = max_items * kTileSplit;  // entries expand into their sub-tiles
-    const unsigned grid = (unsigned)(sub < kPersistBlocks ? sub : kPersistBlocks);
-    k_min_dist_listed<<<grid, kBlock, 0, s>>>(d_sets, n_sets);
+    const unsigned grid = (unsigned)(max_items < kPersistBlocks ? max_items : kPersistBlocks);
+    k_min_dist_listed<<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
   }
   return hipGetLastError();
 }

@@ -54,10 +54,10 @@ __device__ inline void put_blob(const PutBlob& blob, unsigned char* dst) {
 
 // The rollout's standard normals for every (instance, step, sample), drawn in
 // parallel ahead of the sequential rollout (the same counter-based stream); also
-// resets the per-position distance outputs, the pass-B work counter and the
+// resets the per-position distance outputs, the call's cull item counter and the
 // spatial sort's bounding box.
-// Blocks from noise_blocks on compute the sub-tile bounding boxes of the two-pass
-// sets' clouds instead (independent work, one launch fewer).
+// Blocks from noise_blocks on compute the tile and sub-tile bounding boxes of the
+// two-pass sets' clouds instead (independent work, one launch fewer).
 __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__ probs, int n,
                                                   int64_t total, DevParams prm,
                                                   const QuerySet* __restrict__ sets, int n_sets,
@@ -69,7 +69,11 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
     probs = reinterpret_cast<const DevProblem*>(blob.b);
   }
   if ((int64_t)blockIdx.x >= noise_blocks) {
-    cloud_box_block(sets, n_sets, (int64_t)blockIdx.x - noise_blocks);
+    // tile and sub-tile boxes of the raw clouds of the two-pass sets (tile_base order)
+    const int64_t t = (int64_t)blockIdx.x - noise_blocks;
+    const int si = find_owner(sets, n_sets, t, [](const QuerySet& q) { return q.tile_base; });
+    const QuerySet& S = sets[si];
+    tile_boxes(S.cloud, nullptr, S.n_points, t - S.tile_base, S.tbox, S.sbox);
     return;
   }
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -88,9 +92,9 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   AERO_GLOBAL unsigned* __restrict__ out_slot = global_ptr(P.out_slot);
   AERO_GLOBAL int32_t* __restrict__ nidx = global_ptr(P.nidx);
   if (local == 0) {
-    AERO_GLOBAL int32_t* __restrict__ work_count = global_ptr(P.work_count);
+    AERO_GLOBAL int32_t* __restrict__ item_count = global_ptr(P.item_count);
     AERO_GLOBAL unsigned* __restrict__ sort_box = global_ptr(P.sort_box);
-    if (work_count) *work_count = 0;  // pass B's work list of this call
+    if (item_count) *item_count = 0;  // the call's (query block, sub-tile) item list
     if (sort_box)
       for (int cp = 0; cp < kBoxCopies; ++cp)
         for (int a = 0; a < 3; ++a) {

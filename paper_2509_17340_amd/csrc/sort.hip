@@ -1,13 +1,16 @@
 // Spatial sort of the rollout positions before the first distance pass (the
-// positions' bounding box is merged by the rollout kernel as it writes them).
+// positions' bounding box is merged by the rollout kernel as it writes them), and of
+// the cloud in the same launches.
 //
-// The first pass takes blocks of consecutive positions; its per-block bound and its
-// record of which cloud tiles a block came near are only as tight as the block is
-// compact.  Positions of one (instance, step) are spread by the sampling noise, so
-// they are reordered along a Morton (Z-order) curve over their bounding box: a
-// stable LSD radix sort on the top 16 bits of a 24-bit key (8 bits per axis), in two
-// passes of 8 bits (cells of 1/32 of the box per axis; within a cell the original
-// order is kept).
+// The first pass takes blocks of consecutive positions; its per-block bound and the
+// cloud sub-tiles a block comes near are only as tight as the block is compact.
+// Positions of one (instance, step) are spread by the sampling noise, so they are
+// reordered along a Morton (Z-order) curve over their bounding box: a stable LSD
+// radix sort on the top 16 bits of a 24-bit key (8 bits per axis), in two passes of
+// 8 bits (cells of 1/32 of the box per axis; within a cell the original order is
+// kept).  The cloud is keyed on the same box widened by a margin, so that its points
+// near the positions fall into compact sub-tiles; a cloud made of several
+// accumulated sweeps is far less compact in its given order.
 // Every pass ranks elements without atomics (ballots inside a wave, per-wave counts
 // in LDS, per-block counts scanned in digit-major order), so the permutation is
 // deterministic and the same for a problem alone or inside a batch.
@@ -56,15 +59,16 @@ __device__ inline Elem locate(const SortSet* sets, int n_sets) {
   return e;
 }
 
-// Morton key of an element from its position and the set's bounding box.
-// box: the set's bounding box (order-preserving bits), merged from the rollout's
-// copies by merge_box_copies.
-__device__ inline uint32_t morton_key(const unsigned box[6], const float p[3]) {
+// Morton key of an element from its position and the key box (the set's bounding
+// box widened by `margin`; positions outside it are clamped to its boundary cells).
+// box: the positions' bounding box (order-preserving bits), merged from the rollout's
+// copies by the first pass.
+__device__ inline uint32_t morton_key(const unsigned box[6], float margin, const float p[3]) {
   float lo[3], ext = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = ord_float(box[a]);
-    ext = fmaxf(ext, ord_float(box[3 + a]) - lo[a]);
+    lo[a] = ord_float(box[a]) - margin;
+    ext = fmaxf(ext, (ord_float(box[3 + a]) + margin) - lo[a]);
   }
   const float scale = ext > 0.0f ? 255.99f / ext : 0.0f;
   uint32_t key = 0;
@@ -104,9 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
   uint32_t key = 0;
   if (e.active) {
     if (pass == 0) {
-      p[0] = S.px[e.i];
-      p[1] = S.py[e.i];
-      p[2] = S.pz[e.i];
+      const int64_t at = e.i * S.stride;
+      p[0] = S.px[at];
+      p[1] = S.py[at];
+      p[2] = S.pz[at];
     } else {
       key = S.key[src][e.i];
     }
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
   AERO_GLOBAL int32_t* __restrict__ table = global_ptr(S.table);
   const int64_t n_blocks = S.n_blocks;
   if (e.active && pass == 0) {  // the first pass also builds the keys
-    key = morton_key(box, p);
+    key = morton_key(box, S.margin, p);
     AERO_GLOBAL uint32_t* __restrict__ key0 = global_ptr(S.key[0]);
     AERO_GLOBAL int32_t* __restrict__ val0 = global_ptr(S.val[0]);
     key0[e.i] = key;
@@ -220,15 +225,20 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
       const bool last = pass == kSortPasses - 1 && v >= 0 && v < Q;
       AERO_GLOBAL int32_t* __restrict__ inv = global_ptr(S.inv);
       AERO_GLOBAL float* __restrict__ sp = global_ptr(S.sp);
+      float4* __restrict__ sc = S.sc;
       float p[3] = {0.0f, 0.0f, 0.0f};
       if (last) {
-        p[0] = S.px[v];
-        p[1] = S.py[v];
-        p[2] = S.pz[v];
+        const int64_t at = (int64_t)v * S.stride;
+        p[0] = S.px[at];
+        p[1] = S.py[at];
+        p[2] = S.pz[at];
       }
       key_out[pos] = k;
       val_out[pos] = v;
-      if (last) {
+      if (last && sc) {
+        // a cloud: the points in key order with their original index
+        sc[pos] = make_float4(p[0], p[1], p[2], __int_as_float(v));
+      } else if (last) {
         // the inverse permutation, and the positions in slot order for the
         // distance passes (read there without a gather through the permutation)
         inv[v] = (int32_t)pos;

@@ -179,15 +179,18 @@ def test_indexed_backward_ignores_out_of_range_indices():
 
 def test_backward_identical_across_pass_a_variants():
     """The filter pass only decides which positions get the exact search: gradients
-    are bitwise the same whichever variant runs it."""
+    are bitwise the same whichever variant runs it, with the cull step or over the
+    whole cloud."""
     prob = make_ensemble_problem()
     outs = []
-    for v in (0, 1, 2):
+    for v, cull in ((0, True), (1, True), (2, True), (2, False)):
         aero.set_pass_a_variant(v)
+        aero.set_pass_a_cull(cull)
         try:
             outs.append(gpu_backward(prob, scale=0.5))
         finally:
             aero.set_pass_a_variant(-1)
+            aero.set_pass_a_cull(True)
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
 

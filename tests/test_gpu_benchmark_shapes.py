@@ -1,0 +1,126 @@
+"""GPU parity at the benchmarked shapes, against the FP64 oracle.
+
+  * the ensemble forest step (M=8, K=1024, N=40, 50k points): S1 and the nearest
+    distances of every sample (the oracle's distances through its k-d tree, which
+    its own tests pin to brute force), the clipped perturbations and the
+    teacher-forced update of every instance, S2 and the selected instance
+  * the 64 uneven problems in one batched Stage-I and one batched Stage-II call:
+    S1 of four samples of every instance of every problem, the teacher-forced update
+    of every instance, every S2 and the selected instance of every problem; the
+    autotuner's trial variants and its settled one give bit-identical costs
+  * one pose of the closed loop at full shape (1,000,000 points, M=16, K=8192, N=60):
+    partition bit-exact, S1 of four samples per instance, the teacher-forced update
+    of every instance, every S2 and the selected instance
+
+The bar is the one of tests/test_gpu_parity.py (Sec. IV-C eq. (total cost) for S1
+and S2, Sec. III-B eqs. (mppi_weights) and (mppi_update) for the update).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2509_17340_amd as aero  # noqa: E402
+from fixtures import make_batched_problems, make_ensemble_problem, make_loop_step  # noqa: E402
+from oracle import mppi as OM  # noqa: E402
+from oracle import partition as OP  # noqa: E402
+from oracle.cost import nearest_kdtree  # noqa: E402
+from paper_2509_17340_amd.planner import PlanStep  # noqa: E402
+from test_gpu_parity import compare_stage1, np_, sync  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def check_select(prob, u_new, S2, best):
+    sel = OM.select_best(prob, u_new, nearest_fn=nearest_kdtree)
+    assert np.all(np.abs(S2 - sel["S2"]) <= 1e-4 * np.abs(sel["S2"])), (S2, sel["S2"])
+    srt = np.sort(sel["S2"])
+    if len(srt) < 2 or srt[1] - srt[0] > 1e-6 * abs(srt[0]):
+        assert best == sel["best"]
+    return sel
+
+
+def debug_outputs(ps):
+    return dict(coef=np_(ps.coef), deff=np_(ps.delta_eff), md2=np_(ps.min_dist2),
+                S1=np_(ps.S1), u_new=np_(ps.u_nom))
+
+
+def test_ensemble_forest_every_sample():
+    prob = make_ensemble_problem()
+    print("ensemble forest: every sample against the oracle", flush=True)
+    ps = PlanStep(prob, keep_debug=True)
+    ps.front_end()
+    ps.stage1()
+    sync()
+    g = debug_outputs(ps)
+    rep = compare_stage1(prob, g, nearest_fn=nearest_kdtree)
+    print(rep, flush=True)
+    ps.stage2()
+    sync()
+    check_select(prob, g["u_new"], np_(ps.S2), int(np_(ps.best)[0]))
+
+
+def test_batched_uneven_64_against_oracle():
+    probs = make_batched_problems()
+    print(f"64 uneven problems: {sum(p['M'] * p['K'] * p['N'] for p in probs)} positions",
+          flush=True)
+    steps = [PlanStep(p, keep_debug=True) for p in probs]
+    for s in steps:
+        s.front_end()
+    pr = [s.problem for s in steps]
+    ws = torch.empty(max(aero.workspace_size(aero.CALL_MPPI_STEP, pr),
+                         aero.workspace_size(aero.CALL_SELECT_BEST, pr)),
+                     dtype=torch.uint8, device="cuda")
+    S2 = torch.empty(sum(p["M"] for p in probs), dtype=torch.float64, device="cuda")
+    best = torch.empty(len(probs), dtype=torch.int32, device="cuda")
+    aero.set_pass_a_variant(-1)
+    runs = []
+    for r in range(5):  # the autotuner's three trials, then its choice
+        for s in steps:
+            s.reset()
+        aero.mppi_step(probs[0]["params"], pr, ws)
+        sync()
+        runs.append([np_(s.S1) for s in steps])
+        print(f"batched call {r}: variant {aero.pass_a_variant(pr)}", flush=True)
+    for run in runs[1:]:
+        for a, b in zip(runs[0], run):
+            assert np.array_equal(a, b)
+    aero.select_best(probs[0]["params"], pr, S2, best, ws)
+    sync()
+    S2_all, best_all = np_(S2), np_(best)
+    off = 0
+    rng = np.random.default_rng(5)
+    for b, (p, s) in enumerate(zip(probs, steps)):
+        K = p["K"]
+        sub = np.unique(np.concatenate([[0, K - 1], rng.choice(K, 2, replace=False)]))
+        g = debug_outputs(s)
+        rep = compare_stage1(p, g, samples=sub, nearest_fn=nearest_kdtree)
+        check_select(p, g["u_new"], S2_all[off:off + p["M"]], int(best_all[b]))
+        off += p["M"]
+        print(f"problem {b} {p['name']} M={p['M']} K={K} N={p['N']}: {rep}", flush=True)
+
+
+def test_closed_loop_pose_full_shape():
+    prob = make_loop_step(0)
+    M, K, N = prob["M"], prob["K"], prob["N"]
+    print(f"closed-loop pose: M={M} K={K} N={N} P={len(prob['cloud'])}", flush=True)
+    ps = PlanStep(prob, keep_debug=True)
+    ps.front_end()
+    sync()
+    part = prob["partition"]
+    o = OP.partition_anchors(prob["cloud"], prob["goal_dir"], part["n_az_c"], part["n_el_c"],
+                             part["f_a"], part["f_e"], part["r_max"], part["ell"],
+                             prob["M_h"], prob["M_v"])
+    assert np.array_equal(np_(ps.fine_idx), o["fine_idx"])
+    assert np.array_equal(np_(ps.coarse_best), o["coarse_best"])
+    assert np.array_equal(np_(ps.anchor_fine), o["anchor_fine"])
+    print("partition bit-exact", flush=True)
+    ps.stage1()
+    sync()
+    g = debug_outputs(ps)
+    sub = np.array([0, K // 3, 2 * K // 3, K - 1])
+    rep = compare_stage1(prob, g, samples=sub, nearest_fn=nearest_kdtree)
+    print(rep, flush=True)
+    ps.stage2()
+    sync()
+    check_select(prob, g["u_new"], np_(ps.S2), int(np_(ps.best)[0]))

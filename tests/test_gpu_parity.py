@@ -162,13 +162,14 @@ def compare_stage1(prob, g, samples=None, nearest_fn=nearest):
     p2["K"] = len(sub)
     st = OM.mppi_step(p2, coef, normals=normals[:, sub], nearest_fn=nearest_fn)
     gd = np.sqrt(np.transpose(g["md2"], (0, 2, 1))[:, sub].astype(np.float64))
-    fin = np.isfinite(st["d"])
-    assert np.array_equal(fin, np.isfinite(gd))
     d_max = float(np.float32(prm["d_max"]))
     # exact wherever the collision penalty depends on d (below d_max); beyond, the
-    # reported value only has to stay on the zero-penalty side of d_max
-    near = fin & (st["d"] < d_max)
-    far = fin & ~near
+    # reported value only has to stay on the zero-penalty side of d_max (+inf where
+    # no cloud point lies within the cull step's reach of the position's block, as
+    # for an empty cloud)
+    near = np.isfinite(st["d"]) & (st["d"] < d_max)
+    far = ~near
+    assert not np.isnan(gd).any()
     assert np.abs(gd[near] - st["d"][near]).max(initial=0.0) <= 1e-5
     assert np.all(gd[far] >= d_max - 1e-5)
     strad = straddles(st["d"], float(np.float32(prm["d_max"])))
@@ -187,12 +188,28 @@ def compare_stage1(prob, g, samples=None, nearest_fn=nearest):
                 u_tf_rel=float((num / den).max()), kappa=float(kappa))
 
 
-@pytest.fixture(params=[0, 1, 2], ids=["valu", "mfma", "f16s"])
-def pass_a(request):
-    """Run the test with the first distance pass forced to one variant."""
-    aero.set_pass_a_variant(request.param)
-    yield request.param
+# (variant, cull step on): the three first-pass variants over the culled pairs, and
+# the split-FP16 pass over every (block, sub-tile) pair (brute force)
+PASS_A_MODES = [(0, True), (1, True), (2, True), (2, False)]
+
+
+def set_pass_a_mode(mode):
+    aero.set_pass_a_variant(mode[0])
+    aero.set_pass_a_cull(mode[1])
+
+
+def reset_pass_a_mode():
     aero.set_pass_a_variant(-1)
+    aero.set_pass_a_cull(True)
+
+
+@pytest.fixture(params=PASS_A_MODES, ids=["valu", "f16s512", "f16s1024", "brute"])
+def pass_a(request):
+    """Run the test with the first distance pass forced to one variant (and the cull
+    step on or off)."""
+    set_pass_a_mode(request.param)
+    yield request.param
+    reset_pass_a_mode()
 
 
 def test_stage1_plain_cylinders_full(pass_a):
@@ -338,14 +355,14 @@ def test_stage1_deterministic_and_batched_equals_plain(pass_a):
         assert np.array_equal(np_(s.min_dist2), ref[2])
 
 
-def variant_outputs(prob, variants=(0, 1, 2)):
+def variant_outputs(prob, modes=tuple(PASS_A_MODES)):
     outs = []
-    for v in variants:
-        aero.set_pass_a_variant(v)
+    for m in modes:
+        set_pass_a_mode(m)
         try:
             ps, g = run_stage1(prob)
         finally:
-            aero.set_pass_a_variant(-1)
+            reset_pass_a_mode()
         outs.append(g)
     return outs
 
@@ -363,8 +380,9 @@ def assert_same_costs(prob, outs, min_near=0):
 
 
 def test_pass_a_variants_give_identical_costs():
-    """Every first-pass variant yields bitwise-identical S1, u_nom and exact distances
-    below d_max (they may differ only in first-pass values beyond d_max)."""
+    """Every first-pass variant, with the cull step or over the whole cloud, yields
+    bitwise-identical S1, u_nom and exact distances below d_max (they may differ only
+    in first-pass values beyond d_max)."""
     prob = make_ensemble_problem()
     print("pass-A variants on the ensemble forest", flush=True)
     assert_same_costs(prob, variant_outputs(prob), min_near=1000)
