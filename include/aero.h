@@ -57,6 +57,9 @@ typedef enum aero_status {
 #define AERO_FRAMES_MAX 256   /* most LiDAR frames per accumulated cloud          */
 #define AERO_POSITIONS_MAX 2147483647LL /* rollout positions M*N*K of one problem and  *
                                          * their sum over one call stay below this     */
+#define AERO_NOALLOC_SCRATCH_BYTES (32u << 20) /* device scratch of                  *
+                                         * aero_select_best_noalloc, per GPU             */
+#define AERO_NOALLOC_BATCH_MAX 16 /* most problems per aero_select_best_noalloc call  */
 
 /* Table I parameters shared by all problems of a call (float32 values). */
 typedef struct aero_params {
@@ -217,6 +220,25 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h_problems,
 int aero_select_best(const aero_params* h_prm, const aero_problem* h_problems,
                      int32_t n_problems, double* d_S2, int32_t* d_best, void* d_ws,
                      size_t ws_bytes, void* stream);
+
+/* aero_select_best without a workspace argument, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels and outputs as aero_select_best (bit for bit);
+ * the workspace is a library-internal device array of AERO_NOALLOC_SCRATCH_BYTES
+ * (32 MiB) that every GPU the call runs on holds from its first call until the
+ * process ends (looked up on the current device, which must own `stream`).  The call
+ * allocates nothing and records no timing events.
+ * Limits: at most AERO_NOALLOC_BATCH_MAX problems, and the workspace that
+ * aero_workspace_size(AERO_CALL_SELECT_BEST, ...) reports for them at most
+ * AERO_NOALLOC_SCRATCH_BYTES (about 124 bytes per Stage-II position M*N, so one
+ * problem of AERO_M_MAX x AERO_N_MAX fits).
+ * Every call on one GPU uses the same array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Errors: as aero_select_best; AERO_ERR_SHAPE for more than AERO_NOALLOC_BATCH_MAX
+ * problems, AERO_ERR_WORKSPACE when the problems need more than the array holds
+ * (both checked on the host before any device work). */
+int aero_select_best_noalloc(const aero_params* h_prm, const aero_problem* h_problems,
+                             int32_t n_problems, double* d_S2, int32_t* d_best, void* stream);
 
 /* Adjoint of L = g * sum_{m,k} S1[m,k] for one problem, evaluated at the
  * problem's u_nom (read only) with the same noise as aero_mppi_step:

@@ -83,6 +83,7 @@ _SIGS = {
                                          _P, _P]),
     "aero_mppi_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "aero_select_best": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
+    "aero_select_best_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "aero_mppi_step_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "aero_mppi_step_backward_indexed": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                                        _P]),
@@ -322,6 +323,18 @@ def select_best(prm, problems, S2, best, ws, ws_bytes=None, stream=None):
     _check(_lib.aero_select_best(ctypes.byref(p), ctypes.cast(arr, ctypes.c_void_p), len(problems),
                                  _ptr(S2), _ptr(best), _ptr(ws), nbytes, _stream(stream)),
            "aero_select_best")
+
+
+def select_best_noalloc(prm, problems, S2, best, stream=None):
+    """Stage II without a workspace (the library's per-GPU scratch array; see
+    aero_select_best_noalloc: calls that overlap on one GPU race)."""
+    p = params_struct(prm) if isinstance(prm, dict) else prm
+    arr = _problem_array(problems)
+    _need(S2, sum(q.M for q in problems), "f64", "S2")
+    _need(best, len(problems), "i32", "best")
+    _check(_lib.aero_select_best_noalloc(ctypes.byref(p), ctypes.cast(arr, ctypes.c_void_p),
+                                         len(problems), _ptr(S2), _ptr(best), _stream(stream)),
+           "aero_select_best_noalloc")
 
 
 def shift_controls(src, index, shift, dst, stream=None):

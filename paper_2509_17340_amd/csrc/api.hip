@@ -538,9 +538,12 @@ void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& b
   }
 }
 
+// Host records of a Stage-II call live in arrays that the caller of plan_select
+// provides (heap vectors for the workspace entry point, stack arrays for the one that
+// allocates nothing).
 struct SelectPlan {
-  std::vector<DevSelect> sel;
-  std::vector<QuerySet> sets;
+  DevSelect* sel = nullptr;     // [n] host records
+  QuerySet* sets = nullptr;     // [n]
   DevSelect* d_sel = nullptr;
   QuerySet* d_sets = nullptr;
   int64_t total_inst = 0, total_blocks = 0;
@@ -560,8 +563,10 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
   Cursor cur{ws};
   pl.d_sel = cur.take<DevSelect>(n);
   pl.d_sets = cur.take<QuerySet>(n);
-  pl.sel.assign(n, DevSelect{});
-  pl.sets.assign(n, QuerySet{});
+  for (int b = 0; b < n; ++b) {
+    pl.sel[b] = DevSelect{};
+    pl.sets[b] = QuerySet{};
+  }
   int64_t qblocks = 0;
   for (int b = 0; b < n; ++b)
     if (h[b].n_points > 0) {
@@ -618,6 +623,72 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
 }
 
 inline int dev_status(hipError_t e) { return e == hipSuccess ? AERO_OK : AERO_ERR_DEVICE; }
+
+// A launch bracketed by the optional event timers, or plain (the entry point that
+// allocates nothing records no events: creating one may allocate).
+template <typename F>
+hipError_t maybe_timed(bool timing, int kernel, hipStream_t s, F&& launch) {
+  return timing ? timed(kernel, s, launch) : launch();
+}
+
+// Descriptor image of a Stage-II plan (records then query sets, at their workspace
+// offsets) in `blob`, which holds select_blob_bytes(pl, n) bytes; returns that size.
+size_t select_blob_bytes(const SelectPlan& pl, int n) {
+  return (size_t)((const char*)pl.d_sets - (const char*)pl.d_sel) + n * sizeof(QuerySet);
+}
+size_t select_blob(const SelectPlan& pl, int n, char* blob) {
+  const size_t off = (const char*)pl.d_sets - (const char*)pl.d_sel;
+  memset(blob, 0, off);
+  memcpy(blob, pl.sel, n * sizeof(DevSelect));
+  memcpy(blob + off, pl.sets, n * sizeof(QuerySet));
+  return off + n * sizeof(QuerySet);
+}
+
+// The launch sequence of a planned Stage-II call (the plan is laid out in its workspace).
+hipError_t run_select(const SelectPlan& pl, int n, const DevParams& prm, const char* blob,
+                      size_t blob_bytes, bool timing, hipStream_t s) {
+  hipError_t he = maybe_timed(timing, AERO_K_SEL_ROLLOUT, s, [&] {
+    return launch_select_rollout(pl.d_sel, n, pl.total_inst, prm, blob, blob_bytes, s);
+  });
+  if (he == hipSuccess && pl.total_blocks > 0)
+    he = maybe_timed(timing, AERO_K_SEL_MIN_DIST, s,
+                     [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, s); });
+  if (he == hipSuccess)
+    he = maybe_timed(timing, AERO_K_SEL_FINAL, s,
+                     [&] { return launch_select_final(pl.d_sel, n, prm, s); });
+  return he;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of aero_select_best_noalloc: a file-scope device array, of which every
+// GPU holds its own copy (at its own address) from the first call on it until the
+// process ends.  Host code never names the array in a launch or copy: it uses the
+// address that hipGetSymbolAddress returned on that device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[AERO_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device with that device
+// current; nullptr if the runtime reports an error.
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Stack room for the descriptor image of AERO_NOALLOC_BATCH_MAX problems.
+constexpr size_t kNoAllocBlobBytes =
+    (AERO_NOALLOC_BATCH_MAX * sizeof(DevSelect) + kAlign - 1) / kAlign * kAlign +
+    AERO_NOALLOC_BATCH_MAX * sizeof(QuerySet);
 
 void table_angles(int32_t n_az, int32_t n_el, float* out) {
   float* az_b = out;
@@ -689,7 +760,11 @@ size_t aero_workspace_size(int which, const aero_problem* h, int32_t n) {
     return bp.bytes;
   }
   if (which == AERO_CALL_SELECT_BEST) {
+    std::vector<DevSelect> sel(n);
+    std::vector<QuerySet> sets(n);
     SelectPlan pl;
+    pl.sel = sel.data();
+    pl.sets = sets.data();
     plan_select(h, n, nullptr, nullptr, nullptr, pl);
     return pl.bytes;
   }
@@ -790,23 +865,41 @@ int aero_select_best(const aero_params* h_prm, const aero_problem* h, int32_t n,
   e = check_problems(h, n, false);
   if (e) return e;
   if (!d_S2 || !d_best) return AERO_ERR_NULL;
+  std::vector<DevSelect> sel(n);
+  std::vector<QuerySet> sets(n);
   SelectPlan pl;
+  pl.sel = sel.data();
+  pl.sets = sets.data();
   plan_select(h, n, nullptr, nullptr, nullptr, pl);
   if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
   plan_select(h, n, (char*)d_ws, d_S2, d_best, pl);
-  const hipStream_t s = (hipStream_t)stream;
-  const DevParams prm = promote(*h_prm);
-  std::vector<char> blob((char*)pl.d_sets - (char*)pl.d_sel + n * sizeof(QuerySet));
-  memcpy(blob.data(), pl.sel.data(), n * sizeof(DevSelect));
-  memcpy(blob.data() + ((char*)pl.d_sets - (char*)pl.d_sel), pl.sets.data(), n * sizeof(QuerySet));
-  hipError_t he = timed(AERO_K_SEL_ROLLOUT, s, [&] {
-    return launch_select_rollout(pl.d_sel, n, pl.total_inst, prm, blob.data(), blob.size(), s);
-  });
-  if (he == hipSuccess && pl.total_blocks > 0)
-    he = timed(AERO_K_SEL_MIN_DIST, s, [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, s); });
-  if (he == hipSuccess)
-    he = timed(AERO_K_SEL_FINAL, s, [&] { return launch_select_final(pl.d_sel, n, prm, s); });
-  return dev_status(he);
+  std::vector<char> blob(select_blob_bytes(pl, n));
+  select_blob(pl, n, blob.data());
+  return dev_status(run_select(pl, n, promote(*h_prm), blob.data(), blob.size(), true,
+                               (hipStream_t)stream));
+}
+
+int aero_select_best_noalloc(const aero_params* h_prm, const aero_problem* h, int32_t n,
+                             double* d_S2, int32_t* d_best, void* stream) {
+  int e = check_params(h_prm);
+  if (e) return e;
+  e = check_problems(h, n, false);
+  if (e) return e;
+  if (!d_S2 || !d_best) return AERO_ERR_NULL;
+  if (n > AERO_NOALLOC_BATCH_MAX) return AERO_ERR_SHAPE;
+  DevSelect sel[AERO_NOALLOC_BATCH_MAX];
+  QuerySet sets[AERO_NOALLOC_BATCH_MAX];
+  SelectPlan pl;
+  pl.sel = sel;
+  pl.sets = sets;
+  plan_select(h, n, nullptr, nullptr, nullptr, pl);
+  if (pl.bytes > (size_t)AERO_NOALLOC_SCRATCH_BYTES) return AERO_ERR_WORKSPACE;
+  void* ws = scratch_address();
+  if (!ws) return AERO_ERR_DEVICE;
+  plan_select(h, n, (char*)ws, d_S2, d_best, pl);
+  alignas(16) char blob[kNoAllocBlobBytes];
+  const size_t nb = select_blob(pl, n, blob);
+  return dev_status(run_select(pl, n, promote(*h_prm), blob, nb, false, (hipStream_t)stream));
 }
 
 int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h,

@@ -255,3 +255,24 @@ def test_binding_refuses_values_where_device_pointers_go():
     with pytest.raises(ValueError):
         aero.advance_state(params(), torch.zeros(10), FakeTensor((2, 5, 4)),
                            FakeTensor((1,)), FakeTensor((10,)))
+
+
+def test_select_best_noalloc_limits_without_device():
+    """The entry point that allocates nothing checks its limits on the host, before any
+    device work: at most AERO_NOALLOC_BATCH_MAX problems, and a Stage-II workspace that
+    fits its AERO_NOALLOC_SCRATCH_BYTES array."""
+    ok = make_problem()
+    S2, best = FakeTensor((4096,)), FakeTensor((64,))
+    fn = aero.select_best_noalloc
+    expect_status(1, fn, params(), [ok], None, best)
+    expect_status(1, fn, params(), [ok], S2, None)
+    expect_status(2, fn, params(), [make_problem(N=0)], S2, best)
+    expect_status(3, fn, params(mass=0.0), [ok], S2, best)
+    expect_status(2, fn, params(), [ok] * 17, S2, best)             # beyond the batch limit
+    big = make_problem(M=256, N=512, K=1)                            # one fits ...
+    ws_one = aero.workspace_size(aero.CALL_SELECT_BEST, [big])
+    assert 0 < ws_one <= 32 << 20
+    expect_status(4, fn, params(), [big, big, big], S2, best)        # ... three do not
+    assert aero.workspace_size(aero.CALL_SELECT_BEST, [big] * 3) > 32 << 20
+    lib = aero.lib()
+    assert lib.aero_select_best_noalloc(None, None, 1, None, None, None) == 1
