@@ -240,6 +240,12 @@ class LoopRunner:
         ps.cloud.copy_(torch.from_numpy(np.ascontiguousarray(prob["cloud"], np.float32)))
         self.set_state(prob["x0"], prob["p_goal"])
 
+    def load_device(self, cloud, prob):
+        """Next replayed pose from a cloud already in device memory (same size), copied
+        into the planner's cloud buffer on the current stream, and the pose's goal."""
+        self.ps.cloud.copy_(cloud)
+        self.set_state(prob["x0"], prob["p_goal"])
+
     def set_points(self, n_points):
         self.ps.set_points(n_points)
         self.ref_problem.n_points = self.cand_problem.n_points = self.ps.n_points
@@ -250,8 +256,17 @@ class LoopRunner:
             p.x0, p.p_goal = self.ps.problem.x0, self.ps.problem.p_goal
 
     def step(self):
+        self.plan()
+        self.refine()
+
+    def plan(self):
+        """The planning step (partition, guides, Stage I, Stage II)."""
+        self.ps.run()
+
+    def refine(self):
+        """One gradient step on the selected sequence's Stage-II cost, then the warm
+        start of every instance from the refined sequence advanced by one step."""
         ps = self.ps
-        ps.run()
         self._shift(ps.u_nom, ps.best, 0, self.u_sel)
         self._bwd(self.refine_params, self.ref_problem, None, self.grad, self.grad_w, self.ws_b)
         self._cand(ps.params, self.u_sel[0], self.grad[0], self.s0, self.beta, self.cands)
