@@ -37,7 +37,6 @@ FP32_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
 F16_PEAK_TFLOPS = 2500.0      # MI355X published FP16 dense matrix peak
 HBM_PEAK_GBS = 8000.0         # MI355X published HBM3E bandwidth
 FLOP_PER_PAIR = 8             # 3 sub + 3 mul + 2 add per (position, point) pair
-SUB_PTS = 256                 # cloud points per cull item (a sub-tile)
 
 # Pass-A variants: kernel, roofline bound and the published peak of the unit it runs
 # on, the FLOP it executes per pair, and the positions of one query block.
@@ -215,32 +214,65 @@ def kernel_ms(kt, n):
     return {k: v[0] / n for k, v in kt.items() if v[1]}
 
 
-def pass_a_roofline(aero, kt, variant, pairs_evaluated, pairs_brute, label):
-    """Roofline of pass A from the library's live event timers: algorithmic FLOP = 8 per
-    (position, point) pair it evaluates (the cull step's items x block positions x 256
-    points), and the brute-force-equivalent rate beside it."""
+def distance_rooflines(kt, steps, stats, brute_pairs, variant, label):
+    """Rooflines of the two distance passes from the library's live event timers and the
+    work counted by aero_read_distance_stats, summed over the same `steps` planning
+    steps: algorithmic FLOP = 8 per (position, point) pair a pass evaluates (pass A:
+    the cull step's items x block positions x sub-tile points; pass B: the pairs of its
+    hit words), with the brute-force-equivalent rate beside pass A's."""
+    out = {}
     va = PASS_A[variant]
-    ms, n = kt["min_dist"]
-    avg = ms / max(n, 1)
-    pair_rate = pairs_evaluated / n / (avg * 1e-3)
-    achieved = FLOP_PER_PAIR * pair_rate / 1e12
-    out = {
-        "bound": va["bound"], "kernel": f"{va['kernel']} ({label}; autotuned variant {variant})",
-        "achieved": achieved, "peak": va["peak"], "unit": "TFLOP/s", "peak_is": va["unit_note"],
-        "frac": achieved / va["peak"],
-        "flop_counted": "8 per (position, point) pair evaluated: cull items x block positions "
-                        "x 256 points per item",
-        "pairs_evaluated_per_launch": pairs_evaluated / n, "avg_launch_ms": avg,
-        "pairs_per_s": pair_rate,
-        "executed_tflops": va["executed_flop_per_pair"] * pair_rate / 1e12,
-        "executed_frac": va["executed_flop_per_pair"] * pair_rate / 1e12 / va["peak"],
-        "brute_force_pairs_per_launch": pairs_brute / n,
-        "brute_force_equivalent_tflops": FLOP_PER_PAIR * pairs_brute / n / (avg * 1e-3) / 1e12,
-    }
-    if va["bound"] == "mfma":
-        out["pair_ceiling_per_s"] = F16S_PAIR_CEILING
-        out["frac_of_pair_ceiling"] = pair_rate / F16S_PAIR_CEILING
+    ms_a, n_a = kt["min_dist"]
+    if n_a:
+        t = ms_a * 1e-3
+        rate = stats["pairs_a"] / t
+        achieved = FLOP_PER_PAIR * rate / 1e12
+        a = {"bound": va["bound"], "kernel": f"{va['kernel']} ({label}, first pass; autotuned "
+                                             f"variant {variant})",
+             "achieved": achieved, "peak": va["peak"], "unit": "TFLOP/s",
+             "peak_is": va["unit_note"], "frac": achieved / va["peak"],
+             "flop_counted": "8 per (position, point) pair evaluated: cull items x block "
+                             "positions x sub-tile points",
+             "pairs_per_launch": stats["pairs_a"] / n_a, "avg_launch_ms": ms_a / n_a,
+             "pairs_per_s": rate,
+             "executed_tflops": va["executed_flop_per_pair"] * rate / 1e12,
+             "executed_frac": va["executed_flop_per_pair"] * rate / 1e12 / va["peak"],
+             "brute_force_pairs_per_launch": brute_pairs / n_a,
+             "brute_force_equivalent_tflops": FLOP_PER_PAIR * brute_pairs / t / 1e12}
+        if va["bound"] == "mfma":
+            a["pair_ceiling_per_s"] = F16S_PAIR_CEILING
+            a["frac_of_pair_ceiling"] = rate / F16S_PAIR_CEILING
+        out["pass_a"] = a
+    ms_b, n_b = kt["min_dist_exact"]
+    if n_b:
+        t = ms_b * 1e-3
+        rate = stats["pairs_b"] / t
+        achieved = FLOP_PER_PAIR * rate / 1e12
+        out["pass_b"] = {
+            "bound": "alu", "kernel": f"k_pass_b ({label}, exact pass over the hit pairs)",
+            "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "peak_is": "FP32 vector (VALU) peak", "frac": achieved / FP32_PEAK_TFLOPS,
+            "flop_counted": "8 per (position, point) pair of pass A's hit words (3 sub, "
+                            "3 mul, 2 add)",
+            "pairs_per_launch": stats["pairs_b"] / n_b, "avg_launch_ms": ms_b / n_b,
+            "pairs_per_s": rate,
+            "issue_ceiling_tflops": FP32_PEAK_TFLOPS * FLOP_PER_PAIR / 14,
+            "issue_ceiling_note": "per pair 3 v_sub + v_mul + 2 v_fma at full rate and half "
+                                  "a v_min3 at half rate: 7 issue slots for 8 FLOP, against "
+                                  "14 FLOP for 7 FMAs",
+            "items": stats["items_b"], "items_taken_whole": stats["items_whole"]}
     return out
+
+
+def dominant(rl, kt):
+    """The roofline of the slower distance pass."""
+    if "pass_b" in rl and (kt["min_dist_exact"][0] > kt["min_dist"][0] or "pass_a" not in rl):
+        return dict(rl["pass_b"])
+    return dict(rl["pass_a"])
+
+
+def sum_stats(a, b):
+    return {k: a.get(k, 0) + b[k] for k in b}
 
 
 def bench_loop(poses, warmup, steps, n_total):
@@ -281,13 +313,24 @@ def bench_loop(poses, warmup, steps, n_total):
     kt = aero.timing_read(reset=True)
     timing[0] = False
     total_ms = ev[0].elapsed_time(ev[steps])
-    items = aero.cull_items([ps.problem], ps.ws)   # of the last timed pose
     for i in range(steps, n_total):              # the flight goes on (not in `value`)
         step(i)
         ev[i + 1].record()
     torch.cuda.synchronize()
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(n_total)]
-    return dict(total_ms=total_ms, per=per, kt=kt, items=items, M=ps.M, K=ps.K, N=ps.N,
+    # the timed poses again from the same start (every result is reproducible bit for
+    # bit), reading the distance passes' work after each: not timed
+    ps.reset()
+    stats = {}
+    for i in range(steps):
+        lr.load_device(clouds[i], poses[i])
+        ps.front_end()
+        ps.stage1()
+        torch.cuda.synchronize()       # read before Stage II reuses the workspace
+        stats = sum_stats(stats, aero.distance_stats([ps.problem], ps.ws))
+        ps.stage2()
+        lr.refine()
+    return dict(total_ms=total_ms, per=per, kt=kt, stats=stats, M=ps.M, K=ps.K, N=ps.N,
                 P=ps.n_points, variant=aero.pass_a_variant([ps.problem]))
 
 
@@ -316,7 +359,12 @@ def bench_ensemble(prob, steps, warmup):
     kt = aero.timing_read(reset=True)
     aero.timing_enable(False)
     eager = e0.elapsed_time(e1) / steps
-    items = aero.cull_items([ps.problem], ps.ws)
+    ps.reset()
+    ps.front_end()
+    ps.stage1()
+    torch.cuda.synchronize()           # read before Stage II reuses the workspace
+    st = aero.distance_stats([ps.problem], ps.ws)
+    stats = {k: v * steps for k, v in st.items()}
     g = GraphStep(ps)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
@@ -329,13 +377,13 @@ def bench_ensemble(prob, steps, warmup):
     p50, p99 = pcts([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     M, K, N, P = ps.M, ps.K, ps.N, ps.n_points
     variant = aero.pass_a_variant([ps.problem])
-    pairs = items * PASS_A[variant]["qpb"] * SUB_PTS * steps
+    rl = distance_rooflines(kt, steps, stats, M * K * N * P * steps, variant,
+                            "Stage I nearest distance")
     return {
         "ms_per_step": gms, "eager_ms_per_step": eager, "p50_ms": p50, "p99_ms": p99,
         "rollout_steps_per_s": steps_per_plan_of(M, K, N) / (gms * 1e-3),
         "launch_mode": "hip_graph",
-        "roofline_pass_a": pass_a_roofline(aero, kt, variant, pairs, M * K * N * P * steps,
-                                           "Stage I nearest distance, first pass"),
+        "roofline": dominant(rl, kt), "distance_passes": rl, "distance_work_per_step": st,
         "kernels_ms_per_step": kernel_ms(kt, steps),
         "workload": f"ensemble-forest-50k: one planning step (partition 32x8 coarse x 4x4, "
                     f"M={M}, K={K}, N={N}, dt=0.05, {P}-point LiDAR cloud, Stage I + Stage II)",
@@ -525,7 +573,8 @@ def main():
         f"{n_total}: {a50:.2f} / {a99:.2f} ms")
     kt = loop["kt"]
     variant = loop["variant"]
-    pairs = loop["items"] * PASS_A[variant]["qpb"] * SUB_PTS * kt["min_dist"][1]
+    rl = distance_rooflines(kt, K_steps, loop["stats"], M * K * N * P * K_steps, variant,
+                            "Stage I nearest distance")
     out = {
         "metric": METRIC,
         "value": steps_per_plan_of(M, K, N) / (ms * 1e-3),
@@ -552,9 +601,9 @@ def main():
                                f"refinement + warm start)",
                    "M": M, "K": K, "N": N, "points": P, "collision_set": "raw cloud",
                    "rollout_steps_per_plan": steps_per_plan_of(M, K, N)},
-        "roofline": pass_a_roofline(aero, kt, variant, pairs,
-                                    M * K * N * P * kt["min_dist"][1],
-                                    "Stage I nearest distance, first pass"),
+        "roofline": dominant(rl, kt),
+        "distance_passes": rl,
+        "distance_work_per_step": {k: v / K_steps for k, v in loop["stats"].items()},
         "kernels_ms_per_step": kernel_ms(kt, K_steps),
         "kernels_note": "event-timed kernels of the planning step (partition .. Stage II); "
                         "the refinement and warm start run untimed after them",

@@ -362,14 +362,23 @@ int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems);
  * AERO_ERR_PARAM for other values. */
 int aero_set_pass_a_cull(int on);
 
-/* Profiling aid: the number of (query block, cloud sub-tile) items that the cull step
- * of the last aero_mppi_step on this workspace listed (the first pass evaluates
- * items x 256 x block-size position-point pairs).  Reads device memory synchronously
- * (hipMemcpy): call it once the stream has finished the step.  Errors: AERO_ERR_NULL,
- * AERO_ERR_SHAPE / AERO_ERR_PARAM as aero_mppi_step's size checks, AERO_ERR_WORKSPACE,
- * AERO_ERR_DEVICE. */
-int aero_cull_items(const aero_problem* h_problems, int32_t n_problems, const void* d_ws,
-                    size_t ws_bytes, int64_t* h_items);
+/* Profiling aid: the work of the two distance passes of the last aero_mppi_step on
+ * this workspace (same problems), counted from the cull step's items and pass A's hit
+ * words.  Reads device memory synchronously (hipMemcpy): call it once the stream has
+ * finished the step and before any other call reuses the workspace (aero_select_best
+ * on the same workspace overwrites what it reads).  Errors: AERO_ERR_NULL, AERO_ERR_SHAPE / AERO_ERR_PARAM as
+ * aero_mppi_step's size checks, AERO_ERR_WORKSPACE, AERO_ERR_DEVICE. */
+typedef struct aero_distance_stats {
+  int64_t items;        /* (query block, cloud sub-tile) items the cull step listed      */
+  int64_t pairs_a;      /* position-point pairs of those items (pass A evaluates them)   */
+  int64_t items_b;      /* items in which some query came under its block's bound        */
+  int64_t pairs_b;      /* position-point pairs pass B evaluates exactly                 */
+  int64_t items_whole;  /* marked items without room for their hit words (pass B takes
+                           every query of the block)                                     */
+  int64_t positions;    /* rollout positions of the two-pass sets                        */
+} aero_distance_stats;
+int aero_read_distance_stats(const aero_problem* h_problems, int32_t n_problems, const void* d_ws,
+                             size_t ws_bytes, aero_distance_stats* h_out);
 
 /* ---- per-kernel timing (profiling aid) ---------------------------------------- */
 
@@ -386,8 +395,9 @@ typedef enum aero_kernel {
   AERO_K_SEL_ROLLOUT = 6,  /* Stage-II rollout (+ the call's descriptors)           */
   AERO_K_SEL_MIN_DIST = 7, /* Stage-II nearest distance                             */
   AERO_K_SEL_FINAL = 8,    /* Stage-II S2 and argmin                                */
-  AERO_K_FLAG = 9,         /* Stage-I compaction of positions near the cloud        */
-  AERO_K_MIN_DIST_EXACT = 10, /* Stage-I nearest distance, pass B (flagged only)   */
+  AERO_K_FLAG = 9,         /* (retired: the exact pass needs no compaction step;
+                              reads 0)                                               */
+  AERO_K_MIN_DIST_EXACT = 10, /* Stage-I nearest distance, pass B (the hit pairs)   */
   AERO_K_NEAREST = 11,     /* backward: nearest indices of flagged positions         */
   AERO_K_ADJOINT = 12,     /* backward: per-sample reverse sweep                     */
   AERO_K_GRAD_REDUCE = 13, /* backward: sums over samples                            */

@@ -20,7 +20,7 @@ __all__ = [
     "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
     "KERNELS", "shift_controls", "step_candidates", "set_pass_a_variant", "pass_a_variant",
-    "set_pass_a_cull", "cull_items",
+    "set_pass_a_cull", "distance_stats",
     "use_library", "accumulate_cloud", "advance_state", "mppi_step_backward_indexed",
 ]
 
@@ -90,7 +90,7 @@ _SIGS = {
     "aero_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "aero_set_pass_a_variant": (ctypes.c_int, [ctypes.c_int]),
     "aero_set_pass_a_cull": (ctypes.c_int, [ctypes.c_int]),
-    "aero_cull_items": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "aero_read_distance_stats": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "aero_shift_controls": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                            _P, ctypes.c_int32, _P]),
     "aero_step_candidates": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float,
@@ -404,14 +404,20 @@ def set_pass_a_cull(on=True):
     _check(_lib.aero_set_pass_a_cull(1 if on else 0), "aero_set_pass_a_cull")
 
 
-def cull_items(problems, ws, ws_bytes=None):
-    """Items (query block, cloud sub-tile) the last mppi_step on `ws` listed (synchronous)."""
+class DistanceStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("items", "pairs_a", "items_b", "pairs_b",
+                                              "items_whole", "positions")]
+
+
+def distance_stats(problems, ws, ws_bytes=None):
+    """Work of the two distance passes of the last mppi_step on `ws` (synchronous):
+    dict with items, pairs_a, items_b, pairs_b, items_whole, positions."""
     arr = _problem_array(problems)
-    out = ctypes.c_int64()
+    out = DistanceStats()
     nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
-    _check(_lib.aero_cull_items(ctypes.cast(arr, ctypes.c_void_p), len(problems), _ptr(ws), nbytes,
-                                ctypes.byref(out)), "aero_cull_items")
-    return out.value
+    _check(_lib.aero_read_distance_stats(ctypes.cast(arr, ctypes.c_void_p), len(problems), _ptr(ws),
+                                    nbytes, ctypes.byref(out)), "aero_read_distance_stats")
+    return {k: getattr(out, k) for k, _ in DistanceStats._fields_}
 
 
 def pass_a_variant(problems):

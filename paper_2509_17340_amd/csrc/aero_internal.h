@@ -71,6 +71,8 @@ struct DevProblem {
   const int32_t* nidx_in;  // nearest indices given by the caller (indexed adjoint)
   int64_t elem_base;     // prefix of M*N*K over problems
   const float* w_dev;    // optional [5] device term weights replacing DevParams::w
+  unsigned long long* nn;  // the set's pass-B nearest records by slot (reset with the
+                           //   distances), or nullptr
 };
 
 // Spatial sort of one problem's rollout positions, or of its cloud (stable LSD radix
@@ -103,15 +105,15 @@ struct SortSet {
 
 // One set of query positions scored against one cloud by the distance kernels.
 //
-// Exact sets (list == nullptr) run the direct-form kernel over every query against
+// Exact sets (items == nullptr) run the direct-form kernel over every query against
 // every cloud point.  Two-pass sets are cut into query blocks of qpbA consecutive
-// (spatially sorted) positions.  The cull step gives each block a centre, a bound
-// `thresh` on its pass-A rounding error, and the list of cloud sub-tiles whose
-// bounding box lies within reach of the block's box, in the raw or the sorted cloud
-// order (whichever lists fewer); pass A runs the recentred expanded form over those
-// (block, sub-tile) items only and marks the items in which some query came under
-// the bound; the flag step lists the queries under the bound, and pass B reruns the
-// direct form for them against the marked items.
+// (spatially sorted) positions.  The cull step gives each block a centre, a bound on
+// its pass-A rounding error, and the list of cloud sub-tiles whose bounding box lies
+// within reach of the block's box, in the raw or the sorted cloud order (whichever
+// lists fewer); pass A runs the recentred expanded form over those (block, sub-tile)
+// items only and records, per item, which of the block's queries came under the
+// bound there; pass B reruns the direct form for exactly those (query, sub-tile)
+// pairs.
 struct QuerySet {
   const float* px;
   const float* py;
@@ -131,13 +133,8 @@ struct QuerySet {
   int32_t qpbA;          // positions per query block
   int64_t block_base;    // exact sets: prefix of n_qblocks * n_chunks over sets
   // two-pass extension
-  float* thresh;         // [n_qblocks] flag bound on the pass-A squared distance
-  int32_t* list;         // [n_qblocks * qpbA] flagged queries, segment qb at qb * qpbA
-                         //   (nullptr: exact set)
-  int32_t* seg_count;    // [n_qblocks] flagged queries of each query block
-  float4* fpos;          // [n_qblocks * qpbA] positions of the flagged queries, in the
-                         //   order of `list` (written by the flag kernel)
-  float4* binfo;         // [n_qblocks] block centre (x, y, z) and thresh (w)
+  float4* binfo;         // [n_qblocks] block centre (x, y, z) and flag bound (w) on the
+                         //   pass-A squared distance
   float* tbox;           // [n_tiles][6] tile bounding boxes (lo, hi) of the raw cloud
   float* sbox;           // [n_sub][6] sub-tile bounding boxes of the raw cloud
   const float4* scloud;  // [n_points] the cloud in Morton order (x, y, z, original
@@ -148,6 +145,12 @@ struct QuerySet {
                          //   << 31); a block's items are consecutive
   int32_t* item_count;   // entries of `items` (zeroed by the noise kernel)
   unsigned char* hitf;   // [items]: 1 where some query of the block came under the bound
+  uint32_t* hmask;       // the call's hit words: item i's qpbA bits at i * (qpbA / 32)
+                         //   (bit j of word w: query w * 32 + j of the block came under
+                         //   the bound in the item's sub-tile), for the items with
+                         //   (i + 1) * qpbA / 32 <= mask_words; pass B takes every
+                         //   query of the block for a marked item beyond that
+  int64_t mask_words;
   int64_t qb_base;       // prefix of n_qblocks over two-pass sets (global block index)
   int64_t tile_base;     // prefix of n_tiles over two-pass sets
   int64_t query_base;    // prefix of ceil(Q / kBlock) flag blocks over sets
@@ -157,10 +160,12 @@ struct QuerySet {
   int32_t pad1;
   const int32_t* perm;   // [Q] slot -> query, spatially sorted (nullptr: identity)
   unsigned* out_slot;    // two-pass sets: [Q] squared distances by slot (== out without
-                         //   a sort); scattered back to `out` once pass B is done
-  unsigned long long* nn;  // optional [n_qblocks * qpbA]: pass B also keeps
-                           // (d^2 bits << 32 | index) per list slot (lowest index on ties)
-  int32_t* nidx;           // with nn: [Q] nearest index per query (-1 where not flagged)
+                         //   a sort), exact where pass B evaluated some pair of the
+                         //   query, +inf elsewhere (no point within d_max); read back to
+                         //   `out` by the finalize kernel
+  unsigned long long* nn;  // optional [Q]: pass B also keeps (d^2 bits << 32 | index) per
+                           // slot (lowest index on ties)
+  int32_t* nidx;           // with nn: [Q] nearest index per query (-1: none evaluated)
 };
 
 // Parameters promoted once on the host.
@@ -268,10 +273,10 @@ hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
 hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* items,
                                 const int32_t* item_count, unsigned char* hitf, int64_t max_items,
                                 int variant, hipStream_t s);
-hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_queries, hipStream_t s);
-hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, const int2* items,
-                                  const int32_t* item_count, const unsigned char* hitf,
-                                  int64_t max_items, hipStream_t s);
+// Pass B over the marked items (the hit words of every set of the call share one array).
+hipError_t launch_pass_b(const QuerySet* d_sets, int n_sets, const int2* items,
+                         const int32_t* item_count, const unsigned char* hitf, int64_t max_items,
+                         hipStream_t s);
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s);

@@ -269,7 +269,7 @@ struct MppiPlan {
   DevProblem* d_probs = nullptr;
   QuerySet* d_sets = nullptr;
   SortSet* d_sorts = nullptr;   // adjacent to d_sets: one descriptor upload
-  int64_t total_samples = 0, total_rows = 0, flag_blocks = 0;
+  int64_t total_samples = 0, total_rows = 0;
   int64_t sort_blocks = 0;
   int64_t total_tiles = 0;      // cloud tiles of the two-pass sets (box launches)
   int64_t total_qblocks = 0;    // query blocks of the two-pass sets (cull launch)
@@ -278,6 +278,8 @@ struct MppiPlan {
   int2* items = nullptr;
   int32_t* item_count = nullptr;
   unsigned char* hitf = nullptr;
+  uint32_t* hmask = nullptr;    // the call's hit words (see QuerySet::hmask)
+  int64_t mask_words = 0;
   bool any_sorted = false;      // some set works in sorted slots
   bool any_scloud = false;      // some set has a sorted cloud
   bool any_nn = false;          // some set records nearest indices
@@ -307,7 +309,13 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   pl.items = cur.take<int2>(cap);
   pl.hitf = cur.take<unsigned char>(cap);
   pl.item_count = cur.take<int32_t>(1);
-  int64_t sort_blocks = 0, eb = 0, sb = 0, rb = 0, fb = 0, qbb = 0, tb = 0;
+  // hit words: item i's at i * qpbA / 32.  A call whose marked items all had their
+  // words would need cap * 16 words (cap counts 512-position blocks); this holds a
+  // sixteenth of that, and at least 4 MiB: items past it are taken whole by pass B
+  // (every query of the block), which is exact, only slower.
+  pl.mask_words = cap > 0 ? std::max<int64_t>(int64_t(1) << 20, cap) : 0;
+  pl.hmask = cur.take<uint32_t>(pl.mask_words);
+  int64_t sort_blocks = 0, eb = 0, sb = 0, rb = 0, qbb = 0, tb = 0;
   for (int b = 0; b < n; ++b) {
     const aero_problem& q = h[b];
     DevProblem& d = pl.probs[b];
@@ -362,24 +370,20 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     qs.n_tiles = (int32_t)n_tiles;
     qs.qb_base = qbb;
     qs.tile_base = tb;
-    qs.query_base = fb;
     if (two_pass) {
       qbb += qs.n_qblocks;
       tb += n_tiles;
-      fb += (MNK + kBlock - 1) / kBlock;
       // sized for the smallest block size (the most blocks), so the layout does not
       // depend on the variant
       const int64_t max_blocks = (MNK + kPassAMinQPB - 1) / kPassAMinQPB;
-      qs.thresh = cur.take<float>(max_blocks);
-      qs.seg_count = cur.take<int32_t>(max_blocks);
       qs.binfo = cur.take<float4>(max_blocks);
-      qs.list = cur.take<int32_t>(MNK + kQueriesPerBlock);
-      qs.fpos = cur.take<float4>(MNK + kQueriesPerBlock);
       qs.tbox = cur.take<float>(6 * n_tiles);
       qs.sbox = cur.take<float>(6 * n_sub);
       qs.items = pl.items;
       qs.item_count = pl.item_count;
       qs.hitf = pl.hitf;
+      qs.hmask = pl.hmask;
+      qs.mask_words = pl.mask_words;
     }
     // spatial order of the positions, and of the cloud, for the cull step
     SortSet& so = pl.sorts[2 * b];
@@ -440,15 +444,15 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     if (track_nearest && q.nearest_idx) {
       d.nidx = q.nearest_idx;  // reset to -1 by the noise kernel
       if (two_pass) {
-        qs.nn = cur.take<unsigned long long>(MNK + kQueriesPerBlock);
+        qs.nn = cur.take<unsigned long long>(MNK);  // reset by the noise kernel
         qs.nidx = q.nearest_idx;
+        d.nn = qs.nn;
         pl.any_nn = true;
       }
     }
   }
   pl.total_samples = sb;
   pl.total_rows = rb;
-  pl.flag_blocks = fb;
   pl.total_tiles = tb;
   pl.total_qblocks = qbb;
   pl.sort_blocks = sort_blocks;
@@ -468,7 +472,7 @@ std::vector<char> mppi_blob(const MppiPlan& pl, int n) {
 }
 
 // The distance passes of a planned Stage-I call: the spatial sorts, the cull step,
-// pass A (timed by `tev` when given), the flag step and pass B.
+// pass A (timed by `tev` when given) and pass B.
 hipError_t run_distance(const MppiPlan& pl, int n, int variant, hipEvent_t* tev, hipStream_t s) {
   hipError_t he = hipSuccess;
   if (pl.sort_blocks > 0)
@@ -487,12 +491,9 @@ hipError_t run_distance(const MppiPlan& pl, int n, int variant, hipEvent_t* tev,
                            s);
     });
   if (he == hipSuccess && tev) he = hipEventRecord(tev[1], s);
-  if (he == hipSuccess && pl.flag_blocks > 0)
-    he = timed(AERO_K_FLAG, s, [&] { return launch_flag(pl.d_sets, n, pl.flag_blocks, s); });
   if (he == hipSuccess && pl.item_cap > 0)
     he = timed(AERO_K_MIN_DIST_EXACT, s, [&] {
-      return launch_min_dist_listed(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap,
-                                    s);
+      return launch_pass_b(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap, s);
     });
   return he;
 }
@@ -520,7 +521,7 @@ void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& b
   bp.J = cur.take<double>(5 * MK);
   int32_t* ni = cur.take<int32_t>(q.nearest_idx ? 0 : MNK);
   bp.nidx = q.nearest_idx ? q.nearest_idx : ni;
-  bp.nn = cur.take<unsigned long long>(q.n_points > 0 ? MNK + kQueriesPerBlock : 0);
+  bp.nn = cur.take<unsigned long long>(q.n_points > 0 ? MNK : 0);
   bp.ckpt = cur.take<double>(n_seg * 10 * MK);
   bp.seg = cur.take<double>(8 * 10 * MK);
   bp.gsamp = cur.take<double>(MNK * 4);
@@ -534,6 +535,7 @@ void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& b
     if (q.n_points > 0) {
       qs.nn = bp.nn;
       qs.nidx = bp.nidx;
+      d.nn = bp.nn;  // reset by the noise kernel
     }
   }
 }
@@ -960,6 +962,7 @@ int aero_mppi_step_backward_indexed(const aero_params* h_prm, const aero_problem
   // the stored indices are an input: nothing resets or rewrites them
   DevProblem& dp = pl.probs[0];
   dp.nidx = nullptr;
+  dp.nn = nullptr;
   dp.nidx_in = h[0].nearest_idx;
   pl.sets[0].nn = nullptr;
   pl.sets[0].nidx = nullptr;
@@ -1038,19 +1041,66 @@ int aero_set_pass_a_variant(int variant) {
   return AERO_OK;
 }
 
-int aero_cull_items(const aero_problem* h, int32_t n, const void* d_ws, size_t ws_bytes,
-                    int64_t* h_items) {
-  if (!h_items || !d_ws) return AERO_ERR_NULL;
+int aero_read_distance_stats(const aero_problem* h, int32_t n, const void* d_ws,
+                             size_t ws_bytes, aero_distance_stats* out) {
+  if (!out || !d_ws) return AERO_ERR_NULL;
   const int e = check_problems(h, n, false);
   if (e) return e;
   MppiPlan pl;
   plan_mppi(h, n, nullptr, 1.0f, pl, kPassAValu, true);
   if (ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
   plan_mppi(h, n, (char*)const_cast<void*>(d_ws), 1.0f, pl, kPassAValu, true);
-  int32_t v = 0;
-  if (hipMemcpy(&v, pl.item_count, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+  *out = aero_distance_stats{};
+  if (pl.item_cap == 0) return AERO_OK;
+  // the descriptors as the call wrote them (block sizes of the variant that ran)
+  std::vector<QuerySet> sets(n);
+  int32_t cnt = 0;
+  if (hipMemcpy(sets.data(), pl.d_sets, n * sizeof(QuerySet), hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(&cnt, pl.item_count, sizeof cnt, hipMemcpyDeviceToHost) != hipSuccess)
     return AERO_ERR_DEVICE;
-  *h_items = v;
+  const int64_t ni = std::min<int64_t>(std::max(cnt, 0), pl.item_cap);
+  std::vector<int2> items(ni);
+  std::vector<unsigned char> hit(ni);
+  if (ni > 0 && (hipMemcpy(items.data(), pl.items, ni * sizeof(int2), hipMemcpyDeviceToHost) !=
+                     hipSuccess ||
+                 hipMemcpy(hit.data(), pl.hitf, ni, hipMemcpyDeviceToHost) != hipSuccess))
+    return AERO_ERR_DEVICE;
+  const int64_t W = sets[0].qpbA / 32;
+  const int64_t with_words = std::min<int64_t>(ni, W > 0 ? pl.mask_words / W : 0);
+  std::vector<uint32_t> words(with_words * W);
+  if (!words.empty() && hipMemcpy(words.data(), pl.hmask, words.size() * 4,
+                                  hipMemcpyDeviceToHost) != hipSuccess)
+    return AERO_ERR_DEVICE;
+  for (int b = 0; b < n; ++b)
+    if (sets[b].items) out->positions += sets[b].Q;
+  for (int64_t i = 0; i < ni; ++i) {
+    const int64_t gqb = items[i].x;
+    int b = 0;
+    while (b + 1 < n && sets[b + 1].qb_base <= gqb) ++b;
+    const QuerySet& S = sets[b];
+    const int64_t qb = gqb - S.qb_base;
+    const int64_t sub = (int64_t)((unsigned)items[i].y & 0x7fffffffu);
+    const int64_t nq = std::min<int64_t>(S.qpbA, S.Q - qb * S.qpbA);
+    const int64_t np = std::min<int64_t>(kSubPts, (int64_t)S.n_points - sub * kSubPts);
+    if (nq <= 0 || np <= 0) continue;
+    out->items += 1;
+    out->pairs_a += nq * np;
+    if (!hit[i]) continue;
+    out->items_b += 1;
+    if (i < with_words) {
+      int64_t h = 0;
+      for (int64_t j = 0; j < W; ++j) {
+        const int64_t lo = 32 * j;
+        const uint32_t valid = lo >= nq ? 0u : (nq - lo >= 32 ? 0xffffffffu : (1u << (nq - lo)) - 1u);
+        h += __builtin_popcount(words[i * W + j] & valid);
+      }
+      out->pairs_b += h * np;
+    } else {
+      out->items_whole += 1;
+      out->pairs_b += nq * np;
+    }
+  }
   return AERO_OK;
 }
 

@@ -107,11 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
     const float span = sqrtf(rr) * 1.001f + d_max;
     thr = span <= 64.0f ? d_max * d_max + 0x1p-15f * span * span + 1e-6f : INFINITY;
   }
-  if (lane == 0) {
-    S.thresh[qb] = thr;
-    S.seg_count[qb] = 0;
-    S.binfo[qb] = make_float4(c[0], c[1], c[2], thr);
-  }
+  if (lane == 0) S.binfo[qb] = make_float4(c[0], c[1], c[2], thr);
   const int64_t n_tiles = S.n_tiles;
   const int64_t n_sub = ((int64_t)S.n_points + kSubPts - 1) / kSubPts;
   const float lim = S.cull ? reach_limit(thr, d_max) : INFINITY;

@@ -1,23 +1,23 @@
-// Brute-force nearest squared distance from rollout positions to the raw cloud
-// (the d_t of the collision cost, Sec. IV-C).
+// Nearest squared distance from rollout positions to the raw cloud (the d_t of the
+// collision cost, Sec. IV-C).
 //
-//   k_min_dist_exact   direct form (p - o)^2 per pair; cloud tiles staged in LDS
-//                      and read as wave-wide broadcasts, kQueriesPerLane queries
-//                      per lane in registers.  Over every query of a set, or (pass
-//                      B) over a flagged list with a persistent grid.
-//   k_min_dist_approx  pass A: the expanded form |o'|^2 - 2 p'.o' with query and
-//                      cloud recentred on the query block's bounding-box centre:
-//                      three FMAs and half a min3 per pair.  Also writes, per query
-//                      block, the bound below which the approximate value may hide
-//                      a true distance under d_max (from its rounding-error bound).
-//   k_flag             compacts the queries under that bound into a list and resets
-//                      them for pass B.
+//   k_min_dist_exact   direct form (p - o)^2 per pair over every query of a set and
+//                      every cloud point (Stage II); cloud tiles staged in LDS and
+//                      read as wave-wide broadcasts, queries in registers.
+//   k_pass_a_valu      pass A over the cull step's (query block, sub-tile) items: the
+//                      expanded form |o'|^2 - 2 p'.o' with query and cloud recentred on
+//                      the block's centre, three FMAs and half a min3 per pair; per
+//                      item, the hit words of the queries that came under the block's
+//                      bound (the matrix-core variants live in distance_mfma.hip).
+//   k_pass_b           pass B: the direct form for exactly the (query, sub-tile) pairs
+//                      of the hit words.
+//   k_scatter_nearest  nearest indices from pass B's records (when requested).
 //
-// Chunks of the cloud combine through atomicMin on the float bit patterns of the
-// non-negative squared distances (exact and order independent), so every result
-// is bitwise reproducible.  Queries left unflagged keep their pass-A value, which
-// is then provably >= d_max^2: there the collision penalty is 0 whatever the exact
-// distance.
+// Results combine through atomicMin on the float bit patterns of the non-negative
+// squared distances (exact and order independent), so every result is bitwise
+// reproducible.  A query that no pass-B pair reaches keeps +inf: its pass-A values
+// stayed over the bound everywhere, so its distance is provably >= d_max, where the
+// collision penalty is 0 whatever the exact value.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -132,41 +132,75 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
 }
 
 
-// One pass-B item: the flagged queries of query block qb (R per lane; their
-// positions as the flag kernel wrote them) against the points of one cloud sub-tile
-// (raw or sorted order).  With kIdx also the lowest point index attaining the
-// minimum (the sorted order visits indices in any order, so ties compare indices).
+// Pass B: the exact direct form (p - o)^2 for the (query, sub-tile) pairs that pass A
+// marked: for a marked item, the queries of its block whose pass-A value came under
+// the bound in its sub-tile (all of the block's queries for an item without room
+// for its hit words).  A query's nearest point within d_max lies in such a sub-tile
+// (its pass-A value there is under the bound), and every other point of the reach is
+// farther than d_max, so the minimum over the evaluated pairs is exact below d_max.
+// Persistent grid, items strided over the workgroups; per item the sub-tile is
+// staged in LDS, wave 0 lists the hit queries from the item's words, and the listed
+// queries x points are spread over the threads: R queries per thread when kBlock or
+// more are listed, else each listed query's points split among kBlock / h threads.
+// Results combine through atomicMin on float bits (and on (d^2 bits, index) pairs for
+// the nearest index, lowest index on ties), so they are order independent.
+template <bool kIdx>
+__device__ inline void pass_b_result(const QuerySet& S, int64_t slot, float best, int32_t bidx) {
+  atomicMin(S.out_slot + slot, __float_as_uint(best));
+  if constexpr (kIdx)
+    atomicMin(S.nn + slot, ((unsigned long long)__float_as_uint(best) << 32) |
+                               (unsigned long long)(unsigned)bidx);
+}
+
+// Direct form of one query against tile points [p0, p1) (p1 - p0 even, or the tile
+// holds a far record at p1).
+template <bool kIdx>
+__device__ inline void pass_b_scan(const float4* tile, int p0, int p1, float px, float py,
+                                   float pz, float& best, int32_t& bidx) {
+  for (int j = p0; j < p1; j += 2) {
+    const float4 a = tile[j];
+    const float4 c = tile[j + 1];
+    const float ax = px - a.x, ay = py - a.y, az = pz - a.z;
+    const float cx = px - c.x, cy = py - c.y, cz = pz - c.z;
+    const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
+    const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+    if constexpr (kIdx) {
+      const int32_t ia = __float_as_int(a.w), ic = __float_as_int(c.w);
+      if (da < best || (da == best && ia < bidx)) {
+        best = da;
+        bidx = ia;
+      }
+      if (dc < best || (dc == best && ic < bidx)) {
+        best = dc;
+        bidx = ic;
+      }
+    } else {
+      best = min3f(best, da, dc);
+    }
+  }
+}
+
+// R listed queries per thread (the k-th listed query goes to thread k % kBlock), all
+// n2 points of the tile.
 template <int R, bool kIdx>
-__device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, unsigned ys,
-                                   float4* tile) {
+__device__ inline void pass_b_rows(const QuerySet& S, int64_t slot0, int h,
+                                   const uint16_t* qlist, const float4* tile, int n2) {
   const int tid = threadIdx.x;
-  const int64_t lbase = qb * S.qpbA;
+  const int64_t Q = S.Q;
   float px[R], py[R], pz[R], best[R];
-  int32_t qi[R], bidx[R];
+  int32_t bidx[R];
+  int64_t sl[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int j = r * kBlock + tid;
-    const bool ok = j < cnt;
-    const int64_t e = lbase + (ok ? j : 0);  // cnt >= 1: entry 0 exists
-    qi[r] = ok ? S.list[e] : -1;
-    const float4 p = S.fpos[e];
-    px[r] = p.x;
-    py[r] = p.y;
-    pz[r] = p.z;
+    const int k = r * kBlock + tid;
+    sl[r] = k < h ? slot0 + qlist[k] : -1;
+    const int64_t q = sl[r] >= 0 ? sl[r] : slot0;  // always a valid position
+    px[r] = S.sp[q];
+    py[r] = S.sp[Q + q];
+    pz[r] = S.sp[2 * Q + q];
     best[r] = __uint_as_float(kInfBits);
     bidx[r] = 0x7fffffff;
   }
-  float x, y, z;
-  int32_t idx;
-  bool in;
-  int n;
-  item_point(S, ys, x, y, z, idx, in, n);
-  // every thread writes its own slot (a far record past the sub-tile's points), so an
-  // odd count still leaves a valid record after the last point
-  tile[tid] = in ? make_float4(x, y, z, __int_as_float(idx))
-                 : make_float4(kFar, kFar, kFar, __int_as_float(0x7fffffff));
-  const int n2 = (n + 1) & ~1;  // even: the loop takes points in pairs
-  __syncthreads();
 #pragma unroll 2
   for (int j = 0; j < n2; j += 2) {
     const float4 a = tile[j];
@@ -192,60 +226,106 @@ __device__ inline void listed_item(const QuerySet& S, int64_t qb, int cnt, unsig
       }
     }
   }
-  __syncthreads();  // the next item stages over the tile
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (qi[r] < 0) continue;
-    atomicMin(S.out_slot + qi[r], __float_as_uint(best[r]));
-    if constexpr (kIdx)
-      atomicMin(S.nn + lbase + r * kBlock + tid,
-                ((unsigned long long)__float_as_uint(best[r]) << 32) |
-                    (unsigned long long)(unsigned)bidx[r]);
+  for (int r = 0; r < R; ++r)
+    if (sl[r] >= 0) pass_b_result<kIdx>(S, sl[r], best[r], bidx[r]);
+}
+
+template <bool kIdx>
+__device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int h, const uint16_t* qlist,
+                                   const float4* tile, int n) {
+  const int tid = threadIdx.x;
+  const int n2 = (n + 1) & ~1;  // even: the loops take points in pairs
+  if (h < kBlock) {
+    // each listed query's points split among `sp` threads, in even-sized parts
+    const int sp = kBlock / h;
+    if (tid >= h * sp) return;
+    const int k = tid % h, part = tid / h;
+    const int half = n2 / 2;
+    const int p0 = 2 * (part * half / sp), p1 = 2 * ((part + 1) * half / sp);
+    const int64_t slot = slot0 + qlist[k];
+    const int64_t Q = S.Q;
+    float best = __uint_as_float(kInfBits);
+    int32_t bidx = 0x7fffffff;
+    pass_b_scan<kIdx>(tile, p0, p1, S.sp[slot], S.sp[Q + slot], S.sp[2 * Q + slot], best, bidx);
+    if (p0 < p1) pass_b_result<kIdx>(S, slot, best, bidx);
+    return;
+  }
+  switch ((h + kBlock - 1) / kBlock) {
+    case 1: pass_b_rows<1, kIdx>(S, slot0, h, qlist, tile, n2); break;
+    case 2: pass_b_rows<2, kIdx>(S, slot0, h, qlist, tile, n2); break;
+    case 3: pass_b_rows<3, kIdx>(S, slot0, h, qlist, tile, n2); break;
+    case 4: pass_b_rows<4, kIdx>(S, slot0, h, qlist, tile, n2); break;
+    case 5: pass_b_rows<5, kIdx>(S, slot0, h, qlist, tile, n2); break;
+    case 6: pass_b_rows<6, kIdx>(S, slot0, h, qlist, tile, n2); break;
+    case 7: pass_b_rows<7, kIdx>(S, slot0, h, qlist, tile, n2); break;
+    default: pass_b_rows<kQueriesPerLane, kIdx>(S, slot0, h, qlist, tile, n2); break;
   }
 }
 
-template <int R>
-__device__ inline void listed_item_r(const QuerySet& S, int64_t qb, int cnt, unsigned ys,
-                                     float4* tile) {
-  if (S.nn)
-    listed_item<R, true>(S, qb, cnt, ys, tile);
-  else
-    listed_item<R, false>(S, qb, cnt, ys, tile);
-}
-
-// Pass B: exact direct form for the flagged queries, only against the items (block,
-// sub-tile) that pass A marked for their block (a query's nearest point within d_max
-// always lies in one).  Persistent grid over the call's item list, whose length is
-// read on the device.
-__global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __restrict__ sets,
-                                                            int n_sets,
-                                                            const int2* __restrict__ items,
-                                                            const int32_t* __restrict__ item_count,
-                                                            const unsigned char* __restrict__ hitf) {
+__global__ __launch_bounds__(kBlock) void k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
+                                                   const int2* __restrict__ items,
+                                                   const int32_t* __restrict__ item_count,
+                                                   const unsigned char* __restrict__ hitf) {
   __shared__ float4 tile[kSubPts];
+  __shared__ uint16_t qlist[kQueriesPerBlock];  // listed queries (block-local index)
+  __shared__ int htot;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t total = *item_count;
+  const uint32_t* __restrict__ hmask = sets[0].hmask;
+  const int64_t mask_words = sets[0].mask_words;
   SetCache cache{0, 0, 0};
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     if (!hitf[it]) continue;  // block-uniform
     const int2 e = items[it];
     const int s = set_of(sets, n_sets, e.x, cache);
-    const QuerySet S = sets[s];
-    if (!block_of(S, e.x) || !S.list) continue;
+    const QuerySet S = sets[s];  // a copy: the stores below cannot alias it
+    if (!block_of(S, e.x)) continue;
     const int64_t qb = e.x - S.qb_base;
-    const int cnt = min(S.seg_count[qb], S.qpbA);
-    if (cnt <= 0) continue;
-    const int nr = (cnt + kBlock - 1) / kBlock;
-    // exactly as many flagged queries per lane as the block has (no idle groups)
-    switch (nr) {
-      case 1: listed_item_r<1>(S, qb, cnt, (unsigned)e.y, tile); break;
-      case 2: listed_item_r<2>(S, qb, cnt, (unsigned)e.y, tile); break;
-      case 3: listed_item_r<3>(S, qb, cnt, (unsigned)e.y, tile); break;
-      case 4: listed_item_r<4>(S, qb, cnt, (unsigned)e.y, tile); break;
-      case 5: listed_item_r<5>(S, qb, cnt, (unsigned)e.y, tile); break;
-      case 6: listed_item_r<6>(S, qb, cnt, (unsigned)e.y, tile); break;
-      case 7: listed_item_r<7>(S, qb, cnt, (unsigned)e.y, tile); break;
-      default: listed_item_r<kQueriesPerLane>(S, qb, cnt, (unsigned)e.y, tile); break;
+    const int64_t slot0 = qb * S.qpbA;
+    const int nq = (int)min<int64_t>(S.qpbA, S.Q - slot0);  // queries of the block
+    const int W = S.qpbA / 32;
+    float x, y, z;
+    int32_t idx;
+    bool in;
+    int n;
+    item_point(S, (unsigned)e.y, x, y, z, idx, in, n);
+    // every thread writes its own slot (a far record past the sub-tile's points), so an
+    // odd count still leaves a valid record after the last point
+    tile[tid] = in ? make_float4(x, y, z, __int_as_float(idx))
+                   : make_float4(kFar, kFar, kFar, __int_as_float(0x7fffffff));
+    if (w == 0) {
+      // bits of the block's existing queries in this lane's word
+      const int lo = lane * 32;
+      const uint32_t valid =
+          lo >= nq ? 0u : (nq - lo >= 32 ? 0xffffffffu : (1u << (nq - lo)) - 1u);
+      uint32_t word = 0;
+      if (lane < W)  // without room for the item's words: every query of the block
+        word = (it + 1) * W <= mask_words ? hmask[it * W + lane] & valid : valid;
+      const int c = __popc(word);
+      int incl = c;  // inclusive scan over the wave
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y2 = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y2;
+      }
+      int at = incl - c;
+      while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1u;
+        qlist[at++] = (uint16_t)(lo + b);
+      }
+      if (lane == 63) htot = incl;
     }
+    __syncthreads();
+    const int h = min(htot, nq);
+    if (h > 0 && n > 0) {
+      if (S.nn)
+        pass_b_item<true>(S, slot0, h, qlist, tile, n);
+      else
+        pass_b_item<false>(S, slot0, h, qlist, tile, n);
+    }
+    __syncthreads();  // the next item stages over the tile and the list
   }
 }
 
@@ -253,7 +333,10 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_listed(const QuerySet* __re
 // matrix-core pass): a block's kQueriesPerBlock positions are recentred on its
 // centre and held in registers (kQueriesPerLane per lane) while the run of its items
 // goes by; each item's sub-tile is staged in LDS as (-2 o', |o'|^2) records (double
-// buffered), and t = |o'|^2 - 2 p'.o' takes three FMAs and half a min3 per pair.
+// buffered), and t = |o'|^2 - 2 p'.o' takes three FMAs and half a min3 per pair.  Per
+// item, the block's queries whose value came under the bound form the item's hit
+// words (query r kBlock + tid is bit (r kBlock + tid) % 32 of word
+// (r kBlock + tid) / 32).
 constexpr int kPassAGridValu = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restrict__ sets,
@@ -261,25 +344,22 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
                                                         const int32_t* __restrict__ item_count,
                                                         unsigned char* __restrict__ hitf) {
   constexpr int R = kQueriesPerLane;
+  constexpr int W = kQueriesPerBlock / 32;  // hit words per item
   __shared__ float4 tile[2][kSubPts];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t total = *item_count;
   const int64_t G = gridDim.x;
   const int64_t per = (total + G - 1) / G;
   const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min<int64_t>(total, i0 + per);
   if (i0 >= i1) return;  // block-uniform
   SetCache cache{0, 0, 0};
-  int64_t cur = -1, slot0 = 0;
-  unsigned* out_slot = nullptr;
+  int64_t cur = -1;
   unsigned okm = 0;  // bit r: this lane's query r exists
   float c[3] = {0.0f, 0.0f, 0.0f}, thr = 0.0f;
-  float px[R], py[R], pz[R], pp[R], tmin[R];
-  auto flush = [&]() {
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if ((okm >> r) & 1u)
-        atomicMin(out_slot + slot0 + r * kBlock, __float_as_uint(fmaxf(pp[r] + tmin[r], 0.0f)));
-  };
+  float px[R], py[R], pz[R], pp[R];
+  // the hit words of every set of the call share one array
+  AERO_GLOBAL uint32_t* __restrict__ hmask = global_ptr(sets[0].hmask);
+  const int64_t mask_items = sets[0].mask_words / W;  // items with room for their words
   int2 it = items[i0];
   int ns = set_of(sets, n_sets, it.x, cache);
   float ox, oy, oz;
@@ -294,18 +374,16 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
     const int icnt = cnt;
     const bool ivalid = valid;
     if (ivalid && gqb != cur) {  // block-uniform
-      if (cur >= 0) flush();
       const QuerySet& S = sets[ns];
       const int64_t qb = gqb - S.qb_base;
       const int64_t Q = S.Q;
       const float* __restrict__ sp = S.sp;
-      out_slot = S.out_slot;
       const float4 bi = S.binfo[qb];
       c[0] = bi.x;
       c[1] = bi.y;
       c[2] = bi.z;
       thr = bi.w;
-      slot0 = qb * kQueriesPerBlock + tid;
+      const int64_t slot0 = qb * kQueriesPerBlock + tid;
       okm = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -317,7 +395,6 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
         py[r] = sp[Q + qs] - c[1];
         pz[r] = sp[2 * Q + qs] - c[2];
         pp[r] = fmaf(pz[r], pz[r], fmaf(py[r], py[r], px[r] * px[r]));
-        tmin[r] = kFarT;
       }
       cur = gqb;
     }
@@ -353,73 +430,31 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
       }
     }
     bool hit = false;
+    const bool room = i < mask_items;  // block-uniform
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      hit |= ((okm >> r) & 1u) && pp[r] + tt[r] < thr;
-      tmin[r] = fminf(tmin[r], tt[r]);
+      const bool hq = ((okm >> r) & 1u) && pp[r] + tt[r] < thr;
+      hit |= hq;
+      const uint64_t hb = __ballot(hq);
+      if (room && lane < 2)  // the wave's 64 queries r kBlock + 64 w + [0, 64): two words
+        hmask[i * W + r * (kBlock / 32) + 2 * w + lane] =
+            (uint32_t)(lane ? (hb >> 32) : (hb & 0xffffffffull));
     }
     mark_hit(hit, hitf, i);
   }
-  if (cur >= 0) flush();
 }
 
-// Compact the queries of two-pass sets whose pass-A value is under the bound into
-// the list segment of their pass-A block.
-// Block = 256 consecutive queries of one set; one atomic per block.
-__global__ __launch_bounds__(kBlock) void k_flag(const QuerySet* __restrict__ sets, int n_sets) {
-  __shared__ int wave_cnt[4];
-  __shared__ int base;
-  const int64_t bid = blockIdx.x;
-  // query_base holds the prefix of ceil(Q / kBlock) blocks over sets
-  const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.query_base; });
-  const QuerySet S = sets[s];  // a copy: the stores below cannot alias it
-  // pass-A slots in order; the query of a slot comes from the spatial sort
-  const int64_t slot = (bid - S.query_base) * kBlock + threadIdx.x;
-  bool flag = false;
-  if (slot < S.Q) {
-    const float d2 = __uint_as_float(S.out_slot[slot]);
-    flag = d2 < S.thresh[slot / S.qpbA];
-  }
-  const uint64_t mask = __ballot(flag);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int before = __popcll(mask & ((1ull << lane) - 1ull));
-  if (lane == 0) wave_cnt[w] = __popcll(mask);
-  __syncthreads();
-  // the block's 256 queries lie in one pass-A block (qpbA is a multiple of 256)
-  const int64_t qb = ((bid - S.query_base) * kBlock) / S.qpbA;
-  if (threadIdx.x == 0) {
-    const int tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
-    base = tot ? atomicAdd(S.seg_count + qb, tot) : 0;
-  }
-  __syncthreads();
-  if (flag) {
-    int off = base + before;
-    for (int i = 0; i < w; ++i) off += wave_cnt[i];
-    const int64_t e = qb * S.qpbA + off;
-    S.list[e] = (int32_t)slot;
-    S.fpos[e] = make_float4(S.sp[slot], S.sp[S.Q + slot], S.sp[2 * S.Q + slot],
-                            0.0f);  // read back by pass B
-    S.out_slot[slot] = kInfBits;
-    if (S.nn) S.nn[e] = ~0ull;
-  }
-}
-
-// Nearest indices of the flagged queries (sets with nn), persistent grid over the
-// segment slots of every query block.
+// Nearest indices (sets with nn) from pass B's (d^2 bits, index) records by slot.
 __global__ __launch_bounds__(kBlock) void k_scatter_nearest(const QuerySet* __restrict__ sets,
                                                             int n_sets) {
   for (int s = 0; s < n_sets; ++s) {
     const QuerySet S = sets[s];  // a copy: the stores below cannot alias it
-    if (!S.nn || !S.list) continue;
-    const int64_t slots = (int64_t)S.n_qblocks * S.qpbA;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < slots;
+    if (!S.nn || !S.items) continue;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < S.Q;
          i += (int64_t)gridDim.x * kBlock) {
-      const int64_t qb = i / S.qpbA;
-      if (i - qb * S.qpbA >= S.seg_count[qb]) continue;
       const unsigned long long v = S.nn[i];
       const unsigned idx = (unsigned)(v & 0xffffffffull);
-      S.nidx[perm_query(S, S.list[i])] =
-          (v == ~0ull || idx >= (unsigned)S.n_points) ? -1 : (int32_t)idx;
+      S.nidx[perm_query(S, i)] = (v == ~0ull || idx >= (unsigned)S.n_points) ? -1 : (int32_t)idx;
     }
   }
 }
@@ -443,22 +478,17 @@ hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
   return hipGetLastError();
 }
 
-hipError_t launch_flag(const QuerySet* d_sets, int n_sets, int64_t total_blocks, hipStream_t s) {
-  if (total_blocks > 0) k_flag<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
-  return hipGetLastError();
-}
-
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_t s) {
   k_scatter_nearest<<<256, kBlock, 0, s>>>(d_sets, n_sets);
   return hipGetLastError();
 }
 
-hipError_t launch_min_dist_listed(const QuerySet* d_sets, int n_sets, const int2* items,
-                                  const int32_t* item_count, const unsigned char* hitf,
-                                  int64_t max_items, hipStream_t s) {
+hipError_t launch_pass_b(const QuerySet* d_sets, int n_sets, const int2* items,
+                         const int32_t* item_count, const unsigned char* hitf, int64_t max_items,
+                         hipStream_t s) {
   if (max_items > 0) {
     const unsigned grid = (unsigned)(max_items < kPersistBlocks ? max_items : kPersistBlocks);
-    k_min_dist_listed<<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
+    k_pass_b<<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
   }
   return hipGetLastError();
 }

@@ -4,10 +4,10 @@
 // finite padding constant), so that chained fminf become v_min3_f32 without
 // NaN canonicalisation, and with MFMA results in VGPRs (no accumulator-register
 // reads); the compiler inserts the MFMA-to-VALU wait states.  The kernel writes the
-// same outputs as the VALU pass A: a per-query value, combined across items with
-// atomicMin on float bits, that is exact up to the stated rounding for every pair
-// closer than d_max, and the mark of every item in which some query of its block
-// came under the block's flag bound.
+// same outputs as the VALU pass A: per item, the hit words of the block's queries
+// whose value (exact up to the stated rounding for every pair closer than d_max) came
+// under the block's flag bound in the item's sub-tile, and the mark of every item
+// with such a query.
 //
 // Every recentred coordinate is split into two halves, v = hi + lo (hi = half(v),
 // lo = half(v - hi)), and one v_mfma_f32_32x32x16_f16 evaluates, for 32 cloud
@@ -30,8 +30,9 @@
 // takes the g-th run of ceil(items / grid) consecutive items.  A block's queries are
 // set up (positions recentred on the block's centre, split, in registers) when the
 // run reaches its first item; each item's 256 points are staged in LDS (double
-// buffered: the next item's point is loaded while this one is reduced), and the
-// block's minima go out by atomicMin when the run leaves the block.
+// buffered: the next item's point is loaded while this one is reduced).  Query
+// 32 COLS w + 32 b + col of the block (wave w, column block b, column col) is bit col
+// of hit word COLS w + b.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -84,6 +85,7 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
               const int32_t* __restrict__ item_count, unsigned char* __restrict__ hitf) {
   static_assert(COLS % kF16Pipe == 0, "column blocks come in groups of kF16Pipe");
   constexpr int QPB = 4 * 32 * COLS;
+  constexpr int W = QPB / 32;  // hit words per item
   __shared__ half8 tile[2][kSubPts];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int col = lane & 31, kh = lane >> 5;
@@ -94,21 +96,14 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
   if (i0 >= i1) return;  // block-uniform
   SetCache cache{0, 0, 0};
   // the current query block
-  int64_t cur = -1, slot0 = 0;
-  unsigned* out_slot = nullptr;
+  int64_t cur = -1;
   unsigned okm = 0;  // bit b: column block b's query of this lane exists
   float c[3] = {0.0f, 0.0f, 0.0f}, thr = 0.0f;
   half8 bop[COLS];
-  float pp[COLS], tmin[COLS];
-  auto flush = [&]() {
-#pragma unroll
-    for (int b = 0; b < COLS; ++b) {
-      float v = tmin[b];
-      v = fminf(v, __shfl_xor(v, 32, 64));  // the two lane halves hold different rows
-      if (((okm >> b) & 1u) && kh == 0)
-        atomicMin(out_slot + slot0 + b * 32, __float_as_uint(fmaxf(pp[b] + v, 0.0f)));
-    }
-  };
+  float pp[COLS];
+  // the hit words of every set of the call share one array
+  AERO_GLOBAL uint32_t* __restrict__ hmask = global_ptr(sets[0].hmask);
+  const int64_t mask_items = sets[0].mask_words / W;  // items with room for their words
   // the first item's point
   int2 it = items[i0];
   int ns = set_of(sets, n_sets, it.x, cache);
@@ -124,18 +119,16 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
     const int icnt = cnt;
     const bool ivalid = valid;
     if (ivalid && gqb != cur) {  // block-uniform
-      if (cur >= 0) flush();
       const QuerySet& S = sets[ns];
       const int64_t qb = gqb - S.qb_base;
       const int64_t Q = S.Q;
       const float* __restrict__ sp = S.sp;
-      out_slot = S.out_slot;
       const float4 bi = S.binfo[qb];
       c[0] = bi.x;
       c[1] = bi.y;
       c[2] = bi.z;
       thr = bi.w;
-      slot0 = qb * QPB + w * (32 * COLS) + col;
+      const int64_t slot0 = qb * QPB + w * (32 * COLS) + col;
       okm = 0;
 #pragma unroll
       for (int b = 0; b < COLS; ++b) {
@@ -161,7 +154,6 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
         }
         if (!ok) v = (half8){};
         bop[b] = v;
-        tmin[b] = kF16FarT;
       }
       cur = gqb;
     }
@@ -200,14 +192,18 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
       }
     }
     bool hit = false;
+    const bool room = i < mask_items;  // block-uniform
 #pragma unroll
     for (int b = 0; b < COLS; ++b) {
-      hit |= ((okm >> b) & 1u) && pp[b] + tt[b] < thr;
-      tmin[b] = fminf(tmin[b], tt[b]);
+      // the two lane halves hold different rows (points) of the same column (query)
+      const float v = fminf(tt[b], __shfl_xor(tt[b], 32, 64));
+      const bool hq = ((okm >> b) & 1u) && pp[b] + v < thr;
+      hit |= hq;
+      const uint64_t hb = __ballot(hq);
+      if (room && lane == 0) hmask[i * W + w * COLS + b] = (uint32_t)(hb & 0xffffffffull);
     }
     mark_hit(hit, hitf, i);
   }
-  if (cur >= 0) flush();
 }
 
 }  // namespace

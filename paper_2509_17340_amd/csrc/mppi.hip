@@ -54,8 +54,8 @@ __device__ inline void put_blob(const PutBlob& blob, unsigned char* dst) {
 
 // The rollout's standard normals for every (instance, step, sample), drawn in
 // parallel ahead of the sequential rollout (the same counter-based stream); also
-// resets the per-position distance outputs, the call's cull item counter and the
-// spatial sort's bounding box.
+// resets the per-position distance outputs (and nearest records), the call's cull
+// item counter and the spatial sort's bounding box.
 // Blocks from noise_blocks on compute the tile and sub-tile bounding boxes of the
 // two-pass sets' clouds instead (independent work, one launch fewer).
 __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__ probs, int n,
@@ -91,6 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   AERO_GLOBAL unsigned* __restrict__ mind2 = global_ptr(P.mind2);
   AERO_GLOBAL unsigned* __restrict__ out_slot = global_ptr(P.out_slot);
   AERO_GLOBAL int32_t* __restrict__ nidx = global_ptr(P.nidx);
+  AERO_GLOBAL unsigned long long* __restrict__ nn = global_ptr(P.nn);
   if (local == 0) {
     AERO_GLOBAL int32_t* __restrict__ item_count = global_ptr(P.item_count);
     AERO_GLOBAL unsigned* __restrict__ sort_box = global_ptr(P.sort_box);
@@ -108,8 +109,9 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   for (int c = 0; c < 4; ++c) noise[(row * 4 + c) * K + k] = nz[c];
   // per-position outputs of this call start empty
   mind2[local] = kInfBits;
-  if (out_slot) out_slot[local] = kInfBits;
+  if (out_slot) out_slot[local] = kInfBits;  // by slot: the slots are a permutation
   if (nidx) nidx[local] = -1;
+  if (nn) nn[local] = ~0ull;
 }
 
 // Merge the position bounds of a wave's rollouts into their problems' sort boxes
