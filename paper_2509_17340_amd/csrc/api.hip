@@ -309,11 +309,11 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   pl.items = cur.take<int2>(cap);
   pl.hitf = cur.take<unsigned char>(cap);
   pl.item_count = cur.take<int32_t>(1);
-  // hit words: item i's at i * qpbA / 32.  A call whose marked items all had their
-  // words would need cap * 16 words (cap counts 512-position blocks); this holds a
-  // sixteenth of that, and at least 4 MiB: items past it are taken whole by pass B
+  // hit words: item i's at i * qpbA / 32.  A call whose every listable item had its
+  // words would need cap * 16 words (cap counts 512-position blocks); this holds an
+  // eighth of that, and at least 4 MiB: items past it are taken whole by pass B
   // (every query of the block), which is exact, only slower.
-  pl.mask_words = cap > 0 ? std::max<int64_t>(int64_t(1) << 20, cap) : 0;
+  pl.mask_words = cap > 0 ? std::max<int64_t>(int64_t(1) << 20, 2 * cap) : 0;
   pl.hmask = cur.take<uint32_t>(pl.mask_words);
   int64_t sort_blocks = 0, eb = 0, sb = 0, rb = 0, qbb = 0, tb = 0;
   for (int b = 0; b < n; ++b) {

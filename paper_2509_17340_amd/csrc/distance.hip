@@ -138,12 +138,19 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
 // for its hit words).  A query's nearest point within d_max lies in such a sub-tile
 // (its pass-A value there is under the bound), and every other point of the reach is
 // farther than d_max, so the minimum over the evaluated pairs is exact below d_max.
-// Persistent grid, items strided over the workgroups; per item the sub-tile is
-// staged in LDS, wave 0 lists the hit queries from the item's words, and the listed
-// queries x points are spread over the threads: R queries per thread when kBlock or
-// more are listed, else each listed query's points split among kBlock / h threads.
-// Results combine through atomicMin on float bits (and on (d^2 bits, index) pairs for
-// the nearest index, lowest index on ties), so they are order independent.
+//
+// Each wave works alone (no workgroup barriers): waves take the marked items in turn
+// (items strided over every wave of the grid), list the item's hit queries from its
+// words into the wave's own LDS row, hold up to kQueriesPerLane of them per lane and
+// run them against the sub-tile's points, which every lane reads at the same address:
+// through the constant address space (the points are not written while the kernel
+// runs), so they arrive as scalar loads into SGPRs and cost no LDS bandwidth and no
+// vector-memory issue.  Results combine through atomicMin on float bits (and on
+// (d^2 bits, index) pairs for the nearest index, lowest index on ties), so they are
+// order independent.
+typedef const __attribute__((address_space(4))) float cfloat;
+typedef const __attribute__((address_space(4))) int32_t cint;
+
 template <bool kIdx>
 __device__ inline void pass_b_result(const QuerySet& S, int64_t slot, float best, int32_t bidx) {
   atomicMin(S.out_slot + slot, __float_as_uint(best));
@@ -152,47 +159,38 @@ __device__ inline void pass_b_result(const QuerySet& S, int64_t slot, float best
                                (unsigned long long)(unsigned)bidx);
 }
 
-// Direct form of one query against tile points [p0, p1) (p1 - p0 even, or the tile
-// holds a far record at p1).
-template <bool kIdx>
-__device__ inline void pass_b_scan(const float4* tile, int p0, int p1, float px, float py,
-                                   float pz, float& best, int32_t& bidx) {
-  for (int j = p0; j < p1; j += 2) {
-    const float4 a = tile[j];
-    const float4 c = tile[j + 1];
-    const float ax = px - a.x, ay = py - a.y, az = pz - a.z;
-    const float cx = px - c.x, cy = py - c.y, cz = pz - c.z;
-    const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
-    const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-    if constexpr (kIdx) {
-      const int32_t ia = __float_as_int(a.w), ic = __float_as_int(c.w);
-      if (da < best || (da == best && ia < bidx)) {
-        best = da;
-        bidx = ia;
-      }
-      if (dc < best || (dc == best && ic < bidx)) {
-        best = dc;
-        bidx = ic;
-      }
+// One point (x, y, z, index) against the R queries of this lane.
+template <int R, bool kIdx>
+__device__ __forceinline__ void pass_b_point(float ox, float oy, float oz, int32_t oi,
+                                             const float* px, const float* py, const float* pz,
+                                             float* best, int32_t* bidx) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float ax = px[r] - ox, ay = py[r] - oy, az = pz[r] - oz;
+    const float d = fmaf(az, az, fmaf(ay, ay, ax * ax));
+    if constexpr (kIdx) {  // branch-free: no short-circuit evaluation
+      const bool take = (d < best[r]) | ((d == best[r]) & (oi < bidx[r]));
+      bidx[r] = take ? oi : bidx[r];
+      best[r] = take ? d : best[r];
     } else {
-      best = min3f(best, da, dc);
+      best[r] = fminf(best[r], d);
     }
   }
 }
 
-// R listed queries per thread (the k-th listed query goes to thread k % kBlock), all
-// n2 points of the tile.
-template <int R, bool kIdx>
-__device__ inline void pass_b_rows(const QuerySet& S, int64_t slot0, int h,
-                                   const uint16_t* qlist, const float4* tile, int n2) {
-  const int tid = threadIdx.x;
+// Listed queries k = k0 + r * 64 + lane (r < R, k < h) of the item against its n points
+// (sorted records, or the raw cloud from point g0 on).
+template <int R, bool kIdx, bool kSorted>
+__device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, int h,
+                                      const uint16_t* qlist, int64_t g0, int n) {
+  const int lane = threadIdx.x & 63;
   const int64_t Q = S.Q;
   float px[R], py[R], pz[R], best[R];
   int32_t bidx[R];
   int64_t sl[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int k = r * kBlock + tid;
+    const int k = k0 + r * 64 + lane;
     sl[r] = k < h ? slot0 + qlist[k] : -1;
     const int64_t q = sl[r] >= 0 ? sl[r] : slot0;  // always a valid position
     px[r] = S.sp[q];
@@ -201,65 +199,54 @@ __device__ inline void pass_b_rows(const QuerySet& S, int64_t slot0, int h,
     best[r] = __uint_as_float(kInfBits);
     bidx[r] = 0x7fffffff;
   }
-#pragma unroll 2
-  for (int j = 0; j < n2; j += 2) {
-    const float4 a = tile[j];
-    const float4 c = tile[j + 1];
+  if constexpr (kSorted) {
+    cfloat* rec = (cfloat*)(S.scloud + g0);  // (x, y, z, index bits) per point
+    cint* irec = (cint*)(S.scloud + g0);
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float ax = px[r] - a.x, ay = py[r] - a.y, az = pz[r] - a.z;
-      const float cx = px[r] - c.x, cy = py[r] - c.y, cz = pz[r] - c.z;
-      const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
-      const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-      if constexpr (kIdx) {
-        const int32_t ia = __float_as_int(a.w), ic = __float_as_int(c.w);
-        if (da < best[r] || (da == best[r] && ia < bidx[r])) {
-          best[r] = da;
-          bidx[r] = ia;
-        }
-        if (dc < best[r] || (dc == best[r] && ic < bidx[r])) {
-          best[r] = dc;
-          bidx[r] = ic;
-        }
-      } else {
-        best[r] = min3f(best[r], da, dc);
-      }
+      for (int u = 0; u < 4; ++u)
+        pass_b_point<R, kIdx>(rec[4 * (j + u)], rec[4 * (j + u) + 1], rec[4 * (j + u) + 2],
+                              irec[4 * (j + u) + 3], px, py, pz, best, bidx);
     }
+    for (; j < n; ++j)
+      pass_b_point<R, kIdx>(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], irec[4 * j + 3], px, py,
+                            pz, best, bidx);
+  } else {
+    cfloat* rec = (cfloat*)(S.cloud + 3 * g0);
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        pass_b_point<R, kIdx>(rec[3 * (j + u)], rec[3 * (j + u) + 1], rec[3 * (j + u) + 2],
+                              (int32_t)(g0 + j + u), px, py, pz, best, bidx);
+    }
+    for (; j < n; ++j)
+      pass_b_point<R, kIdx>(rec[3 * j], rec[3 * j + 1], rec[3 * j + 2], (int32_t)(g0 + j), px,
+                            py, pz, best, bidx);
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (sl[r] >= 0) pass_b_result<kIdx>(S, sl[r], best[r], bidx[r]);
 }
 
-template <bool kIdx>
-__device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int h, const uint16_t* qlist,
-                                   const float4* tile, int n) {
-  const int tid = threadIdx.x;
-  const int n2 = (n + 1) & ~1;  // even: the loops take points in pairs
-  if (h < kBlock) {
-    // each listed query's points split among `sp` threads, in even-sized parts
-    const int sp = kBlock / h;
-    if (tid >= h * sp) return;
-    const int k = tid % h, part = tid / h;
-    const int half = n2 / 2;
-    const int p0 = 2 * (part * half / sp), p1 = 2 * ((part + 1) * half / sp);
-    const int64_t slot = slot0 + qlist[k];
-    const int64_t Q = S.Q;
-    float best = __uint_as_float(kInfBits);
-    int32_t bidx = 0x7fffffff;
-    pass_b_scan<kIdx>(tile, p0, p1, S.sp[slot], S.sp[Q + slot], S.sp[2 * Q + slot], best, bidx);
-    if (p0 < p1) pass_b_result<kIdx>(S, slot, best, bidx);
-    return;
-  }
-  switch ((h + kBlock - 1) / kBlock) {
-    case 1: pass_b_rows<1, kIdx>(S, slot0, h, qlist, tile, n2); break;
-    case 2: pass_b_rows<2, kIdx>(S, slot0, h, qlist, tile, n2); break;
-    case 3: pass_b_rows<3, kIdx>(S, slot0, h, qlist, tile, n2); break;
-    case 4: pass_b_rows<4, kIdx>(S, slot0, h, qlist, tile, n2); break;
-    case 5: pass_b_rows<5, kIdx>(S, slot0, h, qlist, tile, n2); break;
-    case 6: pass_b_rows<6, kIdx>(S, slot0, h, qlist, tile, n2); break;
-    case 7: pass_b_rows<7, kIdx>(S, slot0, h, qlist, tile, n2); break;
-    default: pass_b_rows<kQueriesPerLane, kIdx>(S, slot0, h, qlist, tile, n2); break;
+template <bool kIdx, bool kSorted>
+__device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int h,
+                                   const uint16_t* qlist, int64_t g0, int n) {
+  constexpr int kChunk = 64 * kQueriesPerLane;
+  for (int k0 = 0; k0 < h; k0 += kChunk) {  // wave-uniform
+    switch (min((h - k0 + 63) / 64, kQueriesPerLane)) {
+      case 1: pass_b_queries<1, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+      case 2: pass_b_queries<2, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+      case 3: pass_b_queries<3, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+      case 4: pass_b_queries<4, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+      case 5: pass_b_queries<5, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+      case 6: pass_b_queries<6, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+      case 7: pass_b_queries<7, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+      default:
+        pass_b_queries<kQueriesPerLane, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n);
+        break;
+    }
   }
 }
 
@@ -267,65 +254,68 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(const QuerySet* __restrict__ 
                                                    const int2* __restrict__ items,
                                                    const int32_t* __restrict__ item_count,
                                                    const unsigned char* __restrict__ hitf) {
-  __shared__ float4 tile[kSubPts];
-  __shared__ uint16_t qlist[kQueriesPerBlock];  // listed queries (block-local index)
-  __shared__ int htot;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ uint16_t qlists[kBlock / 64][kQueriesPerBlock];  // each wave's own row
+  // the wave index as a wave-uniform value, so that everything derived from it (the
+  // item, its set, the point addresses) stays in scalar registers
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint16_t* qlist = qlists[w];
   const int64_t total = *item_count;
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
   const uint32_t* __restrict__ hmask = sets[0].hmask;
   const int64_t mask_words = sets[0].mask_words;
   SetCache cache{0, 0, 0};
-  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    if (!hitf[it]) continue;  // block-uniform
+  for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + w; it < total; it += n_waves) {
+    if (!hitf[it]) continue;  // wave-uniform
     const int2 e = items[it];
     const int s = set_of(sets, n_sets, e.x, cache);
     const QuerySet S = sets[s];  // a copy: the stores below cannot alias it
-    if (!block_of(S, e.x)) continue;
+    if (!block_of(S, e.x) || S.n_points <= 0) continue;
     const int64_t qb = e.x - S.qb_base;
     const int64_t slot0 = qb * S.qpbA;
     const int nq = (int)min<int64_t>(S.qpbA, S.Q - slot0);  // queries of the block
     const int W = S.qpbA / 32;
-    float x, y, z;
-    int32_t idx;
-    bool in;
-    int n;
-    item_point(S, (unsigned)e.y, x, y, z, idx, in, n);
-    // every thread writes its own slot (a far record past the sub-tile's points), so an
-    // odd count still leaves a valid record after the last point
-    tile[tid] = in ? make_float4(x, y, z, __int_as_float(idx))
-                   : make_float4(kFar, kFar, kFar, __int_as_float(0x7fffffff));
-    if (w == 0) {
-      // bits of the block's existing queries in this lane's word
-      const int lo = lane * 32;
-      const uint32_t valid =
-          lo >= nq ? 0u : (nq - lo >= 32 ? 0xffffffffu : (1u << (nq - lo)) - 1u);
-      uint32_t word = 0;
-      if (lane < W)  // without room for the item's words: every query of the block
-        word = (it + 1) * W <= mask_words ? hmask[it * W + lane] & valid : valid;
-      const int c = __popc(word);
-      int incl = c;  // inclusive scan over the wave
+    const unsigned ys = (unsigned)e.y;
+    const int64_t g0 = (int64_t)(ys & 0x7fffffffu) * kSubPts;
+    const bool srt = (ys >> 31) != 0 && S.scloud;
+    const int n = g0 < S.n_points ? (int)min<int64_t>(kSubPts, S.n_points - g0) : 0;
+    if (n <= 0) continue;
+    // list the hit queries: lane j holds word j (bits of existing queries only)
+    const int lo = lane * 32;
+    const uint32_t valid = lo >= nq ? 0u : (nq - lo >= 32 ? 0xffffffffu : (1u << (nq - lo)) - 1u);
+    uint32_t word = 0;
+    if (lane < W)  // without room for the item's words: every query of the block
+      word = (it + 1) * W <= mask_words ? hmask[it * W + lane] & valid : valid;
+    const int c = __popc(word);
+    int incl = c;  // inclusive scan over the wave
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y2 = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y2;
-      }
-      int at = incl - c;
-      while (word) {
-        const int b = __ffs(word) - 1;
-        word &= word - 1u;
-        qlist[at++] = (uint16_t)(lo + b);
-      }
-      if (lane == 63) htot = incl;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y2 = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y2;
     }
-    __syncthreads();
-    const int h = min(htot, nq);
-    if (h > 0 && n > 0) {
-      if (S.nn)
-        pass_b_item<true>(S, slot0, h, qlist, tile, n);
-      else
-        pass_b_item<false>(S, slot0, h, qlist, tile, n);
+    int at = incl - c;
+    while (word) {
+      const int b = __ffs(word) - 1;
+      word &= word - 1u;
+      qlist[at++] = (uint16_t)(lo + b);
     }
-    __syncthreads();  // the next item stages over the tile and the list
+    const int h = __shfl(incl, 63, 64);
+    // the row is written and read by this wave only: order its LDS accesses
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (h > 0) {
+      if (S.nn) {
+        if (srt) pass_b_item<true, true>(S, slot0, h, qlist, g0, n);
+        else pass_b_item<true, false>(S, slot0, h, qlist, g0, n);
+      } else {
+        if (srt) pass_b_item<false, true>(S, slot0, h, qlist, g0, n);
+        else pass_b_item<false, false>(S, slot0, h, qlist, g0, n);
+      }
+    }
+    // the next item's list overwrites the row
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
