@@ -273,10 +273,11 @@ hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
 hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* items,
                                 const int32_t* item_count, unsigned char* hitf, int64_t max_items,
                                 int variant, hipStream_t s);
-// Pass B over the marked items (the hit words of every set of the call share one array).
+// Pass B over the marked items (the hit words of every set of the call share one array);
+// track_nearest: some set keeps nearest indices (nn).
 hipError_t launch_pass_b(const QuerySet* d_sets, int n_sets, const int2* items,
                          const int32_t* item_count, const unsigned char* hitf, int64_t max_items,
-                         hipStream_t s);
+                         bool track_nearest, hipStream_t s);
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n, hipStream_t s);
 hipError_t launch_adjoint(const DevProblem* d_prob, const DevParams& prm, int64_t samples,
                           double* ckpt, double* seg, double* gsamp, hipStream_t s);

@@ -493,7 +493,8 @@ hipError_t run_distance(const MppiPlan& pl, int n, int variant, hipEvent_t* tev,
   if (he == hipSuccess && tev) he = hipEventRecord(tev[1], s);
   if (he == hipSuccess && pl.item_cap > 0)
     he = timed(AERO_K_MIN_DIST_EXACT, s, [&] {
-      return launch_pass_b(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap, s);
+      return launch_pass_b(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap,
+                           pl.any_nn, s);
     });
   return he;
 }
@@ -536,6 +537,7 @@ void plan_backward(const aero_problem* h, char* ws, float d_max, BackwardPlan& b
       qs.nn = bp.nn;
       qs.nidx = bp.nidx;
       d.nn = bp.nn;  // reset by the noise kernel
+      bp.fwd.any_nn = true;
     }
   }
 }

@@ -179,23 +179,25 @@ __device__ __forceinline__ void pass_b_point(float ox, float oy, float oz, int32
 }
 
 // Listed queries k = k0 + r * 64 + lane (r < R, k < h) of the item against its n points
-// (sorted records, or the raw cloud from point g0 on).
+// (sorted records, or the raw cloud from point g0 on).  Points go U at a time (fewer
+// when R is large, so that the unrolled differences stay within the register budget).
 template <int R, bool kIdx, bool kSorted>
 __device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, int h,
                                       const uint16_t* qlist, int64_t g0, int n) {
+  constexpr int U = R <= 2 ? 4 : 2;
   const int lane = threadIdx.x & 63;
   const int64_t Q = S.Q;
+  const float* __restrict__ sp = S.sp;
   float px[R], py[R], pz[R], best[R];
-  int32_t bidx[R];
-  int64_t sl[R];
+  int32_t bidx[R], jq[R];  // jq: block-local query index, -1 for an idle row
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int k = k0 + r * 64 + lane;
-    sl[r] = k < h ? slot0 + qlist[k] : -1;
-    const int64_t q = sl[r] >= 0 ? sl[r] : slot0;  // always a valid position
-    px[r] = S.sp[q];
-    py[r] = S.sp[Q + q];
-    pz[r] = S.sp[2 * Q + q];
+    jq[r] = k < h ? (int32_t)qlist[k] : -1;
+    const int64_t q = slot0 + (jq[r] >= 0 ? jq[r] : 0);  // always a valid position
+    px[r] = sp[q];
+    py[r] = sp[Q + q];
+    pz[r] = sp[2 * Q + q];
     best[r] = __uint_as_float(kInfBits);
     bidx[r] = 0x7fffffff;
   }
@@ -203,9 +205,9 @@ __device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, 
     cfloat* rec = (cfloat*)(S.scloud + g0);  // (x, y, z, index bits) per point
     cint* irec = (cint*)(S.scloud + g0);
     int j = 0;
-    for (; j + 4 <= n; j += 4) {
+    for (; j + U <= n; j += U) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < U; ++u)
         pass_b_point<R, kIdx>(rec[4 * (j + u)], rec[4 * (j + u) + 1], rec[4 * (j + u) + 2],
                               irec[4 * (j + u) + 3], px, py, pz, best, bidx);
     }
@@ -215,9 +217,9 @@ __device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, 
   } else {
     cfloat* rec = (cfloat*)(S.cloud + 3 * g0);
     int j = 0;
-    for (; j + 4 <= n; j += 4) {
+    for (; j + U <= n; j += U) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < U; ++u)
         pass_b_point<R, kIdx>(rec[3 * (j + u)], rec[3 * (j + u) + 1], rec[3 * (j + u) + 2],
                               (int32_t)(g0 + j + u), px, py, pz, best, bidx);
     }
@@ -227,7 +229,7 @@ __device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, 
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (sl[r] >= 0) pass_b_result<kIdx>(S, sl[r], best[r], bidx[r]);
+    if (jq[r] >= 0) pass_b_result<kIdx>(S, slot0 + jq[r], best[r], bidx[r]);
 }
 
 template <bool kIdx, bool kSorted>
@@ -250,7 +252,14 @@ __device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int h,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
+// kIdx: the call keeps nearest indices (some set has nn; the index-tracking loops need
+// more registers, so the plain forward runs its own instantiation).
+#ifndef AERO_PASS_B_WPE
+#define AERO_PASS_B_WPE 8  // waves per SIMD (at most 64 VGPRs): measured fastest
+#endif
+template <bool kIdx>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AERO_PASS_B_WPE))) void
+k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
                                                    const int2* __restrict__ items,
                                                    const int32_t* __restrict__ item_count,
                                                    const unsigned char* __restrict__ hitf) {
@@ -304,9 +313,9 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(const QuerySet* __restrict__ 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (h > 0) {
-      if (S.nn) {
-        if (srt) pass_b_item<true, true>(S, slot0, h, qlist, g0, n);
-        else pass_b_item<true, false>(S, slot0, h, qlist, g0, n);
+      if (kIdx && S.nn) {
+        if (srt) pass_b_item<kIdx, true>(S, slot0, h, qlist, g0, n);
+        else pass_b_item<kIdx, false>(S, slot0, h, qlist, g0, n);
       } else {
         if (srt) pass_b_item<false, true>(S, slot0, h, qlist, g0, n);
         else pass_b_item<false, false>(S, slot0, h, qlist, g0, n);
@@ -475,10 +484,13 @@ hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_
 
 hipError_t launch_pass_b(const QuerySet* d_sets, int n_sets, const int2* items,
                          const int32_t* item_count, const unsigned char* hitf, int64_t max_items,
-                         hipStream_t s) {
+                         bool track_nearest, hipStream_t s) {
   if (max_items > 0) {
     const unsigned grid = (unsigned)(max_items < kPersistBlocks ? max_items : kPersistBlocks);
-    k_pass_b<<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
+    if (track_nearest)
+      k_pass_b<true><<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
+    else
+      k_pass_b<false><<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
   }
   return hipGetLastError();
 }
