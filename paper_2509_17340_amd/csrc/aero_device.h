@@ -419,13 +419,14 @@ __device__ inline void mark_hit(bool hit, unsigned char* hitf, int64_t i) {
   if (hb && (int)(threadIdx.x & 63) == __ffsll((long long)hb) - 1) hitf[i] = 1;
 }
 
-// Bounding boxes of cloud tile `t` (kTilePts consecutive points) and of its kTileSplit
-// sub-tiles, from the raw points ([n][3], c4 == nullptr) or the sorted records (c4).
-// One workgroup of kBlock threads; sub-tile j's points are taken one per thread.
-// Sub-tiles past the end of the cloud are not written.
+// Bounding boxes of cloud tile `t` (kTilePts consecutive points), of its kTileSplit
+// sub-tiles and of their kGroupsPerSub groups of 32 points (gbox, when given), from
+// the raw points ([n][3], c4 == nullptr) or the sorted records (c4).  One workgroup of
+// kBlock threads; sub-tile j's points are taken one per thread.  Sub-tiles past the
+// end of the cloud are not written; a group without points gets an empty box.
 __device__ inline void tile_boxes(const float* __restrict__ c3, const float4* __restrict__ c4,
                                   int64_t n_points, int64_t t, float* __restrict__ tbox,
-                                  float* __restrict__ sbox) {
+                                  float* __restrict__ sbox, float* __restrict__ gbox) {
   static_assert(kSubPts == kBlock, "one point per thread");
   constexpr int kW = kBlock / 64;
   __shared__ float red[kTileSplit][6][kW];
@@ -450,8 +451,20 @@ __device__ inline void tile_boxes(const float* __restrict__ c3, const float4* __
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      lo[a] = wave_minf(lo[a]);
-      hi[a] = wave_maxf(hi[a]);
+      // the 32-point group of each half wave first, then the whole wave
+#pragma unroll
+      for (int o = 1; o < 32; o <<= 1) {
+        lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+        hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+      }
+      const int64_t sub = t * kTileSplit + j;
+      if (gbox && (lane & 31) == 0 && sub * kSubPts < n_points) {
+        float* gb = gbox + 6 * (sub * kGroupsPerSub + 2 * w + (lane >> 5));
+        gb[a] = lo[a];
+        gb[3 + a] = hi[a];
+      }
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], 32, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], 32, 64));
       if (lane == 0) {
         red[j][a][w] = lo[a];
         red[j][3 + a][w] = hi[a];

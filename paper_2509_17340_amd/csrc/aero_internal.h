@@ -25,6 +25,7 @@ constexpr int kBoxCopies = 16;
 constexpr int kBoxStride = 64;  // words per copy
 constexpr int kTileSplit = 4;                            // sub-tiles per tile
 constexpr int kSubPts = kTilePts / kTileSplit;           // cloud points per sub-tile (work unit)
+constexpr int kGroupsPerSub = kSubPts / 32;              // 32-point groups per sub-tile
 constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
 constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
 static_assert(kSubPts == kBlock, "a sub-tile is staged one point per thread");
@@ -137,10 +138,12 @@ struct QuerySet {
                          //   pass-A squared distance
   float* tbox;           // [n_tiles][6] tile bounding boxes (lo, hi) of the raw cloud
   float* sbox;           // [n_sub][6] sub-tile bounding boxes of the raw cloud
+  float* gbox;           // [n_sub * kGroupsPerSub][6] boxes of their 32-point groups
   const float4* scloud;  // [n_points] the cloud in Morton order (x, y, z, original
                          //   index bits), or nullptr: raw order only
-  float* stbox;          // [n_tiles][6], [n_sub][6]: boxes of the sorted cloud
-  float* ssbox;
+  float* stbox;          // [n_tiles][6], [n_sub][6], [n_sub * kGroupsPerSub][6]: boxes
+  float* ssbox;          //   of the sorted cloud
+  float* sgbox;
   int2* items;           // the call's item list: (global query block, sub-tile | order
                          //   << 31); a block's items are consecutive
   int32_t* item_count;   // entries of `items` (zeroed by the noise kernel)

@@ -379,6 +379,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.binfo = cur.take<float4>(max_blocks);
       qs.tbox = cur.take<float>(6 * n_tiles);
       qs.sbox = cur.take<float>(6 * n_sub);
+      qs.gbox = cur.take<float>(6 * n_sub * kGroupsPerSub);
       qs.items = pl.items;
       qs.item_count = pl.item_count;
       qs.hitf = pl.hitf;
@@ -435,6 +436,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.scloud = sc.sc;
       qs.stbox = cur.take<float>(6 * n_tiles);
       qs.ssbox = cur.take<float>(6 * n_sub);
+      qs.sgbox = cur.take<float>(6 * n_sub * kGroupsPerSub);
       pl.any_scloud = true;
     } else {
       sc.block_base = sort_blocks;

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_sorted_boxes(const QuerySet* __restr
   const int s = find_owner(sets, n_sets, t, [](const QuerySet& q) { return q.tile_base; });
   const QuerySet& S = sets[s];
   if (!S.scloud) return;  // block-uniform
-  tile_boxes(nullptr, S.scloud, S.n_points, t - S.tile_base, S.stbox, S.ssbox);
+  tile_boxes(nullptr, S.scloud, S.n_points, t - S.tile_base, S.stbox, S.ssbox, S.sgbox);
 }
 
 __device__ inline int wave_sum_i(int v) {

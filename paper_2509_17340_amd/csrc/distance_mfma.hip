@@ -99,6 +99,10 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
   int64_t cur = -1;
   unsigned okm = 0;  // bit b: column block b's query of this lane exists
   float c[3] = {0.0f, 0.0f, 0.0f}, thr = 0.0f;
+  // the bounding box of this wave's queries and the block's reach: a 32-point group of
+  // a sub-tile whose box lies beyond it cannot hold a point whose value falls under
+  // the bound, so the wave skips it
+  float wlo[3] = {0.0f, 0.0f, 0.0f}, whi[3] = {0.0f, 0.0f, 0.0f}, wlim = 0.0f;
   half8 bop[COLS];
   float pp[COLS];
   // the hit words of every set of the call share one array
@@ -118,6 +122,8 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
     const int64_t gqb = it.x;
     const int icnt = cnt;
     const bool ivalid = valid;
+    const unsigned iys = (unsigned)it.y;
+    const int ins = ns;
     if (ivalid && gqb != cur) {  // block-uniform
       const QuerySet& S = sets[ns];
       const int64_t qb = gqb - S.qb_base;
@@ -129,6 +135,12 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
       c[2] = bi.z;
       thr = bi.w;
       const int64_t slot0 = qb * QPB + w * (32 * COLS) + col;
+      wlim = S.cull ? reach_limit(thr, S.d_max) : INFINITY;  // brute force: every group
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        wlo[a] = INFINITY;
+        whi[a] = -INFINITY;
+      }
       okm = 0;
 #pragma unroll
       for (int b = 0; b < COLS; ++b) {
@@ -136,7 +148,16 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
         const bool ok = slot < Q;
         okm |= ok ? 1u << b : 0u;
         const int64_t qs = ok ? slot : 0;  // positions in slot order
-        const float x = sp[qs] - c[0], y = sp[Q + qs] - c[1], z = sp[2 * Q + qs] - c[2];
+        const float ax = sp[qs], ay = sp[Q + qs], az = sp[2 * Q + qs];
+        if (ok) {
+          wlo[0] = fminf(wlo[0], ax);
+          wlo[1] = fminf(wlo[1], ay);
+          wlo[2] = fminf(wlo[2], az);
+          whi[0] = fmaxf(whi[0], ax);
+          whi[1] = fmaxf(whi[1], ay);
+          whi[2] = fmaxf(whi[2], az);
+        }
+        const float x = ax - c[0], y = ay - c[1], z = az - c[2];
         pp[b] = fmaf(z, z, fmaf(y, y, x * x));
         _Float16 xh, xl, yh, yl, zh, zl;
         split_half(x, xh, xl);
@@ -155,6 +176,11 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
         if (!ok) v = (half8){};
         bop[b] = v;
       }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        wlo[a] = wave_minf(wlo[a]);
+        whi[a] = wave_maxf(whi[a]);
+      }
       cur = gqb;
     }
     if (ivalid) tile[buf][tid] = point_record(ox - c[0], oy - c[1], oz - c[2], oin);
@@ -172,8 +198,17 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
     float tt[COLS];
 #pragma unroll
     for (int b = 0; b < COLS; ++b) tt[b] = kF16FarT;
+    // the item's 32-point groups within reach of this wave's queries (lane q tests
+    // group q; bit q of the ballot)
+    const QuerySet& IS = sets[ins];
+    const float* gbs = ((iys >> 31) && IS.scloud ? IS.sgbox : IS.gbox) +
+                       6 * (int64_t)(iys & 0x7fffffffu) * kGroupsPerSub;
+    const uint64_t keep = __ballot(lane < kGroupsPerSub && lane * 32 < icnt &&
+                                   box_dist2(gbs + 6 * min(lane, kGroupsPerSub - 1), wlo, whi) <=
+                                       wlim);
     const int cnt32 = (icnt + 31) & ~31;  // groups of 32 points; the padding is far
     for (int g = 0; g < cnt32; g += 32) {
+      if (!((keep >> (g >> 5)) & 1ull)) continue;  // wave-uniform
       const half8 a = tl[g + col];
       // kF16Pipe products in flight: the minima of one overlap the next MFMA
 #pragma unroll

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
     const int64_t t = (int64_t)blockIdx.x - noise_blocks;
     const int si = find_owner(sets, n_sets, t, [](const QuerySet& q) { return q.tile_base; });
     const QuerySet& S = sets[si];
-    tile_boxes(S.cloud, nullptr, S.n_points, t - S.tile_base, S.tbox, S.sbox);
+    tile_boxes(S.cloud, nullptr, S.n_points, t - S.tile_base, S.tbox, S.sbox, S.gbox);
     return;
   }
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
