@@ -542,6 +542,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lean", action="store_true",
                     help="headline only (no named legs, no CPU baseline)")
+    ap.add_argument("--only", choices=("ensemble", "batched", "adjoint", "paper"),
+                    help="run one named leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -550,6 +552,14 @@ def main():
     K_steps, W = max(1, args.steps), max(0, args.warmup)
     n_total = max(args.poses, K_steps)
     workers = pool_size()
+    if args.only:
+        from fixtures import make_ensemble_problem
+        leg = {"ensemble": lambda: bench_ensemble(make_ensemble_problem(), K_steps, W),
+               "batched": lambda: bench_batched(max(1, args.batched)),
+               "adjoint": lambda: bench_adjoint(make_ensemble_problem()),
+               "paper": lambda: {"K128": bench_paper_point(128), "K256": bench_paper_point(256)}}
+        print(json.dumps({"leg": args.only, **leg[args.only]()}))
+        return
 
     # fixtures on the host pool, before anything touches the GPU
     t0 = time.perf_counter()

@@ -232,11 +232,13 @@ __device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, 
     if (jq[r] >= 0) pass_b_result<kIdx>(S, slot0 + jq[r], best[r], bidx[r]);
 }
 
+// Listed queries [k0, k1) of the item, kQueriesPerLane rows of 64 at a time.
 template <bool kIdx, bool kSorted>
-__device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int h,
+__device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int k0, int k1,
                                    const uint16_t* qlist, int64_t g0, int n) {
   constexpr int kChunk = 64 * kQueriesPerLane;
-  for (int k0 = 0; k0 < h; k0 += kChunk) {  // wave-uniform
+  const int h = k1;
+  for (; k0 < k1; k0 += kChunk) {  // wave-uniform
     switch (min((h - k0 + 63) / 64, kQueriesPerLane)) {
       case 1: pass_b_queries<1, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
       case 2: pass_b_queries<2, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
@@ -273,7 +275,18 @@ k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
   const uint32_t* __restrict__ hmask = sets[0].hmask;
   const int64_t mask_words = sets[0].mask_words;
   SetCache cache{0, 0, 0};
-  for (int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + w; it < total; it += n_waves) {
+  // Work units: part `part` of item it covers the item's listed queries
+  // [part * 64 urows, (part + 1) * 64 urows).  Whole items (8 rows per unit, the
+  // most a lane holds) while the items outnumber the waves enough; smaller parts
+  // when there are too few items to keep every wave busy.
+  const int rows_per_block = sets[0].qpbA / 64;  // the same block size for every set
+  int urows = kQueriesPerLane;
+  while (urows > 1 && total * ((rows_per_block + urows - 1) / urows) < 4 * n_waves) urows /= 2;
+  const int parts = (rows_per_block + urows - 1) / urows;
+  const int64_t total_units = total * parts;
+  for (int64_t u = (int64_t)blockIdx.x * (kBlock / 64) + w; u < total_units; u += n_waves) {
+    const int64_t it = u / parts;
+    const int part = (int)(u - it * parts);
     if (!hitf[it]) continue;  // wave-uniform
     const int2 e = items[it];
     const int s = set_of(sets, n_sets, e.x, cache);
@@ -312,13 +325,14 @@ k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (h > 0) {
+    const int k0 = part * 64 * urows, k1 = min(h, k0 + 64 * urows);
+    if (k0 < k1) {
       if (kIdx && S.nn) {
-        if (srt) pass_b_item<kIdx, true>(S, slot0, h, qlist, g0, n);
-        else pass_b_item<kIdx, false>(S, slot0, h, qlist, g0, n);
+        if (srt) pass_b_item<kIdx, true>(S, slot0, k0, k1, qlist, g0, n);
+        else pass_b_item<kIdx, false>(S, slot0, k0, k1, qlist, g0, n);
       } else {
-        if (srt) pass_b_item<false, true>(S, slot0, h, qlist, g0, n);
-        else pass_b_item<false, false>(S, slot0, h, qlist, g0, n);
+        if (srt) pass_b_item<false, true>(S, slot0, k0, k1, qlist, g0, n);
+        else pass_b_item<false, false>(S, slot0, k0, k1, qlist, g0, n);
       }
     }
     // the next item's list overwrites the row
