@@ -172,6 +172,41 @@ int aero_partition_anchors(const aero_partition_spec* h_spec, const float* d_clo
                            int32_t* d_fine_idx, int32_t* d_coarse_best, int32_t* d_anchor_cell,
                            int32_t* d_anchor_fine, float* d_anchors, void* stream);
 
+/* One problem of a batched front end: the partition of aero_partition_anchors and the
+ * guides of aero_build_guides (end conditions as there), for one cloud. */
+typedef struct aero_front_end_job {
+  aero_partition_spec spec;  /* grid, anchor block, r_max, ell, p0 (also the guides' start
+                                position) and the device direction tables                */
+  const float* d_cloud;      /* [n_points][3] float32, relative to the drone             */
+  int32_t n_points;
+  float goal_dir[3];         /* zero vector = +x heading                                  */
+  float v0[3], a0[3];        /* the guides' start velocity and acceleration              */
+  float horizon_T;           /* the guides' horizon                                       */
+  const float* d_end_vel;    /* [M][3] or NULL: |v0| unit(anchor - p0)                    */
+  const float* d_end_acc;    /* [M][3] or NULL: 0                                         */
+  double* d_fine_key;        /* outputs, as aero_partition_anchors and aero_build_guides  */
+  int32_t* d_fine_idx;
+  int32_t* d_coarse_best;
+  int32_t* d_anchor_cell;
+  int32_t* d_anchor_fine;
+  float* d_anchors;
+  float* d_coef;             /* [M][3][6]                                                 */
+} aero_front_end_job;
+
+/* Device workspace of aero_front_end for n_jobs problems (0 for n_jobs out of range). */
+size_t aero_front_end_workspace_size(int32_t n_jobs);
+
+/* Partition, anchors and guides of n_jobs problems in three launches (Sec. IV-A,
+ * Sec. IV-B, as aero_partition_anchors followed by aero_build_guides for each job;
+ * bit for bit the same outputs).  Jobs may differ in grid, cloud and anchor block.
+ *   h_jobs  host array [n_jobs], read during the call only
+ *   d_ws    device workspace of aero_front_end_workspace_size(n_jobs) bytes
+ * Errors: AERO_ERR_NULL, AERO_ERR_SHAPE (n_jobs outside [1, AERO_BATCH_MAX], or a job
+ * as aero_partition_anchors / aero_build_guides reject it), AERO_ERR_PARAM,
+ * AERO_ERR_WORKSPACE, AERO_ERR_DEVICE; checked for every job before any launch. */
+int aero_front_end(const aero_front_end_job* h_jobs, int32_t n_jobs, void* d_ws, size_t ws_bytes,
+                   void* stream);
+
 /* Filtered collision set P_f of the collision cost (Sec. IV-C: the closest point of
  * every fine cone of the partition).  out[c] = cloud[fine_idx[c]] in cone order
  * c = 0 .. n_fine-1; a cone without a point holds the sentinel (1e18, 1e18, 1e18),

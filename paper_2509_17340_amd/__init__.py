@@ -20,7 +20,8 @@ __all__ = [
     "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
     "KERNELS", "shift_controls", "step_candidates", "set_pass_a_variant", "pass_a_variant",
-    "set_pass_a_cull", "distance_stats",
+    "set_pass_a_cull", "distance_stats", "FrontEndJob", "front_end_job", "front_end",
+    "front_end_workspace_size",
     "use_library", "accumulate_cloud", "advance_state", "mppi_step_backward_indexed",
 ]
 
@@ -72,6 +73,18 @@ class PartitionSpec(ctypes.Structure):
 
 
 _P = ctypes.c_void_p
+
+
+class FrontEndJob(ctypes.Structure):
+    _fields_ = [
+        ("spec", PartitionSpec), ("d_cloud", _P), ("n_points", ctypes.c_int32),
+        ("goal_dir", ctypes.c_float * 3), ("v0", ctypes.c_float * 3), ("a0", ctypes.c_float * 3),
+        ("horizon_T", ctypes.c_float), ("d_end_vel", _P), ("d_end_acc", _P),
+        ("d_fine_key", _P), ("d_fine_idx", _P), ("d_coarse_best", _P), ("d_anchor_cell", _P),
+        ("d_anchor_fine", _P), ("d_anchors", _P), ("d_coef", _P),
+    ]
+
+
 _SIGS = {
     "aero_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "aero_partition_tables_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
@@ -81,6 +94,8 @@ _SIGS = {
                                               _P]),
     "aero_build_guides": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32,
                                          _P, _P]),
+    "aero_front_end_workspace_size": (ctypes.c_size_t, [ctypes.c_int32]),
+    "aero_front_end": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "aero_mppi_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "aero_select_best": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     "aero_select_best_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
@@ -301,6 +316,43 @@ def build_guides(p0, v0, a0, anchors, horizon_T, M, coef, end_vel=None, end_acc=
     _check(_lib.aero_build_guides(p0.ctypes.data, v0.ctypes.data, a0.ctypes.data, _ptr(anchors),
                                   _ptr(end_vel), _ptr(end_acc), float(horizon_T), int(M),
                                   _ptr(coef), _stream(stream)), "aero_build_guides")
+
+
+def front_end_job(n_az_c, n_el_c, f_a, f_e, M_h, M_v, r_max, ell, p0, d_tables, cloud, goal_dir,
+                  v0, a0, horizon_T, fine_key, fine_idx, coarse_best, anchor_cell, anchor_fine,
+                  anchors, coef, end_vel=None, end_acc=None, n_points=None):
+    """One aero_front_end_job: the arguments of partition_anchors and build_guides
+    (the guides start at p0, the partition's origin)."""
+    j = FrontEndJob()
+    sp = j.spec
+    sp.n_az_c, sp.n_el_c, sp.f_a, sp.f_e = n_az_c, n_el_c, f_a, f_e
+    sp.M_h, sp.M_v, sp.r_max, sp.ell = M_h, M_v, float(r_max), float(ell)
+    sp.p0[:] = [float(v) for v in p0]
+    sp.d_tables = _ptr(d_tables)
+    n = int(cloud.shape[0]) if n_points is None else int(n_points)
+    j.d_cloud = _ptr(cloud) if n > 0 else None
+    j.n_points = n
+    j.goal_dir[:] = [float(v) for v in goal_dir]
+    j.v0[:] = [float(v) for v in v0]
+    j.a0[:] = [float(v) for v in a0]
+    j.horizon_T = float(horizon_T)
+    j.d_end_vel, j.d_end_acc = _ptr(end_vel), _ptr(end_acc)
+    j.d_fine_key, j.d_fine_idx = _ptr(fine_key), _ptr(fine_idx)
+    j.d_coarse_best, j.d_anchor_cell = _ptr(coarse_best), _ptr(anchor_cell)
+    j.d_anchor_fine, j.d_anchors, j.d_coef = _ptr(anchor_fine), _ptr(anchors), _ptr(coef)
+    return j
+
+
+def front_end_workspace_size(n_jobs):
+    return int(_lib.aero_front_end_workspace_size(int(n_jobs)))
+
+
+def front_end(jobs, ws, ws_bytes=None, stream=None):
+    """Partition, anchors and guides of all jobs (FrontEndJob list) in three launches."""
+    arr = (FrontEndJob * max(len(jobs), 1))(*jobs)
+    nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    _check(_lib.aero_front_end(ctypes.cast(arr, ctypes.c_void_p), len(jobs), _ptr(ws), nbytes,
+                               _stream(stream)), "aero_front_end")
 
 
 def workspace_size(which, problems):

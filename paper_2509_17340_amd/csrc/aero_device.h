@@ -146,6 +146,25 @@ __device__ __forceinline__ void rk4(double* x, const double* u, double dt, const
   x[6] *= inv;
 }
 
+// Bytes carried in a kernel argument (descriptors written without a host staging
+// buffer).  16-byte aligned, so that records read in place from the argument are
+// aligned.
+constexpr int kPutBytes = 2048;
+struct alignas(16) PutBlob {
+  uint32_t n;
+  uint32_t pad;
+  unsigned char b[kPutBytes];
+};
+
+// A launch that carries the call's descriptors in `blob` (blob.n > 0) reads them
+// from the argument and has its block 0 write them to the workspace at `dst` for the
+// kernels that follow (no separate upload launch).
+__device__ inline void put_blob(const PutBlob& blob, unsigned char* dst) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(blob.b);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (uint32_t i = threadIdx.x; i < blob.n / 4; i += blockDim.x) d[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
 // The same RK4 step spread over the four lanes of a quad (one rollout per quad).
 // Lane c (0..3) holds the quaternion component q_c (w, x, y, z) and, for c < 3, the

@@ -171,6 +171,27 @@ struct QuerySet {
   int32_t* nidx;           // with nn: [Q] nearest index per query (-1: none evaluated)
 };
 
+// One planning problem's front end (partition, anchors, guides) as the batched
+// front-end kernels read it; built on the host from aero_front_end_job.
+struct FrontJob {
+  const float* tables;      // direction tables of the fine grid (aero_partition_tables)
+  const float* cloud;       // [n_points][3]
+  unsigned long long* key;  // [n_fine] binary64 bits of the cone minima
+  unsigned* idx;            // [n_fine] lowest point index attaining them
+  int32_t* coarse_best;     // [n_coarse]
+  int32_t* anchor_cell;     // [M]
+  int32_t* anchor_fine;     // [M]
+  float* anchors;           // [M][3]
+  float* coef;              // [M][3][6] guide coefficients
+  const float* end_vel;     // optional [M][3]
+  const float* end_acc;     // optional [M][3]
+  int64_t cell_base;        // prefix of fine cells over jobs
+  int64_t block_base;       // prefix of point blocks (kBlock points) over jobs
+  int32_t n_points, n_az_c, n_el_c, f_a, f_e, M_h, M_v, pad;
+  float r_max, ell, T, pad1;
+  float p0[3], goal[3], v0[3], a0[3];
+};
+
 // Parameters promoted once on the host.
 struct DevParams {
   double dt, lambda, mass, gravity;
@@ -253,6 +274,10 @@ hipError_t launch_partition(const aero_partition_spec& spec, const float* cloud,
                             float* anchors, hipStream_t s);
 hipError_t launch_filter_cloud(const float* cloud, int n_points, const int32_t* fine_idx,
                                int n_fine, float* out, hipStream_t s);
+// Partition, anchors and guides of n jobs in three launches (descriptors carried in
+// the first launch's argument when they fit, else uploaded to d_jobs first).
+hipError_t launch_front_end(FrontJob* d_jobs, const FrontJob* h_jobs, int n, int64_t total_cells,
+                            int64_t total_blocks, hipStream_t s);
 hipError_t launch_guides(const double p0[3], const double v0[3], const double a0[3],
                          const float* anchors, const float* end_vel, const float* end_acc,
                          double T, int M, float* coef, hipStream_t s);

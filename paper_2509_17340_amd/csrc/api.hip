@@ -777,11 +777,15 @@ size_t aero_workspace_size(int which, const aero_problem* h, int32_t n) {
   return 0;
 }
 
-int aero_partition_anchors(const aero_partition_spec* spec, const float* d_cloud, int32_t n_points,
-                           const float* h_goal_dir, double* d_fine_key, int32_t* d_fine_idx,
-                           int32_t* d_coarse_best, int32_t* d_anchor_cell, int32_t* d_anchor_fine,
-                           float* d_anchors, void* stream) {
-  if (!spec || !h_goal_dir || !d_fine_key || !d_fine_idx || !d_coarse_best || !d_anchor_cell ||
+namespace {
+
+// Host checks of aero_partition_anchors (outputs and tables present, grid and block in
+// range, finite parameters).
+int check_partition(const aero_partition_spec* spec, const float* d_cloud, int32_t n_points,
+                    const float* goal_dir, const void* d_fine_key, const void* d_fine_idx,
+                    const void* d_coarse_best, const void* d_anchor_cell,
+                    const void* d_anchor_fine, const void* d_anchors) {
+  if (!spec || !goal_dir || !d_fine_key || !d_fine_idx || !d_coarse_best || !d_anchor_cell ||
       !d_anchor_fine || !d_anchors || !spec->d_tables)
     return AERO_ERR_NULL;
   if (n_points < 0) return AERO_ERR_SHAPE;
@@ -795,11 +799,87 @@ int aero_partition_anchors(const aero_partition_spec* spec, const float* d_cloud
     return AERO_ERR_SHAPE;
   if (!finite(spec->r_max) || !(spec->r_max > 0.f) || !finite(spec->ell)) return AERO_ERR_PARAM;
   for (int i = 0; i < 3; ++i)
-    if (!finite(spec->p0[i]) || !finite(h_goal_dir[i])) return AERO_ERR_PARAM;
+    if (!finite(spec->p0[i]) || !finite(goal_dir[i])) return AERO_ERR_PARAM;
+  return AERO_OK;
+}
+
+}  // namespace
+
+int aero_partition_anchors(const aero_partition_spec* spec, const float* d_cloud, int32_t n_points,
+                           const float* h_goal_dir, double* d_fine_key, int32_t* d_fine_idx,
+                           int32_t* d_coarse_best, int32_t* d_anchor_cell, int32_t* d_anchor_fine,
+                           float* d_anchors, void* stream) {
+  const int e = check_partition(spec, d_cloud, n_points, h_goal_dir, d_fine_key, d_fine_idx,
+                                d_coarse_best, d_anchor_cell, d_anchor_fine, d_anchors);
+  if (e) return e;
   const hipStream_t s = (hipStream_t)stream;
   return dev_status(timed(AERO_K_PARTITION, s, [&] {
     return launch_partition(*spec, d_cloud, n_points, h_goal_dir, d_fine_key, d_fine_idx,
                             d_coarse_best, d_anchor_cell, d_anchor_fine, d_anchors, s);
+  }));
+}
+
+
+size_t aero_front_end_workspace_size(int32_t n) {
+  if (n < 1 || n > AERO_BATCH_MAX) return 0;
+  return align_up((size_t)n * sizeof(FrontJob));
+}
+
+int aero_front_end(const aero_front_end_job* h, int32_t n, void* d_ws, size_t ws_bytes,
+                   void* stream) {
+  if (!h) return AERO_ERR_NULL;
+  if (n < 1 || n > AERO_BATCH_MAX) return AERO_ERR_SHAPE;
+  std::vector<FrontJob> jobs(n);
+  int64_t cells = 0, blocks = 0;
+  for (int b = 0; b < n; ++b) {
+    const aero_front_end_job& q = h[b];
+    const int e = check_partition(&q.spec, q.d_cloud, q.n_points, q.goal_dir, q.d_fine_key,
+                                  q.d_fine_idx, q.d_coarse_best, q.d_anchor_cell, q.d_anchor_fine,
+                                  q.d_anchors);
+    if (e) return e;
+    if (!q.d_coef) return AERO_ERR_NULL;
+    if (!finite(q.horizon_T) || !(q.horizon_T > 0.f)) return AERO_ERR_PARAM;
+    for (int i = 0; i < 3; ++i)
+      if (!finite(q.v0[i]) || !finite(q.a0[i])) return AERO_ERR_PARAM;
+    FrontJob& J = jobs[b];
+    J.tables = q.spec.d_tables;
+    J.cloud = q.n_points > 0 ? q.d_cloud : nullptr;
+    J.key = reinterpret_cast<unsigned long long*>(q.d_fine_key);
+    J.idx = reinterpret_cast<unsigned*>(q.d_fine_idx);
+    J.coarse_best = q.d_coarse_best;
+    J.anchor_cell = q.d_anchor_cell;
+    J.anchor_fine = q.d_anchor_fine;
+    J.anchors = q.d_anchors;
+    J.coef = q.d_coef;
+    J.end_vel = q.d_end_vel;
+    J.end_acc = q.d_end_acc;
+    J.cell_base = cells;
+    J.block_base = blocks;
+    J.n_points = q.n_points;
+    J.n_az_c = q.spec.n_az_c;
+    J.n_el_c = q.spec.n_el_c;
+    J.f_a = q.spec.f_a;
+    J.f_e = q.spec.f_e;
+    J.M_h = q.spec.M_h;
+    J.M_v = q.spec.M_v;
+    J.pad = 0;
+    J.r_max = q.spec.r_max;
+    J.ell = q.spec.ell;
+    J.T = q.horizon_T;
+    J.pad1 = 0.f;
+    for (int i = 0; i < 3; ++i) {
+      J.p0[i] = q.spec.p0[i];
+      J.goal[i] = q.goal_dir[i];
+      J.v0[i] = q.v0[i];
+      J.a0[i] = q.a0[i];
+    }
+    cells += (int64_t)q.spec.n_az_c * q.spec.f_a * q.spec.n_el_c * q.spec.f_e;
+    blocks += (q.n_points + kBlock - 1) / kBlock;
+  }
+  if (!d_ws || ws_bytes < aero_front_end_workspace_size(n)) return AERO_ERR_WORKSPACE;
+  const hipStream_t s = (hipStream_t)stream;
+  return dev_status(timed(AERO_K_PARTITION, s, [&] {
+    return launch_front_end(static_cast<FrontJob*>(d_ws), jobs.data(), n, cells, blocks, s);
   }));
 }
 

@@ -33,25 +33,6 @@ __device__ inline void load_rg(const float* qg, double Rg[9]) {
   rotmat(w, x, y, z, Rg);
 }
 
-// Bytes carried in a kernel argument (descriptors written without a host staging
-// buffer).  16-byte aligned, so that records read in place from the argument are
-// aligned.
-constexpr int kPutBytes = 2048;
-struct alignas(16) PutBlob {
-  uint32_t n;
-  uint32_t pad;
-  unsigned char b[kPutBytes];
-};
-
-// A launch that carries the call's descriptors in `blob` (blob.n > 0) reads them
-// from the argument and has its block 0 write them to the workspace at `dst` for the
-// kernels that follow (no separate upload launch).
-__device__ inline void put_blob(const PutBlob& blob, unsigned char* dst) {
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(blob.b);
-  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-  for (uint32_t i = threadIdx.x; i < blob.n / 4; i += blockDim.x) d[i] = src[i];
-}
-
 // The rollout's standard normals for every (instance, step, sample), drawn in
 // parallel ahead of the sequential rollout (the same counter-based stream); also
 // resets the per-position distance outputs (and nearest records), the call's cull

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "aero_device.h"
 #include "aero_internal.h"
@@ -108,9 +109,10 @@ __global__ void k_part_init(unsigned long long* key, unsigned* idx, int n, unsig
 // still left after that issue their own atomic.  The minimum is the same either way.
 constexpr int kConeRounds = 8;
 
-__global__ void k_part_key(const float* __restrict__ cloud, int n_points, const float* tab,
-                           int n_az, int n_el, double rmax2, unsigned long long* key) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void part_key_block(const float* __restrict__ cloud, int n_points,
+                                      const float* tab, int n_az, int n_el, double rmax2,
+                                      unsigned long long* key, int blk) {
+  const int p = blk * blockDim.x + threadIdx.x;
   bool pending = false;
   int c = 0;
   unsigned long long k = ~0ull;
@@ -143,11 +145,16 @@ __global__ void k_part_key(const float* __restrict__ cloud, int n_points, const 
   if (pending) atomicMin(key + c, k);
 }
 
+__global__ void k_part_key(const float* __restrict__ cloud, int n_points, const float* tab,
+                           int n_az, int n_el, double rmax2, unsigned long long* key) {
+  part_key_block(cloud, n_points, tab, n_az, n_el, rmax2, key, blockIdx.x);
+}
+
 // Pass 2: the lowest point index attaining the cone minimum.
 __device__ inline void part_idx_block(const float* __restrict__ cloud, int n_points,
                                       const float* tab, int n_az, int n_el, double rmax2,
-                                      const unsigned long long* key, unsigned* idx) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+                                      const unsigned long long* key, unsigned* idx, int blk) {
+  const int p = blk * blockDim.x + threadIdx.x;
   if (p >= n_points) return;
   const float x = cloud[3 * p], y = cloud[3 * p + 1], z = cloud[3 * p + 2];
   const double r2 = range_key(x, y, z);
@@ -225,23 +232,18 @@ __global__ __launch_bounds__(kBlock) void k_part_idx_anchor(
     float p0y, float p0z, int32_t* anchor_cell, int32_t* anchor_fine, float* anchors,
     int n_idx_blocks) {
   if ((int)blockIdx.x < n_idx_blocks) {  // block-uniform
-    part_idx_block(cloud, n_points, tab, n_az_c * f_a, n_el_c * f_e, rmax2, key, idx);
+    part_idx_block(cloud, n_points, tab, n_az_c * f_a, n_el_c * f_e, rmax2, key, idx, blockIdx.x);
     return;
   }
   coarse_anchor_block(tab, n_az_c, n_el_c, f_a, f_e, key, coarse_best, gx, gy, gz, M_h, M_v, ell,
                       p0x, p0y, p0z, anchor_cell, anchor_fine, anchors);
 }
 
-// Closed-form quintic per (anchor, axis): a0 = p0, a1 = v0, a2 = a0/2 and
+// Closed-form quintic of anchor m, axis ax: a0 = p0, a1 = v0, a2 = a0/2 and
 // a3..a5 from the end conditions.
-__global__ void k_guides(double p0x, double p0y, double p0z, double v0x, double v0y, double v0z,
-                         double a0x, double a0y, double a0z, const float* anchors,
-                         const float* end_vel, const float* end_acc, double T, int M,
-                         float* coef) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= M * 3) return;
-  const int m = id / 3, ax = id % 3;
-  const double p0[3] = {p0x, p0y, p0z}, v0[3] = {v0x, v0y, v0z}, a0[3] = {a0x, a0y, a0z};
+__device__ inline void guide_axis(const double p0[3], const double v0[3], const double a0[3],
+                                  const float* anchors, const float* end_vel,
+                                  const float* end_acc, double T, int m, int ax, float* coef) {
   const double pT = anchors[3 * m + ax];
   double vT, aT;
   if (end_vel) {
@@ -266,6 +268,75 @@ __global__ void k_guides(double p0x, double p0y, double p0z, double v0x, double 
   c[3] = (float)((10.0 * dP - 4.0 * dV + 0.5 * dA) / T3);
   c[4] = (float)((-15.0 * dP + 7.0 * dV - dA) / T4);
   c[5] = (float)((6.0 * dP - 3.0 * dV + 0.5 * dA) / T5);
+}
+
+__global__ void k_guides(double p0x, double p0y, double p0z, double v0x, double v0y, double v0z,
+                         double a0x, double a0y, double a0z, const float* anchors,
+                         const float* end_vel, const float* end_acc, double T, int M,
+                         float* coef) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= M * 3) return;
+  const double p0[3] = {p0x, p0y, p0z}, v0[3] = {v0x, v0y, v0z}, a0[3] = {a0x, a0y, a0z};
+  guide_axis(p0, v0, a0, anchors, end_vel, end_acc, T, id / 3, id % 3, coef);
+}
+
+// ---------------------------------------------------------------------------
+// Batched front end: the same passes for many problems in three launches, with the
+// guides computed by the block that finds a problem's anchors.
+// ---------------------------------------------------------------------------
+__device__ inline const FrontJob& job_of_cell(const FrontJob* jobs, int n, int64_t gid) {
+  return jobs[find_owner(jobs, n, gid, [](const FrontJob& j) { return j.cell_base; })];
+}
+
+__device__ inline double job_rmax2(const FrontJob& J) {
+  return (double)J.r_max * (double)J.r_max;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fe_init(FrontJob* jobs, int n, int64_t total_cells,
+                                                    PutBlob blob) {
+  const FrontJob* jr = jobs;
+  if (blob.n > 0) {  // descriptors in the argument (see put_blob)
+    if (blockIdx.x == 0) put_blob(blob, (unsigned char*)jobs);
+    jr = reinterpret_cast<const FrontJob*>(blob.b);
+  }
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= total_cells) return;
+  const FrontJob& J = job_of_cell(jr, n, gid);
+  const int64_t c = gid - J.cell_base;
+  J.key[c] = (unsigned long long)__double_as_longlong(job_rmax2(J));
+  J.idx[c] = 0xFFFFFFFFu;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fe_key(const FrontJob* __restrict__ jobs, int n) {
+  const int j = find_owner(jobs, n, (int64_t)blockIdx.x,
+                           [](const FrontJob& q) { return q.block_base; });
+  const FrontJob& J = jobs[j];
+  part_key_block(J.cloud, J.n_points, J.tables, J.n_az_c * J.f_a, J.n_el_c * J.f_e, job_rmax2(J),
+                 J.key, (int)(blockIdx.x - J.block_base));
+}
+
+// Blocks below total_blocks: pass 2 of their job; block total_blocks + j: job j's
+// coarse argmax, anchors and guides.
+__global__ __launch_bounds__(kBlock) void k_fe_idx_anchor(const FrontJob* __restrict__ jobs,
+                                                          int n, int64_t total_blocks) {
+  if ((int64_t)blockIdx.x < total_blocks) {  // block-uniform
+    const int j = find_owner(jobs, n, (int64_t)blockIdx.x,
+                             [](const FrontJob& q) { return q.block_base; });
+    const FrontJob& J = jobs[j];
+    part_idx_block(J.cloud, J.n_points, J.tables, J.n_az_c * J.f_a, J.n_el_c * J.f_e,
+                   job_rmax2(J), J.key, J.idx, (int)(blockIdx.x - J.block_base));
+    return;
+  }
+  const FrontJob J = jobs[blockIdx.x - total_blocks];  // a copy: the stores below cannot alias it
+  coarse_anchor_block(J.tables, J.n_az_c, J.n_el_c, J.f_a, J.f_e, J.key, J.coarse_best,
+                      J.goal[0], J.goal[1], J.goal[2], J.M_h, J.M_v, J.ell, J.p0[0], J.p0[1],
+                      J.p0[2], J.anchor_cell, J.anchor_fine, J.anchors);
+  __syncthreads();  // the anchors written above are read by other threads below
+  const int M = J.M_h * J.M_v;
+  const double p0[3] = {J.p0[0], J.p0[1], J.p0[2]}, v0[3] = {J.v0[0], J.v0[1], J.v0[2]},
+               a0[3] = {J.a0[0], J.a0[1], J.a0[2]};
+  for (int id = threadIdx.x; id < 3 * M; id += kBlock)
+    guide_axis(p0, v0, a0, J.anchors, J.end_vel, J.end_acc, (double)J.T, id / 3, id % 3, J.coef);
 }
 
 // P_f: the closest point of every fine cone, in cone order, sentinel when empty.
@@ -312,6 +383,27 @@ hipError_t launch_partition(const aero_partition_spec& spec, const float* cloud,
       cloud, n_points, spec.d_tables, spec.n_az_c, spec.n_el_c, spec.f_a, spec.f_e, rmax2, key,
       idx, coarse_best, goal[0], goal[1], goal[2], spec.M_h, spec.M_v, spec.ell, spec.p0[0],
       spec.p0[1], spec.p0[2], anchor_cell, anchor_fine, anchors, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_end(FrontJob* d_jobs, const FrontJob* h_jobs, int n, int64_t total_cells,
+                            int64_t total_blocks, hipStream_t s) {
+  const size_t bytes = (size_t)n * sizeof(FrontJob);
+  PutBlob blob;
+  blob.n = 0;
+  blob.pad = 0;
+  if (bytes <= (size_t)kPutBytes && total_cells > 0) {
+    blob.n = (uint32_t)bytes;
+    memcpy(blob.b, h_jobs, bytes);
+  } else {
+    const hipError_t e = launch_put_bytes(d_jobs, h_jobs, bytes, s);
+    if (e != hipSuccess) return e;
+  }
+  if (total_cells > 0)
+    k_fe_init<<<(unsigned)((total_cells + kBlock - 1) / kBlock), kBlock, 0, s>>>(d_jobs, n,
+                                                                               total_cells, blob);
+  if (total_blocks > 0) k_fe_key<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_jobs, n);
+  k_fe_idx_anchor<<<(unsigned)(total_blocks + n), kBlock, 0, s>>>(d_jobs, n, total_blocks);
   return hipGetLastError();
 }
 

@@ -7,8 +7,8 @@ import numpy as np
 import torch
 
 from . import (CALL_MPPI_STEP, CALL_SELECT_BEST, Problem, accumulate_cloud, advance_state,
-               build_guides, filtered_cloud, mppi_step, partition_anchors, partition_tables,
-               select_best, workspace_size)
+               build_guides, filtered_cloud, front_end, front_end_job, front_end_workspace_size,
+               mppi_step, partition_tables, select_best, workspace_size)
 
 
 class PlanStep:
@@ -72,6 +72,7 @@ class PlanStep:
         ws = max(workspace_size(CALL_MPPI_STEP, [self.problem]),
                  workspace_size(CALL_SELECT_BEST, [self.problem]))
         self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
+        self.fe_ws = torch.empty(front_end_workspace_size(1), dtype=torch.uint8, device=dev)
         self.params = prob["params"]
         self.n_iter = int(prob.get("n_iter", 1))
         if self.n_iter < 1:
@@ -103,17 +104,29 @@ class PlanStep:
         self.p0, self.v0 = x0[0:3].copy(), x0[7:10].copy()
         self.problem.x0, self.problem.p_goal = x0, p_goal
 
+    def front_end_job(self):
+        """This problem's partition + guides job (None with fixed anchors)."""
+        if self.fixed_anchors is not None:
+            return None
+        p = self.part
+        return front_end_job(p["n_az_c"], p["n_el_c"], p["f_a"], p["f_e"], self.prob["M_h"],
+                             self.prob["M_v"], p["r_max"], p["ell"], self.p0, self.tables,
+                             self.cloud, self.prob["goal_dir"], self.v0, self.a0, self.T,
+                             self.fine_key, self.fine_idx, self.coarse_best, self.anchor_cell,
+                             self.anchor_fine, self.anchors, self.coef, n_points=self.n_points)
+
+    def front_end_rest(self):
+        """What follows the partition + guides job: P_f, or the guides of fixed anchors."""
+        if self.fixed_anchors is not None:
+            build_guides(self.p0, self.v0, self.a0, self.anchors, self.T, self.M, self.coef)
+        elif self.pf is not None:
+            filtered_cloud(self.cloud, self.fine_idx, self.pf)
+
     def front_end(self):
-        if self.fixed_anchors is None:
-            p = self.part
-            partition_anchors(p["n_az_c"], p["n_el_c"], p["f_a"], p["f_e"], self.prob["M_h"],
-                              self.prob["M_v"], p["r_max"], p["ell"], self.p0, self.tables,
-                              self.cloud, self.prob["goal_dir"], self.fine_key, self.fine_idx,
-                              self.coarse_best, self.anchor_cell, self.anchor_fine, self.anchors,
-                              n_points=self.n_points)
-            if self.pf is not None:
-                filtered_cloud(self.cloud, self.fine_idx, self.pf)
-        build_guides(self.p0, self.v0, self.a0, self.anchors, self.T, self.M, self.coef)
+        job = self.front_end_job()
+        if job is not None:
+            front_end([job], self.fe_ws)
+        self.front_end_rest()
 
     def stage1(self):
         for prm in self.iter_params:
@@ -136,8 +149,8 @@ class PlanStep:
 class BatchPlan:
     """Many independent planning problems: per-problem calls or one batched call.
 
-    Both modes run the same partition/guide calls per problem; Stage I and Stage
-    II are either 2 x n_problems plain calls or 2 batched calls.
+    Both modes run one batched partition + guides call; Stage I and Stage II are
+    either 2 x n_problems plain calls or 2 batched calls.
     """
 
     def __init__(self, probs, device="cuda"):
@@ -150,6 +163,8 @@ class BatchPlan:
         self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)
         self.S2 = torch.empty(sum(s.M for s in self.steps), dtype=torch.float64, device=dev)
         self.best = torch.empty(len(self.steps), dtype=torch.int32, device=dev)
+        self.fe_ws = torch.empty(max(front_end_workspace_size(len(self.steps)), 1),
+                                 dtype=torch.uint8, device=dev)
         self.rollout_steps = sum(s.M * s.K * s.N + s.M * s.N for s in self.steps)
         self.pairs = sum(s.M * s.K * s.N * int(s.cloud.shape[0]) for s in self.steps)
 
@@ -158,8 +173,13 @@ class BatchPlan:
             s.reset()
 
     def front_end(self):
+        """Partition and guides of every problem in one batched call, then P_f and the
+        guides of problems with fixed anchors."""
+        jobs = [j for j in (s.front_end_job() for s in self.steps) if j is not None]
+        if jobs:
+            front_end(jobs, self.fe_ws)
         for s in self.steps:
-            s.front_end()
+            s.front_end_rest()
 
     def run_plain(self):
         self.front_end()

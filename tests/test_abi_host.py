@@ -202,6 +202,36 @@ def test_partition_and_guides_validation_without_device():
     expect_status(1, aero.build_guides, z, z, z, None, 2.0, 1, FakeTensor((1,)))
 
 
+def test_front_end_validation_without_device():
+    t = FakeTensor((100,))
+    names = ["fine_key", "fine_idx", "coarse_best", "anchor_cell", "anchor_fine", "anchors",
+             "coef"]
+
+    def job(**over):
+        a = dict(n_az_c=32, n_el_c=8, f_a=4, f_e=4, M_h=4, M_v=2, r_max=30.0, ell=5.0,
+                 p0=(0, 0, 0), d_tables=t, cloud=FakeTensor((10, 3)), goal_dir=(1, 0, 0),
+                 v0=(1, 0, 0), a0=(0, 0, 0), horizon_T=2.0)
+        a.update({n: FakeTensor((1,)) for n in names})
+        a.update(over)
+        return aero.front_end_job(**a)
+
+    n_ws = aero.front_end_workspace_size(2)
+    assert n_ws > 0
+    assert aero.front_end_workspace_size(0) == 0
+    ws = FakeTensor((n_ws,))
+    expect_status(2, aero.front_end, [], ws)
+    expect_status(4, aero.front_end, [job(), job()], FakeTensor((n_ws - 1,)))
+    # every job is checked before any launch: a bad second job fails the call
+    expect_status(2, aero.front_end, [job(), job(M_h=33, M_v=1)], ws)
+    expect_status(2, aero.front_end, [job(), job(n_points=-1)], ws)
+    expect_status(3, aero.front_end, [job(), job(horizon_T=0.0)], ws)
+    expect_status(3, aero.front_end, [job(), job(v0=(np.inf, 0, 0))], ws)
+    expect_status(3, aero.front_end, [job(), job(r_max=float("nan"))], ws)
+    expect_status(1, aero.front_end, [job(), job(coef=None)], ws)
+    expect_status(1, aero.front_end, [job(), job(d_tables=None)], ws)
+    expect_status(1, aero.front_end, [job(), job(cloud=None, n_points=5)], ws)
+
+
 def test_loop_calls_validation_without_device():
     ring, st, off = FakeTensor((10, 3)), FakeTensor((2,)), FakeTensor((3,))
     poses, org, out = FakeTensor((2, 7)), FakeTensor((3,)), FakeTensor((10, 3))
