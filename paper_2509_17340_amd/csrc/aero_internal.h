@@ -74,6 +74,8 @@ struct DevProblem {
   const float* w_dev;    // optional [5] device term weights replacing DevParams::w
   unsigned long long* nn;  // the set's pass-B nearest records by slot (reset with the
                            //   distances), or nullptr
+  unsigned* amin;          // the set's least pass-A values by slot (reset with the
+                           //   distances), or nullptr
 };
 
 // Spatial sort of one problem's rollout positions, or of its cloud (stable LSD radix
@@ -169,6 +171,11 @@ struct QuerySet {
   unsigned long long* nn;  // optional [Q]: pass B also keeps (d^2 bits << 32 | index) per
                            // slot (lowest index on ties)
   int32_t* nidx;           // with nn: [Q] nearest index per query (-1: none evaluated)
+  unsigned* amin;          // two-pass sets: [Q] by slot, the least pass-A value of each
+                           //   query over the items where it came under the bound (float
+                           //   bits, clamped at 0; +inf elsewhere): with the block's
+                           //   bound it caps the query's nearest squared distance, so
+                           //   pass B skips point groups beyond that cap
 };
 
 // One planning problem's front end (partition, anchors, guides) as the batched

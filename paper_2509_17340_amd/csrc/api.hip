@@ -380,6 +380,8 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.tbox = cur.take<float>(6 * n_tiles);
       qs.sbox = cur.take<float>(6 * n_sub);
       qs.gbox = cur.take<float>(6 * n_sub * kGroupsPerSub);
+      qs.amin = cur.take<unsigned>(MNK);  // reset by the noise kernel
+      d.amin = qs.amin;
       qs.items = pl.items;
       qs.item_count = pl.item_count;
       qs.hitf = pl.hitf;

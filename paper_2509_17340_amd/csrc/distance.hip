@@ -8,9 +8,12 @@
 //                      expanded form |o'|^2 - 2 p'.o' with query and cloud recentred on
 //                      the block's centre, three FMAs and half a min3 per pair; per
 //                      item, the hit words of the queries that came under the block's
-//                      bound (the matrix-core variants live in distance_mfma.hip).
-//   k_pass_b           pass B: the direct form for exactly the (query, sub-tile) pairs
-//                      of the hit words.
+//                      bound, and each query's least value over its hit items (the
+//                      matrix-core variants live in distance_mfma.hip).
+//   k_pass_b           pass B: the direct form for the (query, sub-tile) pairs of the
+//                      hit words, skipping the sub-tile's 32-point groups that lie
+//                      beyond every listed query's cap (its least pass-A value plus
+//                      the block's error allowance, or d_max).
 //   k_scatter_nearest  nearest indices from pass B's records (when requested).
 //
 // Results combine through atomicMin on the float bit patterns of the non-negative
@@ -148,6 +151,15 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
 // vector-memory issue.  Results combine through atomicMin on float bits (and on
 // (d^2 bits, index) pairs for the nearest index, lowest index on ties), so they are
 // order independent.
+#ifndef AERO_PASS_B_ROWS
+#define AERO_PASS_B_ROWS AERO_QUERIES_PER_LANE
+#endif
+#ifndef AERO_PASS_B_SKIP
+#define AERO_PASS_B_SKIP 1
+#endif
+constexpr int kPassBRows = AERO_PASS_B_ROWS;  // listed queries per lane at a time
+constexpr bool kPassBSkip = AERO_PASS_B_SKIP != 0;
+
 typedef const __attribute__((address_space(4))) float cfloat;
 typedef const __attribute__((address_space(4))) int32_t cint;
 
@@ -178,17 +190,45 @@ __device__ __forceinline__ void pass_b_point(float ox, float oy, float oz, int32
   }
 }
 
+// The group-skipping bound of pass B: a group box at single-precision squared distance
+// of at least this from a query holds only points whose single-precision squared
+// distance exceeds d_max^2.  The box distance and a point's direct-form distance
+// each carry a relative error of at most about 5 units in the last place (exact
+// differences of floats rounded once, then one multiply and two fused adds), and
+// every point lies at least as far as the box, so a margin of 2^-19 relative
+// (32 units) suffices; the result is rounded up to single precision.
+__device__ inline float pass_b_reach(float d_max) {
+  const double r = (double)d_max * (double)d_max * (1.0 + 0x1p-19);
+  const float f = (float)r;
+  return (double)f >= r ? f : __uint_as_float(__float_as_uint(f) + 1u);
+}
+
+// The cap of pass B on a query's squared distances: a point group whose box lies at
+// least this far holds no point that can be the query's nearest.  m is the query's
+// least pass-A value (clamped at 0) over its hit items and slack the block's
+// allowance for pass A's error (its bound less d_max^2): the point attaining m lies
+// within m + slack exactly, so its direct-form value does too up to the relative
+// margin above, and every point of a farther group exceeds it.
+__device__ inline float pass_b_cap(float m, float slack) {
+  return (m + slack) * (1.0f + 0x1p-19f);
+}
+
 // Listed queries k = k0 + r * 64 + lane (r < R, k < h) of the item against its n points
-// (sorted records, or the raw cloud from point g0 on).  Points go U at a time (fewer
-// when R is large, so that the unrolled differences stay within the register budget).
+// (sorted records, or the raw cloud from point g0 on), one 32-point group at a time.
+// A group whose box lies beyond `reach` from every listed query of the wave is skipped
+// (gb: the sub-tile's group boxes, or nullptr to take every group): its points are
+// all farther than d_max from those queries (see pass_b_reach).  Points go U at a time
+// (fewer when R is large, so that the unrolled differences stay within the register
+// budget).
 template <int R, bool kIdx, bool kSorted>
 __device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, int h,
-                                      const uint16_t* qlist, int64_t g0, int n) {
+                                      const uint16_t* qlist, int64_t g0, int n, const float* gb,
+                                      float reach, float slack) {
   constexpr int U = R <= 2 ? 4 : 2;
   const int lane = threadIdx.x & 63;
   const int64_t Q = S.Q;
   const float* __restrict__ sp = S.sp;
-  float px[R], py[R], pz[R], best[R];
+  float px[R], py[R], pz[R], best[R], lim[R];
   int32_t bidx[R], jq[R];  // jq: block-local query index, -1 for an idle row
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -200,55 +240,75 @@ __device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, 
     pz[r] = sp[2 * Q + q];
     best[r] = __uint_as_float(kInfBits);
     bidx[r] = 0x7fffffff;
+    lim[r] = reach;
+    if (gb && S.amin) lim[r] = fminf(reach, pass_b_cap(__uint_as_float(S.amin[q]), slack));
   }
-  if constexpr (kSorted) {
-    cfloat* rec = (cfloat*)(S.scloud + g0);  // (x, y, z, index bits) per point
-    cint* irec = (cint*)(S.scloud + g0);
-    int j = 0;
-    for (; j + U <= n; j += U) {
+  cfloat* gbc = (cfloat*)gb;
+  for (int j0 = 0; j0 < n; j0 += 32) {  // wave-uniform
+    const int j1 = min(n, j0 + 32);
+    if (gbc) {
+      cfloat* b = gbc + 6 * (j0 >> 5);
+      const float lx = b[0], ly = b[1], lz = b[2], hx = b[3], hy = b[4], hz = b[5];
+      bool near = false;
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        pass_b_point<R, kIdx>(rec[4 * (j + u)], rec[4 * (j + u) + 1], rec[4 * (j + u) + 2],
-                              irec[4 * (j + u) + 3], px, py, pz, best, bidx);
+      for (int r = 0; r < R; ++r) {
+        const float dx = fmaxf(fmaxf(lx - px[r], px[r] - hx), 0.0f);
+        const float dy = fmaxf(fmaxf(ly - py[r], py[r] - hy), 0.0f);
+        const float dz = fmaxf(fmaxf(lz - pz[r], pz[r] - hz), 0.0f);
+        near |= (jq[r] >= 0) & (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < lim[r]);
+      }
+      if (!__builtin_amdgcn_ballot_w64(near)) continue;  // no listed query within reach
     }
-    for (; j < n; ++j)
-      pass_b_point<R, kIdx>(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], irec[4 * j + 3], px, py,
-                            pz, best, bidx);
-  } else {
-    cfloat* rec = (cfloat*)(S.cloud + 3 * g0);
-    int j = 0;
-    for (; j + U <= n; j += U) {
+    if constexpr (kSorted) {
+      cfloat* rec = (cfloat*)(S.scloud + g0);  // (x, y, z, index bits) per point
+      cint* irec = (cint*)(S.scloud + g0);
+      int j = j0;
+      for (; j + U <= j1; j += U) {
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        pass_b_point<R, kIdx>(rec[3 * (j + u)], rec[3 * (j + u) + 1], rec[3 * (j + u) + 2],
-                              (int32_t)(g0 + j + u), px, py, pz, best, bidx);
+        for (int u = 0; u < U; ++u)
+          pass_b_point<R, kIdx>(rec[4 * (j + u)], rec[4 * (j + u) + 1], rec[4 * (j + u) + 2],
+                                irec[4 * (j + u) + 3], px, py, pz, best, bidx);
+      }
+      for (; j < j1; ++j)
+        pass_b_point<R, kIdx>(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], irec[4 * j + 3], px,
+                              py, pz, best, bidx);
+    } else {
+      cfloat* rec = (cfloat*)(S.cloud + 3 * g0);
+      int j = j0;
+      for (; j + U <= j1; j += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          pass_b_point<R, kIdx>(rec[3 * (j + u)], rec[3 * (j + u) + 1], rec[3 * (j + u) + 2],
+                                (int32_t)(g0 + j + u), px, py, pz, best, bidx);
+      }
+      for (; j < j1; ++j)
+        pass_b_point<R, kIdx>(rec[3 * j], rec[3 * j + 1], rec[3 * j + 2], (int32_t)(g0 + j), px,
+                              py, pz, best, bidx);
     }
-    for (; j < n; ++j)
-      pass_b_point<R, kIdx>(rec[3 * j], rec[3 * j + 1], rec[3 * j + 2], (int32_t)(g0 + j), px,
-                            py, pz, best, bidx);
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (jq[r] >= 0) pass_b_result<kIdx>(S, slot0 + jq[r], best[r], bidx[r]);
 }
 
-// Listed queries [k0, k1) of the item, kQueriesPerLane rows of 64 at a time.
+// Listed queries [k0, k1) of the item, kPassBRows rows of 64 at a time.
 template <bool kIdx, bool kSorted>
 __device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int k0, int k1,
-                                   const uint16_t* qlist, int64_t g0, int n) {
-  constexpr int kChunk = 64 * kQueriesPerLane;
+                                   const uint16_t* qlist, int64_t g0, int n, const float* gb,
+                                   float reach, float slack) {
+  constexpr int kChunk = 64 * kPassBRows;
   const int h = k1;
   for (; k0 < k1; k0 += kChunk) {  // wave-uniform
-    switch (min((h - k0 + 63) / 64, kQueriesPerLane)) {
-      case 1: pass_b_queries<1, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
-      case 2: pass_b_queries<2, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
-      case 3: pass_b_queries<3, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
-      case 4: pass_b_queries<4, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
-      case 5: pass_b_queries<5, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
-      case 6: pass_b_queries<6, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
-      case 7: pass_b_queries<7, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n); break;
+    switch (min((h - k0 + 63) / 64, kPassBRows)) {
+      case 1: pass_b_queries<1, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
+      case 2: pass_b_queries<2, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
+      case 3: pass_b_queries<3, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
+      case 4: pass_b_queries<4, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
+      case 5: pass_b_queries<5, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
+      case 6: pass_b_queries<6, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
+      case 7: pass_b_queries<7, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
       default:
-        pass_b_queries<kQueriesPerLane, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n);
+        pass_b_queries<kPassBRows, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack);
         break;
     }
   }
@@ -327,12 +387,18 @@ k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int k0 = part * 64 * urows, k1 = min(h, k0 + 64 * urows);
     if (k0 < k1) {
+      const float* gbs = srt ? S.sgbox : S.gbox;
+      const float* gb = (kPassBSkip && gbs) ? gbs + 6 * (ys & 0x7fffffffu) * kGroupsPerSub
+                                            : nullptr;
+      const float reach = pass_b_reach(S.d_max);
+      // pass A's error allowance of the block (its bound less d_max^2)
+      const float slack = fmaxf(S.binfo[qb].w - S.d_max * S.d_max, 0.0f);
       if (kIdx && S.nn) {
-        if (srt) pass_b_item<kIdx, true>(S, slot0, k0, k1, qlist, g0, n);
-        else pass_b_item<kIdx, false>(S, slot0, k0, k1, qlist, g0, n);
+        if (srt) pass_b_item<kIdx, true>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
+        else pass_b_item<kIdx, false>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
       } else {
-        if (srt) pass_b_item<false, true>(S, slot0, k0, k1, qlist, g0, n);
-        else pass_b_item<false, false>(S, slot0, k0, k1, qlist, g0, n);
+        if (srt) pass_b_item<false, true>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
+        else pass_b_item<false, false>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
       }
     }
     // the next item's list overwrites the row
@@ -370,6 +436,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
   unsigned okm = 0;  // bit r: this lane's query r exists
   float c[3] = {0.0f, 0.0f, 0.0f}, thr = 0.0f;
   float px[R], py[R], pz[R], pp[R];
+  int64_t qslot0 = 0;        // this lane's slot of row 0
+  unsigned* amin = nullptr;  // the block's set's least pass-A values
   // the hit words of every set of the call share one array
   AERO_GLOBAL uint32_t* __restrict__ hmask = global_ptr(sets[0].hmask);
   const int64_t mask_items = sets[0].mask_words / W;  // items with room for their words
@@ -397,6 +465,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
       c[2] = bi.z;
       thr = bi.w;
       const int64_t slot0 = qb * kQueriesPerBlock + tid;
+      qslot0 = slot0;
+      amin = S.amin;
       okm = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -446,12 +516,15 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
     const bool room = i < mask_items;  // block-uniform
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const bool hq = ((okm >> r) & 1u) && pp[r] + tt[r] < thr;
+      const float t = pp[r] + tt[r];
+      const bool hq = ((okm >> r) & 1u) && t < thr;
       hit |= hq;
       const uint64_t hb = __ballot(hq);
       if (room && lane < 2)  // the wave's 64 queries r kBlock + 64 w + [0, 64): two words
         hmask[i * W + r * (kBlock / 32) + 2 * w + lane] =
             (uint32_t)(lane ? (hb >> 32) : (hb & 0xffffffffull));
+      // the query's least value so far
+      if (hq && amin) atomicMin(amin + qslot0 + r * kBlock, __float_as_uint(fmaxf(t, 0.0f)));
     }
     mark_hit(hit, hitf, i);
   }

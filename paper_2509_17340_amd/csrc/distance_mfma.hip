@@ -105,6 +105,8 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
   float wlo[3] = {0.0f, 0.0f, 0.0f}, whi[3] = {0.0f, 0.0f, 0.0f}, wlim = 0.0f;
   half8 bop[COLS];
   float pp[COLS];
+  int64_t qslot0 = 0;         // this lane's slot of column block 0
+  unsigned* amin = nullptr;   // the block's set's least pass-A values
   // the hit words of every set of the call share one array
   AERO_GLOBAL uint32_t* __restrict__ hmask = global_ptr(sets[0].hmask);
   const int64_t mask_items = sets[0].mask_words / W;  // items with room for their words
@@ -135,6 +137,8 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
       c[2] = bi.z;
       thr = bi.w;
       const int64_t slot0 = qb * QPB + w * (32 * COLS) + col;
+      qslot0 = slot0;
+      amin = S.amin;
       wlim = S.cull ? reach_limit(thr, S.d_max) : INFINITY;  // brute force: every group
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -232,10 +236,13 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
     for (int b = 0; b < COLS; ++b) {
       // the two lane halves hold different rows (points) of the same column (query)
       const float v = fminf(tt[b], __shfl_xor(tt[b], 32, 64));
-      const bool hq = ((okm >> b) & 1u) && pp[b] + v < thr;
+      const float t = pp[b] + v;
+      const bool hq = ((okm >> b) & 1u) && t < thr;
       hit |= hq;
       const uint64_t hb = __ballot(hq);
       if (room && lane == 0) hmask[i * W + w * COLS + b] = (uint32_t)(hb & 0xffffffffull);
+      // the query's least value so far (both lane halves hold it: the lower one stores)
+      if (hq && kh == 0 && amin) atomicMin(amin + qslot0 + b * 32, __float_as_uint(fmaxf(t, 0.0f)));
     }
     mark_hit(hit, hitf, i);
   }

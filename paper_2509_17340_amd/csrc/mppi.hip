@@ -73,6 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   AERO_GLOBAL unsigned* __restrict__ out_slot = global_ptr(P.out_slot);
   AERO_GLOBAL int32_t* __restrict__ nidx = global_ptr(P.nidx);
   AERO_GLOBAL unsigned long long* __restrict__ nn = global_ptr(P.nn);
+  AERO_GLOBAL unsigned* __restrict__ amin = global_ptr(P.amin);
   if (local == 0) {
     AERO_GLOBAL int32_t* __restrict__ item_count = global_ptr(P.item_count);
     AERO_GLOBAL unsigned* __restrict__ sort_box = global_ptr(P.sort_box);
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(const DevProblem* __restrict__
   if (out_slot) out_slot[local] = kInfBits;  // by slot: the slots are a permutation
   if (nidx) nidx[local] = -1;
   if (nn) nn[local] = ~0ull;
+  if (amin) amin[local] = kInfBits;  // by slot, as out_slot
 }
 
 // Merge the position bounds of a wave's rollouts into their problems' sort boxes
