@@ -144,32 +144,22 @@ __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __res
 //
 // Each wave works alone (no workgroup barriers): waves take the marked items in turn
 // (items strided over every wave of the grid), list the item's hit queries from its
-// words into the wave's own LDS row, hold up to kQueriesPerLane of them per lane and
-// run them against the sub-tile's points, which every lane reads at the same address:
-// through the constant address space (the points are not written while the kernel
-// runs), so they arrive as scalar loads into SGPRs and cost no LDS bandwidth and no
-// vector-memory issue.  Results combine through atomicMin on float bits (and on
-// (d^2 bits, index) pairs for the nearest index, lowest index on ties), so they are
-// order independent.
+// words into the wave's own LDS row and, per listed query, the sub-tile's 32-point
+// groups within the query's cap (see pass_b_cap).  Group by group, the wave then runs
+// the queries that need the group, up to kPassBRows of them per lane, against the
+// group's points, which every lane reads at the same address: through the constant
+// address space (the points are not written while the kernel runs), so they arrive
+// as scalar loads into SGPRs and cost no LDS bandwidth and no vector-memory issue.
+// Results combine through minima on float bits (and on (d^2 bits, index) pairs for
+// the nearest index, lowest index on ties), in LDS per unit and then by atomicMin in
+// device memory, so they are order independent.
 #ifndef AERO_PASS_B_ROWS
 #define AERO_PASS_B_ROWS AERO_QUERIES_PER_LANE
 #endif
-#ifndef AERO_PASS_B_SKIP
-#define AERO_PASS_B_SKIP 1
-#endif
 constexpr int kPassBRows = AERO_PASS_B_ROWS;  // listed queries per lane at a time
-constexpr bool kPassBSkip = AERO_PASS_B_SKIP != 0;
 
 typedef const __attribute__((address_space(4))) float cfloat;
 typedef const __attribute__((address_space(4))) int32_t cint;
-
-template <bool kIdx>
-__device__ inline void pass_b_result(const QuerySet& S, int64_t slot, float best, int32_t bidx) {
-  atomicMin(S.out_slot + slot, __float_as_uint(best));
-  if constexpr (kIdx)
-    atomicMin(S.nn + slot, ((unsigned long long)__float_as_uint(best) << 32) |
-                               (unsigned long long)(unsigned)bidx);
-}
 
 // One point (x, y, z, index) against the R queries of this lane.
 template <int R, bool kIdx>
@@ -213,103 +203,179 @@ __device__ inline float pass_b_cap(float m, float slack) {
   return (m + slack) * (1.0f + 0x1p-19f);
 }
 
-// Listed queries k = k0 + r * 64 + lane (r < R, k < h) of the item against its n points
-// (sorted records, or the raw cloud from point g0 on), one 32-point group at a time.
-// A group whose box lies beyond `reach` from every listed query of the wave is skipped
-// (gb: the sub-tile's group boxes, or nullptr to take every group): its points are
-// all farther than d_max from those queries (see pass_b_reach).  Points go U at a time
-// (fewer when R is large, so that the unrolled differences stay within the register
-// budget).
+// A wave's LDS record of a listed query's least value: the float bits of d^2, or
+// (d^2 bits << 32 | point index) when nearest indices are kept; all ones: none yet.
+template <bool kIdx>
+struct PassBBest {
+  typedef unsigned T;
+};
+template <>
+struct PassBBest<true> {
+  typedef unsigned long long T;
+};
+
+constexpr int kUnitQ = 64 * kQueriesPerLane;  // the most listed queries of a work unit
+static_assert(kGroupsPerSub <= 8, "a row's group mask holds 8 bits");
+
+// Queries of one point group: entries c0 + r * 64 + lane (r < R, below ng) of the
+// group's list, each an index into the unit's list of block-local queries, against
+// the group's n points from point g0 on (sorted records, or the raw cloud).  Every
+// lane reads the same point at a time, through the constant address space (scalar
+// loads into SGPRs).  Each query's least value joins its LDS record (an entry occurs
+// once in a group's list, so the records' minima do not race).
 template <int R, bool kIdx, bool kSorted>
-__device__ inline void pass_b_queries(const QuerySet& S, int64_t slot0, int k0, int h,
-                                      const uint16_t* qlist, int64_t g0, int n, const float* gb,
-                                      float reach, float slack) {
+__device__ inline void pass_b_group(const QuerySet& S, int64_t slot0, const uint16_t* qlist,
+                                    const uint16_t* glist, int c0, int ng, int64_t g0, int n,
+                                    typename PassBBest<kIdx>::T* bl) {
   constexpr int U = R <= 2 ? 4 : 2;
   const int lane = threadIdx.x & 63;
   const int64_t Q = S.Q;
   const float* __restrict__ sp = S.sp;
-  float px[R], py[R], pz[R], best[R], lim[R];
-  int32_t bidx[R], jq[R];  // jq: block-local query index, -1 for an idle row
+  float px[R], py[R], pz[R], best[R];
+  int32_t bidx[R], e[R];  // e: the unit-list entry, -1 for an idle row
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int k = k0 + r * 64 + lane;
-    jq[r] = k < h ? (int32_t)qlist[k] : -1;
-    const int64_t q = slot0 + (jq[r] >= 0 ? jq[r] : 0);  // always a valid position
+    const int k = c0 + r * 64 + lane;
+    e[r] = k < ng ? (int32_t)glist[k] : -1;
+    const int64_t q = slot0 + (e[r] >= 0 ? qlist[e[r]] : 0);  // always a valid position
     px[r] = sp[q];
     py[r] = sp[Q + q];
     pz[r] = sp[2 * Q + q];
     best[r] = __uint_as_float(kInfBits);
     bidx[r] = 0x7fffffff;
-    lim[r] = reach;
-    if (gb && S.amin) lim[r] = fminf(reach, pass_b_cap(__uint_as_float(S.amin[q]), slack));
   }
-  cfloat* gbc = (cfloat*)gb;
-  for (int j0 = 0; j0 < n; j0 += 32) {  // wave-uniform
-    const int j1 = min(n, j0 + 32);
-    if (gbc) {
-      cfloat* b = gbc + 6 * (j0 >> 5);
-      const float lx = b[0], ly = b[1], lz = b[2], hx = b[3], hy = b[4], hz = b[5];
-      bool near = false;
+  if constexpr (kSorted) {
+    cfloat* rec = (cfloat*)(S.scloud + g0);  // (x, y, z, index bits) per point
+    cint* irec = (cint*)(S.scloud + g0);
+    int j = 0;
+    for (; j + U <= n; j += U) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float dx = fmaxf(fmaxf(lx - px[r], px[r] - hx), 0.0f);
-        const float dy = fmaxf(fmaxf(ly - py[r], py[r] - hy), 0.0f);
-        const float dz = fmaxf(fmaxf(lz - pz[r], pz[r] - hz), 0.0f);
-        near |= (jq[r] >= 0) & (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < lim[r]);
-      }
-      if (!__builtin_amdgcn_ballot_w64(near)) continue;  // no listed query within reach
+      for (int u = 0; u < U; ++u)
+        pass_b_point<R, kIdx>(rec[4 * (j + u)], rec[4 * (j + u) + 1], rec[4 * (j + u) + 2],
+                              irec[4 * (j + u) + 3], px, py, pz, best, bidx);
     }
-    if constexpr (kSorted) {
-      cfloat* rec = (cfloat*)(S.scloud + g0);  // (x, y, z, index bits) per point
-      cint* irec = (cint*)(S.scloud + g0);
-      int j = j0;
-      for (; j + U <= j1; j += U) {
+    for (; j < n; ++j)
+      pass_b_point<R, kIdx>(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], irec[4 * j + 3], px, py,
+                            pz, best, bidx);
+  } else {
+    cfloat* rec = (cfloat*)(S.cloud + 3 * g0);
+    int j = 0;
+    for (; j + U <= n; j += U) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          pass_b_point<R, kIdx>(rec[4 * (j + u)], rec[4 * (j + u) + 1], rec[4 * (j + u) + 2],
-                                irec[4 * (j + u) + 3], px, py, pz, best, bidx);
-      }
-      for (; j < j1; ++j)
-        pass_b_point<R, kIdx>(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], irec[4 * j + 3], px,
-                              py, pz, best, bidx);
-    } else {
-      cfloat* rec = (cfloat*)(S.cloud + 3 * g0);
-      int j = j0;
-      for (; j + U <= j1; j += U) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          pass_b_point<R, kIdx>(rec[3 * (j + u)], rec[3 * (j + u) + 1], rec[3 * (j + u) + 2],
-                                (int32_t)(g0 + j + u), px, py, pz, best, bidx);
-      }
-      for (; j < j1; ++j)
-        pass_b_point<R, kIdx>(rec[3 * j], rec[3 * j + 1], rec[3 * j + 2], (int32_t)(g0 + j), px,
-                              py, pz, best, bidx);
+      for (int u = 0; u < U; ++u)
+        pass_b_point<R, kIdx>(rec[3 * (j + u)], rec[3 * (j + u) + 1], rec[3 * (j + u) + 2],
+                              (int32_t)(g0 + j + u), px, py, pz, best, bidx);
     }
+    for (; j < n; ++j)
+      pass_b_point<R, kIdx>(rec[3 * j], rec[3 * j + 1], rec[3 * j + 2], (int32_t)(g0 + j), px,
+                            py, pz, best, bidx);
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (jq[r] >= 0) pass_b_result<kIdx>(S, slot0 + jq[r], best[r], bidx[r]);
+  for (int r = 0; r < R; ++r) {
+    if (e[r] < 0) continue;
+    if constexpr (kIdx)
+      atomicMin(bl + e[r], ((unsigned long long)__float_as_uint(best[r]) << 32) |
+                               (unsigned long long)(unsigned)bidx[r]);
+    else
+      atomicMin(bl + e[r], __float_as_uint(best[r]));
+  }
 }
 
-// Listed queries [k0, k1) of the item, kPassBRows rows of 64 at a time.
+// Orders this wave's LDS accesses (lists and records are written and read by the
+// wave alone, across lanes).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One work unit: the hu listed queries of qlist (block-local indices) against the
+// item's sub-tile (n points from point g0 on; gb: its group boxes, or nullptr to take
+// every group).  Each query takes only the groups within its cap, so the wave runs
+// group by group, each over the compacted list of the queries that need it, and
+// every query's least value meets in LDS before one global minimum per query.
 template <bool kIdx, bool kSorted>
-__device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int k0, int k1,
-                                   const uint16_t* qlist, int64_t g0, int n, const float* gb,
-                                   float reach, float slack) {
-  constexpr int kChunk = 64 * kPassBRows;
-  const int h = k1;
-  for (; k0 < k1; k0 += kChunk) {  // wave-uniform
-    switch (min((h - k0 + 63) / 64, kPassBRows)) {
-      case 1: pass_b_queries<1, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
-      case 2: pass_b_queries<2, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
-      case 3: pass_b_queries<3, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
-      case 4: pass_b_queries<4, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
-      case 5: pass_b_queries<5, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
-      case 6: pass_b_queries<6, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
-      case 7: pass_b_queries<7, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack); break;
-      default:
-        pass_b_queries<kPassBRows, kIdx, kSorted>(S, slot0, k0, h, qlist, g0, n, gb, reach, slack);
-        break;
+__device__ inline void pass_b_unit(const QuerySet& S, int64_t slot0, const uint16_t* qlist,
+                                   int hu, int64_t g0, int n, const float* gb, float reach,
+                                   float slack, uint16_t* glist,
+                                   typename PassBBest<kIdx>::T* bl) {
+  typedef typename PassBBest<kIdx>::T BestT;
+  const int lane = threadIdx.x & 63;
+  const int nr = (hu + 63) / 64;     // rows of the unit
+  const int ngr = (n + 31) / 32;     // groups of the sub-tile
+  const int64_t Q = S.Q;
+  const float* __restrict__ sp = S.sp;
+  const unsigned* __restrict__ amin = S.amin;
+  cfloat* gbc = (cfloat*)gb;
+  // group masks, 8 bits per row: bit g of row r, group g within the cap of query
+  // r * 64 + lane
+  uint64_t gm = 0;
+  for (int r = 0; r < nr; ++r) {  // wave-uniform
+    const int k = r * 64 + lane;
+    if (k >= hu) continue;
+    bl[k] = ~BestT(0);
+    uint32_t m;
+    if (gbc) {
+      const int64_t q = slot0 + qlist[k];
+      const float x = sp[q], y = sp[Q + q], z = sp[2 * Q + q];
+      const float lim = amin ? fminf(reach, pass_b_cap(__uint_as_float(amin[q]), slack)) : reach;
+      m = 0;
+#pragma unroll
+      for (int g = 0; g < kGroupsPerSub; ++g) {
+        cfloat* bx = gbc + 6 * g;
+        const float dx = fmaxf(fmaxf(bx[0] - x, x - bx[3]), 0.0f);
+        const float dy = fmaxf(fmaxf(bx[1] - y, y - bx[4]), 0.0f);
+        const float dz = fmaxf(fmaxf(bx[2] - z, z - bx[5]), 0.0f);
+        m |= fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < lim ? 1u << g : 0u;
+      }
+    } else {
+      m = (1u << ngr) - 1u;
+    }
+    gm |= (uint64_t)m << (8 * r);
+  }
+  for (int g = 0; g < ngr; ++g) {  // wave-uniform
+    // the list of the queries that need group g
+    wave_lds_sync();  // the previous group's readers are done with the list
+    int ng = 0;
+    for (int r = 0; r < nr; ++r) {
+      const bool bit = (gm >> (8 * r + g)) & 1ull;
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(bit);
+      if (bit) glist[ng + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] =
+          (uint16_t)(r * 64 + lane);
+      ng += __popcll(bal);
+    }
+    if (ng == 0) continue;
+    wave_lds_sync();
+    const int64_t gg = g0 + 32 * g;
+    const int gn = min(32, n - 32 * g);
+    for (int c0 = 0; c0 < ng; c0 += 64 * kPassBRows) {  // wave-uniform
+      switch (min((ng - c0 + 63) / 64, kPassBRows)) {
+        case 1: pass_b_group<1, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl); break;
+        case 2: pass_b_group<2, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl); break;
+        case 3: pass_b_group<3, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl); break;
+        case 4: pass_b_group<4, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl); break;
+        case 5: pass_b_group<5, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl); break;
+        case 6: pass_b_group<6, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl); break;
+        case 7: pass_b_group<7, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl); break;
+        default:
+          pass_b_group<kPassBRows, kIdx, kSorted>(S, slot0, qlist, glist, c0, ng, gg, gn, bl);
+          break;
+      }
+    }
+  }
+  wave_lds_sync();  // every group's minima are in
+  for (int r = 0; r < nr; ++r) {
+    const int k = r * 64 + lane;
+    if (k >= hu) continue;
+    const BestT v = bl[k];
+    if (v == ~BestT(0)) continue;  // no group of this sub-tile within the query's cap
+    const int64_t slot = slot0 + qlist[k];
+    if constexpr (kIdx) {
+      atomicMin(S.out_slot + slot, (unsigned)(v >> 32));
+      atomicMin(S.nn + slot, v);
+    } else {
+      atomicMin(S.out_slot + slot, v);
     }
   }
 }
@@ -321,15 +387,17 @@ __device__ inline void pass_b_item(const QuerySet& S, int64_t slot0, int k0, int
 #endif
 template <bool kIdx>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AERO_PASS_B_WPE))) void
-k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
-                                                   const int2* __restrict__ items,
-                                                   const int32_t* __restrict__ item_count,
-                                                   const unsigned char* __restrict__ hitf) {
-  __shared__ uint16_t qlists[kBlock / 64][kQueriesPerBlock];  // each wave's own row
+k_pass_b(const QuerySet* __restrict__ sets, int n_sets, const int2* __restrict__ items,
+         const int32_t* __restrict__ item_count, const unsigned char* __restrict__ hitf) {
+  // each wave's own rows: the unit's listed queries, one group's entries, the records
+  __shared__ uint16_t qlists[kBlock / 64][kUnitQ];
+  __shared__ uint16_t glists[kBlock / 64][kUnitQ];
+  __shared__ typename PassBBest<kIdx>::T bests[kBlock / 64][kUnitQ];
   // the wave index as a wave-uniform value, so that everything derived from it (the
   // item, its set, the point addresses) stays in scalar registers
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint16_t* qlist = qlists[w];
+  uint16_t* glist = glists[w];
   const int64_t total = *item_count;
   const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
   const uint32_t* __restrict__ hmask = sets[0].hmask;
@@ -361,7 +429,7 @@ k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
     const bool srt = (ys >> 31) != 0 && S.scloud;
     const int n = g0 < S.n_points ? (int)min<int64_t>(kSubPts, S.n_points - g0) : 0;
     if (n <= 0) continue;
-    // list the hit queries: lane j holds word j (bits of existing queries only)
+    // the hit queries: lane j holds word j (bits of existing queries only)
     const int lo = lane * 32;
     const uint32_t valid = lo >= nq ? 0u : (nq - lo >= 32 ? 0xffffffffu : (1u << (nq - lo)) - 1u);
     uint32_t word = 0;
@@ -374,37 +442,36 @@ k_pass_b(const QuerySet* __restrict__ sets, int n_sets,
       const int y2 = __shfl_up(incl, o, 64);
       if (lane >= o) incl += y2;
     }
-    int at = incl - c;
-    while (word) {
-      const int b = __ffs(word) - 1;
-      word &= word - 1u;
-      qlist[at++] = (uint16_t)(lo + b);
-    }
     const int h = __shfl(incl, 63, 64);
-    // the row is written and read by this wave only: order its LDS accesses
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int k0 = part * 64 * urows, k1 = min(h, k0 + 64 * urows);
-    if (k0 < k1) {
-      const float* gbs = srt ? S.sgbox : S.gbox;
-      const float* gb = (kPassBSkip && gbs) ? gbs + 6 * (ys & 0x7fffffffu) * kGroupsPerSub
-                                            : nullptr;
-      const float reach = pass_b_reach(S.d_max);
-      // pass A's error allowance of the block (its bound less d_max^2)
-      const float slack = fmaxf(S.binfo[qb].w - S.d_max * S.d_max, 0.0f);
-      if (kIdx && S.nn) {
-        if (srt) pass_b_item<kIdx, true>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
-        else pass_b_item<kIdx, false>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
-      } else {
-        if (srt) pass_b_item<false, true>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
-        else pass_b_item<false, false>(S, slot0, k0, k1, qlist, g0, n, gb, reach, slack);
+    if (k0 >= k1) continue;  // wave-uniform
+    // this unit's part of the list: entries [k0, k1)
+    wave_lds_sync();  // the previous unit is done with the rows
+    int at = incl - c;
+    if (at < k1 && incl > k0) {
+      while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1u;
+        if (at >= k0 && at < k1) qlist[at - k0] = (uint16_t)(lo + b);
+        ++at;
       }
     }
-    // the next item's list overwrites the row
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
+    const float* gbs = srt ? S.sgbox : S.gbox;
+    const float* gb = gbs ? gbs + 6 * (int64_t)(ys & 0x7fffffffu) * kGroupsPerSub : nullptr;
+    const float reach = pass_b_reach(S.d_max);
+    // pass A's error allowance of the block (its bound less d_max^2)
+    const float slack = fmaxf(S.binfo[qb].w - S.d_max * S.d_max, 0.0f);
+    const int hu = k1 - k0;
+    if (kIdx && S.nn) {
+      auto* bl = reinterpret_cast<typename PassBBest<kIdx>::T*>(bests[w]);
+      if (srt) pass_b_unit<kIdx, true>(S, slot0, qlist, hu, g0, n, gb, reach, slack, glist, bl);
+      else pass_b_unit<kIdx, false>(S, slot0, qlist, hu, g0, n, gb, reach, slack, glist, bl);
+    } else {
+      auto* bl = reinterpret_cast<unsigned*>(bests[w]);
+      if (srt) pass_b_unit<false, true>(S, slot0, qlist, hu, g0, n, gb, reach, slack, glist, bl);
+      else pass_b_unit<false, false>(S, slot0, qlist, hu, g0, n, gb, reach, slack, glist, bl);
+    }
   }
 }
 

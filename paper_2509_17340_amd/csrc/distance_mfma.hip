@@ -51,7 +51,12 @@ namespace {
 #endif
 constexpr int kF16Pipe = AERO_F16_PIPE;  // products reduced together
 constexpr float kF16FarT = 32768.0f;
-constexpr int kPassAGrid = 1024;         // persistent workgroups (4 per CU)
+#ifndef AERO_PASS_A_GRID
+#define AERO_PASS_A_GRID 4096
+#endif
+// persistent workgroups: 16 per CU, so that the ranges of items they take are short
+// and the CUs finish together
+constexpr int kPassAGrid = AERO_PASS_A_GRID;
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -223,10 +228,13 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
           dv[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bop[b + j], (floatx16){}, 0, 0, 0);
 #pragma unroll
         for (int j = 0; j < kF16Pipe; ++j) {
-          float m = tt[b + j];
-#pragma unroll
-          for (int r = 0; r < 16; r += 2) m = fminf(fminf(m, dv[j][r]), dv[j][r + 1]);
-          tt[b + j] = m;
+          // a tree of minima (depth 3, eight min3) rather than a chain of eight
+          const floatx16& d = dv[j];
+          const float t0 = fminf(fminf(d[0], d[1]), d[2]), t1 = fminf(fminf(d[3], d[4]), d[5]);
+          const float t2 = fminf(fminf(d[6], d[7]), d[8]), t3 = fminf(fminf(d[9], d[10]), d[11]);
+          const float t4 = fminf(fminf(d[12], d[13]), d[14]);
+          const float u0 = fminf(fminf(t0, t1), t2), u1 = fminf(fminf(t3, t4), d[15]);
+          tt[b + j] = fminf(fminf(tt[b + j], u0), u1);
         }
       }
     }
