@@ -398,19 +398,24 @@ int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems);
 int aero_set_pass_a_cull(int on);
 
 /* Profiling aid: the work of the two distance passes of the last aero_mppi_step on
- * this workspace (same problems), counted from the cull step's items and pass A's hit
- * words.  Reads device memory synchronously (hipMemcpy): call it once the stream has
- * finished the step and before any other call reuses the workspace (aero_select_best
- * on the same workspace overwrites what it reads).  Errors: AERO_ERR_NULL, AERO_ERR_SHAPE / AERO_ERR_PARAM as
- * aero_mppi_step's size checks, AERO_ERR_WORKSPACE, AERO_ERR_DEVICE. */
+ * this workspace (same problems), counted from the cull step's items, pass A's hit
+ * words and, for pass_b_eval, by a counting kernel that takes pass B's own work
+ * units and group masks (launched on the null stream; the call synchronizes the
+ * device).  Reads device memory synchronously: call it once the stream has finished
+ * the step and before any other call reuses the workspace (aero_select_best on the
+ * same workspace overwrites what it reads).  Errors: AERO_ERR_NULL, AERO_ERR_SHAPE /
+ * AERO_ERR_PARAM as aero_mppi_step's size checks, AERO_ERR_WORKSPACE, AERO_ERR_DEVICE. */
 typedef struct aero_distance_stats {
   int64_t items;        /* (query block, cloud sub-tile) items the cull step listed      */
   int64_t pairs_a;      /* position-point pairs of those items (pass A evaluates them)   */
   int64_t items_b;      /* items in which some query came under its block's bound        */
-  int64_t pairs_b;      /* position-point pairs pass B evaluates exactly                 */
+  int64_t pairs_b;      /* position-point pairs of pass A's hit words (the listed
+                           queries against their items' whole sub-tiles)                 */
   int64_t items_whole;  /* marked items without room for their hit words (pass B takes
                            every query of the block)                                     */
   int64_t positions;    /* rollout positions of the two-pass sets                        */
+  int64_t pairs_b_eval; /* position-point pairs pass B evaluates exactly: each listed
+                           query against the point groups within its cap                 */
 } aero_distance_stats;
 int aero_read_distance_stats(const aero_problem* h_problems, int32_t n_problems, const void* d_ws,
                              size_t ws_bytes, aero_distance_stats* h_out);

@@ -458,12 +458,12 @@ def set_pass_a_cull(on=True):
 
 class DistanceStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("items", "pairs_a", "items_b", "pairs_b",
-                                              "items_whole", "positions")]
+                                              "items_whole", "positions", "pairs_b_eval")]
 
 
 def distance_stats(problems, ws, ws_bytes=None):
     """Work of the two distance passes of the last mppi_step on `ws` (synchronous):
-    dict with items, pairs_a, items_b, pairs_b, items_whole, positions."""
+    dict with items, pairs_a, items_b, pairs_b, items_whole, positions, pairs_b_eval."""
     arr = _problem_array(problems)
     out = DistanceStats()
     nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes

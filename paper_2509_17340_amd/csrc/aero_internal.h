@@ -310,6 +310,10 @@ hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* 
                                 int variant, hipStream_t s);
 // Pass B over the marked items (the hit words of every set of the call share one array);
 // track_nearest: some set keeps nearest indices (nn).
+// Pairs pass B evaluates on the items of the last call (synchronous, null stream).
+hipError_t count_pass_b_pairs(const QuerySet* d_sets, int n_sets, const int2* items,
+                              const int32_t* item_count, const unsigned char* hitf,
+                              int64_t max_items, unsigned long long* h_pairs);
 hipError_t launch_pass_b(const QuerySet* d_sets, int n_sets, const int2* items,
                          const int32_t* item_count, const unsigned char* hitf, int64_t max_items,
                          bool track_nearest, hipStream_t s);

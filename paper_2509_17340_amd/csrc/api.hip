@@ -1187,6 +1187,11 @@ int aero_read_distance_stats(const aero_problem* h, int32_t n, const void* d_ws,
       out->pairs_b += nq * np;
     }
   }
+  unsigned long long ev = 0;
+  if (count_pass_b_pairs(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap, &ev) !=
+      hipSuccess)
+    return AERO_ERR_DEVICE;
+  out->pairs_b_eval = (int64_t)ev;
   return AERO_OK;
 }
 

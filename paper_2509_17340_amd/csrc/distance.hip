@@ -289,6 +289,28 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The groups of the sub-tile (n points; gb: its group boxes, or nullptr for every
+// group) within the cap of the query at slot q: bit g for group g.
+__device__ inline uint32_t pass_b_group_mask(const QuerySet& S, int64_t q, const float* gb,
+                                             int n, float reach, float slack) {
+  if (!gb) return (1u << ((n + 31) / 32)) - 1u;
+  const int64_t Q = S.Q;
+  const float x = S.sp[q], y = S.sp[Q + q], z = S.sp[2 * Q + q];
+  const float lim =
+      S.amin ? fminf(reach, pass_b_cap(__uint_as_float(S.amin[q]), slack)) : reach;
+  cfloat* gbc = (cfloat*)gb;
+  uint32_t m = 0;
+#pragma unroll
+  for (int g = 0; g < kGroupsPerSub; ++g) {
+    cfloat* bx = gbc + 6 * g;
+    const float dx = fmaxf(fmaxf(bx[0] - x, x - bx[3]), 0.0f);
+    const float dy = fmaxf(fmaxf(bx[1] - y, y - bx[4]), 0.0f);
+    const float dz = fmaxf(fmaxf(bx[2] - z, z - bx[5]), 0.0f);
+    m |= fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < lim ? 1u << g : 0u;
+  }
+  return m;
+}
+
 // One work unit: the hu listed queries of qlist (block-local indices) against the
 // item's sub-tile (n points from point g0 on; gb: its group boxes, or nullptr to take
 // every group).  Each query takes only the groups within its cap, so the wave runs
@@ -303,10 +325,6 @@ __device__ inline void pass_b_unit(const QuerySet& S, int64_t slot0, const uint1
   const int lane = threadIdx.x & 63;
   const int nr = (hu + 63) / 64;     // rows of the unit
   const int ngr = (n + 31) / 32;     // groups of the sub-tile
-  const int64_t Q = S.Q;
-  const float* __restrict__ sp = S.sp;
-  const unsigned* __restrict__ amin = S.amin;
-  cfloat* gbc = (cfloat*)gb;
   // group masks, 8 bits per row: bit g of row r, group g within the cap of query
   // r * 64 + lane
   uint64_t gm = 0;
@@ -314,24 +332,7 @@ __device__ inline void pass_b_unit(const QuerySet& S, int64_t slot0, const uint1
     const int k = r * 64 + lane;
     if (k >= hu) continue;
     bl[k] = ~BestT(0);
-    uint32_t m;
-    if (gbc) {
-      const int64_t q = slot0 + qlist[k];
-      const float x = sp[q], y = sp[Q + q], z = sp[2 * Q + q];
-      const float lim = amin ? fminf(reach, pass_b_cap(__uint_as_float(amin[q]), slack)) : reach;
-      m = 0;
-#pragma unroll
-      for (int g = 0; g < kGroupsPerSub; ++g) {
-        cfloat* bx = gbc + 6 * g;
-        const float dx = fmaxf(fmaxf(bx[0] - x, x - bx[3]), 0.0f);
-        const float dy = fmaxf(fmaxf(bx[1] - y, y - bx[4]), 0.0f);
-        const float dz = fmaxf(fmaxf(bx[2] - z, z - bx[5]), 0.0f);
-        m |= fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < lim ? 1u << g : 0u;
-      }
-    } else {
-      m = (1u << ngr) - 1u;
-    }
-    gm |= (uint64_t)m << (8 * r);
+    gm |= (uint64_t)pass_b_group_mask(S, slot0 + qlist[k], gb, n, reach, slack) << (8 * r);
   }
   for (int g = 0; g < ngr; ++g) {  // wave-uniform
     // the list of the queries that need group g
@@ -378,6 +379,80 @@ __device__ inline void pass_b_unit(const QuerySet& S, int64_t slot0, const uint1
       atomicMin(S.out_slot + slot, v);
     }
   }
+}
+
+// One work unit of pass B as its pair count takes it (the same steps as k_pass_b,
+// which keeps them inline: its registers are at the budget of eight waves per SIMD):
+// part `part` of item `it` (e, of set S) covers the item's listed queries
+// [part * 64 urows, (part + 1) * 64 urows), listed into qlist (the wave's LDS row).
+// Returns false when the unit has nothing to run.
+struct PassBUnit {
+  int64_t slot0, g0;
+  const float* gb;
+  int n, hu;
+  float reach, slack;
+  bool srt;
+};
+__device__ __forceinline__ bool pass_b_take_unit(const QuerySet& S, int2 e,
+                                                 const uint32_t* __restrict__ hmask,
+                                                 int64_t mask_words, int64_t it, int part,
+                                                 int urows, uint16_t* qlist, PassBUnit& U) {
+  const int lane = threadIdx.x & 63;
+  if (!block_of(S, e.x) || S.n_points <= 0) return false;
+  const int64_t qb = e.x - S.qb_base;
+  U.slot0 = qb * S.qpbA;
+  const int nq = (int)min<int64_t>(S.qpbA, S.Q - U.slot0);  // queries of the block
+  const int W = S.qpbA / 32;
+  const unsigned ys = (unsigned)e.y;
+  U.g0 = (int64_t)(ys & 0x7fffffffu) * kSubPts;
+  U.srt = (ys >> 31) != 0 && S.scloud;
+  U.n = U.g0 < S.n_points ? (int)min<int64_t>(kSubPts, S.n_points - U.g0) : 0;
+  if (U.n <= 0) return false;
+  // the hit queries: lane j holds word j (bits of existing queries only)
+  const int lo = lane * 32;
+  const uint32_t valid = lo >= nq ? 0u : (nq - lo >= 32 ? 0xffffffffu : (1u << (nq - lo)) - 1u);
+  uint32_t word = 0;
+  if (lane < W)  // without room for the item's words: every query of the block
+    word = (it + 1) * W <= mask_words ? hmask[it * W + lane] & valid : valid;
+  const int c = __popc(word);
+  int incl = c;  // inclusive scan over the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y2 = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y2;
+  }
+  const int h = __shfl(incl, 63, 64);
+  const int k0 = part * 64 * urows, k1 = min(h, k0 + 64 * urows);
+  if (k0 >= k1) return false;  // wave-uniform
+  // this unit's part of the list: entries [k0, k1)
+  wave_lds_sync();  // the previous unit is done with the row
+  int at = incl - c;
+  if (at < k1 && incl > k0) {
+    while (word) {
+      const int b = __ffs(word) - 1;
+      word &= word - 1u;
+      if (at >= k0 && at < k1) qlist[at - k0] = (uint16_t)(lo + b);
+      ++at;
+    }
+  }
+  wave_lds_sync();
+  const float* gbs = U.srt ? S.sgbox : S.gbox;
+  U.gb = gbs ? gbs + 6 * (int64_t)(ys & 0x7fffffffu) * kGroupsPerSub : nullptr;
+  U.reach = pass_b_reach(S.d_max);
+  // pass A's error allowance of the block (its bound less d_max^2)
+  U.slack = fmaxf(S.binfo[qb].w - S.d_max * S.d_max, 0.0f);
+  U.hu = k1 - k0;
+  return true;
+}
+
+// Work units: whole items (8 rows per unit, the most a lane holds) while the items
+// outnumber the waves enough; smaller parts when there are too few items to keep
+// every wave busy (the same for every set: one block size per call).
+__device__ inline int pass_b_unit_rows(const QuerySet* sets, int64_t total, int64_t n_waves) {
+  const int rows_per_block = sets[0].qpbA / 64;
+  int urows = kQueriesPerLane;
+  while (urows > 1 && total * ((rows_per_block + urows - 1) / urows) < 4 * n_waves) urows /= 2;
+  return urows;
 }
 
 // kIdx: the call keeps nearest indices (some set has nn; the index-tracking loops need
@@ -473,6 +548,44 @@ k_pass_b(const QuerySet* __restrict__ sets, int n_sets, const int2* __restrict__
       else pass_b_unit<false, false>(S, slot0, qlist, hu, g0, n, gb, reach, slack, glist, bl);
     }
   }
+}
+
+// The (query, point) pairs pass B evaluates, for the statistics call: the same work
+// units, lists and group masks, summing the points of the groups within each listed
+// query's cap into pass_b_pairs.
+__device__ unsigned long long pass_b_pairs;
+__global__ __launch_bounds__(kBlock) void k_pass_b_count(const QuerySet* __restrict__ sets,
+                                                         int n_sets,
+                                                         const int2* __restrict__ items,
+                                                         const int32_t* __restrict__ item_count,
+                                                         const unsigned char* __restrict__ hitf) {
+  __shared__ uint16_t qlists[kBlock / 64][kUnitQ];
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint16_t* qlist = qlists[w];
+  const int64_t total = *item_count;
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
+  SetCache cache{0, 0, 0};
+  const int urows = pass_b_unit_rows(sets, total, n_waves);
+  const int parts = (sets[0].qpbA / 64 + urows - 1) / urows;
+  const int64_t total_units = total * parts;
+  unsigned long long cnt = 0;
+  for (int64_t u = (int64_t)blockIdx.x * (kBlock / 64) + w; u < total_units; u += n_waves) {
+    const int64_t it = u / parts;
+    if (!hitf[it]) continue;  // wave-uniform
+    const int2 e = items[it];
+    const QuerySet S = sets[set_of(sets, n_sets, e.x, cache)];
+    PassBUnit U;
+    if (!pass_b_take_unit(S, e, sets[0].hmask, sets[0].mask_words, it, (int)(u - it * parts),
+                          urows, qlist, U))
+      continue;
+    for (int k = lane; k < U.hu; k += 64) {
+      const uint32_t m = pass_b_group_mask(S, U.slot0 + qlist[k], U.gb, U.n, U.reach, U.slack);
+      for (int g = 0; g < kGroupsPerSub; ++g)
+        if ((m >> g) & 1u) cnt += (unsigned long long)min(32, U.n - 32 * g);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if (lane == 0 && cnt) atomicAdd(&pass_b_pairs, cnt);
 }
 
 // Pass A on the VALU.  Persistent grid over the cull step's item list (see the
@@ -634,6 +747,22 @@ hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
 hipError_t launch_scatter_nearest(const QuerySet* d_sets, int n_sets, hipStream_t s) {
   k_scatter_nearest<<<256, kBlock, 0, s>>>(d_sets, n_sets);
   return hipGetLastError();
+}
+
+hipError_t count_pass_b_pairs(const QuerySet* d_sets, int n_sets, const int2* items,
+                              const int32_t* item_count, const unsigned char* hitf,
+                              int64_t max_items, unsigned long long* h_pairs) {
+  const unsigned long long zero = 0;
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(pass_b_pairs), &zero, sizeof zero, 0,
+                                   hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  if (max_items > 0) {
+    k_pass_b_count<<<kPersistBlocks, kBlock, 0, 0>>>(d_sets, n_sets, items, item_count, hitf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+  return hipMemcpyFromSymbol(h_pairs, HIP_SYMBOL(pass_b_pairs), sizeof *h_pairs, 0,
+                             hipMemcpyDeviceToHost);
 }
 
 hipError_t launch_pass_b(const QuerySet* d_sets, int n_sets, const int2* items,

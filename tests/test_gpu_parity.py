@@ -437,6 +437,32 @@ def test_pass_b_subtile_reach_on_ordered_cloud():
         compare_stage1(pr, outs[2])
 
 
+def test_distance_stats_invariants():
+    """The work counts of the distance passes after one Stage-I step on the forest:
+    pass B's listed pairs are a subset of pass A's, the pairs it evaluates (groups
+    within each query's cap) a subset of those; with the cull step off, pass A covers
+    every (position, point) pair."""
+    prob = make_ensemble_problem()
+    ps = PlanStep(prob)
+    ps.front_end()
+    Q = ps.M * ps.N * ps.K
+    try:
+        for cull in (1, 0):
+            aero.set_pass_a_cull(cull)
+            ps.reset()
+            ps.stage1()
+            sync()
+            st = aero.distance_stats([ps.problem], ps.ws)
+            print(f"cull={cull}: {st}", flush=True)
+            assert st["positions"] == Q
+            assert st["pairs_a"] >= st["pairs_b"] >= st["pairs_b_eval"] > 0
+            assert st["pairs_b_eval"] < st["pairs_b"]
+            if not cull:
+                assert st["pairs_a"] == Q * ps.n_points
+    finally:
+        aero.set_pass_a_cull(1)
+
+
 def test_autotuner_settles_and_keeps_results():
     prob = make_plain_problem()
     aero.set_pass_a_variant(-1)
