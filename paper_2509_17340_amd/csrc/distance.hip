@@ -311,6 +311,61 @@ __device__ inline uint32_t pass_b_group_mask(const QuerySet& S, int64_t q, const
   return m;
 }
 
+// A unit of a single row (hu <= 64 listed queries, one per lane): the row's queries
+// stay in registers across the groups, and a group runs when some query of the row
+// needs it (with one row there is nothing to compact).  One device-memory minimum per
+// query at the end.
+template <bool kIdx, bool kSorted>
+__device__ inline void pass_b_row(const QuerySet& S, int64_t slot0, const uint16_t* qlist,
+                                  int hu, int64_t g0, int n, const float* gb, float reach,
+                                  float slack) {
+  const int lane = threadIdx.x & 63;
+  const int64_t Q = S.Q;
+  const bool on = lane < hu;
+  const int64_t q = slot0 + (on ? qlist[lane] : qlist[0]);  // always a valid position
+  float px[1] = {S.sp[q]}, py[1] = {S.sp[Q + q]}, pz[1] = {S.sp[2 * Q + q]};
+  float best[1] = {__uint_as_float(kInfBits)};
+  int32_t bidx[1] = {0x7fffffff};
+  const uint32_t m = on ? pass_b_group_mask(S, q, gb, n, reach, slack) : 0u;
+  const int ngr = (n + 31) / 32;
+  for (int g = 0; g < ngr; ++g) {  // wave-uniform
+    if (!__builtin_amdgcn_ballot_w64((m >> g) & 1u)) continue;
+    const int64_t gg = g0 + 32 * g;
+    const int gn = min(32, n - 32 * g);
+    if constexpr (kSorted) {
+      cfloat* rec = (cfloat*)(S.scloud + gg);
+      cint* irec = (cint*)(S.scloud + gg);
+      int j = 0;
+      for (; j + 4 <= gn; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          pass_b_point<1, kIdx>(rec[4 * (j + u)], rec[4 * (j + u) + 1], rec[4 * (j + u) + 2],
+                                irec[4 * (j + u) + 3], px, py, pz, best, bidx);
+      }
+      for (; j < gn; ++j)
+        pass_b_point<1, kIdx>(rec[4 * j], rec[4 * j + 1], rec[4 * j + 2], irec[4 * j + 3], px,
+                              py, pz, best, bidx);
+    } else {
+      cfloat* rec = (cfloat*)(S.cloud + 3 * gg);
+      int j = 0;
+      for (; j + 4 <= gn; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          pass_b_point<1, kIdx>(rec[3 * (j + u)], rec[3 * (j + u) + 1], rec[3 * (j + u) + 2],
+                                (int32_t)(gg + j + u), px, py, pz, best, bidx);
+      }
+      for (; j < gn; ++j)
+        pass_b_point<1, kIdx>(rec[3 * j], rec[3 * j + 1], rec[3 * j + 2], (int32_t)(gg + j), px,
+                              py, pz, best, bidx);
+    }
+  }
+  if (!on || best[0] == __uint_as_float(kInfBits)) return;  // no group within the cap
+  atomicMin(S.out_slot + q, __float_as_uint(best[0]));
+  if constexpr (kIdx)
+    atomicMin(S.nn + q, ((unsigned long long)__float_as_uint(best[0]) << 32) |
+                            (unsigned long long)(unsigned)bidx[0]);
+}
+
 // One work unit: the hu listed queries of qlist (block-local indices) against the
 // item's sub-tile (n points from point g0 on; gb: its group boxes, or nullptr to take
 // every group).  Each query takes only the groups within its cap, so the wave runs
@@ -322,6 +377,10 @@ __device__ inline void pass_b_unit(const QuerySet& S, int64_t slot0, const uint1
                                    float slack, uint16_t* glist,
                                    typename PassBBest<kIdx>::T* bl) {
   typedef typename PassBBest<kIdx>::T BestT;
+  if (hu <= 64) {  // wave-uniform
+    pass_b_row<kIdx, kSorted>(S, slot0, qlist, hu, g0, n, gb, reach, slack);
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const int nr = (hu + 63) / 64;     // rows of the unit
   const int ngr = (n + 31) / 32;     // groups of the sub-tile
