@@ -529,12 +529,33 @@ def bench_batched(n_steps):
         outs[mode] = [(s.u_nom.cpu().numpy().copy(), s.S1.cpu().numpy().copy()) for s in bp.steps]
         outs[mode].append((bp.S2.cpu().numpy().copy(), bp.best.cpu().numpy().copy()))
         log(f"batched workload {mode}: {ms:.2f} ms/step")
+    # the batched step captured as one HIP graph and replayed
+    g = bp.graph()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_steps + 1)]
+    ev[0].record()
+    for i in range(n_steps):
+        g.replay()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[-1]) / n_steps
+    p50, p99 = pcts([ev[i].elapsed_time(ev[i + 1]) for i in range(n_steps)])
+    graph_out = [(s.u_nom.cpu().numpy().copy(), s.S1.cpu().numpy().copy()) for s in bp.steps]
+    res["batched_graph"] = {
+        "ms_per_step": ms, "p50_ms": p50, "p99_ms": p99,
+        "rollout_steps_per_s": bp.rollout_steps / (ms * 1e-3),
+        "equals_eager_batched_bitwise": bool(
+            all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+                for a, b in zip(outs["batched"][:-1], graph_out))
+            and np.array_equal(bp.S2.cpu().numpy(), outs["batched"][-1][0]))}
+    log(f"batched workload graph: {ms:.2f} ms/step")
     same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
                for a, b in zip(outs["plain"][:-1], outs["batched"][:-1]))
     plain_S2 = np.concatenate([s.S2.cpu().numpy() for s in bp.steps])
     same = same and np.array_equal(plain_S2, outs["batched"][-1][0])
     res.update(problems=len(probs), rollout_steps=bp.rollout_steps, pairs_brute_force=bp.pairs,
                speedup=res["plain"]["ms_per_step"] / res["batched"]["ms_per_step"],
+               speedup_graph=res["plain"]["ms_per_step"] / res["batched_graph"]["ms_per_step"],
                batched_equals_plain_bitwise=bool(same), steps=n_steps,
                workload="64 uneven problems: forest / verticals+wall / incline scenes, "
                         "P ~ LogNormal(ln 5e4, 0.5) in [1e4, 2e5], M ~ U{4..16}, "

@@ -193,26 +193,33 @@ class BatchPlan:
         mppi_step(self.params, self.problems, self.ws)
         select_best(self.params, self.problems, self.S2, self.best, self.ws)
 
+    def graph(self, warmup=4):
+        """The batched step captured as one HIP graph (see GraphStep)."""
+        return GraphStep(self, warmup=warmup, run=self.run_batched)
+
 
 class GraphStep:
-    """A PlanStep captured once into a HIP graph (torch.cuda.CUDAGraph) and
-    replayed: reset of u_nom followed by the four library calls.  Valid while the
-    step's buffers and host inputs stay unchanged."""
+    """A PlanStep (or a BatchPlan, with run=its run_batched) captured once into a HIP
+    graph (torch.cuda.CUDAGraph) and replayed: reset of u_nom followed by the step's
+    library calls.  The warm-up runs settle the autotuner's per-shape choice (its
+    timing trials synchronize, so they must not fall inside the capture).  Valid while
+    the step's buffers and host inputs stay unchanged."""
 
-    def __init__(self, step, warmup=4):
+    def __init__(self, step, warmup=4, run=None):
         self.step = step
+        run = run or step.run
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             for _ in range(warmup):
                 step.reset()
-                step.run()
+                run()
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             step.reset()
-            step.run()
+            run()
         torch.cuda.synchronize()
 
     def replay(self):
