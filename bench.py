@@ -438,7 +438,7 @@ def bench_adjoint(prob, iters=20):
     }
     for name in ("forward", "backward", "backward_self_contained"):
         once = legs[name]
-        for _ in range(3):
+        for _ in range(7):              # past the autotuner's per-shape timing trials
             once()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -505,7 +505,7 @@ def bench_batched(n_steps):
     outs = {}
     for mode in ("plain", "batched"):
         run = bp.run_plain if mode == "plain" else bp.run_batched
-        for _ in range(4):              # past the autotuner's per-shape timing trials
+        for _ in range(7):              # past the autotuner's per-shape timing trials
             bp.reset()
             run()
         torch.cuda.synchronize()
@@ -567,7 +567,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed closed-loop poses")
-    ap.add_argument("--warmup", type=int, default=5, help="untimed closed-loop poses")
+    ap.add_argument("--warmup", type=int, default=7, help="untimed closed-loop poses")
     ap.add_argument("--poses", type=int, default=200,
                     help="length of the flight for the plan-step distribution")
     ap.add_argument("--batched", type=int, default=3,

@@ -378,9 +378,10 @@ int aero_advance_state(const aero_params* h_prm, const float* d_x0, const float*
  * implementations: 0 = VALU FMAs on blocks of 2048 positions, 1 = half-precision
  * matrix cores on hi/lo-split coordinates with blocks of 512 positions, 2 = the same
  * with blocks of 1024.  By default (-1) the library autotunes per call shape (sum of
- * M N K, sum of cloud sizes, problem count): the first three calls of a shape each
- * time one variant with HIP events on the call's stream, a later call keeps the
- * fastest for that shape.  Costs, controls and selections are bitwise identical for
+ * M N K, sum of cloud sizes, problem count) over five launch configurations (variant
+ * 0 on 1024 persistent workgroups, variants 1 and 2 on 4096 and on 1024): the first
+ * five calls of a shape each time one configuration with HIP events on the call's
+ * stream, a later call keeps the fastest for that shape.  Costs, controls and selections are bitwise identical for
  * every variant, with or without the cull step; only min_dist2 and nearest_idx
  * entries beyond d_max may differ.  While the stream is being captured into a graph
  * an unsettled shape uses variant 0 and records nothing.
@@ -390,6 +391,11 @@ int aero_set_pass_a_variant(int variant);
 
 /* The variant in use for this call shape: 0, 1 or 2, or -1 while still being tuned. */
 int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems);
+/* The persistent workgroups the tuner settled on for pass A at the shape of these
+ * problems (it times each variant at two grid sizes, 1024 and 4096 workgroups for
+ * the matrix-core variants), the forced variant's default grid, or -1 while the shape
+ * is not settled. */
+int aero_pass_a_grid(const aero_problem* h_problems, int32_t n_problems);
 
 /* on = 1 (default): the cull step lists only the sub-tiles within reach of each block;
  * on = 0: every sub-tile of every block (the two passes become brute force over the

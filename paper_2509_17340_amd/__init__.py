@@ -20,7 +20,7 @@ __all__ = [
     "build_guides", "filtered_cloud", "workspace_size", "mppi_step", "select_best", "mppi_step_backward",
     "CALL_MPPI_STEP", "CALL_SELECT_BEST", "CALL_BACKWARD", "timing_enable", "timing_read",
     "KERNELS", "shift_controls", "step_candidates", "set_pass_a_variant", "pass_a_variant",
-    "set_pass_a_cull", "distance_stats", "FrontEndJob", "front_end_job", "front_end",
+    "set_pass_a_cull", "distance_stats", "pass_a_grid", "FrontEndJob", "front_end_job", "front_end",
     "front_end_workspace_size",
     "use_library", "accumulate_cloud", "advance_state", "mppi_step_backward_indexed",
 ]
@@ -111,6 +111,7 @@ _SIGS = {
     "aero_step_candidates": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_int32, _P, _P]),
     "aero_pass_a_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "aero_pass_a_grid": (ctypes.c_int, [_P, ctypes.c_int32]),
     "aero_accumulate_cloud": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32,
                                              ctypes.c_int32, _P, _P, _P, _P]),
     "aero_advance_state": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
@@ -475,6 +476,12 @@ def distance_stats(problems, ws, ws_bytes=None):
 def pass_a_variant(problems):
     arr = _problem_array(problems)
     return int(_lib.aero_pass_a_variant(ctypes.cast(arr, ctypes.c_void_p), len(problems)))
+
+
+def pass_a_grid(problems):
+    """Persistent workgroups of the settled pass-A configuration (-1 while tuning)."""
+    arr = _problem_array(problems)
+    return int(_lib.aero_pass_a_grid(ctypes.cast(arr, ctypes.c_void_p), len(problems)))
 
 
 def timing_enable(on=True):

@@ -39,6 +39,17 @@ constexpr int kPassAF16s8 = 2;   //   the same with 8 column blocks: 1024 per bl
 constexpr int kPassAVariants = 3;
 constexpr int kPassAQPB[kPassAVariants] = {kQueriesPerBlock, 4 * 32 * 4, 4 * 32 * 8};
 constexpr int kPassAMinQPB = 4 * 32 * 4;
+// Launch configurations the autotuner chooses among: a pass-A variant and the number
+// of persistent workgroups it runs with.  Configuration v < kPassAVariants is variant
+// v at its default grid (a forced variant runs that).
+struct PassAConfig {
+  int variant;
+  int grid;
+};
+constexpr int kPassAConfigs = 5;
+constexpr PassAConfig kPassAConf[kPassAConfigs] = {
+    {kPassAValu, 1024}, {kPassAF16s4, 4096}, {kPassAF16s8, 4096},
+    {kPassAF16s4, 1024}, {kPassAF16s8, 1024}};
 // Pass B gives each lane at most kQueriesPerLane queries of one pass-A block.
 static_assert(kQueriesPerBlock <= kQueriesPerLane * kBlock && kPassAMinQPB <= kQueriesPerBlock &&
                   4 * 32 * 8 <= kQueriesPerBlock, "pass-A blocks must fit one pass-B block");
@@ -304,10 +315,10 @@ hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blo
 // every two-pass set of the call); max_items bounds the list (the grid is sized by it).
 hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
                          const int32_t* item_count, unsigned char* hitf, int64_t max_items,
-                         int variant, hipStream_t s);
+                         int variant, int grid, hipStream_t s);
 hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* items,
                                 const int32_t* item_count, unsigned char* hitf, int64_t max_items,
-                                int variant, hipStream_t s);
+                                int variant, int grid, hipStream_t s);
 // Pass B over the marked items (the hit words of every set of the call share one array);
 // track_nearest: some set keeps nearest indices (nn).
 // Pairs pass B evaluates on the items of the last call (synchronous, null stream).

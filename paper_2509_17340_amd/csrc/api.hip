@@ -72,11 +72,12 @@ hipError_t timed(int kernel, hipStream_t s, F&& launch) {
 }
 
 // ---------------------------------------------------------------------------
-// Online autotuner of the pass-A variant, keyed by the call's shape.  The first
-// kPassAVariants calls of a shape time one variant each with HIP events; the next
-// reads them all and keeps the fastest.  Every variant yields bitwise-identical costs and
-// controls, so tuning never changes results.  While a stream is being captured
-// into a graph no events are recorded and an unsettled shape uses the VALU pass.
+// Online autotuner of the pass-A launch configuration (variant and persistent grid,
+// kPassAConf), keyed by the call's shape.  The first kPassAConfigs calls of a shape
+// time one configuration each with HIP events; the next reads them all and keeps the
+// fastest.  Every configuration yields bitwise-identical costs and controls, so
+// tuning never changes results.  While a stream is being captured into a graph no
+// events are recorded and an unsettled shape uses the VALU pass.
 // ---------------------------------------------------------------------------
 struct TuneKey {
   int64_t q, p;
@@ -88,8 +89,8 @@ struct TuneKey {
 struct TuneState {
   int trials = 0;
   int choice = -1;
-  hipEvent_t ev[kPassAVariants][2] = {};
-  float ms[kPassAVariants] = {};
+  hipEvent_t ev[kPassAConfigs][2] = {};
+  float ms[kPassAConfigs] = {};
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneState> g_tune;
@@ -104,16 +105,18 @@ TuneKey tune_key(const aero_problem* h, int n) {
   return k;
 }
 
-// The forced or already settled variant of a shape, else the VALU pass (no trials).
-int settled_variant(const TuneKey& key) {
+// The forced or already settled configuration of a shape, else the VALU pass (no
+// trials).
+int settled_config(const TuneKey& key) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (g_forced_variant >= 0) return g_forced_variant;
   auto it = g_tune.find(key);
   return (it != g_tune.end() && it->second.choice >= 0) ? it->second.choice : kPassAValu;
 }
 
-// Variant for this call; *ev receives the event pair to record around pass A (or null).
-int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
+// Configuration for this call; *ev receives the event pair to record around pass A
+// (or null).
+int pick_config(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
   *ev = nullptr;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (g_forced_variant >= 0) return g_forced_variant;
@@ -122,7 +125,7 @@ int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return kPassAValu;
-  if (st.trials < kPassAVariants) {
+  if (st.trials < kPassAConfigs) {
     const int v = st.trials;
     if (hipEventCreate(&st.ev[v][0]) != hipSuccess || hipEventCreate(&st.ev[v][1]) != hipSuccess)
       return kPassAValu;
@@ -132,10 +135,10 @@ int pick_variant(const TuneKey& key, hipStream_t s, hipEvent_t** ev) {
   }
   // the trials are read without waiting: while the last one is still in flight this
   // call runs the VALU pass and a later call settles the shape
-  for (int v = 0; v < kPassAVariants; ++v)
+  for (int v = 0; v < kPassAConfigs; ++v)
     if (hipEventQuery(st.ev[v][1]) == hipErrorNotReady) return kPassAValu;
   int best = kPassAValu;
-  for (int v = 0; v < kPassAVariants; ++v) {
+  for (int v = 0; v < kPassAConfigs; ++v) {
     if (hipEventElapsedTime(&st.ms[v], st.ev[v][0], st.ev[v][1]) != hipSuccess)
       st.ms[v] = 1e30f;
     hipEventDestroy(st.ev[v][0]);
@@ -477,8 +480,9 @@ std::vector<char> mppi_blob(const MppiPlan& pl, int n) {
 
 // The distance passes of a planned Stage-I call: the spatial sorts, the cull step,
 // pass A (timed by `tev` when given) and pass B.
-hipError_t run_distance(const MppiPlan& pl, int n, int variant, hipEvent_t* tev, hipStream_t s) {
+hipError_t run_distance(const MppiPlan& pl, int n, int cfg, hipEvent_t* tev, hipStream_t s) {
   hipError_t he = hipSuccess;
+  const int variant = kPassAConf[cfg].variant;
   if (pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
                [&] { return launch_spatial_sort(pl.d_sorts, 2 * n, pl.sort_blocks, s); });
@@ -492,7 +496,7 @@ hipError_t run_distance(const MppiPlan& pl, int n, int variant, hipEvent_t* tev,
   if (he == hipSuccess && pl.item_cap > 0)
     he = timed(AERO_K_MIN_DIST, s, [&] {
       return launch_pass_a(pl.d_sets, n, pl.items, pl.item_count, pl.hitf, pl.item_cap, variant,
-                           s);
+                           kPassAConf[cfg].grid, s);
     });
   if (he == hipSuccess && tev) he = hipEventRecord(tev[1], s);
   if (he == hipSuccess && pl.item_cap > 0)
@@ -927,8 +931,8 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   if (!d_ws || ws_bytes < pl.bytes) return AERO_ERR_WORKSPACE;
   const hipStream_t s = (hipStream_t)stream;
   hipEvent_t* tev = nullptr;
-  const int variant = pick_variant(tune_key(h, n), s, &tev);
-  plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl, variant, true);
+  const int cfg = pick_config(tune_key(h, n), s, &tev);
+  plan_mppi(h, n, (char*)d_ws, h_prm->d_max, pl, kPassAConf[cfg].variant, true);
   const DevParams prm = promote(*h_prm);
   // One staged copy for both descriptor arrays (they are adjacent in the workspace).
   const std::vector<char> blob = mppi_blob(pl, n);
@@ -936,7 +940,7 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
     return launch_rollout_noise(pl.d_probs, n, pl.total_samples, pl.total_elems, prm, pl.d_sets,
                                 pl.total_tiles, blob.data(), blob.size(), s);
   });
-  if (he == hipSuccess) he = run_distance(pl, n, variant, tev, s);
+  if (he == hipSuccess) he = run_distance(pl, n, cfg, tev, s);
   if (he == hipSuccess && pl.any_nn)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, n, s); });
   if (he == hipSuccess)
@@ -1001,9 +1005,9 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h,
   BackwardPlan bp;
   plan_backward(h, nullptr, h_prm->d_max, bp);
   if (!d_ws || ws_bytes < bp.bytes) return AERO_ERR_WORKSPACE;
-  // pass A only filters; the shape's tuned forward variant serves here too
-  const int variant = settled_variant(tune_key(h, 1));
-  plan_backward(h, (char*)d_ws, h_prm->d_max, bp, variant);
+  // pass A only filters; the shape's tuned forward configuration serves here too
+  const int cfg = settled_config(tune_key(h, 1));
+  plan_backward(h, (char*)d_ws, h_prm->d_max, bp, kPassAConf[cfg].variant);
   MppiPlan& pl = bp.fwd;
   const hipStream_t s = (hipStream_t)stream;
   const DevParams prm = promote(*h_prm);
@@ -1014,7 +1018,7 @@ int aero_mppi_step_backward(const aero_params* h_prm, const aero_problem* h,
     return launch_rollout_noise(pl.d_probs, 1, pl.total_samples, pl.total_elems, prm, pl.d_sets,
                                 pl.total_tiles, blob.data(), blob.size(), s);
   });
-  if (he == hipSuccess) he = run_distance(pl, 1, variant, nullptr, s);
+  if (he == hipSuccess) he = run_distance(pl, 1, cfg, nullptr, s);
   if (he == hipSuccess && q.n_points > 0)
     he = timed(AERO_K_NEAREST, s, [&] { return launch_scatter_nearest(pl.d_sets, 1, s); });
   if (he == hipSuccess)
@@ -1207,7 +1211,17 @@ int aero_pass_a_variant(const aero_problem* h_problems, int32_t n_problems) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (g_forced_variant >= 0) return g_forced_variant;
   auto it = g_tune.find(tune_key(h_problems, n_problems));
-  return it == g_tune.end() ? -1 : it->second.choice;
+  return (it == g_tune.end() || it->second.choice < 0) ? -1
+                                                        : kPassAConf[it->second.choice].variant;
+}
+
+int aero_pass_a_grid(const aero_problem* h_problems, int32_t n_problems) {
+  if (!h_problems || n_problems < 1) return -1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_forced_variant >= 0) return kPassAConf[g_forced_variant].grid;
+  auto it = g_tune.find(tune_key(h_problems, n_problems));
+  return (it == g_tune.end() || it->second.choice < 0) ? -1
+                                                        : kPassAConf[it->second.choice].grid;
 }
 
 int aero_timing_enable(int on) {

@@ -655,7 +655,6 @@ __global__ __launch_bounds__(kBlock) void k_pass_b_count(const QuerySet* __restr
 // item, the block's queries whose value came under the bound form the item's hit
 // words (query r kBlock + tid is bit (r kBlock + tid) % 32 of word
 // (r kBlock + tid) / 32).
-constexpr int kPassAGridValu = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restrict__ sets,
                                                         int n_sets, const int2* __restrict__ items,
@@ -794,12 +793,13 @@ hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blo
 
 hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,
                          const int32_t* item_count, unsigned char* hitf, int64_t max_items,
-                         int variant, hipStream_t s) {
+                         int variant, int grid, hipStream_t s) {
   if (max_items <= 0) return hipSuccess;
   if (variant == kPassAF16s4 || variant == kPassAF16s8)
-    return launch_pass_a_matrix(d_sets, n_sets, items, item_count, hitf, max_items, variant, s);
-  const unsigned grid = (unsigned)(max_items < kPassAGridValu ? max_items : kPassAGridValu);
-  k_pass_a_valu<<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
+    return launch_pass_a_matrix(d_sets, n_sets, items, item_count, hitf, max_items, variant,
+                                grid, s);
+  const unsigned g = (unsigned)(max_items < grid ? max_items : grid);
+  k_pass_a_valu<<<g, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
   return hipGetLastError();
 }
 

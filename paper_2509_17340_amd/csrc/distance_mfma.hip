@@ -51,12 +51,7 @@ namespace {
 #endif
 constexpr int kF16Pipe = AERO_F16_PIPE;  // products reduced together
 constexpr float kF16FarT = 32768.0f;
-#ifndef AERO_PASS_A_GRID
-#define AERO_PASS_A_GRID 4096
-#endif
-// persistent workgroups: 16 per CU, so that the ranges of items they take are short
-// and the CUs finish together
-constexpr int kPassAGrid = AERO_PASS_A_GRID;
+
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -260,9 +255,10 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
 
 hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* items,
                                 const int32_t* item_count, unsigned char* hitf, int64_t max_items,
-                                int variant, hipStream_t s) {
+                                int variant, int grid_max, hipStream_t s) {
   if (max_items > 0) {
-    const unsigned grid = (unsigned)(max_items < kPassAGrid ? max_items : kPassAGrid);
+    // persistent workgroups (the autotuner's choice), each over a range of items
+    const unsigned grid = (unsigned)(max_items < grid_max ? max_items : grid_max);
     if (variant == kPassAF16s4)
       k_pass_a_f16s<4><<<grid, kBlock, 0, s>>>(d_sets, n_sets, items, item_count, hitf);
     else

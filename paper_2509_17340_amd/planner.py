@@ -193,7 +193,7 @@ class BatchPlan:
         mppi_step(self.params, self.problems, self.ws)
         select_best(self.params, self.problems, self.S2, self.best, self.ws)
 
-    def graph(self, warmup=4):
+    def graph(self, warmup=7):
         """The batched step captured as one HIP graph (see GraphStep)."""
         return GraphStep(self, warmup=warmup, run=self.run_batched)
 
@@ -205,7 +205,7 @@ class GraphStep:
     timing trials synchronize, so they must not fall inside the capture).  Valid while
     the step's buffers and host inputs stay unchanged."""
 
-    def __init__(self, step, warmup=4, run=None):
+    def __init__(self, step, warmup=7, run=None):
         self.step = step
         run = run or step.run
         s = torch.cuda.Stream()

@@ -75,7 +75,7 @@ def test_batched_uneven_64_against_oracle():
     best = torch.empty(len(probs), dtype=torch.int32, device="cuda")
     aero.set_pass_a_variant(-1)
     runs = []
-    for r in range(5):  # the autotuner's three trials, then its choice
+    for r in range(7):  # the autotuner's five trials, then its choice
         for s in steps:
             s.reset()
         aero.mppi_step(probs[0]["params"], pr, ws)

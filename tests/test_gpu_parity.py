@@ -469,14 +469,16 @@ def test_autotuner_settles_and_keeps_results():
     ps = PlanStep(prob)
     ps.front_end()
     res = []
-    for i in range(5):
+    for i in range(7):  # five timed configurations, then the choice
         ps.reset()
         ps.stage1()
         sync()
         res.append((np_(ps.S1), np_(ps.u_nom)))
     v = aero.pass_a_variant([ps.problem])
-    print(f"autotuned pass-A variant: {v}")
+    g = aero.pass_a_grid([ps.problem])
+    print(f"autotuned pass-A variant: {v}, {g} workgroups")
     assert v in (0, 1, 2)
+    assert g in (1024, 4096)
     for r in res[1:]:
         assert np.array_equal(r[0], res[0][0]) and np.array_equal(r[1], res[0][1])
 
