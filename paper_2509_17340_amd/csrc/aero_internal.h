@@ -95,6 +95,10 @@ struct DevProblem {
 // near the positions get fine cells and the far ones collect in boundary cells).
 constexpr int kSortDigits = 256;
 constexpr int kSortPasses = 2;
+// Elements per thread of a sort workgroup (1, 2, 4 or 8; tiles of that many times
+// kBlock): the most that still leaves the call about kSortMinGrid tiles.
+constexpr int kSortMaxPerThread = 8;
+constexpr int64_t kSortMinGrid = 1024;
 struct SortSet {
   const float* px;       // element i at px[i * stride] (planes: stride 1; cloud: stride 3)
   const float* py;
@@ -102,7 +106,7 @@ struct SortSet {
   float* sp;             // positions: [3][Q] in slot order (written by the last pass)
   int64_t Q;
   int64_t block_base;    // prefix of n_blocks over sets
-  int32_t n_blocks;      // ceil(Q / kBlock)
+  int32_t n_blocks;      // ceil(Q / tile), tile = kBlock x the call's elements per thread
   int32_t stride;
   unsigned* box;         // [kBoxCopies][kBoxStride] copies; words 0..5 of each hold the
                          //   order-preserving bits of min x, y, z, max x, y, z
@@ -274,7 +278,7 @@ __device__ inline void load_weights(const float* w_dev, DevParams& prm) {
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total_blocks,
-                               hipStream_t s);
+                               int per_thread, hipStream_t s);
 hipError_t launch_accumulate_cloud(const float* ring, int64_t ring_points, const int32_t* start,
                                    const int32_t* offsets, int F, int64_t n_points,
                                    const float* poses, const float* origin, float* out,

@@ -243,9 +243,16 @@ struct Cursor {
   }
 };
 
-// Fewest cloud tiles for which the positions (and the cloud) are spatially sorted
-// before the cull step.
+// Fewest cloud tiles, and fewest positions, for which the positions (and the cloud)
+// are spatially sorted before the cull step.  A few thousand positions make a few
+// query blocks: sorting the whole cloud for them costs more than it saves.
 constexpr int kSortMinTiles = 16;
+constexpr int64_t kSortMinQueries = 8192;
+
+bool sorts(const aero_problem& q) {
+  return q.n_points > 0 && ((int64_t)q.n_points + kTilePts - 1) / kTilePts >= kSortMinTiles &&
+         (int64_t)q.M * q.N * q.K >= kSortMinQueries;
+}
 
 // Split P points into about `want` chunks of a multiple of `align` points (exact sets).
 void set_chunks(int64_t P, int64_t want, int32_t& n_chunks, int32_t& chunk_pts,
@@ -274,6 +281,7 @@ struct MppiPlan {
   SortSet* d_sorts = nullptr;   // adjacent to d_sets: one descriptor upload
   int64_t total_samples = 0, total_rows = 0;
   int64_t sort_blocks = 0;
+  int sort_per_thread = 1;      // elements per thread of the sort's tiles
   int64_t total_tiles = 0;      // cloud tiles of the two-pass sets (box launches)
   int64_t total_qblocks = 0;    // query blocks of the two-pass sets (cull launch)
   int64_t item_cap = 0;         // capacity of the call's item list
@@ -319,6 +327,16 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   pl.mask_words = cap > 0 ? std::max<int64_t>(int64_t(1) << 20, 2 * cap) : 0;
   pl.hmask = cur.take<uint32_t>(pl.mask_words);
   int64_t sort_blocks = 0, eb = 0, sb = 0, rb = 0, qbb = 0, tb = 0;
+  // the sort's tile: as many elements per thread as still leave about kSortMinGrid
+  // tiles over the call's sorted positions and clouds
+  int64_t sort_elems = 0;
+  for (int b = 0; b < n; ++b)
+    if (sorts(h[b]))
+      sort_elems += (int64_t)h[b].M * h[b].N * h[b].K + h[b].n_points;
+  int spt = 1;
+  while (spt < kSortMaxPerThread && sort_elems / (2 * spt * kBlock) >= kSortMinGrid) spt *= 2;
+  pl.sort_per_thread = spt;
+  const int64_t sort_tile = (int64_t)spt * kBlock;
   for (int b = 0; b < n; ++b) {
     const aero_problem& q = h[b];
     DevProblem& d = pl.probs[b];
@@ -395,13 +413,13 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     SortSet& so = pl.sorts[2 * b];
     SortSet& sc = pl.sorts[2 * b + 1];
     so.block_base = sort_blocks;
-    if (two_pass && n_tiles >= kSortMinTiles) {
+    if (two_pass && sorts(q)) {
       so.px = qs.px;
       so.py = qs.py;
       so.pz = qs.pz;
       so.stride = 1;
       so.Q = MNK;
-      so.n_blocks = (int32_t)((MNK + kBlock - 1) / kBlock);
+      so.n_blocks = (int32_t)((MNK + sort_tile - 1) / sort_tile);
       so.box = cur.take<unsigned>(kBoxCopies * kBoxStride);
       so.key[0] = cur.take<uint32_t>(MNK);
       so.key[1] = cur.take<uint32_t>(MNK);
@@ -427,7 +445,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       sc.pz = q.cloud ? q.cloud + 2 : nullptr;
       sc.stride = 3;
       sc.Q = P;
-      sc.n_blocks = (int32_t)((P + kBlock - 1) / kBlock);
+      sc.n_blocks = (int32_t)((P + sort_tile - 1) / sort_tile);
       sc.box = so.box;
       sc.margin = d_max + 1.0f;
       sc.key[0] = cur.take<uint32_t>(P);
@@ -485,7 +503,10 @@ hipError_t run_distance(const MppiPlan& pl, int n, int cfg, hipEvent_t* tev, hip
   const int variant = kPassAConf[cfg].variant;
   if (pl.sort_blocks > 0)
     he = timed(AERO_K_SORT, s,
-               [&] { return launch_spatial_sort(pl.d_sorts, 2 * n, pl.sort_blocks, s); });
+               [&] {
+                 return launch_spatial_sort(pl.d_sorts, 2 * n, pl.sort_blocks, pl.sort_per_thread,
+                                            s);
+               });
   if (he == hipSuccess && pl.total_qblocks > 0)
     he = timed(AERO_K_CULL, s, [&] {
       hipError_t e = pl.any_scloud ? launch_sorted_boxes(pl.d_sets, n, pl.total_tiles, s)

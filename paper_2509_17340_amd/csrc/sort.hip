@@ -42,21 +42,26 @@ __device__ inline uint32_t spread3(uint32_t v) {
   return v;
 }
 
-struct Elem {
+// The block's tile: R elements per thread (R kBlock per tile, chosen per call so that
+// the call has enough tiles to fill the GPU), element r * kBlock + threadIdx.x of the
+// tile in slice r (slices in index order, so ranks taken slice by slice keep the
+// original order among equal digits).
+struct Tile {
   int s;          // set
-  int64_t blk;    // block within the set
-  int64_t i;      // element within the set
-  bool active;
+  int64_t blk;    // tile within the set
+  int64_t i0;     // first element of the tile
+  int n;          // elements of the tile
 };
 
-__device__ inline Elem locate(const SortSet* sets, int n_sets) {
+template <int R>
+__device__ inline Tile locate(const SortSet* sets, int n_sets) {
   const int64_t bid = blockIdx.x;
-  Elem e;
-  e.s = find_owner(sets, n_sets, bid, [](const SortSet& q) { return q.block_base; });
-  e.blk = bid - sets[e.s].block_base;
-  e.i = e.blk * kBlock + threadIdx.x;
-  e.active = e.i < sets[e.s].Q;
-  return e;
+  Tile t;
+  t.s = find_owner(sets, n_sets, bid, [](const SortSet& q) { return q.block_base; });
+  t.blk = bid - sets[t.s].block_base;
+  t.i0 = t.blk * (R * kBlock);
+  t.n = (int)min<int64_t>(R * kBlock, sets[t.s].Q - t.i0);
+  return t;
 }
 
 // Morton key of an element from its position and the key box (the set's bounding
@@ -95,25 +100,33 @@ __device__ inline void wave_rank(bool active, uint32_t dig, int& rank, int& coun
   count = __popcll(match);
 }
 
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict__ sets, int n_sets,
                                                       int pass, int src) {
   __shared__ int hist[kWaves][kSortDigits];
   __shared__ unsigned box[6];
-  const Elem e = locate(sets, n_sets);
-  const SortSet& S = sets[e.s];
+  const Tile t = locate<R>(sets, n_sets);
+  const SortSet& S = sets[t.s];
   for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
-  // this element's input, loaded before the barrier so that its latency overlaps the
-  // merge of the box copies
-  float p[3] = {0.0f, 0.0f, 0.0f};
-  uint32_t key = 0;
-  if (e.active) {
-    if (pass == 0) {
-      const int64_t at = e.i * S.stride;
-      p[0] = S.px[at];
-      p[1] = S.py[at];
-      p[2] = S.pz[at];
-    } else {
-      key = S.key[src][e.i];
+  // this thread's inputs, loaded before the barrier so that their latency overlaps
+  // the merge of the box copies
+  float p[R][3];
+  uint32_t key[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = r * kBlock + threadIdx.x;
+    const int64_t i = t.i0 + j;
+    p[r][0] = p[r][1] = p[r][2] = 0.0f;
+    key[r] = 0;
+    if (j < t.n) {
+      if (pass == 0) {
+        const int64_t at = i * S.stride;
+        p[r][0] = S.px[at];
+        p[r][1] = S.py[at];
+        p[r][2] = S.pz[at];
+      } else {
+        key[r] = S.key[src][i];
+      }
     }
   }
   if (pass == 0 && threadIdx.x < 6) {  // merge the box copies (minima, then maxima)
@@ -128,22 +141,34 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const SortSet* __restrict_
   __syncthreads();
   AERO_GLOBAL int32_t* __restrict__ table = global_ptr(S.table);
   const int64_t n_blocks = S.n_blocks;
-  if (e.active && pass == 0) {  // the first pass also builds the keys
-    key = morton_key(box, S.margin, p);
+  const int w = threadIdx.x >> 6;
+  if (pass == 0) {  // the first pass also builds the keys
     AERO_GLOBAL uint32_t* __restrict__ key0 = global_ptr(S.key[0]);
     AERO_GLOBAL int32_t* __restrict__ val0 = global_ptr(S.val[0]);
-    key0[e.i] = key;
-    val0[e.i] = (int32_t)e.i;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = r * kBlock + threadIdx.x;
+      if (j < t.n) {
+        key[r] = morton_key(box, S.margin, p[r]);
+        key0[t.i0 + j] = key[r];
+        val0[t.i0 + j] = (int32_t)(t.i0 + j);
+      }
+    }
   }
-  const uint32_t dig = (key >> (kSortShift0 + 8 * pass)) & 0xffu;
-  int rank, count;
-  wave_rank(e.active, dig, rank, count);
-  if (e.active && rank == 0) hist[threadIdx.x >> 6][dig] = count;
+  // the wave's digit counts over its slices (the wave's own row: no barrier needed)
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool on = r * kBlock + (int)threadIdx.x < t.n;
+    const uint32_t dig = (key[r] >> (kSortShift0 + 8 * pass)) & 0xffu;
+    int rank, count;
+    wave_rank(on, dig, rank, count);
+    if (on && rank == 0) hist[w][dig] += count;
+  }
   __syncthreads();
   for (int d = threadIdx.x; d < kSortDigits; d += kBlock) {
     int tot = 0;
-    for (int w = 0; w < kWaves; ++w) tot += hist[w][d];
-    table[(int64_t)d * n_blocks + e.blk] = tot;
+    for (int u = 0; u < kWaves; ++u) tot += hist[u][d];
+    table[(int64_t)d * n_blocks + t.blk] = tot;
   }
 }
 
@@ -190,62 +215,116 @@ __global__ __launch_bounds__(kBlock) void k_sort_rowscan(const SortSet* __restri
   if (threadIdx.x == 0) S.rowsum[d] = total;
 }
 
+// Scatter of one pass: the tile's elements are ranked slice by slice (stable), placed
+// in LDS in digit order, and written out from there, so that consecutive threads
+// store consecutive addresses of a digit's run.
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restrict__ sets,
                                                          int n_sets, int pass, int src) {
-  __shared__ int hist[kWaves][kSortDigits];
-  __shared__ int base[kSortDigits];
-  const Elem e = locate(sets, n_sets);
-  const SortSet& S = sets[e.s];
-  for (int k = threadIdx.x; k < kWaves * kSortDigits; k += kBlock) (&hist[0][0])[k] = 0;
-  // this element's key and value, loaded before the scan so that their latency
-  // overlaps it
-  const uint32_t k = e.active ? S.key[src][e.i] : 0u;
-  const int32_t v = e.active ? S.val[src][e.i] : 0;
-  // digit bases: exclusive scan of the digit totals (kBlock == kSortDigits)
+  __shared__ int hist[2][kWaves][kSortDigits];  // per slice (two in flight)
+  __shared__ int run[kSortDigits];   // elements of each digit in the earlier slices
+  __shared__ int dstart[kSortDigits];  // first LDS slot of each digit
+  __shared__ int64_t gbase[kSortDigits];  // output position of each digit's first element
+  __shared__ uint32_t sk[R > 1 ? R * kBlock : 1];
+  __shared__ int32_t sv[R > 1 ? R * kBlock : 1];
+  const Tile t = locate<R>(sets, n_sets);
+  const SortSet& S = sets[t.s];
+  for (int k = threadIdx.x; k < 2 * kWaves * kSortDigits; k += kBlock) (&hist[0][0][0])[k] = 0;
+  run[threadIdx.x] = 0;
+  // this thread's keys and values, loaded before the scans so that their latency
+  // overlaps them
+  uint32_t key[R];
+  int32_t val[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = r * kBlock + threadIdx.x;
+    key[r] = j < t.n ? S.key[src][t.i0 + j] : 0u;
+    val[r] = j < t.n ? S.val[src][t.i0 + j] : 0;
+  }
+  // digit bases: exclusive scan of the digit totals (kBlock == kSortDigits), plus the
+  // tile's offset among the tiles
   int total;
-  base[threadIdx.x] = block_exclusive_scan(S.rowsum[threadIdx.x], &total);
-  __syncthreads();
-  const uint32_t dig = (k >> (kSortShift0 + 8 * pass)) & 0xffu;
-  int rank, count;
-  wave_rank(e.active, dig, rank, count);
+  const int64_t db = block_exclusive_scan(S.rowsum[threadIdx.x], &total);
+  gbase[threadIdx.x] = db + S.table[(int64_t)threadIdx.x * S.n_blocks + t.blk];
   const int w = threadIdx.x >> 6;
-  if (e.active && rank == 0) hist[w][dig] = count;
-  __syncthreads();
-  if (e.active) {
-    int before = 0;
-    for (int u = 0; u < w; ++u) before += hist[u][dig];
-    const int64_t pos = (int64_t)base[dig] + S.table[(int64_t)dig * S.n_blocks + e.blk] + before +
-                        rank;
-    const int64_t Q = S.Q;
-    if (pos >= 0 && pos < Q) {  // always true for consistent counts; never write outside
-      // every field used below is read before the first store (a store could alias
-      // the descriptor and force it to be read again behind the stores)
-      AERO_GLOBAL uint32_t* __restrict__ key_out = global_ptr(S.key[1 - src]);
-      AERO_GLOBAL int32_t* __restrict__ val_out = global_ptr(S.val[1 - src]);
-      const bool last = pass == kSortPasses - 1 && v >= 0 && v < Q;
-      AERO_GLOBAL int32_t* __restrict__ inv = global_ptr(S.inv);
-      AERO_GLOBAL float* __restrict__ sp = global_ptr(S.sp);
-      float4* __restrict__ sc = S.sc;
-      float p[3] = {0.0f, 0.0f, 0.0f};
-      if (last) {
-        const int64_t at = (int64_t)v * S.stride;
-        p[0] = S.px[at];
-        p[1] = S.py[at];
-        p[2] = S.pz[at];
+  int lr[R];  // rank of each element among the tile's elements of its digit
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool on = r * kBlock + (int)threadIdx.x < t.n;
+    const uint32_t dig = (key[r] >> (kSortShift0 + 8 * pass)) & 0xffu;
+    int rank, count;
+    wave_rank(on, dig, rank, count);
+    int(*h)[kSortDigits] = hist[r & 1];
+    if (on && rank == 0) h[w][dig] = count;
+    __syncthreads();  // this slice's counts (and, at r = 0, the cleared rows) are in
+    int before = run[dig];
+    for (int u = 0; u < w; ++u) before += h[u][dig];
+    lr[r] = before + rank;
+    __syncthreads();  // every lane has read run and this slice's counts
+    {
+      const int d = threadIdx.x;
+      int add = 0;
+      for (int u = 0; u < kWaves; ++u) {
+        add += h[u][d];
+        h[u][d] = 0;  // the row serves slice r + 2 next
       }
-      key_out[pos] = k;
-      val_out[pos] = v;
-      if (last && sc) {
-        // a cloud: the points in key order with their original index
-        sc[pos] = make_float4(p[0], p[1], p[2], __int_as_float(v));
-      } else if (last) {
-        // the inverse permutation, and the positions in slot order for the
-        // distance passes (read there without a gather through the permutation)
-        inv[v] = (int32_t)pos;
-        sp[pos] = p[0];
-        sp[Q + pos] = p[1];
-        sp[2 * Q + pos] = p[2];
-      }
+      run[d] += add;
+    }
+  }
+  __syncthreads();  // run holds the tile's digit totals
+  if constexpr (R > 1) {  // stage the tile in digit order
+    int tt;
+    dstart[threadIdx.x] = block_exclusive_scan(run[threadIdx.x], &tt);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r * kBlock + (int)threadIdx.x >= t.n) continue;
+      const uint32_t dig = (key[r] >> (kSortShift0 + 8 * pass)) & 0xffu;
+      const int at = dstart[dig] + lr[r];
+      sk[at] = key[r];
+      sv[at] = val[r];
+    }
+    __syncthreads();
+  }
+  // every field used below is read before the first store (a store could alias the
+  // descriptor and force it to be read again behind the stores)
+  AERO_GLOBAL uint32_t* __restrict__ key_out = global_ptr(S.key[1 - src]);
+  AERO_GLOBAL int32_t* __restrict__ val_out = global_ptr(S.val[1 - src]);
+  AERO_GLOBAL int32_t* __restrict__ inv = global_ptr(S.inv);
+  AERO_GLOBAL float* __restrict__ sp = global_ptr(S.sp);
+  float4* __restrict__ sc = S.sc;
+  const float* __restrict__ px = S.px;
+  const float* __restrict__ py = S.py;
+  const float* __restrict__ pz = S.pz;
+  const int64_t stride = S.stride;
+  const int64_t Q = S.Q;
+  const bool last_pass = pass == kSortPasses - 1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = r * kBlock + threadIdx.x;
+    if (j >= t.n) continue;
+    // one element per thread: written from registers (a tile of one slice gains
+    // nothing from staging)
+    const uint32_t k = R > 1 ? sk[j] : key[r];
+    const int32_t v = R > 1 ? sv[j] : val[r];
+    const uint32_t dig = (k >> (kSortShift0 + 8 * pass)) & 0xffu;
+    const int64_t pos = gbase[dig] + (R > 1 ? j - dstart[dig] : lr[r]);
+    if (pos < 0 || pos >= Q) continue;  // never for consistent counts; never write outside
+    key_out[pos] = k;
+    val_out[pos] = v;
+    if (!last_pass || v < 0 || v >= Q) continue;
+    const int64_t at = (int64_t)v * stride;
+    const float x = px[at], y = py[at], z = pz[at];
+    if (sc) {
+      // a cloud: the points in key order with their original index
+      sc[pos] = make_float4(x, y, z, __int_as_float(v));
+    } else {
+      // the inverse permutation, and the positions in slot order for the distance
+      // passes (read there without a gather through the permutation)
+      inv[v] = (int32_t)pos;
+      sp[pos] = x;
+      sp[Q + pos] = y;
+      sp[2 * Q + pos] = z;
     }
   }
 }
@@ -253,15 +332,25 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
 }  // namespace
 
 hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total_blocks,
-                               hipStream_t s) {
+                               int per_thread, hipStream_t s) {
   static_assert(kBlock == kSortDigits, "one thread per digit in the scans");
   if (total_blocks <= 0 || n_sets <= 0) return hipSuccess;
   const unsigned g = (unsigned)total_blocks;
   int src = 0;
   for (int pass = 0; pass < kSortPasses; ++pass) {
-    k_sort_hist<<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src);
+    switch (per_thread) {
+      case 8: k_sort_hist<8><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+      case 4: k_sort_hist<4><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+      case 2: k_sort_hist<2><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+      default: k_sort_hist<1><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+    }
     k_sort_rowscan<<<(unsigned)(n_sets * kSortDigits), kBlock, 0, s>>>(d_sorts);
-    k_sort_scatter<<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src);
+    switch (per_thread) {
+      case 8: k_sort_scatter<8><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+      case 4: k_sort_scatter<4><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+      case 2: k_sort_scatter<2><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+      default: k_sort_scatter<1><<<g, kBlock, 0, s>>>(d_sorts, n_sets, pass, src); break;
+    }
     src = 1 - src;
   }
   return hipGetLastError();

@@ -214,6 +214,9 @@ class GraphStep:
             for _ in range(warmup):
                 step.reset()
                 run()
+                # the tuner reads its trials' events without waiting: let each call
+                # finish, so that the shape is settled before the capture
+                torch.cuda.synchronize()
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
