@@ -676,6 +676,21 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
   float px[R], py[R], pz[R], pp[R];
   int64_t qslot0 = 0;        // this lane's slot of row 0
   unsigned* amin = nullptr;  // the block's set's least pass-A values
+  // each query's least value over the block's items taken so far by this workgroup
+  // (they come in runs): one atomic minimum per query and run instead of per item
+  float tmin[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) tmin[r] = INFINITY;
+  auto flush = [&]() {
+    if (amin) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (((okm >> r) & 1u) && tmin[r] < thr)  // existing queries that came under
+          atomicMin(amin + qslot0 + r * kBlock, __float_as_uint(fmaxf(tmin[r], 0.0f)));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) tmin[r] = INFINITY;
+  };
   // the hit words of every set of the call share one array
   AERO_GLOBAL uint32_t* __restrict__ hmask = global_ptr(sets[0].hmask);
   const int64_t mask_items = sets[0].mask_words / W;  // items with room for their words
@@ -693,6 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
     const int icnt = cnt;
     const bool ivalid = valid;
     if (ivalid && gqb != cur) {  // block-uniform
+      flush();  // the previous block's least values
       const QuerySet& S = sets[ns];
       const int64_t qb = gqb - S.qb_base;
       const int64_t Q = S.Q;
@@ -761,11 +777,11 @@ __global__ __launch_bounds__(kBlock) void k_pass_a_valu(const QuerySet* __restri
       if (room && lane < 2)  // the wave's 64 queries r kBlock + 64 w + [0, 64): two words
         hmask[i * W + r * (kBlock / 32) + 2 * w + lane] =
             (uint32_t)(lane ? (hb >> 32) : (hb & 0xffffffffull));
-      // the query's least value so far
-      if (hq && amin) atomicMin(amin + qslot0 + r * kBlock, __float_as_uint(fmaxf(t, 0.0f)));
+      tmin[r] = fminf(tmin[r], t);
     }
     mark_hit(hit, hitf, i);
   }
+  flush();
 }
 
 // Nearest indices (sets with nn) from pass B's (d^2 bits, index) records by slot.

@@ -107,6 +107,21 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
   float pp[COLS];
   int64_t qslot0 = 0;         // this lane's slot of column block 0
   unsigned* amin = nullptr;   // the block's set's least pass-A values
+  // each query's least value over the block's items taken so far by this workgroup
+  // (they come in runs): one atomic minimum per query and run instead of per item
+  float tmin[COLS];
+#pragma unroll
+  for (int b = 0; b < COLS; ++b) tmin[b] = INFINITY;
+  auto flush = [&]() {
+    if (kh == 0 && amin) {
+#pragma unroll
+      for (int b = 0; b < COLS; ++b)
+        if (((okm >> b) & 1u) && tmin[b] < thr)  // existing queries that came under
+          atomicMin(amin + qslot0 + b * 32, __float_as_uint(fmaxf(tmin[b], 0.0f)));
+    }
+#pragma unroll
+    for (int b = 0; b < COLS; ++b) tmin[b] = INFINITY;
+  };
   // the hit words of every set of the call share one array
   AERO_GLOBAL uint32_t* __restrict__ hmask = global_ptr(sets[0].hmask);
   const int64_t mask_items = sets[0].mask_words / W;  // items with room for their words
@@ -127,6 +142,7 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
     const unsigned iys = (unsigned)it.y;
     const int ins = ns;
     if (ivalid && gqb != cur) {  // block-uniform
+      flush();  // the previous block's least values
       const QuerySet& S = sets[ns];
       const int64_t qb = gqb - S.qb_base;
       const int64_t Q = S.Q;
@@ -237,18 +253,21 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
     const bool room = i < mask_items;  // block-uniform
 #pragma unroll
     for (int b = 0; b < COLS; ++b) {
-      // the two lane halves hold different rows (points) of the same column (query)
-      const float v = fminf(tt[b], __shfl_xor(tt[b], 32, 64));
+      // the two lane halves hold different rows (points) of the same column (query):
+      // one lane-half swap gives every lane both halves' minima
+      const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(tt[b]),
+                                                       __float_as_uint(tt[b]), false, false);
+      const float v = fminf(__uint_as_float(sw[0]), __uint_as_float(sw[1]));
       const float t = pp[b] + v;
       const bool hq = ((okm >> b) & 1u) && t < thr;
       hit |= hq;
       const uint64_t hb = __ballot(hq);
       if (room && lane == 0) hmask[i * W + w * COLS + b] = (uint32_t)(hb & 0xffffffffull);
-      // the query's least value so far (both lane halves hold it: the lower one stores)
-      if (hq && kh == 0 && amin) atomicMin(amin + qslot0 + b * 32, __float_as_uint(fmaxf(t, 0.0f)));
+      tmin[b] = fminf(tmin[b], t);  // both lane halves hold it: the lower one stores
     }
     mark_hit(hit, hitf, i);
   }
+  flush();
 }
 
 }  // namespace
