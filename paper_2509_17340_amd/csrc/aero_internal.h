@@ -65,8 +65,9 @@ struct DevProblem {
   float* u_nom;          // [M][N][4]
   double* S1;            // [M][K]
   double* J_ctrl;        // [M][K]  control term, written by the rollout
-  double* state;         // [M][N][K][10] state after every step (p, q, v), written by the
-                         //   rollout and scored by the finalize kernel
+  float* state;          // [M][N][K][10] state after every step (p, q, v) rounded to
+                         //   float32, written by the rollout and scored by the finalize
+                         //   kernel
   float* deff;           // [M][N][4][K]
   float* pos;            // [3][M][N][K] planes x, y, z
   unsigned* mind2;       // [M][N][K] float bits of the squared nearest distance
@@ -87,6 +88,9 @@ struct DevProblem {
                            //   distances), or nullptr
   unsigned* amin;          // the set's least pass-A values by slot (reset with the
                            //   distances), or nullptr
+  int64_t inst_base;       // prefix of M over problems
+  double* wexp;            // [M][K] e_k = exp(-(S1_k - rho) / lambda) of each instance
+  double* eta;             // [M] sum_k e_k
 };
 
 // Spatial sort of one problem's rollout positions, or of its cloud (stable LSD radix
@@ -341,7 +345,9 @@ hipError_t launch_grad_reduce(const DevProblem* d_prob, const DevParams& prm, in
 size_t grad_w_parts();  // doubles of the weight-gradient partial sums
 hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total_samples,
                            const DevParams& prm, bool write_s1, hipStream_t s);
-hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
+// The control update: per instance the weights (rho, e_k, eta), then per (instance,
+// step) row the weighted perturbation sum.
+hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_inst, int64_t total_rows,
                          const DevParams& prm, hipStream_t s);
 hipError_t launch_select_rollout(const DevSelect* d_sel, int n, int64_t total_inst,
                                  const DevParams& prm, const void* h_blob, size_t blob_bytes,

@@ -279,7 +279,7 @@ struct MppiPlan {
   DevProblem* d_probs = nullptr;
   QuerySet* d_sets = nullptr;
   SortSet* d_sorts = nullptr;   // adjacent to d_sets: one descriptor upload
-  int64_t total_samples = 0, total_rows = 0;
+  int64_t total_samples = 0, total_rows = 0, total_inst = 0;
   int64_t sort_blocks = 0;
   int sort_per_thread = 1;      // elements per thread of the sort's tiles
   int64_t total_tiles = 0;      // cloud tiles of the two-pass sets (box launches)
@@ -326,7 +326,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   // (every query of the block), which is exact, only slower.
   pl.mask_words = cap > 0 ? std::max<int64_t>(int64_t(1) << 20, 2 * cap) : 0;
   pl.hmask = cur.take<uint32_t>(pl.mask_words);
-  int64_t sort_blocks = 0, eb = 0, sb = 0, rb = 0, qbb = 0, tb = 0;
+  int64_t sort_blocks = 0, eb = 0, sb = 0, rb = 0, qbb = 0, tb = 0, ib = 0;
   // the sort's tile: as many elements per thread as still leave about kSortMinGrid
   // tiles over the call's sorted positions and clouds
   int64_t sort_elems = 0;
@@ -364,9 +364,13 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
     d.mind2 = q.min_dist2 ? reinterpret_cast<unsigned*>(q.min_dist2) : md;
     d.sample_base = sb;
     d.row_base = rb;
+    d.inst_base = ib;
+    d.wexp = cur.take<double>(MK);
+    d.eta = cur.take<double>(q.M);
+    ib += q.M;
     d.elem_base = eb;
     d.noise = cur.take<double>(4 * MNK);
-    d.state = cur.take<double>(10 * MNK);
+    d.state = cur.take<float>(10 * MNK);
     d.item_count = pl.item_count;
     sb += MK;
     rb += MN;
@@ -478,6 +482,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
   }
   pl.total_samples = sb;
   pl.total_rows = rb;
+  pl.total_inst = ib;
   pl.total_tiles = tb;
   pl.total_qblocks = qbb;
   pl.sort_blocks = sort_blocks;
@@ -967,7 +972,9 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h, int32_t n, v
   if (he == hipSuccess)
     he = timed(AERO_K_FINALIZE, s, [&] { return launch_finalize(pl.d_probs, n, pl.total_samples, prm, true, s); });
   if (he == hipSuccess)
-    he = timed(AERO_K_UPDATE, s, [&] { return launch_update(pl.d_probs, n, pl.total_rows, prm, s); });
+    he = timed(AERO_K_UPDATE, s, [&] {
+      return launch_update(pl.d_probs, n, pl.total_inst, pl.total_rows, prm, s);
+    });
   return dev_status(he);
 }
 

@@ -4,14 +4,15 @@
 //                  parallel; resets the per-call outputs
 //   k_rollout      one quad of lanes per (problem, instance, sample): clip, RK4 in
 //                  binary64, the control term; writes the clipped perturbations and
-//                  float32 positions as sample-fastest planes, the binary64 state
-//                  after every step as one 80-byte record per position, and the
-//                  positions' bounding box for the spatial sort
+//                  float32 positions as sample-fastest planes, the state after
+//                  every step rounded to float32 as one 40-byte record per
+//                  position, and the positions' bounding box for the spatial sort
 //   (the nearest-distance kernels live in distance.hip)
 //   k_finalize     per sample, the state terms (tracking, speed, goal) and J_col,
 //                  with the horizon split into eight parts per sample; S1
-//   k_update       per (instance, step): rho, eta, and sum_k eps_k delta_eff_k
-//                  with fixed-order wave/block reductions in binary64
+//   k_weights      per instance: rho, e_k and eta
+//   k_update       per (instance, step): sum_k e_k delta_eff_k / eta
+//                  (both with fixed-order wave/block reductions in binary64)
 //   k_sel_rollout  Stage II noise-free rollouts (states and positions)
 //   k_sel_final    Stage II goal and collision terms per state, S2 and the argmin
 #include <hip/hip_runtime.h>
@@ -26,7 +27,7 @@ namespace aero {
 namespace {
 
 constexpr unsigned kInfBits = 0x7f800000u;
-typedef double dvec2 __attribute__((ext_vector_type(2)));  // 16-byte state accesses
+typedef float fvec2 __attribute__((ext_vector_type(2)));  // 8-byte state accesses
 
 __device__ inline void load_rg(const float* qg, double Rg[9]) {
   const double w = qg[0], x = qg[1], y = qg[2], z = qg[3];
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __rest
     AERO_GLOBAL const float* __restrict__ u_nom = global_ptr(P.u_nom);
     AERO_GLOBAL float* __restrict__ deff = global_ptr(P.deff);
     AERO_GLOBAL float* __restrict__ pos = global_ptr(P.pos);
-    AERO_GLOBAL double* __restrict__ state = global_ptr(P.state);
+    AERO_GLOBAL float* __restrict__ state = global_ptr(P.state);
     const Dyn dyn{1.0 / prm.mass, prm.gravity};
     // this lane's channel constants (selected, not indexed: the arrays are kernel
     // arguments)
@@ -216,16 +217,16 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(const DevProblem* __rest
         const QuadControl qc = quad_control(u, L, dyn);
         quad_rk4(p, v, q, qa, qc, L, prm.dt, dyn);
         const int64_t qi = row * K + k;
-        // one 80-byte record [p, q, v] per position, written by the quad.  The loop
-        // body has no branch (so that the compiler's waits for the loads ahead stay
-        // exact): lane 3, which has no position or velocity, stores its own values
-        // again to its own addresses instead.
-        AERO_GLOBAL double* rec = state + qi * 10;
-        const float pf = (float)p;
-        rec[3 + c] = q;
+        // one 40-byte record [p, q, v] per position (rounded to float32), written by
+        // the quad.  The loop body has no branch (so that the compiler's waits for the
+        // loads ahead stay exact): lane 3, which has no position or velocity, stores
+        // its own values again to its own addresses instead.
+        AERO_GLOBAL float* rec = state + qi * 10;
+        const float pf = (float)p, qf = (float)q, vf = (float)v;
+        rec[3 + c] = qf;
         *(pv ? pos + c * MNK + qi : de_at) = pv ? pf : de;
-        rec[pv ? c : 6] = pv ? p : q;
-        rec[pv ? 7 + c : 6] = pv ? v : q;
+        rec[pv ? c : 6] = pv ? pf : qf;
+        rec[pv ? 7 + c : 6] = pv ? vf : qf;
         lo = fminf(lo, pv ? pf : INFINITY);
         hi = fmaxf(hi, pv ? pf : -INFINITY);
         const double du = u - up;
@@ -296,14 +297,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const DevProblem* __re
     // binary64, so skipping d^2 >= d_max^2 changes no sum
     const double dmax2 = prm.d_max * prm.d_max;
     // the next step's state is loaded while this one is scored
-    AERO_GLOBAL const double* __restrict__ state = global_ptr(P.state);
-    double xn[10];
+    AERO_GLOBAL const float* __restrict__ state = global_ptr(P.state);
+    float xn[10];
     auto load_state = [&](int t) {
       const int64_t qi = ((int64_t)m * N + (t < t1 ? t : t1 - 1)) * K + k;
-      AERO_GLOBAL const dvec2* st = reinterpret_cast<AERO_GLOBAL const dvec2*>(state + qi * 10);
+      AERO_GLOBAL const fvec2* st = reinterpret_cast<AERO_GLOBAL const fvec2*>(state + qi * 10);
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
-        const dvec2 v = st[i];
+        const fvec2 v = st[i];
         xn[2 * i] = v[0];
         xn[2 * i + 1] = v[1];
       }
@@ -414,8 +415,37 @@ __device__ inline void block_sum5(double v[5], double* sh) {
   for (int i = 0; i < 5; ++i) v[i] = ((sh[i * 4] + sh[i * 4 + 1]) + sh[i * 4 + 2]) + sh[i * 4 + 3];
 }
 
-__global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict__ probs, int n,
-                                                   DevParams prm) {
+// Per instance: rho = min_k S1_k, e_k = exp(-(S1_k - rho) / lambda) and eta = sum_k e_k
+// (Sec. III-B, eq. (mppi_weights)), once, for every row of the update to read.  Thread
+// t sums its samples t, t + kBlock, ... in order, then the block sums in a fixed
+// order.
+__global__ __launch_bounds__(kBlock) void k_weights(const DevProblem* __restrict__ probs, int n,
+                                                    DevParams prm) {
+  __shared__ double sh[20];
+  const int64_t gid = blockIdx.x;
+  const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.inst_base; });
+  const DevProblem& P = probs[b];
+  const int K = P.K;
+  const int m = (int)(gid - P.inst_base);
+  const double* S = P.S1 + (int64_t)m * K;
+  AERO_GLOBAL double* __restrict__ wexp = global_ptr(P.wexp) + (int64_t)m * K;
+  double mn = INFINITY;
+  for (int k = threadIdx.x; k < K; k += kBlock) mn = fmin(mn, S[k]);
+  const double rho = block_min(mn, sh);
+  const double inv_lam = 1.0 / prm.lambda;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < K; k += kBlock) {
+    const double e = exp(-(S[k] - rho) * inv_lam);
+    wexp[k] = e;
+    acc[0] += e;
+  }
+  block_sum5(acc, sh);
+  if (threadIdx.x == 0) P.eta[m] = acc[0];
+}
+
+// Per (instance, step) row: u_nom += sum_k e_k delta_eff_k / eta (Sec. III-B, eq.
+// (mppi_update)), the samples summed per thread in order, then over the block.
+__global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict__ probs, int n) {
   __shared__ double sh[20];
   const int64_t gid = blockIdx.x;
   const int b = find_owner(probs, n, gid, [](const DevProblem& p) { return p.row_base; });
@@ -423,42 +453,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict_
   const int K = P.K, N = P.N;
   const int64_t row = gid - P.row_base;  // m * N + t
   const int m = (int)(row / N);
-  const double* S = P.S1 + (int64_t)m * K;
-  const float* D = P.deff + row * 4 * K;
-  // The first kUpdCache samples of each thread are loaded (costs and perturbations)
-  // before the minimum is reduced, so that the perturbations' loads overlap the
-  // reduction; the sums run over the samples in the same order as without the cache.
-  constexpr int kUpdCache = 4;
-  double sv[kUpdCache];
-  float dv[kUpdCache][4];
-  double mn = INFINITY;
-#pragma unroll
-  for (int j = 0; j < kUpdCache; ++j) {
-    const int k = threadIdx.x + j * kBlock;
-    sv[j] = 0.0;
-    if (k < K) {
-      sv[j] = S[k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dv[j][c] = D[c * K + k];
-      mn = fmin(mn, sv[j]);
-    }
-  }
-  for (int k = threadIdx.x + kUpdCache * kBlock; k < K; k += kBlock) mn = fmin(mn, S[k]);
-  const double rho = block_min(mn, sh);
-  const double inv_lam = 1.0 / prm.lambda;
+  const double* __restrict__ W = P.wexp + (int64_t)m * K;
+  const float* __restrict__ D = P.deff + row * 4 * K;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < kUpdCache; ++j) {
-    if (threadIdx.x + j * kBlock < K) {
-      const double e = exp(-(sv[j] - rho) * inv_lam);
-      acc[0] += e;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[1 + c] += e * (double)dv[j][c];
-    }
-  }
-  for (int k = threadIdx.x + kUpdCache * kBlock; k < K; k += kBlock) {
-    const double e = exp(-(S[k] - rho) * inv_lam);
-    acc[0] += e;
+  for (int k = threadIdx.x; k < K; k += kBlock) {
+    const double e = W[k];
     acc[1] += e * (double)D[k];
     acc[2] += e * (double)D[K + k];
     acc[3] += e * (double)D[2 * K + k];
@@ -468,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const DevProblem* __restrict_
   if (threadIdx.x < 4) {
     const int c = threadIdx.x;
     float* u = P.u_nom + row * 4 + c;
-    *u = (float)((double)*u + acc[1 + c] / acc[0]);
+    *u = (float)((double)*u + acc[1 + c] / P.eta[m]);
   }
 }
 
@@ -701,9 +700,11 @@ hipError_t launch_finalize(const DevProblem* d_probs, int n, int64_t total, cons
   return hipGetLastError();
 }
 
-hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_rows,
+hipError_t launch_update(const DevProblem* d_probs, int n, int64_t total_inst, int64_t total_rows,
                          const DevParams& prm, hipStream_t s) {
-  k_update<<<(unsigned)total_rows, kBlock, 0, s>>>(d_probs, n, prm);
+  if (total_inst <= 0) return hipSuccess;
+  k_weights<<<(unsigned)total_inst, kBlock, 0, s>>>(d_probs, n, prm);
+  k_update<<<(unsigned)total_rows, kBlock, 0, s>>>(d_probs, n);
   return hipGetLastError();
 }
 
