@@ -108,6 +108,7 @@ struct SortSet {
   const float* py;
   const float* pz;
   float* sp;             // positions: [3][Q] in slot order (written by the last pass)
+  float* tp;             // [3][Q] the coordinates in the first pass's output order
   int64_t Q;
   int64_t block_base;    // prefix of n_blocks over sets
   int32_t n_blocks;      // ceil(Q / tile), tile = kBlock x the call's elements per thread

@@ -431,6 +431,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       so.val[1] = cur.take<int32_t>(MNK);
       so.inv = cur.take<int32_t>(MNK);
       so.sp = cur.take<float>(3 * MNK);
+      so.tp = cur.take<float>(3 * MNK);
       so.table = cur.take<int32_t>((int64_t)kSortDigits * so.n_blocks);
       so.rowsum = cur.take<int32_t>(kSortDigits);
       sort_blocks += so.n_blocks;
@@ -459,6 +460,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       sc.table = cur.take<int32_t>((int64_t)kSortDigits * sc.n_blocks);
       sc.rowsum = cur.take<int32_t>(kSortDigits);
       sc.sc = cur.take<float4>(P);
+      sc.tp = cur.take<float>(3 * P);
       sort_blocks += sc.n_blocks;
       qs.scloud = sc.sc;
       qs.stbox = cur.take<float>(6 * n_tiles);

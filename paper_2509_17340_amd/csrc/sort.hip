@@ -227,6 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
   __shared__ int64_t gbase[kSortDigits];  // output position of each digit's first element
   __shared__ uint32_t sk[R > 1 ? R * kBlock : 1];
   __shared__ int32_t sv[R > 1 ? R * kBlock : 1];
+  __shared__ uint16_t ssrc[R > 1 ? R * kBlock : 1];  // the staged element's place in the tile
   const Tile t = locate<R>(sets, n_sets);
   const SortSet& S = sets[t.s];
   for (int k = threadIdx.x; k < 2 * kWaves * kSortDigits; k += kBlock) (&hist[0][0][0])[k] = 0;
@@ -283,6 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
       const int at = dstart[dig] + lr[r];
       sk[at] = key[r];
       sv[at] = val[r];
+      ssrc[at] = (uint16_t)(r * kBlock + threadIdx.x);
     }
     __syncthreads();
   }
@@ -292,6 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
   AERO_GLOBAL int32_t* __restrict__ val_out = global_ptr(S.val[1 - src]);
   AERO_GLOBAL int32_t* __restrict__ inv = global_ptr(S.inv);
   AERO_GLOBAL float* __restrict__ sp = global_ptr(S.sp);
+  AERO_GLOBAL float* __restrict__ tp = global_ptr(S.tp);
   float4* __restrict__ sc = S.sc;
   const float* __restrict__ px = S.px;
   const float* __restrict__ py = S.py;
@@ -307,14 +310,33 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
     // nothing from staging)
     const uint32_t k = R > 1 ? sk[j] : key[r];
     const int32_t v = R > 1 ? sv[j] : val[r];
+    const int64_t isrc = t.i0 + (R > 1 ? (int)ssrc[j] : j);  // the element's input place
     const uint32_t dig = (k >> (kSortShift0 + 8 * pass)) & 0xffu;
     const int64_t pos = gbase[dig] + (R > 1 ? j - dstart[dig] : lr[r]);
     if (pos < 0 || pos >= Q) continue;  // never for consistent counts; never write outside
     key_out[pos] = k;
     val_out[pos] = v;
-    if (!last_pass || v < 0 || v >= Q) continue;
-    const int64_t at = (int64_t)v * stride;
-    const float x = px[at], y = py[at], z = pz[at];
+    // the coordinates travel with the keys: read from the tile's own input (the
+    // original arrays in the first pass, the first pass's output in the last), not
+    // gathered through the permutation at the end
+    float x, y, z;
+    if (pass == 0) {
+      const int64_t at = isrc * stride;
+      x = px[at];
+      y = py[at];
+      z = pz[at];
+    } else {
+      x = tp[isrc];
+      y = tp[Q + isrc];
+      z = tp[2 * Q + isrc];
+    }
+    if (!last_pass) {
+      tp[pos] = x;
+      tp[Q + pos] = y;
+      tp[2 * Q + pos] = z;
+      continue;
+    }
+    if (v < 0 || v >= Q) continue;
     if (sc) {
       // a cloud: the points in key order with their original index
       sc[pos] = make_float4(x, y, z, __int_as_float(v));
@@ -334,6 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const SortSet* __restri
 hipError_t launch_spatial_sort(const SortSet* d_sorts, int n_sets, int64_t total_blocks,
                                int per_thread, hipStream_t s) {
   static_assert(kBlock == kSortDigits, "one thread per digit in the scans");
+  static_assert(kSortPasses == 2, "the coordinates go original -> tp -> the output");
   if (total_blocks <= 0 || n_sets <= 0) return hipSuccess;
   const unsigned g = (unsigned)total_blocks;
   int src = 0;
