@@ -32,8 +32,12 @@ __device__ inline void control_at(const DevParams& prm, const DevProblem& P, int
   if (P.noise) {  // the normals the rollout drew (same counters, same values)
 #pragma unroll
     for (int c = 0; c < 4; ++c) nz[c] = P.noise[(row * 4 + c) * P.K + k];
-  } else {
+  } else if (prm.sigma[0] != 0.0 || prm.sigma[1] != 0.0 || prm.sigma[2] != 0.0 ||
+             prm.sigma[3] != 0.0) {
     normals4(prm, P.problem_id, (uint32_t)k, (uint32_t)t, (uint32_t)m, nz);
+  } else {  // a noise-free rollout: the noise term vanishes, nothing to draw
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nz[c] = 0.0;
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -297,6 +301,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const DevProblem* __restr
   for (int i = 0; i < 10; ++i) xnext[i] = x[i];
   const int n_seg = (N + kSeg - 1) / kSeg;
   double u_after[4] = {0, 0, 0, 0};  // u_{t+1} while sweeping backwards
+  // u_t and its clip mask, carried from the step after (its u_{t-1}) once known
+  double u[4];
+  bool msk[4];
+  bool have_u = false;
   for (int sgi = n_seg - 1; sgi >= 0; --sgi) {
     const int t0 = sgi * kSeg, t1 = min(t0 + kSeg, N);
     const double* c = ckpt + (int64_t)sgi * 10 * MK + gid;
@@ -308,10 +316,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const DevProblem* __restr
 #pragma unroll
       for (int i = 0; i < 10; ++i) sp[i * MK] = x[i];
       if (t + 1 < t1) {
-        double u[4];
-        bool msk[4];
-        control_at(prm, P, m, k, t, u, msk);
-        rk4(x, u, prm.dt, dyn);
+        double uc[4];
+        bool mc[4];
+        control_at(prm, P, m, k, t, uc, mc);
+        rk4(x, uc, prm.dt, dyn);
       }
     }
     for (int t = t1 - 1; t >= t0; --t) {
@@ -321,17 +329,13 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const DevProblem* __restr
       double xt[10];
 #pragma unroll
       for (int i = 0; i < 10; ++i) xt[i] = sp[i * MK];
-      double u[4];
-      bool msk[4];
-      control_at(prm, P, m, k, t, u, msk);
+      if (!have_u) control_at(prm, P, m, k, t, u, msk);
       double lu[4] = {0, 0, 0, 0};
       rk4_vjp(xt, u, prm.dt, dyn, lam, lu);
       // control cost: Q_c |u_t|^2 (t <= N-2), Q_cdelta |u_t - u_{t-1}|^2 (1 <= t <= N-2)
       double u_before[4] = {0, 0, 0, 0};
-      if (t >= 1) {
-        bool mb[4];
-        control_at(prm, P, m, k, t - 1, u_before, mb);
-      }
+      bool mb[4] = {false, false, false, false};
+      if (t >= 1) control_at(prm, P, m, k, t - 1, u_before, mb);
       const int64_t row = (int64_t)m * N + t;
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) {
@@ -341,7 +345,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const DevProblem* __restr
         if (t + 1 >= 1 && t + 1 <= N - 2) g -= prm.w[2] * prm.Q_cdelta * 2.0 * (u_after[cc] - u[cc]);
         gsamp[(row * 4 + cc) * K + k] = msk[cc] ? g : 0.0;
         u_after[cc] = u[cc];
+        u[cc] = u_before[cc];
+        msk[cc] = mb[cc];
       }
+      have_u = t >= 1;
 #pragma unroll
       for (int i = 0; i < 10; ++i) xnext[i] = xt[i];
     }

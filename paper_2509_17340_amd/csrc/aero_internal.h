@@ -26,6 +26,7 @@ constexpr int kBoxStride = 64;  // words per copy
 constexpr int kTileSplit = 4;                            // sub-tiles per tile
 constexpr int kSubPts = kTilePts / kTileSplit;           // cloud points per sub-tile (work unit)
 constexpr int kGroupsPerSub = kSubPts / 32;              // 32-point groups per sub-tile
+constexpr int kSuperTiles = 16;                          // tiles per super-tile (cull step)
 constexpr int kQueriesPerLane = AERO_QUERIES_PER_LANE;   // positions in registers per lane
 constexpr int kQueriesPerBlock = kBlock * kQueriesPerLane;
 static_assert(kSubPts == kBlock, "a sub-tile is staged one point per thread");
@@ -166,6 +167,8 @@ struct QuerySet {
   float* stbox;          // [n_tiles][6], [n_sub][6], [n_sub * kGroupsPerSub][6]: boxes
   float* ssbox;          //   of the sorted cloud
   float* sgbox;
+  float* ubox;           // [ceil(n_tiles / kSuperTiles)][6] boxes of kSuperTiles
+  float* subox;          //   consecutive tiles, raw and sorted cloud (cull step)
   int2* items;           // the call's item list: (global query block, sub-tile | order
                          //   << 31); a block's items are consecutive
   int32_t* item_count;   // entries of `items` (zeroed by the noise kernel)

@@ -405,6 +405,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.tbox = cur.take<float>(6 * n_tiles);
       qs.sbox = cur.take<float>(6 * n_sub);
       qs.gbox = cur.take<float>(6 * n_sub * kGroupsPerSub);
+      qs.ubox = cur.take<float>(6 * ((n_tiles + kSuperTiles - 1) / kSuperTiles));
       qs.amin = cur.take<unsigned>(MNK);  // reset by the noise kernel
       d.amin = qs.amin;
       qs.items = pl.items;
@@ -466,6 +467,7 @@ void plan_mppi(const aero_problem* h, int n, char* ws, float d_max, MppiPlan& pl
       qs.stbox = cur.take<float>(6 * n_tiles);
       qs.ssbox = cur.take<float>(6 * n_sub);
       qs.sgbox = cur.take<float>(6 * n_sub * kGroupsPerSub);
+      qs.subox = cur.take<float>(6 * ((n_tiles + kSuperTiles - 1) / kSuperTiles));
       pl.any_scloud = true;
     } else {
       sc.block_base = sort_blocks;

@@ -7,13 +7,14 @@
 // The cloud is cut into tiles of kTilePts and sub-tiles of kSubPts consecutive
 // points with bounding boxes; a block lists every sub-tile whose box lies within
 // reach of the block's box, testing tiles first (a tile's box contains its
-// sub-tiles').  Two orders of the cloud are considered when the cloud has been
+// sub-tiles', and a super-tile's box its tiles').  Two orders of the cloud are considered when the cloud has been
 // spatially sorted: the order it was given in (a LiDAR sweep in beam order is already
 // made of compact runs) and the Morton order; each block takes the one that lists
 // fewer sub-tiles.  A block's items are written consecutively, so that the first pass
 // sets a block up once per run of its items.
 //
 //   k_sorted_boxes  tile and sub-tile boxes of the sorted clouds
+//   k_super_boxes   boxes of kSuperTiles consecutive tiles, both orders
 //   k_cull          per query block: bounding box, centre, radius, flag bound,
 //                   and its items
 #include <hip/hip_runtime.h>
@@ -33,6 +34,33 @@ __global__ __launch_bounds__(kBlock) void k_sorted_boxes(const QuerySet* __restr
   const QuerySet& S = sets[s];
   if (!S.scloud) return;  // block-uniform
   tile_boxes(nullptr, S.scloud, S.n_points, t - S.tile_base, S.stbox, S.ssbox, S.sgbox);
+}
+
+// One workgroup per set: the super-tile boxes of the raw cloud and, when sorted, of
+// the sorted cloud, from their tile boxes.
+__global__ __launch_bounds__(kBlock) void k_super_boxes(const QuerySet* __restrict__ sets) {
+  const QuerySet& S = sets[blockIdx.x];
+  if (S.n_qblocks <= 0 || !S.tbox) return;  // block-uniform: a two-pass set only
+  const int64_t n_tiles = S.n_tiles;
+  const int64_t n_super = (n_tiles + kSuperTiles - 1) / kSuperTiles;
+  for (int64_t i = threadIdx.x; i < 2 * n_super; i += kBlock) {
+    const int order = i >= n_super ? 1 : 0;
+    const int64_t u = i - order * n_super;
+    const float* __restrict__ tb = order ? S.stbox : S.tbox;
+    float* __restrict__ ub = order ? S.subox : S.ubox;
+    if (!tb || !ub) continue;
+    float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    const int64_t t1 = min<int64_t>(n_tiles, (u + 1) * kSuperTiles);
+    for (int64_t t = u * kSuperTiles; t < t1; ++t) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(b[a], tb[6 * t + a]);
+        b[3 + a] = fmaxf(b[3 + a], tb[6 * t + 3 + a]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) ub[6 * u + a] = b[a];
+  }
 }
 
 __device__ inline int wave_sum_i(int v) {
@@ -55,6 +83,37 @@ __device__ inline unsigned reach_mask(const float* __restrict__ tbox,
     }
   }
   return mask;
+}
+
+// Calls f(t, mask) for every tile t of one cloud order whose super-tile lies within
+// reach of the block box, with the reach mask of its sub-tiles, the tiles in
+// increasing order across the wave's lanes (16 lanes per super-tile, four super-
+// tiles per round).  Every lane calls f the same number of times, with t = -1 and
+// mask 0 where it holds no tile, so that f may scan over the wave.
+template <typename F>
+__device__ inline void scan_reach(const float* __restrict__ ub, const float* __restrict__ tbox,
+                                  const float* __restrict__ sbox, int64_t n_tiles,
+                                  int64_t n_sub, const float lo[3], const float hi[3],
+                                  float lim, int lane, F&& f) {
+  static_assert(kSuperTiles == 16, "four super-tiles of 16 tiles per wave round");
+  const int64_t n_super = (n_tiles + kSuperTiles - 1) / kSuperTiles;
+  for (int64_t u0 = 0; u0 < n_super; u0 += 64) {
+    const int64_t u = u0 + lane;
+    const bool near = u < n_super && box_dist2(ub + 6 * u, lo, hi) <= lim;
+    unsigned long long hits = __ballot(near);
+    while (hits) {  // wave-uniform
+      int take[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        take[i] = hits ? __ffsll((long long)hits) - 1 : -1;
+        hits &= hits - 1ull;
+      }
+      const int mine = take[lane >> 4];
+      const int64_t t = mine >= 0 ? (u0 + mine) * kSuperTiles + (lane & 15) : n_tiles;
+      const unsigned mask = t < n_tiles ? reach_mask(tbox, sbox, t, n_sub, lo, hi, lim) : 0u;
+      f(t < n_tiles ? t : (int64_t)-1, mask);
+    }
+  }
 }
 
 // One wave per query block (four per workgroup, no workgroup barriers).
@@ -113,13 +172,13 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
   const float lim = S.cull ? reach_limit(thr, d_max) : INFINITY;
   // items of each order
   int cnt_raw = 0, cnt_srt = 0;
-  for (int64_t t = lane; t < n_tiles; t += 64)
-    cnt_raw += __popc(reach_mask(S.tbox, S.sbox, t, n_sub, lo, hi, lim));
+  scan_reach(S.ubox, S.tbox, S.sbox, n_tiles, n_sub, lo, hi, lim, lane,
+             [&](int64_t, unsigned mask) { cnt_raw += __popc(mask); });
   cnt_raw = wave_sum_i(cnt_raw);
   const bool sorted_ok = S.scloud != nullptr && S.cull;
   if (sorted_ok) {
-    for (int64_t t = lane; t < n_tiles; t += 64)
-      cnt_srt += __popc(reach_mask(S.stbox, S.ssbox, t, n_sub, lo, hi, lim));
+    scan_reach(S.subox, S.stbox, S.ssbox, n_tiles, n_sub, lo, hi, lim, lane,
+               [&](int64_t, unsigned mask) { cnt_srt += __popc(mask); });
     cnt_srt = wave_sum_i(cnt_srt);
   }
   const int order = (sorted_ok && cnt_srt < cnt_raw) ? 1 : 0;
@@ -128,6 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
   int base = 0;
   if (lane == 0) base = atomicAdd(S.item_count, cnt);
   base = __shfl(base, 0, 64);
+  const float* __restrict__ ub = order ? S.subox : S.ubox;
   const float* __restrict__ tb = order ? S.stbox : S.tbox;
   const float* __restrict__ sb = order ? S.ssbox : S.sbox;
   int2* __restrict__ items = S.items;
@@ -135,9 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
   const unsigned flag = (unsigned)order << 31;
   // the same tests again, now writing the listed sub-tiles in increasing order
   int run = 0;
-  for (int64_t t0 = 0; t0 < n_tiles; t0 += 64) {
-    const int64_t t = t0 + lane;
-    const unsigned mask = t < n_tiles ? reach_mask(tb, sb, t, n_sub, lo, hi, lim) : 0u;
+  scan_reach(ub, tb, sb, n_tiles, n_sub, lo, hi, lim, lane, [&](int64_t t, unsigned mask) {
     const int m = __popc(mask);
     int x = m;  // inclusive scan over the wave
 #pragma unroll
@@ -156,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
         ++at;
       }
     run += __shfl(x, 63, 64);
-  }
+  });
 }
 
 }  // namespace
@@ -170,9 +228,11 @@ hipError_t launch_sorted_boxes(const QuerySet* d_sets, int n_sets, int64_t total
 hipError_t launch_cull(const QuerySet* d_sets, int n_sets, int64_t total_qblocks, int variant,
                        hipStream_t s) {
   constexpr int per = kBlock / 64;
-  if (total_qblocks > 0)
+  if (total_qblocks > 0) {
+    k_super_boxes<<<(unsigned)n_sets, kBlock, 0, s>>>(d_sets);
     k_cull<<<(unsigned)((total_qblocks + per - 1) / per), kBlock, 0, s>>>(d_sets, n_sets,
                                                                           total_qblocks, variant);
+  }
   return hipGetLastError();
 }
 
