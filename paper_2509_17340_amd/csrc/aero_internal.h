@@ -322,7 +322,7 @@ hipError_t launch_cull(const QuerySet* d_sets, int n_sets, int64_t total_qblocks
 hipError_t launch_rollout(const DevProblem* d_probs, int n, int64_t total_samples,
                           const DevParams& prm, hipStream_t s);
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                           hipStream_t s);
+                           float d_max, hipStream_t s);
 // The first pass over the call's item list (items, item_count and hitf are shared by
 // every two-pass set of the call); max_items bounds the list (the grid is sized by it).
 hipError_t launch_pass_a(const QuerySet* d_sets, int n_sets, const int2* items,

@@ -593,10 +593,13 @@ struct SelectPlan {
 };
 
 // Queries per block of an exact set: kBlock lanes times 1, 2, 4 or 8 queries each,
-// the fewest that hold the set in one block (at most kQueriesPerBlock).
+// the fewest that keep the set within kExactQueryBlocks blocks.  Few queries per lane
+// keep each wave's queries (consecutive positions of one or two rollouts) in a small
+// box, so that the wave skips most cloud tiles; more blocks read the cloud more often.
+constexpr int64_t kExactQueryBlocks = 16;
 int64_t exact_block_queries(int64_t Q) {
   int64_t r = 1;
-  while (r < kQueriesPerLane && r * kBlock < Q) r *= 2;
+  while (r < kQueriesPerLane && r * kBlock * kExactQueryBlocks < Q) r *= 2;
   return r * kBlock;
 }
 
@@ -650,10 +653,11 @@ void plan_select(const aero_problem* h, int n, char* ws, double* S2, int32_t* be
     qs.qpbA = (int32_t)exact_block_queries(MN);
     qs.n_qblocks = (int)((MN + qs.qpbA - 1) / qs.qpbA);
     // few queries: split the cloud so that about 512 workgroups share the work (the
-    // pass is latency-bound at this size), with at most 2048 points each
+    // pass is latency-bound at this size), with at most one tile of points each (the
+    // work of a chunk is concentrated in the tiles near the rollouts)
     set_chunks(q.n_points,
                std::max<int64_t>((512 + qblocks - 1) / std::max<int64_t>(qblocks, 1),
-                                 (q.n_points + 2047) / 2048),
+                                 (q.n_points + kTilePts - 1) / kTilePts),
                qs.n_chunks, qs.chunk_pts);
     qs.block_base = blk;
     blk += (int64_t)qs.n_qblocks * qs.n_chunks;
@@ -694,7 +698,7 @@ hipError_t run_select(const SelectPlan& pl, int n, const DevParams& prm, const c
   });
   if (he == hipSuccess && pl.total_blocks > 0)
     he = maybe_timed(timing, AERO_K_SEL_MIN_DIST, s,
-                     [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, s); });
+                     [&] { return launch_min_dist(pl.d_sets, n, pl.total_blocks, (float)prm.d_max, s); });
   if (he == hipSuccess)
     he = maybe_timed(timing, AERO_K_SEL_FINAL, s,
                      [&] { return launch_select_final(pl.d_sel, n, prm, s); });

@@ -70,16 +70,26 @@ __device__ inline int wave_sum_i(int v) {
 }
 
 // Sub-tiles of one cloud order within reach of the block box [lo, hi]: bit j of the
-// result is sub-tile 4 t + j of tile t.
+// result is sub-tile 4 t + j of tile t.  The sub-tile boxes are read together with
+// the tile's (one memory round trip instead of two).
 __device__ inline unsigned reach_mask(const float* __restrict__ tbox,
                                       const float* __restrict__ sbox, int64_t t, int64_t n_sub,
                                       const float lo[3], const float hi[3], float lim) {
+  float tb[6], sb[kTileSplit][6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) tb[a] = tbox[6 * t + a];
+#pragma unroll
+  for (int j = 0; j < kTileSplit; ++j) {
+    const int64_t sub = min<int64_t>(t * kTileSplit + j, n_sub - 1);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) sb[j][a] = sbox[6 * sub + a];
+  }
   unsigned mask = 0;
-  if (box_dist2(tbox + 6 * t, lo, hi) <= lim) {
+  if (box_dist2(tb, lo, hi) <= lim) {
 #pragma unroll
     for (int j = 0; j < kTileSplit; ++j) {
       const int64_t sub = t * kTileSplit + j;
-      if (sub < n_sub && box_dist2(sbox + 6 * sub, lo, hi) <= lim) mask |= 1u << j;
+      if (sub < n_sub && box_dist2(sb[j], lo, hi) <= lim) mask |= 1u << j;
     }
   }
   return mask;
@@ -128,15 +138,27 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
   const int64_t Q = S.Q;
   const float* __restrict__ sp = S.sp;
   const int64_t s0 = qb * S.qpbA, s1 = min<int64_t>(Q, s0 + S.qpbA);
-  // bounding box of the block's positions (exact min/max: order independent)
+  // bounding box of the block's positions (exact min/max: order independent); the
+  // positions are read kCullU per lane at a time, lanes past the block's end taking
+  // its first position again
+  constexpr int kCullU = 8;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t i = s0 + lane; i < s1; i += 64) {
-    const float p[3] = {sp[i], sp[Q + i], sp[2 * Q + i]};
+  for (int64_t i0 = s0 + lane; i0 < s1; i0 += 64 * kCullU) {
+    float p[kCullU][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], p[a]);
-      hi[a] = fmaxf(hi[a], p[a]);
+    for (int u = 0; u < kCullU; ++u) {
+      const int64_t i = i0 + 64 * u < s1 ? i0 + 64 * u : s0;
+      p[u][0] = sp[i];
+      p[u][1] = sp[Q + i];
+      p[u][2] = sp[2 * Q + i];
     }
+#pragma unroll
+    for (int u = 0; u < kCullU; ++u)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], p[u][a]);
+        hi[a] = fmaxf(hi[a], p[u][a]);
+      }
   }
   float c[3];
 #pragma unroll
@@ -147,9 +169,20 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
   }
   // radius about the centre, formed as the first pass forms |p'|^2
   float rr = 0.0f;
-  for (int64_t i = s0 + lane; i < s1; i += 64) {
-    const float x = sp[i] - c[0], y = sp[Q + i] - c[1], z = sp[2 * Q + i] - c[2];
-    rr = fmaxf(rr, fmaf(z, z, fmaf(y, y, x * x)));
+  for (int64_t i0 = s0 + lane; i0 < s1; i0 += 64 * kCullU) {
+    float p[kCullU][3];
+#pragma unroll
+    for (int u = 0; u < kCullU; ++u) {
+      const int64_t i = i0 + 64 * u < s1 ? i0 + 64 * u : s0;
+      p[u][0] = sp[i];
+      p[u][1] = sp[Q + i];
+      p[u][2] = sp[2 * Q + i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCullU; ++u) {
+      const float x = p[u][0] - c[0], y = p[u][1] - c[1], z = p[u][2] - c[2];
+      rr = fmaxf(rr, fmaf(z, z, fmaf(y, y, x * x)));
+    }
   }
   rr = wave_maxf(rr);
   // Flag bound: the pass-A value of a pair within d_max errs by at most

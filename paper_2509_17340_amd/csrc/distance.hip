@@ -2,8 +2,9 @@
 // collision cost, Sec. IV-C).
 //
 //   k_min_dist_exact   direct form (p - o)^2 per pair over every query of a set and
-//                      every cloud point (Stage II); cloud tiles staged in LDS and
-//                      read as wave-wide broadcasts, queries in registers.
+//                      the cloud tiles within d_max of its wave's queries (Stage II);
+//                      cloud tiles staged in LDS with their boxes and read as wave-
+//                      wide broadcasts, queries in registers.
 //   k_pass_a_valu      pass A over the cull step's (query block, sub-tile) items: the
 //                      expanded form |o'|^2 - 2 p'.o' with query and cloud recentred on
 //                      the block's centre, three FMAs and half a min3 per pair; per
@@ -43,48 +44,75 @@ __device__ __forceinline__ float min3f(float a, float b, float c) {
   return r;
 }
 
-// Direct-form min over the cloud points [g0, g1) for R queries per lane; with
-// kIdx also the lowest point index attaining it (points are visited in
-// increasing index order within a lane and ties never replace).
-template <int R, bool kIdx>
+// Direct-form min over the cloud points [g0, g1) for R queries per lane, the wave's
+// queries lying in the box [qlo, qhi].  Each tile of kTilePts points is staged in LDS
+// with its bounding box; a wave skips a tile whose box lies farther than d_max from
+// its queries' box (squared limit `lim`, rounding margin included): no pair of that
+// tile can come under d_max, and from d_max on the collision penalty is 0, so such a
+// query's result only has to stay >= d_max^2 (+inf when no tile was evaluated).
+template <int R>
 __device__ inline void direct_range(const QuerySet& S, int64_t g0, int64_t g1, float4* tile,
-                                    const float* px, const float* py, const float* pz,
-                                    float* best, int32_t* bidx) {
-  const int tid = threadIdx.x;
+                                    float* tbox, const float qlo[3], const float qhi[3],
+                                    float lim, const float* px, const float* py,
+                                    const float* pz, float* best) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int kStep = 8;  // points per step of the pair loop (LDS reads issued together)
+  static_assert(kTilePts % kStep == 0, "a tile holds whole steps");
   for (int64_t base = g0; base < g1; base += kTilePts) {
     const int cnt = (int)min<int64_t>(kTilePts, g1 - base);
-    const int cnt2 = (cnt + 1) & ~1;  // even: the loop takes points in pairs
-    for (int pt = tid; pt < cnt2; pt += kBlock) {
+    const int cnt8 = (cnt + kStep - 1) / kStep * kStep;  // padded with far points
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int pt = tid; pt < cnt8; pt += kBlock) {
       const int64_t g = base + pt;
       const bool in = pt < cnt;
       const int64_t gg = in ? g : base;  // always a valid address
       const float x = S.cloud[3 * gg], y = S.cloud[3 * gg + 1], z = S.cloud[3 * gg + 2];
       tile[pt] = in ? make_float4(x, y, z, 0.0f) : make_float4(kFar, kFar, kFar, 0.0f);
+      lo[0] = fminf(lo[0], x);
+      lo[1] = fminf(lo[1], y);
+      lo[2] = fminf(lo[2], z);
+      hi[0] = fmaxf(hi[0], x);
+      hi[1] = fmaxf(hi[1], y);
+      hi[2] = fmaxf(hi[2], z);
     }
-    __syncthreads();
-#pragma unroll 2
-    for (int j = 0; j < cnt2; j += 2) {
-      const float4 a = tile[j];
-      const float4 c = tile[j + 1];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float ax = px[r] - a.x, ay = py[r] - a.y, az = pz[r] - a.z;
-        const float cx = px[r] - c.x, cy = py[r] - c.y, cz = pz[r] - c.z;
-        const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
-        const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-        if constexpr (kIdx) {
-          const int ia = (int)(base + j);
-          if (da < best[r]) {
-            best[r] = da;
-            bidx[r] = ia;
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = wave_minf(lo[a]);
+      hi[a] = wave_maxf(hi[a]);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        tbox[6 * w + a] = lo[a];
+        tbox[6 * w + 3 + a] = hi[a];
+      }
+    __syncthreads();
+    float b[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      b[a] = tbox[a];
+      b[3 + a] = tbox[3 + a];
+#pragma unroll
+      for (int v = 1; v < kBlock / 64; ++v) {
+        b[a] = fminf(b[a], tbox[6 * v + a]);
+        b[3 + a] = fmaxf(b[3 + a], tbox[6 * v + 3 + a]);
+      }
+    }
+    if (box_dist2(b, qlo, qhi) <= lim) {  // the same for every lane of the wave
+      for (int j = 0; j < cnt8; j += kStep) {
+        float4 o[kStep];
+#pragma unroll
+        for (int i = 0; i < kStep; ++i) o[i] = tile[j + i];
+#pragma unroll
+        for (int i = 0; i < kStep; i += 2)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const float ax = px[r] - o[i].x, ay = py[r] - o[i].y, az = pz[r] - o[i].z;
+            const float cx = px[r] - o[i + 1].x, cy = py[r] - o[i + 1].y, cz = pz[r] - o[i + 1].z;
+            const float da = fmaf(az, az, fmaf(ay, ay, ax * ax));
+            const float dc = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+            best[r] = min3f(best[r], da, dc);
           }
-          if (dc < best[r]) {
-            best[r] = dc;
-            bidx[r] = ia + 1;
-          }
-        } else {
-          best[r] = min3f(best[r], da, dc);
-        }
       }
     }
     __syncthreads();
@@ -93,44 +121,63 @@ __device__ inline void direct_range(const QuerySet& S, int64_t g0, int64_t g1, f
 
 // Every query of an exact set.  Block = (query block of R * kBlock queries, cloud
 // chunk); R (queries per lane) is sized to the set, so that small sets leave few
-// lanes idle.
+// lanes idle.  Wave w takes the block's queries [w R 64, (w + 1) R 64), consecutive
+// positions of a few rollouts, so that their box is small.
 template <int R>
-__device__ inline void exact_block(const QuerySet& S, int qb, int ch, float4* tile) {
-  const int tid = threadIdx.x;
+__device__ inline void exact_block(const QuerySet& S, int qb, int ch, float lim, float4* tile,
+                                   float* tbox) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t q0 = (int64_t)qb * (R * kBlock) + (int64_t)w * (R * 64) + lane;
   float px[R], py[R], pz[R], best[R];
+  float qlo[3] = {INFINITY, INFINITY, INFINITY}, qhi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t q = (int64_t)qb * (R * kBlock) + r * kBlock + tid;
+    const int64_t q = q0 + r * 64;
     const int64_t qq = q < S.Q ? q : 0;  // out-of-range lanes read query 0, never stored
     px[r] = S.px[qq];
     py[r] = S.py[qq];
     pz[r] = S.pz[qq];
     best[r] = __uint_as_float(kInfBits);
+    if (q < S.Q) {
+      qlo[0] = fminf(qlo[0], px[r]);
+      qlo[1] = fminf(qlo[1], py[r]);
+      qlo[2] = fminf(qlo[2], pz[r]);
+      qhi[0] = fmaxf(qhi[0], px[r]);
+      qhi[1] = fmaxf(qhi[1], py[r]);
+      qhi[2] = fmaxf(qhi[2], pz[r]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qlo[a] = wave_minf(qlo[a]);
+    qhi[a] = wave_maxf(qhi[a]);
   }
   const int64_t g0 = (int64_t)ch * S.chunk_pts;
   const int64_t g1 = min<int64_t>(g0 + S.chunk_pts, S.n_points);
-  direct_range<R, false>(S, g0, g1, tile, px, py, pz, best, nullptr);
+  direct_range<R>(S, g0, g1, tile, tbox, qlo, qhi, lim, px, py, pz, best);
   unsigned* out = S.out + (int64_t)(blockIdx.x % max(S.n_copies, 1)) * S.Q;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t q = (int64_t)qb * (R * kBlock) + r * kBlock + tid;
-    if (q < S.Q) atomicMin(out + q, __float_as_uint(best[r]));
+    const int64_t q = q0 + r * 64;
+    // the outputs start at +inf: a query no evaluated pair reached has nothing to add
+    if (q < S.Q && best[r] < __uint_as_float(kInfBits)) atomicMin(out + q, __float_as_uint(best[r]));
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_min_dist_exact(const QuerySet* __restrict__ sets,
-                                                           int n_sets) {
+                                                           int n_sets, float lim) {
   __shared__ float4 tile[kTilePts];
+  __shared__ float tbox[6 * (kBlock / 64)];
   const int64_t bid = blockIdx.x;
   const int s = find_owner(sets, n_sets, bid, [](const QuerySet& q) { return q.block_base; });
   const QuerySet S = sets[s];
   const int64_t local = bid - S.block_base;
   const int qb = (int)(local / S.n_chunks), ch = (int)(local % S.n_chunks);
   switch (S.qpbA / kBlock) {  // block-uniform
-    case 1: exact_block<1>(S, qb, ch, tile); break;
-    case 2: exact_block<2>(S, qb, ch, tile); break;
-    case 4: exact_block<4>(S, qb, ch, tile); break;
-    default: exact_block<kQueriesPerLane>(S, qb, ch, tile); break;
+    case 1: exact_block<1>(S, qb, ch, lim, tile, tbox); break;
+    case 2: exact_block<2>(S, qb, ch, lim, tile, tbox); break;
+    case 4: exact_block<4>(S, qb, ch, lim, tile, tbox); break;
+    default: exact_block<kQueriesPerLane>(S, qb, ch, lim, tile, tbox); break;
   }
 }
 
@@ -802,8 +849,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter_nearest(const QuerySet* __re
 }  // namespace
 
 hipError_t launch_min_dist(const QuerySet* d_sets, int n_sets, int64_t total_blocks,
-                           hipStream_t s) {
-  if (total_blocks > 0) k_min_dist_exact<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets);
+                           float d_max, hipStream_t s) {
+  // tiles farther than d_max from a wave's queries are skipped; the limit carries a
+  // relative margin for the rounding of the box and pair distances
+  const float lim = d_max * d_max * (1.0f + 1e-5f) + 1e-6f;
+  if (total_blocks > 0)
+    k_min_dist_exact<<<(unsigned)total_blocks, kBlock, 0, s>>>(d_sets, n_sets, lim);
   return hipGetLastError();
 }
 

@@ -587,6 +587,53 @@ def test_stage2_rejects_instance_through_obstacle():
     assert np_(ps.S2)[0] >= 1e6
 
 
+def test_stage2_skipped_tiles_keep_every_point_within_d_max():
+    """Stage II skips, per wave of positions, the cloud tiles whose box lies beyond
+    d_max of the wave's positions (the collision penalty is 0 from d_max on).  A cloud
+    of far filler points, whose tiles are all skipped, with single points planted at
+    0.3 to 1.02 d_max from chosen rollout positions at scattered indices: S2 matches
+    the oracle, whose collision terms these points set."""
+    from oracle.dynamics import rollout
+    rng = np.random.default_rng(41)
+    prob = dict(make_plain_problem())
+    prm = prob["params"]
+    M, N = 5, 30
+    u = np.zeros((M, N, 4), np.float32)  # body rates that fan the instances out
+    u[..., 0] = 10.5
+    u[..., 1] = np.linspace(-1.0, 1.0, M, dtype=np.float32)[:, None]
+    u[..., 2] = np.float32([0.3, -0.3, 0.0, 0.3, -0.3])[:, None]
+    x0 = np.float32([0, 0, 0, 1, 0, 0, 0, 3.0, 0, 0])
+    pos = rollout(x0, u, prm["dt"], prm["mass"], prm["gravity"])[:, 1:, :3]
+    d_max = float(prm["d_max"])
+    # filler: a shell 25-35 m out, beyond d_max of every position
+    P = 14000
+    v = rng.normal(size=(P, 3))
+    filler = v / np.linalg.norm(v, axis=1, keepdims=True) * rng.uniform(25, 35, (P, 1))
+    planted, k = [], 0
+    for m in range(M):
+        for t in (3, 11, 19, 27):
+            f = (0.3, 0.6, 0.9, 0.99, 1.02)[k % 5]
+            w = rng.normal(size=3)
+            planted.append(pos[m, t] + f * d_max * w / np.linalg.norm(w))
+            k += 1
+    idx = np.sort(rng.choice(P, size=len(planted), replace=False))
+    cloud = filler.copy()
+    cloud[idx] = np.asarray(planted)
+    prob.update(M=M, N=N, u_nom=u, x0=x0, M_h=M, M_v=1, cloud=cloud.astype(np.float32),
+                anchors=pos[:, -1].astype(np.float32))
+    print("stage2 planted points near d_max", flush=True)
+    ps = PlanStep(prob)
+    ps.stage2()
+    sync()
+    o = OM.select_best(prob, u)
+    S2 = np_(ps.S2)
+    assert (o["d"] < d_max).sum() >= 12  # the planted points reach the collision term
+    assert np.all(np.abs(S2 - o["S2"]) <= 1e-4 * np.abs(o["S2"]))
+    srt = np.sort(o["S2"])
+    if (srt[1] - srt[0]) > 1e-6 * abs(srt[0]):
+        assert int(np_(ps.best)[0]) == o["best"]
+
+
 # ----------------------------------------------------------------------------
 # the paper's operating point: 120 x 60 partition, 200k-point cloud, P_f collision set
 # ----------------------------------------------------------------------------
