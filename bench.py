@@ -233,24 +233,31 @@ def distance_rooflines(kt, steps, stats, brute_pairs, variant, label):
     ms_a, n_a = kt["min_dist"]
     if n_a:
         t = ms_a * 1e-3
-        rate = stats["pairs_a"] / t
+        rate = stats["pairs_a_eval"] / t
+        prod_rate = stats["pairs_a_products"] / t
         achieved = FLOP_PER_PAIR * rate / 1e12
         a = {"bound": va["bound"], "kernel": f"{va['kernel']} ({label}, first pass; autotuned "
                                              f"variant {variant})",
              "kernel_name": va["kernel"],
              "achieved": achieved, "peak": va["peak"], "unit": "TFLOP/s",
              "peak_is": va["unit_note"], "frac": achieved / va["peak"],
-             "flop_counted": "8 per (position, point) pair evaluated: cull items x block "
-                             "positions x sub-tile points",
-             "pairs_per_launch": stats["pairs_a"] / n_a, "avg_launch_ms": ms_a / n_a,
+             "flop_counted": "8 per (position, point) pair evaluated: per cull item, each "
+                             "wave's existing positions x the points of the 32-point groups "
+                             "it takes (groups beyond reach of the wave's positions skipped)",
+             "pairs_per_launch": stats["pairs_a_eval"] / n_a, "avg_launch_ms": ms_a / n_a,
              "pairs_per_s": rate,
-             "executed_tflops": va["executed_flop_per_pair"] * rate / 1e12,
-             "executed_frac": va["executed_flop_per_pair"] * rate / 1e12 / va["peak"],
+             "listed_pairs_per_launch": stats["pairs_a"] / n_a,
+             "executed_pairs_per_launch": stats["pairs_a_products"] / n_a,
+             "executed_tflops": va["executed_flop_per_pair"] * prod_rate / 1e12,
+             "executed_frac": va["executed_flop_per_pair"] * prod_rate / 1e12 / va["peak"],
+             "executed_is": "the matrix-core products' pairs (32 points x 32 positions, "
+                            "padding included) at 32 FLOP per pair" if va["bound"] == "mfma"
+                            else "the evaluated pairs at the FLOP the kernel executes per pair",
              "brute_force_pairs_per_launch": brute_pairs / n_a,
              "brute_force_equivalent_tflops": FLOP_PER_PAIR * brute_pairs / t / 1e12}
         if va["bound"] == "mfma":
             a["pair_ceiling_per_s"] = F16S_PAIR_CEILING
-            a["frac_of_pair_ceiling"] = rate / F16S_PAIR_CEILING
+            a["frac_of_pair_ceiling"] = prod_rate / F16S_PAIR_CEILING
         out["pass_a"] = a
     ms_b, n_b = kt["min_dist_exact"]
     if n_b:

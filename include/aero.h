@@ -422,6 +422,11 @@ typedef struct aero_distance_stats {
   int64_t positions;    /* rollout positions of the two-pass sets                        */
   int64_t pairs_b_eval; /* position-point pairs pass B evaluates exactly: each listed
                            query against the point groups within its cap                 */
+  int64_t pairs_a_eval; /* position-point pairs pass A evaluates: the matrix-core variants
+                           skip, per wave, the 32-point groups beyond reach of the wave's
+                           positions (the VALU variant: pairs_a)                         */
+  int64_t pairs_a_products; /* pairs of the matrix-core products pass A runs (32 points x
+                           32 positions each, padding included; VALU: pairs_a)            */
 } aero_distance_stats;
 int aero_read_distance_stats(const aero_problem* h_problems, int32_t n_problems, const void* d_ws,
                              size_t ws_bytes, aero_distance_stats* h_out);

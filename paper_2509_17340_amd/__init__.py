@@ -459,12 +459,14 @@ def set_pass_a_cull(on=True):
 
 class DistanceStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("items", "pairs_a", "items_b", "pairs_b",
-                                              "items_whole", "positions", "pairs_b_eval")]
+                                              "items_whole", "positions", "pairs_b_eval",
+                                              "pairs_a_eval", "pairs_a_products")]
 
 
 def distance_stats(problems, ws, ws_bytes=None):
     """Work of the two distance passes of the last mppi_step on `ws` (synchronous):
-    dict with items, pairs_a, items_b, pairs_b, items_whole, positions, pairs_b_eval."""
+    dict with items, pairs_a, items_b, pairs_b, items_whole, positions, pairs_b_eval,
+    pairs_a_eval, pairs_a_products."""
     arr = _problem_array(problems)
     out = DistanceStats()
     nbytes = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes

@@ -333,6 +333,12 @@ hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* 
                                 int variant, int grid, hipStream_t s);
 // Pass B over the marked items (the hit words of every set of the call share one array);
 // track_nearest: some set keeps nearest indices (nn).
+// Pairs pass A evaluates on the items of the last call: h_pairs[0] existing positions x
+// points of the groups taken, h_pairs[1] matrix-core product pairs (synchronous, null
+// stream).
+hipError_t count_pass_a_pairs(const QuerySet* d_sets, int n_sets, const int2* items,
+                              const int32_t* item_count, int64_t max_items,
+                              unsigned long long* h_pairs);
 // Pairs pass B evaluates on the items of the last call (synchronous, null stream).
 hipError_t count_pass_b_pairs(const QuerySet* d_sets, int n_sets, const int2* items,
                               const int32_t* item_count, const unsigned char* hitf,

@@ -1232,6 +1232,11 @@ int aero_read_distance_stats(const aero_problem* h, int32_t n, const void* d_ws,
       hipSuccess)
     return AERO_ERR_DEVICE;
   out->pairs_b_eval = (int64_t)ev;
+  unsigned long long ea[2] = {0, 0};
+  if (count_pass_a_pairs(pl.d_sets, n, pl.items, pl.item_count, pl.item_cap, ea) != hipSuccess)
+    return AERO_ERR_DEVICE;
+  out->pairs_a_eval = (int64_t)ea[0];
+  out->pairs_a_products = (int64_t)ea[1];
   return AERO_OK;
 }
 

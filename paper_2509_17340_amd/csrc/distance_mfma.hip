@@ -270,7 +270,97 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
   flush();
 }
 
+// The pairs pass A evaluates, for the statistics call: the same 32-point groups each
+// wave takes (the matrix-core variants skip the groups beyond reach of the wave's
+// positions; the VALU variant takes every group).  pass_a_pairs[0] sums existing
+// positions x points of the groups taken, pass_a_pairs[1] the matrix-core products'
+// pairs (32 points x the wave's 32 COLS columns per group taken, padding included).
+__device__ unsigned long long pass_a_pairs[2];
+__global__ __launch_bounds__(kBlock) void k_pass_a_count(const QuerySet* __restrict__ sets,
+                                                         int n_sets,
+                                                         const int2* __restrict__ items,
+                                                         const int32_t* __restrict__ item_count) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t total = *item_count;
+  SetCache cache{0, 0, 0};
+  unsigned long long ev = 0, pr = 0;  // this wave's sums (lane 0)
+  for (int64_t i = blockIdx.x; i < total; i += gridDim.x) {
+    const int2 it = items[i];
+    const QuerySet& S = sets[set_of(sets, n_sets, it.x, cache)];
+    if (!block_of(S, it.x) || S.n_points <= 0) continue;
+    const unsigned ys = (unsigned)it.y;
+    const int64_t g0 = (int64_t)(ys & 0x7fffffffu) * kSubPts;
+    const bool srt = (ys >> 31) != 0;
+    const int cnt = (g0 < S.n_points && (!srt || S.scloud))
+                        ? (int)min<int64_t>(kSubPts, S.n_points - g0)
+                        : 0;
+    if (cnt <= 0) continue;
+    const int64_t qb = it.x - S.qb_base, Q = S.Q;
+    const int qpb = S.qpbA;
+    if (qpb == kQueriesPerBlock) {  // the VALU pass: every group of the item
+      if (threadIdx.x == 0) {
+        const int64_t nq = min<int64_t>(qpb, Q - qb * qpb);
+        ev += nq * cnt;
+        pr += nq * cnt;
+      }
+      continue;
+    }
+    const int per_w = qpb / 4;  // 32 COLS positions per wave
+    const int64_t s0 = qb * qpb + (int64_t)w * per_w;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = lane; j < per_w; j += 64) {
+      const int64_t q = s0 + j;
+      if (q >= Q) break;
+      const float p[3] = {S.sp[q], S.sp[Q + q], S.sp[2 * Q + q]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], p[a]);
+        hi[a] = fmaxf(hi[a], p[a]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = wave_minf(lo[a]);
+      hi[a] = wave_maxf(hi[a]);
+    }
+    const int64_t nqw = max<int64_t>(0, min<int64_t>(per_w, Q - s0));
+    const float wlim = S.cull ? reach_limit(S.binfo[qb].w, S.d_max) : INFINITY;
+    const float* gbs = (srt && S.scloud ? S.sgbox : S.gbox) +
+                       6 * (int64_t)(ys & 0x7fffffffu) * kGroupsPerSub;
+    const uint64_t keep = __ballot(lane < kGroupsPerSub && lane * 32 < cnt &&
+                                   box_dist2(gbs + 6 * min(lane, kGroupsPerSub - 1), lo, hi) <=
+                                       wlim);
+    if (lane == 0)
+      for (int g = 0; g < kGroupsPerSub; ++g)
+        if ((keep >> g) & 1ull) {
+          ev += (unsigned long long)(nqw * min(32, cnt - 32 * g));
+          pr += (unsigned long long)(32 * per_w);
+        }
+  }
+  if (lane == 0) {
+    atomicAdd(&pass_a_pairs[0], ev);
+    atomicAdd(&pass_a_pairs[1], pr);
+  }
+}
+
 }  // namespace
+
+hipError_t count_pass_a_pairs(const QuerySet* d_sets, int n_sets, const int2* items,
+                              const int32_t* item_count, int64_t max_items,
+                              unsigned long long* h_pairs) {
+  const unsigned long long zero[2] = {0, 0};
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(pass_a_pairs), zero, sizeof zero, 0,
+                                   hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  if (max_items > 0) {
+    const unsigned grid = (unsigned)(max_items < 4096 ? max_items : 4096);
+    k_pass_a_count<<<grid, kBlock, 0, 0>>>(d_sets, n_sets, items, item_count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+  return hipMemcpyFromSymbol(h_pairs, HIP_SYMBOL(pass_a_pairs), sizeof zero, 0,
+                             hipMemcpyDeviceToHost);
+}
 
 hipError_t launch_pass_a_matrix(const QuerySet* d_sets, int n_sets, const int2* items,
                                 const int32_t* item_count, unsigned char* hitf, int64_t max_items,

@@ -457,8 +457,13 @@ def test_distance_stats_invariants():
             assert st["positions"] == Q
             assert st["pairs_a"] >= st["pairs_b"] >= st["pairs_b_eval"] > 0
             assert st["pairs_b_eval"] < st["pairs_b"]
+            # pass A's evaluated pairs: within the listed ones; its matrix-core products
+            # cover them (padding included)
+            assert st["pairs_b_eval"] <= st["pairs_a_eval"] <= st["pairs_a"]
+            assert st["pairs_a_products"] >= st["pairs_a_eval"]
             if not cull:
                 assert st["pairs_a"] == Q * ps.n_points
+                assert st["pairs_a_eval"] == st["pairs_a"]
     finally:
         aero.set_pass_a_cull(1)
 
