@@ -226,10 +226,16 @@ k_pass_a_f16s(const QuerySet* __restrict__ sets, int n_sets, const int2* __restr
     const uint64_t keep = __ballot(lane < kGroupsPerSub && lane * 32 < icnt &&
                                    box_dist2(gbs + 6 * min(lane, kGroupsPerSub - 1), wlo, whi) <=
                                        wlim);
-    const int cnt32 = (icnt + 31) & ~31;  // groups of 32 points; the padding is far
-    for (int g = 0; g < cnt32; g += 32) {
-      if (!((keep >> (g >> 5)) & 1ull)) continue;  // wave-uniform
-      const half8 a = tl[g + col];
+    // the groups taken, in order (only groups with points can be set: lane * 32 <
+    // icnt), each one's point record read from LDS while the previous one's products
+    // are reduced
+    uint32_t left = (uint32_t)keep;
+    half8 a_next = {};
+    if (left) a_next = tl[32 * (__ffs(left) - 1) + col];
+    while (left) {  // wave-uniform
+      const half8 a = a_next;
+      left &= left - 1u;
+      if (left) a_next = tl[32 * (__ffs(left) - 1) + col];
       // kF16Pipe products in flight: the minima of one overlap the next MFMA
 #pragma unroll
       for (int b = 0; b < COLS; b += kF16Pipe) {
