@@ -255,6 +255,25 @@ def test_stage1_ragged_shapes(M, K, N, P, pass_a):
     compare_stage1(prob, g)
 
 
+def test_stage1_cloud_beyond_64_super_tiles():
+    """A 1.3M-point cloud has 80 boxes of 16 tiles, more than one wave round of the
+    cull step's super-tile scan, in both cloud orders (16,384 positions: the positions
+    and the cloud are spatially sorted).  Sampled S1 and distances against the
+    oracle's k-d tree search."""
+    from oracle.cost import nearest_kdtree
+    rng = np.random.default_rng(77)
+    M, K, N, P = 2, 1024, 8, 1_300_000
+    prob = dict(make_plain_problem())
+    prob.update(M=M, K=K, N=N, M_h=M, M_v=1)
+    prob["cloud"] = (rng.normal(size=(P, 3)) * 4 + np.float32([4, 0, 0])).astype(np.float32)
+    prob["u_nom"] = (np.float32([9.81, 0, 0, 0]) + rng.normal(size=(M, N, 4)) * 0.3).astype(np.float32)
+    prob["anchors"] = (rng.normal(size=(M, 3)) * 3).astype(np.float32)
+    print(f"stage1 M={M} K={K} N={N} P={P}", flush=True)
+    ps, g = run_stage1(prob)
+    sub = np.sort(rng.choice(K, 32, replace=False))
+    print(compare_stage1(prob, g, samples=sub, nearest_fn=nearest_kdtree))
+
+
 def test_stage1_iterations_teacher_forced():
     """Three MPPI iterations in one planning step: each iteration against the oracle
     started from the GPU's u_nom before it; the fused loop equals the single calls."""
