@@ -232,9 +232,10 @@ int aero_build_guides(const float* h_p0, const float* h_v0, const float* h_a0,
                       float horizon_T, int32_t M, float* d_coef, void* stream);
 
 /* One Stage-I MPPI iteration for every instance of every problem (Sec. III-B,
- * Sec. IV-C): Philox noise, clipped controls, RK4 rollouts, S1 (brute-force nearest
- * distance to the raw cloud for J_col), softmax weights and the update of u_nom
- * (in place).  Problems may differ in cloud size, M, K and N; n_problems > 1 runs
+ * Sec. IV-C): Philox noise, clipped controls, RK4 rollouts, S1 (J_col from the
+ * nearest distance to the raw cloud, exact wherever it is below d_max; a position
+ * with no point within d_max, where the penalty is 0, reports a distance of at least
+ * d_max), softmax weights and the update of u_nom (in place).  Problems may differ in cloud size, M, K and N; n_problems > 1 runs
  * them in one batched launch sequence.
  *   h_problems  host array [n_problems]
  *   d_ws        device workspace of aero_workspace_size(AERO_CALL_MPPI_STEP, ...)
@@ -247,7 +248,9 @@ int aero_mppi_step(const aero_params* h_prm, const aero_problem* h_problems,
                    int32_t n_problems, void* d_ws, size_t ws_bytes, void* stream);
 
 /* Stage II (Sec. IV-C): roll out each instance's u_nom without noise, score it with
- * S2 = w_goal J_goal + w_col J_col and pick the lowest (ties: lowest m).
+ * S2 = w_goal J_goal + w_col J_col and pick the lowest (ties: lowest m).  J_col reads
+ * the exact nearest distance wherever it is below d_max (cloud tiles farther than
+ * d_max from a group of positions are skipped: the penalty is 0 there).
  *   d_S2    [sum_b M_b] float64, problems concatenated
  *   d_best  [n_problems] int32
  * coef, S1, delta_eff and min_dist2 of the problems are ignored.
