@@ -658,6 +658,33 @@ def test_stage2_skipped_tiles_keep_every_point_within_d_max():
         assert int(np_(ps.best)[0]) == o["best"]
 
 
+@pytest.mark.parametrize("M,N", [(80, 64), (128, 100), (256, 80)],
+                         ids=["2_per_lane", "4_per_lane", "8_per_lane"])
+def test_stage2_many_positions_per_lane(M, N):
+    """Stage II sets of more than 4096 positions hold 2, 4 or 8 positions per lane
+    (5,120, 12,800 and 20,480 here), each wave's box over its lanes' positions: S2
+    and the selected instance against the oracle (k-d tree search)."""
+    from oracle.cost import nearest_kdtree
+    rng = np.random.default_rng(M + N)
+    prob = dict(make_plain_problem())
+    u = np.zeros((M, N, 4), np.float32)
+    u[..., 0] = 9.81 + rng.normal(size=(M, 1)).astype(np.float32) * 0.5
+    u[..., 1:] = rng.normal(size=(M, 1, 3)).astype(np.float32) * 0.4
+    prob.update(M=M, N=N, u_nom=u, M_h=M, M_v=1,
+                anchors=(rng.normal(size=(M, 3)) * 3).astype(np.float32))
+    print(f"stage2 M={M} N={N} ({M * N} positions) P={len(prob['cloud'])}", flush=True)
+    ps = PlanStep(prob)
+    ps.stage2()
+    sync()
+    o = OM.select_best(prob, u, nearest_fn=nearest_kdtree)
+    S2 = np_(ps.S2)
+    assert (o["d"] < float(prob["params"]["d_max"])).sum() > 0  # some collision terms
+    assert np.all(np.abs(S2 - o["S2"]) <= 1e-4 * np.abs(o["S2"]))
+    srt = np.sort(o["S2"])
+    if (srt[1] - srt[0]) > 1e-6 * abs(srt[0]):
+        assert int(np_(ps.best)[0]) == o["best"]
+
+
 # ----------------------------------------------------------------------------
 # the paper's operating point: 120 x 60 partition, 200k-point cloud, P_f collision set
 # ----------------------------------------------------------------------------
