@@ -658,6 +658,30 @@ def test_stage2_skipped_tiles_keep_every_point_within_d_max():
         assert int(np_(ps.best)[0]) == o["best"]
 
 
+@pytest.mark.parametrize("P", [0, 1, 7, 1025])
+def test_stage2_tiny_clouds(P):
+    """Stage II against clouds of no point, one point, a partial point step and one
+    point past a tile: S2 against the oracle (an empty cloud adds no collision term)."""
+    rng = np.random.default_rng(P + 5)
+    M, N = 3, 20
+    prob = dict(make_plain_problem())
+    u = np.zeros((M, N, 4), np.float32)
+    u[..., 0] = 9.81
+    u[..., 1:] = rng.normal(size=(M, 1, 3)).astype(np.float32) * 0.3
+    x0 = np.float32([0, 0, 0, 1, 0, 0, 0, 2.0, 0, 0])
+    # points near the rollouts' path (within d_max of some positions)
+    cloud = (np.float32([1.5, 0.0, 0.0]) + rng.normal(size=(P, 3)) * 0.5).astype(np.float32)
+    prob.update(M=M, N=N, u_nom=u, x0=x0, M_h=M, M_v=1, cloud=cloud.reshape(-1, 3),
+                anchors=(rng.normal(size=(M, 3)) * 3).astype(np.float32))
+    print(f"stage2 tiny cloud P={P}", flush=True)
+    ps = PlanStep(prob)
+    ps.stage2()
+    sync()
+    o = OM.select_best(prob, u)
+    S2 = np_(ps.S2)
+    assert np.all(np.abs(S2 - o["S2"]) <= 1e-4 * np.abs(o["S2"]))
+
+
 @pytest.mark.parametrize("M,N", [(80, 64), (128, 100), (256, 80)],
                          ids=["2_per_lane", "4_per_lane", "8_per_lane"])
 def test_stage2_many_positions_per_lane(M, N):
