@@ -126,12 +126,22 @@ __device__ inline void scan_reach(const float* __restrict__ ub, const float* __r
   }
 }
 
-// One wave per query block (four per workgroup, no workgroup barriers).
-__global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ sets, int n_sets,
-                                                 int64_t total_qblocks, int variant) {
-  const int lane = threadIdx.x & 63;
-  const int64_t gqb = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (gqb >= total_qblocks) return;  // wave-uniform
+// One wave per query block, kCullWaves per workgroup.  The waves' item counts meet in
+// LDS and the workgroup takes its run of the item list with one atomic addition (one
+// per wave put every wave of the grid in line on a single counter).
+#ifndef AERO_CULL_WAVES
+#define AERO_CULL_WAVES 4
+#endif
+constexpr int kCullWaves = AERO_CULL_WAVES;
+__global__ __launch_bounds__(64 * kCullWaves) void k_cull(const QuerySet* __restrict__ sets,
+                                                          int n_sets, int64_t total_qblocks,
+                                                          int variant) {
+  __shared__ int wstart[kCullWaves];  // each wave's count, then its offset in the run
+  __shared__ int wgbase;              // the workgroup's run in the item list
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t gqb0 = (int64_t)blockIdx.x * kCullWaves + w;
+  const bool live = gqb0 < total_qblocks;  // wave-uniform
+  const int64_t gqb = live ? gqb0 : total_qblocks - 1;  // a valid block for the others
   const int s = find_owner(sets, n_sets, gqb, [](const QuerySet& q) { return q.qb_base; });
   const QuerySet& S = sets[s];
   const int64_t qb = gqb - S.qb_base;
@@ -199,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
     const float span = sqrtf(rr) * 1.001f + d_max;
     thr = span <= 64.0f ? d_max * d_max + 0x1p-15f * span * span + 1e-6f : INFINITY;
   }
-  if (lane == 0) S.binfo[qb] = make_float4(c[0], c[1], c[2], thr);
+  if (live && lane == 0) S.binfo[qb] = make_float4(c[0], c[1], c[2], thr);
   const int64_t n_tiles = S.n_tiles;
   const int64_t n_sub = ((int64_t)S.n_points + kSubPts - 1) / kSubPts;
   const float lim = S.cull ? reach_limit(thr, d_max) : INFINITY;
@@ -215,11 +225,22 @@ __global__ __launch_bounds__(kBlock) void k_cull(const QuerySet* __restrict__ se
     cnt_srt = wave_sum_i(cnt_srt);
   }
   const int order = (sorted_ok && cnt_srt < cnt_raw) ? 1 : 0;
-  const int cnt = order ? cnt_srt : cnt_raw;
-  if (cnt == 0) return;
-  int base = 0;
-  if (lane == 0) base = atomicAdd(S.item_count, cnt);
-  base = __shfl(base, 0, 64);
+  const int cnt = live ? (order ? cnt_srt : cnt_raw) : 0;
+  if (lane == 0) wstart[w] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int v = 0; v < kCullWaves; ++v) {
+      const int cv = wstart[v];
+      wstart[v] = tot;
+      tot += cv;
+    }
+    // wave 0 is live whenever any wave is, and every set of the call shares the counter
+    wgbase = tot > 0 ? atomicAdd(S.item_count, tot) : 0;
+  }
+  __syncthreads();
+  if (cnt == 0) return;  // wave-uniform; no barrier follows
+  const int base = wgbase + wstart[w];
   const float* __restrict__ ub = order ? S.subox : S.ubox;
   const float* __restrict__ tb = order ? S.stbox : S.tbox;
   const float* __restrict__ sb = order ? S.ssbox : S.sbox;
@@ -260,11 +281,10 @@ hipError_t launch_sorted_boxes(const QuerySet* d_sets, int n_sets, int64_t total
 
 hipError_t launch_cull(const QuerySet* d_sets, int n_sets, int64_t total_qblocks, int variant,
                        hipStream_t s) {
-  constexpr int per = kBlock / 64;
   if (total_qblocks > 0) {
     k_super_boxes<<<(unsigned)n_sets, kBlock, 0, s>>>(d_sets);
-    k_cull<<<(unsigned)((total_qblocks + per - 1) / per), kBlock, 0, s>>>(d_sets, n_sets,
-                                                                          total_qblocks, variant);
+    k_cull<<<(unsigned)((total_qblocks + kCullWaves - 1) / kCullWaves), 64 * kCullWaves, 0, s>>>(
+        d_sets, n_sets, total_qblocks, variant);
   }
   return hipGetLastError();
 }
