@@ -5,13 +5,14 @@
 // cloud points within d_max of its queries (plus those whose first-pass value could
 // fall under the block's flag bound, all within the reach sqrt(2 thresh - d_max^2)).
 // The cloud is cut into tiles of kTilePts and sub-tiles of kSubPts consecutive
-// points with bounding boxes; a block lists every sub-tile whose box lies within
-// reach of the block's box, testing tiles first (a tile's box contains its
-// sub-tiles', and a super-tile's box its tiles').  Two orders of the cloud are considered when the cloud has been
-// spatially sorted: the order it was given in (a LiDAR sweep in beam order is already
-// made of compact runs) and the Morton order; each block takes the one that lists
-// fewer sub-tiles.  A block's items are written consecutively, so that the first pass
-// sets a block up once per run of its items.
+// points with bounding boxes, and runs of kSuperTiles tiles (super-tiles) with theirs;
+// a block lists every sub-tile whose box lies within reach of the block's box,
+// testing super-tiles, then their tiles, then the tiles' sub-tiles (each box contains
+// the boxes below it).  Two orders of the cloud are considered when the cloud has
+// been spatially sorted: the order it was given in (a LiDAR sweep in beam order is
+// already made of compact runs) and the Morton order; each block takes the one that
+// lists fewer sub-tiles.  A block's items are written consecutively, so that the
+// first pass sets a block up once per run of its items.
 //
 //   k_sorted_boxes  tile and sub-tile boxes of the sorted clouds
 //   k_super_boxes   boxes of kSuperTiles consecutive tiles, both orders
