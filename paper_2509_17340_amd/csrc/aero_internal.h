@@ -130,7 +130,7 @@ struct SortSet {
 // One set of query positions scored against one cloud by the distance kernels.
 //
 // Exact sets (items == nullptr) run the direct-form kernel over every query against
-// every cloud point.  Two-pass sets are cut into query blocks of qpbA consecutive
+// the cloud tiles within d_max of its wave's queries.  Two-pass sets are cut into query blocks of qpbA consecutive
 // (spatially sorted) positions.  The cull step gives each block a centre, a bound on
 // its pass-A rounding error, and the list of cloud sub-tiles whose bounding box lies
 // within reach of the block's box, in the raw or the sorted cloud order (whichever
