@@ -130,14 +130,14 @@ struct SortSet {
 // One set of query positions scored against one cloud by the distance kernels.
 //
 // Exact sets (items == nullptr) run the direct-form kernel over every query against
-// the cloud tiles within d_max of its wave's queries.  Two-pass sets are cut into query blocks of qpbA consecutive
-// (spatially sorted) positions.  The cull step gives each block a centre, a bound on
-// its pass-A rounding error, and the list of cloud sub-tiles whose bounding box lies
-// within reach of the block's box, in the raw or the sorted cloud order (whichever
-// lists fewer); pass A runs the recentred expanded form over those (block, sub-tile)
-// items only and records, per item, which of the block's queries came under the
-// bound there; pass B reruns the direct form for exactly those (query, sub-tile)
-// pairs.
+// the cloud tiles within d_max of its wave's queries.  Two-pass sets are cut into
+// query blocks of qpbA consecutive (spatially sorted) positions.  The cull step gives
+// each block a centre, a bound on its pass-A rounding error, and the list of cloud
+// sub-tiles whose bounding box lies within reach of the block's box, in the raw or
+// the sorted cloud order (whichever lists fewer); pass A runs the recentred expanded
+// form over those (block, sub-tile) items only and records, per item, which of the
+// block's queries came under the bound there; pass B reruns the direct form for
+// exactly those (query, sub-tile) pairs.
 struct QuerySet {
   const float* px;
   const float* py;
